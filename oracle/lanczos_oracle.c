@@ -1,0 +1,337 @@
+/*
+ * Lanczos oracle for the preconditioned eigenvalue-count estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, FP64 CPU implementation
+ * written directly from the paper (Vecharynski & Yang, "Preconditioned
+ * iterative methods for eigenvalue counts"), used to check the GPU library.
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  It shares no code with the GPU library.
+ *
+ * What it computes, per probe vector v_j and one shift tau
+ * (Section 3.1, Algorithm 1; Section 3.2, Algorithm 2 steps 3-4):
+ *
+ *   C = M (A - tau I) M^*                         (Section 2, eq. negi_T)
+ *   q_1 = v/|v|, q_0 = 0, beta_1 = 0
+ *   for i = 1..k:
+ *     w = C q_i - beta_i q_{i-1}
+ *     alpha_i = q_i^* w ;  w = w - alpha_i q_i
+ *     w = w - Q_i (Q_i^* w)                        (full reorthogonalization,
+ *                                                   one classical Gram-Schmidt
+ *                                                   pass against q_1..q_i)
+ *     beta_{i+1} = |w| ;  q_{i+1} = w / beta_{i+1}
+ *
+ * and returns alpha_1..alpha_k, beta_1..beta_{k+1} (beta_1 = 0) and |v|^2.
+ * The quadrature (eigendecomposition of J_k and the weighted count) is done
+ * by the Python half of the oracle.
+ *
+ * Breakdown (not discussed in the paper): when
+ *   beta_{i+1} <= 1e3 * eps * max(|alpha_1|..|alpha_i|, beta_2..beta_i)
+ * the Krylov space is invariant; the run stops with k_used = i and J_i is
+ * used (Proposition 1 makes the quadrature exact in that case).
+ *
+ * Preconditioners M (T = M^* M, all symmetric here):
+ *   kind 0: M = I.
+ *   kind 1: Jacobi, M_tau = |diag(A) - tau|^(-1/2), built per shift.
+ *   kind 2: M = sum_{j=0}^{d} c_j T_j(B), B = (2 (L + sI) - (lo + hi) I)/(hi - lo),
+ *           L the Dirichlet Laplacian of the grid `dims` (diagonal 2*ndim,
+ *           neighbours -1), evaluated by Clenshaw's recurrence.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int64_t n;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+    int prec_kind;
+    int ndim;
+    int dims[3];
+    double s, lo, hi;
+    int degree;
+    const double *coef;
+    double tau;
+    const double *jac; /* |a_rr - tau|^(-1/2), kind 1 only */
+} op_t;
+
+/* y = (A - tau I) x */
+static void shifted_matvec(const op_t *P, const double *x, double *y)
+{
+    for (int64_t r = 0; r < P->n; ++r) {
+        double acc = 0.0;
+        for (int32_t p = P->row_ptr[r]; p < P->row_ptr[r + 1]; ++p)
+            acc += P->val[p] * x[P->col_idx[p]];
+        y[r] = acc - P->tau * x[r];
+    }
+}
+
+/* y = L x, L the Dirichlet Laplacian on the grid (missing neighbours are 0) */
+static void laplacian(const op_t *P, const double *x, double *y)
+{
+    int nd = P->ndim;
+    int64_t d[3] = {1, 1, 1};
+    for (int a = 0; a < nd; ++a) d[3 - nd + a] = P->dims[a];
+    /* d[0] x d[1] x d[2] with the last axis contiguous */
+    for (int64_t i0 = 0; i0 < d[0]; ++i0)
+        for (int64_t i1 = 0; i1 < d[1]; ++i1)
+            for (int64_t i2 = 0; i2 < d[2]; ++i2) {
+                int64_t r = (i0 * d[1] + i1) * d[2] + i2;
+                double acc = 2.0 * nd * x[r];
+                if (i2 > 0) acc -= x[r - 1];
+                if (i2 + 1 < d[2]) acc -= x[r + 1];
+                if (nd >= 2) {
+                    if (i1 > 0) acc -= x[r - d[2]];
+                    if (i1 + 1 < d[1]) acc -= x[r + d[2]];
+                }
+                if (nd >= 3) {
+                    if (i0 > 0) acc -= x[r - d[1] * d[2]];
+                    if (i0 + 1 < d[0]) acc -= x[r + d[1] * d[2]];
+                }
+                y[r] = acc;
+            }
+}
+
+/* y = B x with B = (2 (L + sI) - (lo + hi) I) / (hi - lo) */
+static void cheb_B(const op_t *P, const double *x, double *y)
+{
+    laplacian(P, x, y);
+    double inv = 1.0 / (P->hi - P->lo);
+    for (int64_t r = 0; r < P->n; ++r)
+        y[r] = (2.0 * (y[r] + P->s * x[r]) - (P->lo + P->hi) * x[r]) * inv;
+}
+
+/* y = M x.  work: 3 vectors of n. */
+static void apply_M(const op_t *P, const double *x, double *y, double *work)
+{
+    int64_t n = P->n;
+    if (P->prec_kind == 0) {
+        memcpy(y, x, (size_t)n * sizeof(double));
+        return;
+    }
+    if (P->prec_kind == 1) {
+        for (int64_t r = 0; r < n; ++r) y[r] = P->jac[r] * x[r];
+        return;
+    }
+    /* Clenshaw: b_{d+1} = b_{d+2} = 0;
+     *           b_j = c_j x + 2 B b_{j+1} - b_{j+2}, j = d..1;
+     *           M x = c_0 x + B b_1 - b_2. */
+    double *b1 = work, *b2 = work + n, *Bb = work + 2 * n; /* b1 = b_{j+1}, b2 = b_{j+2} */
+    memset(b1, 0, (size_t)n * sizeof(double));
+    memset(b2, 0, (size_t)n * sizeof(double));
+    for (int j = P->degree; j >= 1; --j) {
+        cheb_B(P, b1, Bb);
+        for (int64_t r = 0; r < n; ++r) {
+            double bj = P->coef[j] * x[r] + 2.0 * Bb[r] - b2[r];
+            b2[r] = b1[r];
+            b1[r] = bj;
+        }
+    }
+    cheb_B(P, b1, Bb);
+    for (int64_t r = 0; r < n; ++r) y[r] = P->coef[0] * x[r] + Bb[r] - b2[r];
+}
+
+/* y = M (A - tau I) M x.  work: 5 vectors of n. */
+static void apply_C(const op_t *P, const double *x, double *y, double *work)
+{
+    double *t = work, *u = work + P->n, *mw = work + 2 * P->n;
+    apply_M(P, x, t, mw);
+    shifted_matvec(P, t, u);
+    apply_M(P, u, y, mw);
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t r = 0; r < n; ++r) s += a[r] * b[r];
+    return s;
+}
+
+/* Algorithm 1 for one probe.  Q: n x (k+1), column i holds q_{i+1}. */
+static int lanczos_one(const op_t *P, const double *v, int k, double *alpha, double *beta,
+                       double *nu_out, double *Q, double *w, double *h, double *work)
+{
+    int64_t n = P->n;
+    double nu = dot(n, v, v);
+    *nu_out = nu;
+    double inv = 1.0 / sqrt(nu);
+    for (int64_t r = 0; r < n; ++r) Q[r] = v[r] * inv; /* q_1 */
+    beta[0] = 0.0;                                        /* beta_1 */
+    double scale = 0.0;
+    for (int i = 1; i <= k; ++i) {
+        const double *qi = Q + (size_t)(i - 1) * n;
+        apply_C(P, qi, w, work);
+        if (i > 1) {
+            const double *qm = Q + (size_t)(i - 2) * n;
+            for (int64_t r = 0; r < n; ++r) w[r] -= beta[i - 1] * qm[r];
+        }
+        double a = dot(n, qi, w);
+        alpha[i - 1] = a;
+        for (int64_t r = 0; r < n; ++r) w[r] -= a * qi[r];
+        /* one classical Gram-Schmidt pass against q_1..q_i */
+        for (int l = 0; l < i; ++l) h[l] = dot(n, Q + (size_t)l * n, w);
+        for (int l = 0; l < i; ++l) {
+            const double *ql = Q + (size_t)l * n;
+            for (int64_t r = 0; r < n; ++r) w[r] -= h[l] * ql[r];
+        }
+        double b = sqrt(dot(n, w, w));
+        beta[i] = b;
+        if (fabs(a) > scale) scale = fabs(a);
+        if (i > 1 && beta[i - 1] > scale) scale = beta[i - 1];
+        if (b <= 1e3 * DBL_EPSILON * scale) return i; /* invariant Krylov space */
+        double *qn = Q + (size_t)i * n;
+        for (int64_t r = 0; r < n; ++r) qn[r] = w[r] / b;
+    }
+    return k;
+}
+
+/*
+ * Run Algorithm 1 for every probe j = 0..m-1 at shift tau.
+ *   V      n x m row-major probe block (v_j is column j)
+ *   alpha  m x k        (row j: alpha_1..alpha_k of probe j; unused tail = 0)
+ *   beta   m x (k+1)    (row j: beta_1 = 0, beta_2..beta_{k+1})
+ *   k_used m            (k, or the step at which the Krylov space became invariant)
+ *   nu     m            |v_j|^2
+ * Returns 0, or -1 on bad arguments / allocation failure, -2 if the Jacobi
+ * preconditioner is singular (a_rr = tau).
+ */
+int oracle_lanczos(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                   int prec_kind, int ndim, const int32_t *dims, double s, double lo, double hi,
+                   int degree, const double *coef, double tau, const double *V, int64_t m, int k,
+                   int nthreads, double *alpha, double *beta, int32_t *k_used, double *nu)
+{
+    if (n < 1 || m < 1 || k < 1 || k > n) return -1;
+    op_t P;
+    memset(&P, 0, sizeof P);
+    P.n = n;
+    P.row_ptr = row_ptr;
+    P.col_idx = col_idx;
+    P.val = val;
+    P.prec_kind = prec_kind;
+    P.ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) P.dims[a] = dims[a];
+    P.s = s;
+    P.lo = lo;
+    P.hi = hi;
+    P.degree = degree;
+    P.coef = coef;
+    P.tau = tau;
+    double *jac = NULL;
+    if (prec_kind == 1) {
+        jac = (double *)malloc((size_t)n * sizeof(double));
+        if (!jac) return -1;
+        for (int64_t r = 0; r < n; ++r) {
+            double arr = 0.0;
+            for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p)
+                if (col_idx[p] == r) arr = val[p];
+            double d = fabs(arr - tau);
+            if (d == 0.0) {
+                free(jac);
+                return -2;
+            }
+            jac[r] = 1.0 / sqrt(d);
+        }
+        P.jac = jac;
+    }
+    memset(alpha, 0, (size_t)m * k * sizeof(double));
+    memset(beta, 0, (size_t)m * (k + 1) * sizeof(double));
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *Q = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
+        double *w = (double *)malloc((size_t)n * sizeof(double));
+        double *v = (double *)malloc((size_t)n * sizeof(double));
+        double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+        double *h = (double *)malloc((size_t)(k + 1) * sizeof(double));
+        if (!Q || !w || !v || !work || !h) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t j = 0; j < m; ++j) {
+                for (int64_t r = 0; r < n; ++r) v[r] = V[r * m + j];
+                k_used[j] = lanczos_one(&P, v, k, alpha + j * k, beta + j * (k + 1), nu + j, Q, w,
+                                        h, work);
+            }
+        }
+        free(Q);
+        free(w);
+        free(v);
+        free(work);
+        free(h);
+    }
+    free(jac);
+    return failed ? -1 : 0;
+}
+
+/*
+ * Dense preconditioned operator C = M (A - tau I) M for small n, built column
+ * by column with the same operator code (used by moment tests of the oracle).
+ */
+int oracle_dense_operator(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          const double *val, int prec_kind, int ndim, const int32_t *dims, double s,
+                          double lo, double hi, int degree, const double *coef, double tau,
+                          double *Cout /* n x n row-major */)
+{
+    op_t P;
+    memset(&P, 0, sizeof P);
+    P.n = n;
+    P.row_ptr = row_ptr;
+    P.col_idx = col_idx;
+    P.val = val;
+    P.prec_kind = prec_kind;
+    P.ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) P.dims[a] = dims[a];
+    P.s = s;
+    P.lo = lo;
+    P.hi = hi;
+    P.degree = degree;
+    P.coef = coef;
+    P.tau = tau;
+    double *jac = NULL;
+    if (prec_kind == 1) {
+        jac = (double *)malloc((size_t)n * sizeof(double));
+        for (int64_t r = 0; r < n; ++r) {
+            double arr = 0.0;
+            for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p)
+                if (col_idx[p] == r) arr = val[p];
+            jac[r] = 1.0 / sqrt(fabs(arr - tau));
+        }
+        P.jac = jac;
+    }
+    double *e = (double *)calloc((size_t)n, sizeof(double));
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+    for (int64_t c = 0; c < n; ++c) {
+        e[c] = 1.0;
+        apply_C(&P, e, y, work);
+        e[c] = 0.0;
+        for (int64_t r = 0; r < n; ++r) Cout[r * n + c] = y[r];
+    }
+    free(e);
+    free(y);
+    free(work);
+    free(jac);
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,243 @@
+"""Oracle for the preconditioned Lanczos eigenvalue-count estimator.
+
+TEST INFRASTRUCTURE ONLY.  A plain FP64 CPU implementation, written from the
+paper (Vecharynski & Yang, "Preconditioned iterative methods for eigenvalue
+counts"), against which the GPU library is checked.  Only the tests, the
+smoke check and the benchmark's CPU-baseline leg may use it; the product path
+never does.  It shares no code with the GPU library: the Lanczos recurrence
+lives in `lanczos_oracle.c` (plain C, built with gcc), the quadrature below
+uses numpy's dense symmetric eigensolver.
+
+Estimator (one shift tau; Section 3.2, eq. rand_prec_quad and Algorithm 2):
+    s_j(tau) = |v_j|^2 * sum_{i : theta_i < 0} z_i(1)^2
+where theta_i, z_i are the eigenpairs of the k x k Lanczos matrix J_k of
+probe v_j (Section 3.1, eq. gauss_quad), and
+    n_(A - tau I) ~ (1/m) sum_j s_j(tau).
+Interval count (end of Section 3.2): c(xi, eta) = n_(A - eta I) - n_(A - xi I),
+run on the same probe block for both shifts.
+
+Generalized averaged Gauss rule (Section 3.4, eq. GA_Tk): J_k is replaced by
+the (2k-1) x (2k-1) tridiagonal matrix with diagonal
+(alpha_1..alpha_k, alpha_{k-1}..alpha_1) and off-diagonal
+(beta_2..beta_k, beta_{k+1}, beta_{k-1}..beta_2).
+
+Readings where the paper is silent (each listed in the design notes):
+  * the returned count is the unrounded mean (the brackets of Algorithm 2's
+    last step are display rounding);
+  * `variance` is the sample variance of the per-probe differences
+    d_j = s_j(eta) - s_j(xi) divided by m (NaN for m = 1);
+  * h(0) = 0 (strict theta < 0, eq. h), so the count is #{xi <= lambda < eta};
+  * smooth_w > 0 replaces h(theta) by S_w(theta) = erfc(theta / w) / 2
+    (an erf-smoothed step; w -> 0 recovers the paper's estimator).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lanczos_oracle.c")
+_LIB = os.path.join(_HERE, "liblanczos_oracle.so")
+_lib = None
+
+PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2}
+
+
+def build(force: bool = True) -> str:
+    """Compile the C half of the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.oracle_lanczos.restype = ctypes.c_int
+        lib.oracle_lanczos.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int, P,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_int, P, ctypes.c_double, P, ctypes.c_int64,
+                                       ctypes.c_int, ctypes.c_int, P, P, P, P]
+        lib.oracle_dense_operator.restype = ctypes.c_int
+        lib.oracle_dense_operator.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int,
+                                              P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_int, P, ctypes.c_double, P]
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def host_threads() -> int:
+    return len(os.sched_getaffinity(0))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _prec_args(prec, n):
+    kind = PREC_KINDS[prec.kind]
+    dims = np.zeros(3, dtype=np.int32)
+    nd = len(prec.dims) if prec.dims else 0
+    dims[:nd] = prec.dims
+    if kind == 2:
+        coef = np.ascontiguousarray(prec.coef, dtype=np.float64)
+        if int(np.prod(prec.dims)) != n:
+            raise ValueError("preconditioner grid does not match n")
+    else:
+        coef = np.zeros(1)
+    return kind, nd, dims, coef
+
+
+@dataclass
+class LanczosResult:
+    alpha: np.ndarray   # m x k
+    beta: np.ndarray    # m x (k+1), beta[:, 0] = beta_1 = 0
+    k_used: np.ndarray  # m
+    nu: np.ndarray      # m, |v_j|^2
+
+
+def lanczos(A, prec, tau: float, V: np.ndarray, k: int, nthreads: int | None = None) -> LanczosResult:
+    """Algorithm 1 on C = M (A - tau I) M for every column of V (n x m)."""
+    lib = _load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n, m = V.shape
+    if A.n != n:
+        raise ValueError("probe block does not match A")
+    kind, nd, dims, coef = _prec_args(prec, n)
+    alpha = np.zeros((m, k))
+    beta = np.zeros((m, k + 1))
+    k_used = np.zeros(m, dtype=np.int32)
+    nu = np.zeros(m)
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    rc = lib.oracle_lanczos(n, _ptr(rp), _ptr(ci), _ptr(va), kind, nd, _ptr(dims),
+                            float(prec.s), float(prec.lo), float(prec.hi), len(coef) - 1,
+                            _ptr(coef), float(tau), _ptr(V), m, int(k),
+                            int(nthreads or host_threads()), _ptr(alpha), _ptr(beta),
+                            _ptr(k_used), _ptr(nu))
+    if rc == -2:
+        raise ZeroDivisionError("Jacobi preconditioner is singular: a_rr == tau")
+    if rc != 0:
+        raise ValueError("oracle_lanczos failed (%d)" % rc)
+    return LanczosResult(alpha, beta, k_used, nu)
+
+
+def dense_operator(A, prec, tau: float) -> np.ndarray:
+    """C = M (A - tau I) M as a dense matrix (small n only)."""
+    lib = _load()
+    n = A.n
+    kind, nd, dims, coef = _prec_args(prec, n)
+    C = np.zeros((n, n))
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    lib.oracle_dense_operator(n, _ptr(rp), _ptr(ci), _ptr(va), kind, nd, _ptr(dims),
+                              float(prec.s), float(prec.lo), float(prec.hi), len(coef) - 1,
+                              _ptr(coef), float(tau), _ptr(C))
+    return C
+
+
+# ---------------------------------------------------------------------------
+# Quadrature (Section 3.1 eq. gauss_quad; Section 3.4 eq. GA_Tk)
+# ---------------------------------------------------------------------------
+
+
+def jacobi_matrix(alpha: np.ndarray, beta: np.ndarray, k: int, rule: str = "gauss") -> np.ndarray:
+    """Dense tridiagonal matrix of the rule.  alpha: alpha_1..alpha_k (at least),
+    beta: beta_1..beta_{k+1} (beta[0] = beta_1 = 0)."""
+    a = np.asarray(alpha[:k], dtype=np.float64)
+    b = np.asarray(beta[1:k], dtype=np.float64)          # beta_2..beta_k
+    if rule == "ga" and k >= 2:
+        diag = np.concatenate([a, a[:k - 1][::-1]])
+        off = np.concatenate([b, [beta[k]], b[:k - 2][::-1]])
+    elif rule in ("gauss", "ga"):
+        diag, off = a, b
+    else:
+        raise ValueError(rule)
+    return np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+
+
+def step(theta: np.ndarray, smooth_w: float = 0.0) -> np.ndarray:
+    """h(theta) = 1 for theta < 0 else 0 (eq. h); or erfc(theta/w)/2 if w > 0."""
+    if smooth_w > 0.0:
+        return np.array([0.5 * math.erfc(t / smooth_w) for t in theta])
+    return (theta < 0.0).astype(np.float64)
+
+
+def probe_quadrature(alpha_j, beta_j, k_used: int, nu: float, rule: str = "gauss",
+                     smooth_w: float = 0.0):
+    """Return (s_j, min |theta|) for one probe: s_j = nu * sum_i z_i(1)^2 h(theta_i)."""
+    J = jacobi_matrix(alpha_j, beta_j, int(k_used), rule if k_used == len(alpha_j) else "gauss")
+    theta, Z = np.linalg.eigh(J)
+    w = Z[0, :] ** 2
+    return nu * float(np.dot(w, step(theta, smooth_w))), float(np.min(np.abs(theta)))
+
+
+def quadrature(res: LanczosResult, rule: str = "gauss", smooth_w: float = 0.0):
+    m = res.alpha.shape[0]
+    s = np.zeros(m)
+    mins = np.zeros(m)
+    for j in range(m):
+        s[j], mins[j] = probe_quadrature(res.alpha[j], res.beta[j], res.k_used[j], res.nu[j],
+                                         rule, smooth_w)
+    return s, mins
+
+
+def _mean(x) -> float:
+    acc = 0.0
+    for v in x:              # index order
+        acc += float(v)
+    return acc / len(x)
+
+
+@dataclass
+class CountResult:
+    estimate: float
+    variance: float
+    neg_xi: float
+    neg_eta: float
+    s_xi: np.ndarray
+    s_eta: np.ndarray
+    min_abs_ritz: float
+    lan_xi: LanczosResult
+    lan_eta: LanczosResult
+
+
+def negcount(A, prec, tau, V, k, rule="gauss", smooth_w=0.0, nthreads=None):
+    """Algorithm 2: (1/m) sum_j s_j(tau), plus the per-probe s_j."""
+    res = lanczos(A, prec, tau, V, k, nthreads)
+    s, mins = quadrature(res, rule, smooth_w)
+    return _mean(s), s, res, float(np.min(mins))
+
+
+def count(A, prec, xi, eta, V, k, rule="gauss", smooth_w=0.0, nthreads=None) -> CountResult:
+    """Estimate the number of eigenvalues of A in [xi, eta)."""
+    if not (xi < eta):
+        raise ValueError("need xi < eta")
+    _, s_xi, lx, mx = negcount(A, prec, xi, V, k, rule, smooth_w, nthreads)
+    _, s_eta, le, me = negcount(A, prec, eta, V, k, rule, smooth_w, nthreads)
+    m = len(s_xi)
+    d = s_eta - s_xi
+    est = _mean(d)
+    if m > 1:
+        acc = 0.0
+        for v in d:
+            acc += (float(v) - est) ** 2
+        var = acc / ((m - 1) * m)
+    else:
+        var = float("nan")
+    return CountResult(est, var, _mean(s_xi), _mean(s_eta), s_xi, s_eta, min(mx, me), lx, le)

@@ -1,0 +1,48 @@
+"""Exact eigenvalue counts: closed form, dense, sparse LDL^T and plane-wise
+inertia agree, and reproduce the paper's printed exact count."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact
+from paper_1602_02306_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_table1_laplace_exact_count():
+    """Table 1: Laplace, h = 2^-7, n = 16129, n_(A - 3000 I) = 226."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_table1.json")))["laplace"]
+    assert g["grid"][0] * g["grid"][1] == g["n"]
+    assert exact.laplacian_negcount(g["grid"], g["tau"], h=g["h"]) == g["exact_negcount"]
+    A = W.laplacian_csr(g["grid"]).to_scipy() / g["h"] ** 2
+    assert exact.sparse_negcount(A, g["tau"]) == g["exact_negcount"]
+
+
+def test_closed_form_matches_dense():
+    for dims in [(7,), (5, 6), (4, 3, 5)]:
+        L = W.laplacian_csr(dims).to_dense()
+        assert np.allclose(np.sort(exact.laplacian_eigenvalues(dims)), np.linalg.eigvalsh(L),
+                           atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [6, 9])
+def test_inertia_methods_agree(N):
+    wl = W.Workload("t", (N, N, N), "wells", 1, -8.0, -2.0, "cheb", 1, 1)
+    P = W.make_problem(wl)
+    Ad = P.A.to_dense()
+    for tau in (-8.0, -2.0, -20.0):
+        d = exact.dense_negcount(Ad, tau)
+        assert exact.sparse_negcount(P.A.to_scipy(), tau) == d
+        assert exact.planewise_negcount(P.dims, P.V, tau) == d
+
+
+def test_stored_exact_counts_small():
+    data = json.load(open(os.path.join(GOLDEN, "exact_counts.json")))
+    for name in ("c1", "c2_small", "c2_ragged"):
+        wl = W.WORKLOADS[name]
+        Ad = W.make_problem(wl).A.to_dense()
+        assert data[name]["count"] == exact.dense_negcount(Ad, wl.eta) - exact.dense_negcount(Ad, wl.xi)
+    assert data["c1"]["count"] == 72
