@@ -1,0 +1,225 @@
+"""Benchmark: Lanczos probe-steps/s of the eigenvalue-count estimator on one GPU.
+
+One step = one interval count (Algorithm 2 at tau = xi and tau = eta on one
+probe block): 2 * m * k probe-steps (one Lanczos step of one probe at one
+shift each).  Inputs are synthetic (64^3 Gaussian-well Hamiltonian, CSR,
+Chebyshev preconditioner, 256 Rademacher probes, k = 30, FP64) and resident in
+HBM before timing starts.  Prints ONE JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2] [--no-cpu-baseline]
+  python bench.py --copy-calib     (a plain device copy of known size, for
+                                    scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD public specification
+
+WORKLOAD_TEXT = {
+    "c1": "2D 5-pt 30x30 + V~U[0,1] (seed 0), CSR, Jacobi M per shift, [0.5,1.5], m=40, k=20, FP64",
+    "c2": "3D 7-pt 64^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=256, k=30, FP64",
+    "c3": "3D 7-pt 128^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=512, k=30, FP32 vectors",
+    "c5": "3D 7-pt 96^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M, erf-smoothed count w=0.05, [-8,-2], m=128, k=30",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1602_02306_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def copy_calib(nbytes: int = 1 << 30):
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calib_bytes_each_way": nbytes, "launches": 3}), flush=True)
+
+
+def cpu_baseline(P, V, wl, target_s: float):
+    import oracle
+    threads = oracle.host_threads()
+    m = V.shape[1]
+    done, t_tot, batch = 0, 0.0, max(1, min(threads, m))
+    while done < m:
+        s = min(batch, m - done)
+        t0 = time.perf_counter()
+        oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads)
+        dt = time.perf_counter() - t0
+        t_tot += dt
+        done += s
+        log("cpu oracle: %d probes in %.1f s (total %.1f s)" % (s, dt, t_tot))
+        if t_tot >= target_s:
+            break
+        per = t_tot / done
+        batch = max(1, min(m - done, int((target_s - t_tot) / per) + 1, 4 * threads))
+    steps = 2 * done * wl.k
+    return {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
+                      % (done, m, wl.k, steps, t_tot)}
+
+
+def traffic_from_profiles(family: str, per_launch_algo: float):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_sha") != kernel_sources_sha():
+        return None
+    ent = d.get("kernels", {}).get(family)
+    if not ent:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calib", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the estimator on a single "
+              "MI355X (probe columns would shard across GPUs with one 32-byte all-reduce at the "
+              "end, which is not built); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.copy_calib:
+        copy_calib()
+        return
+
+    from paper_1602_02306_amd import ecount as ec
+    from paper_1602_02306_amd import workloads as W
+
+    wl = W.WORKLOADS[args.workload]
+    log("building inputs", wl.name, "n=%d m=%d k=%d" % (wl.n, wl.m, wl.k))
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    vec = wl.vec
+    tdt = torch.float32 if vec == "f32" else torch.float64
+    A = ec.upload_csr(P.A, val_dtype=vec)
+    Vd = torch.from_numpy(V).to("cuda", tdt)
+    S = 2
+    need = ec.workspace_bytes(wl.n, wl.m, S, P.prec, wl.k, vec=vec, smooth_w=wl.smooth_w)
+    ws = ec.Workspace(need)
+    log("workspace %.2f GiB" % (need / 2 ** 30))
+
+    def one():
+        return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
+                        workspace=ws, details=False)
+
+    for i in range(args.warmup):
+        r = one()
+        log("warmup %d: estimate %.6f" % (i, r.estimate))
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ec.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        r = one()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ec.profile_enable(False)
+    prof = ec.profile_read()
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    ev_ms = ev0.elapsed_time(ev1) / args.steps
+    ms = max(wall_ms, ev_ms)
+    probe_steps = S * wl.m * wl.k
+    value = probe_steps / (ms / 1e3)
+    log("timed %d steps: %.3f ms/step (events %.3f), %.0f probe-steps/s" % (args.steps, ms, ev_ms, value))
+
+    fams = {k: v for k, v in prof.items() if v["launches"] > 0}
+    total_kernel_ms = sum(v["ms"] for v in fams.values())
+    algo_bytes = sum(v["bytes"] for v in fams.values()) / args.steps
+    dom = max(fams, key=lambda f: fams[f]["ms"])
+    d = fams[dom]
+    per_launch_bytes = d["bytes"] / d["launches"]
+    per_launch_ms = d["ms"] / d["launches"]
+    achieved = per_launch_bytes / (per_launch_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(dom, per_launch_bytes)
+    kernels = {f: {"launches_per_step": v["launches"] / args.steps,
+                   "ms_per_step": v["ms"] / args.steps,
+                   "share": v["ms"] / total_kernel_ms if total_kernel_ms else None,
+                   "gbs": (v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 and v["bytes"] > 0 else None}
+               for f, v in fams.items()}
+
+    exact = None
+    gpath = os.path.join(ROOT, "tests", "golden", "exact_counts.json")
+    if os.path.exists(gpath):
+        exact = json.load(open(gpath)).get(wl.name, {}).get("count")
+    accuracy = {"estimate": r.estimate, "std_error": math.sqrt(r.variance) if r.variance == r.variance else None,
+                "exact_count": exact, "method_exact": "LDL^T Sylvester inertia" if exact is not None else None,
+                "abs_error": abs(r.estimate - exact) if exact is not None else None,
+                "rel_error": abs(r.estimate - exact) / exact if exact else None}
+
+    out = {
+        "metric": "Lanczos probe-steps/s + HBM GB/s at fixed count error vs LDLᵀ inertia",
+        "value": value,
+        "unit": "probe-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if vec == "f64" else "f32-storage/f64-accumulate",
+        "data": "synthetic",
+        "config": {"workload": wl.name + ": " + WORKLOAD_TEXT.get(wl.name, ""), "n": wl.n,
+                   "probes": wl.m, "shifts": S, "columns": S * wl.m, "k": wl.k,
+                   "probe_steps_per_step": probe_steps},
+        "hbm_gbs_algorithmic": algo_bytes / (ms / 1e3) / 1e9,
+        "algorithmic_bytes_per_probe_step": algo_bytes / probe_steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "avg_launch_ms": per_launch_ms},
+        "kernels": kernels,
+        "accuracy": accuracy,
+        "kernel_sources_sha": kernel_sources_sha(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(P, V, wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ecount.h -- C ABI of the MI355X eigenvalue-count library.
+ *
+ * Estimates the number of eigenvalues of a sparse real symmetric matrix A in
+ * an interval [xi, eta) with the preconditioned Lanczos / Gauss-quadrature /
+ * Hutchinson estimator of Vecharynski & Yang, "Preconditioned iterative
+ * methods for eigenvalue counts":
+ *
+ *   c(xi, eta) = n_(A - eta I) - n_(A - xi I)              (Section 2)
+ *   n_(A - tau I) = trace h(C),  C = M (A - tau I) M^*,   T = M^* M HPD
+ *                                                          (Section 2, eq. negi_T)
+ *   n_(A - tau I) ~ L_tau(k, m) = (1/m) sum_j |v_j|^2 sum_{theta_i < 0} z_i(1)^2
+ *                                                          (Section 3.2, eq. rand_prec_quad,
+ *                                                           Algorithm 2)
+ * where theta_i, z_i are the eigenpairs of the k x k Lanczos matrix J_k from
+ * k steps of Lanczos with full reorthogonalization on C started at v_j
+ * (Section 3.1, Algorithm 1, eq. gauss_quad).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an ecnt_status: 0 on success, < 0 on error; no
+ *     C++ exception crosses the ABI.  ecnt_last_error() gives a message.
+ *   - Pointers marked "device" are HIP device pointers (memory owned by the
+ *     caller); "host" pointers are ordinary host memory.  The library never
+ *     allocates device memory and keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     is enqueued on it.  Functions returning host results synchronize that
+ *     stream before returning.
+ *   - Argument validation happens entirely on the host, before any device
+ *     work is enqueued; a rejected call touches no device state.
+ *   - Block vectors on the device are row-major n x m ("probe-minor": entry
+ *     (r, j) at index r*m + j).
+ */
+#ifndef ECOUNT_H
+#define ECOUNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ECNT_API __attribute__((visibility("default")))
+#else
+#define ECNT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ecnt_status;
+#define ECNT_OK 0
+#define ECNT_EINVAL (-1)       /* invalid argument (null pointer, bad size, xi >= eta, ...) */
+#define ECNT_ENOTHPD (-2)      /* preconditioner not HPD (Jacobi pivot a_rr == tau)       */
+#define ECNT_EWORKSPACE (-3)   /* workspace missing or smaller than ecnt_workspace_bytes() */
+#define ECNT_EDEVICE (-4)      /* HIP runtime error, or the tridiagonal solver diverged   */
+#define ECNT_EUNSUPPORTED (-5) /* valid request outside what this build supports         */
+
+typedef enum { ECNT_F64 = 0, ECNT_F32 = 1 } ecnt_dtype;
+
+/* Sparse A in CSR form on the device.  Real symmetric, both triangles
+ * stored, column indices sorted within a row, diagonal entry present when
+ * non-zero.  int32 indices; values of type val_type (F64 or F32). */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int32_t *row_ptr; /* device, n+1 */
+    const int32_t *col_idx; /* device, nnz */
+    const void *val;        /* device, nnz, val_type */
+    int32_t val_type;
+    int32_t reserved;
+} ecnt_csr;
+
+/* Preconditioner T = M^* M (Section 2; Section 6 lists the paper's choices).
+ *   ECNT_PREC_NONE            M = I.
+ *   ECNT_PREC_JACOBI          M_tau = diag(|a_rr - tau|)^(-1/2), built per shift from
+ *                             the diagonal of A (an HPD absolute-value preconditioner in
+ *                             the sense of Section 6; exact for diagonal A).
+ *   ECNT_PREC_CHEB_LAPLACIAN  M = sum_{j=0}^{degree} coef[j] T_j(B),
+ *                             B = (2 (L + s I) - (lo + hi) I) / (hi - lo),
+ *                             L the Dirichlet Laplacian of the grid `dims` (diagonal
+ *                             2*ndim, neighbours -1; a grid point (x, y, z) is row
+ *                             (x*dims[1] + y)*dims[2] + z), shared by all shifts.
+ *                             M is symmetric; T = M^2 must be HPD (the caller's
+ *                             responsibility: M nonsingular on the spectrum of L). */
+typedef enum {
+    ECNT_PREC_NONE = 0,
+    ECNT_PREC_JACOBI = 1,
+    ECNT_PREC_CHEB_LAPLACIAN = 2
+} ecnt_prec_kind;
+
+typedef struct {
+    int32_t kind;        /* ecnt_prec_kind */
+    int32_t ndim;        /* 1..3 (CHEB only) */
+    int32_t dims[3];     /* grid extents, product == n (CHEB only) */
+    int32_t degree;      /* 0..16 (CHEB only) */
+    double s, lo, hi;    /* shift of L and the interval mapped to [-1, 1] (CHEB only) */
+    const double *coef;  /* host, degree+1 entries, copied at call time (CHEB only) */
+} ecnt_prec;
+
+/* Quadrature rule applied to the Lanczos coefficients. */
+typedef enum {
+    ECNT_RULE_GAUSS = 0, /* k-node Gauss rule from J_k (Section 3.1, eq. gauss_quad) */
+    ECNT_RULE_GA = 1     /* generalized averaged Gauss rule from the (2k-1) x (2k-1)
+                            matrix of Section 3.4, eq. GA_Tk */
+} ecnt_rule;
+
+typedef struct {
+    int32_t k;          /* Lanczos steps, 1 <= k <= min(n, 512) (k <= 256 for GA) */
+    int32_t vec_type;   /* storage of probes, Lanczos vectors and basis: F64 or F32.
+                           alpha/beta, every dot product and norm, and the tridiagonal
+                           eigensolve are FP64 in both cases. */
+    int32_t rule;       /* ecnt_rule */
+    int32_t reserved;   /* must be 0 */
+    double smooth_w;    /* 0: the paper's step h (h(theta) = 1 iff theta < 0).
+                           > 0: h replaced by erfc(theta / smooth_w) / 2. */
+} ecnt_opts;
+
+/* Optional outputs.  Device arrays may be NULL. */
+typedef struct {
+    double neg_xi;        /* L_xi(k, m): estimate of n_(A - xi I)   (count entry)   */
+    double neg_eta;       /* L_eta(k, m): estimate of n_(A - eta I) (count entry)   */
+    double min_abs_ritz;  /* min |theta| over all probes and shifts: a value within
+                             rounding of 0 makes h(theta) tie-sensitive */
+    double *per_probe;    /* device, nshift*m: s_j(tau) = |v_j|^2 sum_{theta<0} z(1)^2,
+                             shift-major (all probes of shift 0 first)             */
+    int32_t *k_used;      /* device, nshift*m: steps actually taken (< k after an
+                             invariant Krylov space was found)                     */
+    double *alpha;        /* device, k x (nshift*m): alpha_1..alpha_k per column    */
+    double *beta;         /* device, (k+1) x (nshift*m): beta_1 = 0, beta_2..beta_{k+1} */
+} ecnt_info;
+
+/* Bytes of device workspace needed by ecnt_count / ecnt_negcounts for n rows,
+ * m probes and nshift shifts (ecnt_count uses nshift = 2).  Returns 0 if the
+ * arguments are invalid. */
+ECNT_API size_t ecnt_workspace_bytes(int64_t n, int64_t m, int32_t nshift, const ecnt_prec *T,
+                            const ecnt_opts *opts);
+
+/* Interval count c(xi, eta) ~ L_eta(k, m) - L_xi(k, m) (end of Section 3.2:
+ * Algorithm 2 run at tau = xi and tau = eta), on the same probe block for
+ * both shifts.
+ *   probes    device, n x m row-major, vec_type.  Any i.i.d. zero-mean
+ *             unit-variance entries (Section 2, eq. trace); read only.
+ *   estimate  host: mean over probes of d_j = s_j(eta) - s_j(xi)
+ *   variance  host: sample variance of d_j divided by m (NaN when m == 1);
+ *             the Hutchinson sampling error only, not the quadrature bias.
+ *   info      host, nullable.
+ * Errors: EINVAL (null pointers, n < 1, m < 1, k < 1, k > n, !(xi < eta),
+ * non-finite xi/eta, bad preconditioner fields), ENOTHPD (Jacobi pivot
+ * a_rr == xi or eta), EWORKSPACE, EUNSUPPORTED (k above the limits above),
+ * EDEVICE. */
+ECNT_API ecnt_status ecnt_count(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                       const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
+                       size_t ws_bytes, void *stream, double *estimate, double *variance,
+                       ecnt_info *info);
+
+/* Algorithm 2 for several shifts at once (spectrum slicing, Section 1): all
+ * nshift x m Lanczos runs share one probe block and one launch sequence.
+ *   taus       host, nshift finite shifts
+ *   negcounts  host, nshift: L_tau(k, m) per shift
+ *   counts     host, nullable, nshift-1: mean of s_j(taus[s+1]) - s_j(taus[s])
+ *   variances  host, nullable, nshift-1: sample variance of those differences / m
+ * Errors as ecnt_count (nshift < 1 or > 64 -> EINVAL). */
+ECNT_API ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const double *taus,
+                           int32_t nshift, const void *probes, int64_t m, const ecnt_opts *opts,
+                           void *ws, size_t ws_bytes, void *stream, double *negcounts,
+                           double *counts, double *variances, ecnt_info *info);
+
+/* Per-kernel-family timing, for measurement.  While enabled, every launch
+ * made by ecnt_count / ecnt_negcounts is bracketed by two hipEvents recorded
+ * on the caller's stream; elapsed times and the algorithmic bytes of each
+ * launch (the distinct block vectors and matrix arrays it must read or write)
+ * are accumulated per kernel family.  Enabling resets the totals. */
+typedef struct {
+    char name[24];       /* kernel family, e.g. "lz_update" */
+    int64_t launches;
+    double total_ms;     /* sum of event-measured launch durations */
+    double bytes;        /* sum of algorithmic bytes over those launches */
+} ecnt_kernel_stat;
+
+ECNT_API ecnt_status ecnt_profile_enable(int32_t on);
+/* Copies up to `max` families into `out`; returns how many were written. */
+ECNT_API int32_t ecnt_profile_read(ecnt_kernel_stat *out, int32_t max);
+
+/* Message for the last failed call on this thread ("" if none). */
+ECNT_API const char *ecnt_last_error(void);
+
+/* Library version string. */
+ECNT_API const char *ecnt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECOUNT_H */

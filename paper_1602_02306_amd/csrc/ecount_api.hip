@@ -1,0 +1,501 @@
+// Host side of the C ABI declared in include/ecount.h: argument validation,
+// workspace carving and the launch sequence of the estimator (Algorithm 2
+// over a block of probes and shifts, Algorithm 1 inside).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ecount.h"
+#include "ecount_internal.h"
+
+namespace ecnt {
+
+// ------------------------------------------------------------------ profiling
+enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_COUNT };
+static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
+                                           "lz_setup", "lz_finalize", "quadrature"};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static ecnt_kernel_stat g_stats[F_COUNT];
+struct PendingEvent {
+    int fam;
+    hipEvent_t a, b;
+    double bytes;
+};
+static thread_local std::vector<PendingEvent> t_pending;
+static thread_local std::vector<hipEvent_t> t_event_pool;
+static thread_local bool t_prof = false;
+
+static hipEvent_t get_event()
+{
+    if (!t_event_pool.empty()) {
+        hipEvent_t e = t_event_pool.back();
+        t_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    int fam;
+    double bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(int f, double b, hipStream_t s) : fam(f), bytes(b), st(s)
+    {
+        if (t_prof && (a = get_event())) (void)hipEventRecord(a, st);
+    }
+    ~Timed()
+    {
+        if (!a) return;
+        hipEvent_t b = get_event();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        t_pending.push_back({fam, a, b, bytes});
+    }
+};
+
+static void collect_profile()
+{
+    if (t_pending.empty()) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &pe : t_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            g_stats[pe.fam].launches += 1;
+            g_stats[pe.fam].total_ms += ms;
+            g_stats[pe.fam].bytes += pe.bytes;
+        }
+        t_event_pool.push_back(pe.a);
+        t_event_pool.push_back(pe.b);
+    }
+    t_pending.clear();
+}
+
+static thread_local std::string g_err;
+
+static ecnt_status fail(ecnt_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t plan_layout(Plan &p, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        off = align_up(off, 256);
+        char *ptr = base ? base + off : nullptr;
+        off += bytes;
+        return ptr;
+    };
+    const size_t bv = p.vec_f32 ? 4 : 8;
+    const size_t blk = (size_t)p.n * p.C * bv;
+    const size_t C = p.C;
+    p.basis = take(blk * (p.k + 1));
+    const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : 0;
+    for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;
+    p.part = (double *)take(sizeof(double) * (size_t)p.nchunk * kBasisChunk * C);
+    p.sig = (double *)take(sizeof(double) * (p.k + 1) * C);
+    p.alpha = (double *)take(sizeof(double) * p.k * C);
+    p.beta = (double *)take(sizeof(double) * (p.k + 1) * C);
+    p.cf = (double *)take(sizeof(double) * (p.k + 1) * C);
+    p.kappa = (double *)take(sizeof(double) * C);
+    p.runmax = (double *)take(sizeof(double) * C);
+    p.nu = (double *)take(sizeof(double) * C);
+    p.taus = (double *)take(sizeof(double) * kMaxShifts);
+    p.s_out = (double *)take(sizeof(double) * C);
+    p.minabs = (double *)take(sizeof(double) * C);
+    p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
+    p.result = (double *)take(sizeof(double) * (4 * kMaxShifts + 8));
+    p.active = (int32_t *)take(sizeof(int32_t) * C);
+    p.kused = (int32_t *)take(sizeof(int32_t) * C);
+    p.flags = (int32_t *)take(sizeof(int32_t) * 4);
+    p.bytes = align_up(off, 256) + 256;   // slack for aligning the caller's pointer
+    return p.bytes;
+}
+
+static void reduction_geometry(Plan &p)
+{
+    p.nct = (p.C + kColTile - 1) / kColTile;
+    // about 2048 workgroups of 4 waves for the column reductions
+    int64_t target = (2048 + p.nct - 1) / p.nct;
+    int64_t maxchunks = (p.n + 3) / 4;
+    if (target > maxchunks) target = maxchunks;
+    if (target < 1) target = 1;
+    p.rpc = (p.n + target - 1) / target;
+    p.nchunk = (int)((p.n + p.rpc - 1) / p.rpc);
+}
+
+static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_prec *T,
+                             const ecnt_opts *o)
+{
+    if (!T || !o) return fail(ECNT_EINVAL, "null preconditioner or options");
+    if (n < 1) return fail(ECNT_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+    if (n > INT32_MAX) return fail(ECNT_EUNSUPPORTED, "n above 2^31-1 is not supported");
+    if (m < 1) return fail(ECNT_EINVAL, "m must be >= 1 (got %lld)", (long long)m);
+    if (S < 1 || S > kMaxShifts) return fail(ECNT_EINVAL, "nshift must be in 1..%d", kMaxShifts);
+    if ((int64_t)m * S > (1 << 24)) return fail(ECNT_EUNSUPPORTED, "too many probe columns");
+    if (o->k < 1 || o->k > n) return fail(ECNT_EINVAL, "k must satisfy 1 <= k <= n (got %d)", o->k);
+    if (o->vec_type != ECNT_F64 && o->vec_type != ECNT_F32)
+        return fail(ECNT_EINVAL, "vec_type must be ECNT_F64 or ECNT_F32");
+    if (o->rule != ECNT_RULE_GAUSS && o->rule != ECNT_RULE_GA)
+        return fail(ECNT_EINVAL, "unknown quadrature rule %d", o->rule);
+    if (o->reserved != 0) return fail(ECNT_EINVAL, "opts.reserved must be 0");
+    if (!(o->smooth_w >= 0.0) || !isfinite(o->smooth_w))
+        return fail(ECNT_EINVAL, "smooth_w must be finite and >= 0");
+    const int kmax = o->rule == ECNT_RULE_GA ? kMaxK / 2 : kMaxK;
+    if (o->k > kmax) return fail(ECNT_EUNSUPPORTED, "k above %d is not supported", kmax);
+    p.n = n;
+    p.m = (int)m;
+    p.S = S;
+    p.C = (int)(m * S);
+    p.k = o->k;
+    p.vec_f32 = o->vec_type == ECNT_F32;
+    p.rule = o->rule;
+    p.smooth_w = o->smooth_w;
+    p.prec_kind = T->kind;
+    switch (T->kind) {
+    case ECNT_PREC_NONE:
+    case ECNT_PREC_JACOBI:
+        break;
+    case ECNT_PREC_CHEB_LAPLACIAN: {
+        if (T->ndim < 1 || T->ndim > 3) return fail(ECNT_EINVAL, "prec.ndim must be 1..3");
+        int64_t prod = 1;
+        int d[3] = {1, 1, 1};
+        for (int a = 0; a < T->ndim; ++a) {
+            if (T->dims[a] < 1) return fail(ECNT_EINVAL, "prec.dims must be >= 1");
+            prod *= T->dims[a];
+            d[3 - T->ndim + a] = T->dims[a];
+        }
+        if (prod != n) return fail(ECNT_EINVAL, "prec grid (%lld points) does not match n", (long long)prod);
+        if (T->degree < 0 || T->degree > 16) return fail(ECNT_EINVAL, "prec.degree must be 0..16");
+        if (!T->coef) return fail(ECNT_EINVAL, "prec.coef is null");
+        if (!isfinite(T->s) || !isfinite(T->lo) || !isfinite(T->hi) || !(T->hi > T->lo))
+            return fail(ECNT_EINVAL, "prec interval must be finite with hi > lo");
+        for (int j = 0; j <= T->degree; ++j) {
+            if (!isfinite(T->coef[j])) return fail(ECNT_EINVAL, "prec.coef[%d] is not finite", j);
+            p.coef[j] = T->coef[j];
+        }
+        p.ndim = T->ndim;
+        p.dims[0] = d[0];
+        p.dims[1] = d[1];
+        p.dims[2] = d[2];
+        p.degree = T->degree;
+        p.s = T->s;
+        p.lo = T->lo;
+        p.hi = T->hi;
+        break;
+    }
+    default:
+        return fail(ECNT_EINVAL, "unknown preconditioner kind %d", T->kind);
+    }
+    reduction_geometry(p);
+    plan_layout(p, nullptr);
+    return ECNT_OK;
+}
+
+struct InitArgs {
+    double taus[kMaxShifts];
+    int S;
+};
+
+__global__ void k_init(InitArgs a, double *taus, int32_t *flags)
+{
+    const int t = threadIdx.x;
+    if (t < a.S) taus[t] = a.taus[t];
+    if (t < 4) flags[t] = 0;
+}
+
+// M x by Clenshaw's recurrence (R of degree d), with x = xs .* X.
+// b_{d+1} = b_{d+2} = 0; b_j = c_j x + 2 B b_{j+1} - b_{j+2}; M x = c_0 x + B b_1 - b_2.
+// Uses the two scratch blocks `t0`, `t1`; writes `out` (which may alias t0 or t1
+// only where noted by the caller: here it must differ from both).
+static double block_bytes(const Plan &p) { return (double)p.n * p.C * (p.vec_f32 ? 4 : 8); }
+
+static void cheb_sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                       bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st)
+{
+    // distinct block vectors read, plus the one written
+    int nread = 1 + ((IN && IN != X) ? 1 : 0) + ((Z && Z != X && Z != IN) ? 1 : 0);
+    Timed t(F_CHEB, (nread + 1) * block_bytes(p), st);
+    launch_cheb_sweep(p, X, xs, cx, IN, in_is_x, cb, Z, cz, out, st);
+}
+
+static void apply_M(const Plan &p, const void *X, const double *xs, void *t0, void *t1, void *out,
+                    hipStream_t st)
+{
+    const double *c = p.coef;
+    const int d = p.degree;
+    if (d == 0) {
+        cheb_sweep(p, X, xs, c[0], nullptr, false, 0.0, nullptr, 0.0, out, st);
+        return;
+    }
+    if (d == 1) {
+        cheb_sweep(p, X, xs, c[0], X, true, c[1], nullptr, 0.0, out, st);
+        return;
+    }
+    // b_{d-1} = c_{d-1} x + 2 c_d B x
+    void *bj1 = t0;   // b_{j+1}
+    cheb_sweep(p, X, xs, c[d - 1], X, true, 2.0 * c[d], nullptr, 0.0, bj1, st);
+    if (d == 2) {
+        // M x = c_0 x + B b_1 - b_2, b_2 = c_2 x
+        cheb_sweep(p, X, xs, c[0] - c[2], bj1, false, 1.0, nullptr, 0.0, out, st);
+        return;
+    }
+    // b_{d-2} = (c_{d-2} - c_d) x + 2 B b_{d-1}
+    void *bj = t1;
+    cheb_sweep(p, X, xs, c[d - 2] - c[d], bj1, false, 2.0, nullptr, 0.0, bj, st);
+    void *bj2 = bj1;  // b_{j+2}
+    bj1 = bj;
+    for (int j = d - 3; j >= 1; --j) {
+        // b_j = c_j x + 2 B b_{j+1} - b_{j+2}, written over b_{j+2} (read point-wise only)
+        cheb_sweep(p, X, xs, c[j], bj1, false, 2.0, bj2, 1.0, bj2, st);
+        void *tmp = bj2;
+        bj2 = bj1;
+        bj1 = tmp;
+    }
+    cheb_sweep(p, X, xs, c[0], bj1, false, 1.0, bj2, 1.0, out, st);
+}
+
+static void enqueue(const Plan &p, const ecnt_csr *A, const double *taus, const void *probes,
+                    hipStream_t st)
+{
+    InitArgs ia;
+    memset(&ia, 0, sizeof ia);
+    for (int s = 0; s < p.S; ++s) ia.taus[s] = taus[s];
+    ia.S = p.S;
+    k_init<<<1, 64, 0, st>>>(ia, p.taus, p.flags);
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
+    if (p.prec_kind == ECNT_PREC_JACOBI) {
+        Timed t(F_SETUP, csr_b + 8.0 * p.S * p.n, st);
+        launch_jacobi_diag(p, A->row_ptr, A->col_idx, A->val, st);
+    }
+    {
+        Timed t(F_SETUP, blk_b + (double)p.n * p.m * (p.vec_f32 ? 4 : 8), st);
+        launch_setup(p, probes, st);
+    }
+    {
+        Timed t(F_FIN, 0.0, st);
+        launch_setup_fin(p, st);
+    }
+    const size_t bv = p.vec_f32 ? 4 : 8;
+    const size_t blk = (size_t)p.n * p.C * bv;
+    char *basis = (char *)p.basis;
+    const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
+    for (int i = 1; i <= p.k; ++i) {
+        void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
+        void *y = basis + (size_t)i * blk;         // slot i receives C q_i
+        const double *xs = p.sig + (size_t)(i - 1) * p.C;
+        if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
+            // t = M q ; u = (A - tau I) t ; y = M u
+            apply_M(p, x, xs, p.tmp[0], p.tmp[1], p.tmp[2], st);
+            {
+                Timed t(F_CSR, 2 * blk_b + csr_b, st);
+                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[2], nullptr, nullptr,
+                              p.tmp[0], st);
+            }
+            apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, st);
+        } else {
+            Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
+            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,
+                          p.prec_kind == ECNT_PREC_JACOBI ? p.jac : nullptr, y, st);
+        }
+        const int sm = i >= 2 ? i - 2 : -1;
+        for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
+            const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;
+            const bool m_in = sm >= l0 && sm < l0 + nb;
+            {
+                Timed t(F_DOTS, (nb + 1 + ((sm >= 0 && !m_in) ? 1 : 0)) * blk_b, st);
+                launch_dots(p, i, l0, nb, st);
+            }
+            Timed t(F_FIN, 0.0, st);
+            launch_dots_fin(p, i, l0, nb, st);
+        }
+        for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
+            const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;
+            const bool first = l0 == 0;
+            const bool m_in = sm >= l0 && sm < l0 + nb;
+            Timed t(F_UPDATE, (nb + 2 + ((first && sm >= 0 && !m_in) ? 1 : 0)) * blk_b, st);
+            launch_update(p, i, l0, nb, first, l0 + kBasisChunk >= i, st);
+        }
+        Timed t(F_FIN, 0.0, st);
+        launch_norm_fin(p, i, st);
+    }
+    Timed t(F_QUAD, 0.0, st);
+    launch_tridiag(p, st);
+    launch_reduce(p, st);
+}
+
+static ecnt_status check_common(const ecnt_csr *A, const void *probes, const ecnt_opts *o,
+                                void *ws, const Plan &p, size_t ws_bytes)
+{
+    if (!A) return fail(ECNT_EINVAL, "A is null");
+    if (!A->row_ptr || !A->col_idx || !A->val) return fail(ECNT_EINVAL, "A has null arrays");
+    if (A->nnz < 0) return fail(ECNT_EINVAL, "A.nnz must be >= 0");
+    if (A->val_type != ECNT_F64 && A->val_type != ECNT_F32)
+        return fail(ECNT_EINVAL, "A.val_type must be ECNT_F64 or ECNT_F32");
+    if (!probes) return fail(ECNT_EINVAL, "probes is null");
+    (void)o;
+    if (!ws) return fail(ECNT_EWORKSPACE, "workspace is null");
+    if (ws_bytes < p.bytes)
+        return fail(ECNT_EWORKSPACE, "workspace too small: %zu bytes given, %zu needed", ws_bytes, p.bytes);
+    return ECNT_OK;
+}
+
+static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_info *info)
+{
+    int32_t flags[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(res_host, p.result, sizeof(double) * (4 * kMaxShifts + 8),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && info) {
+        const size_t C = p.C;
+        if (info->per_probe)
+            e = hipMemcpyAsync(info->per_probe, p.s_out, sizeof(double) * C, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && info->k_used)
+            e = hipMemcpyAsync(info->k_used, p.kused, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && info->alpha)
+            e = hipMemcpyAsync(info->alpha, p.alpha, sizeof(double) * C * p.k, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess && info->beta)
+            e = hipMemcpyAsync(info->beta, p.beta, sizeof(double) * C * (p.k + 1), hipMemcpyDeviceToDevice, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+    collect_profile();
+    if (flags[0]) return fail(ECNT_ENOTHPD, "Jacobi preconditioner singular: a_rr == tau for some row");
+    if (flags[1]) return fail(ECNT_EDEVICE, "tridiagonal eigensolver did not converge");
+    return ECNT_OK;
+}
+
+static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus, int S,
+                       const void *probes, int64_t m, const ecnt_opts *o, void *ws,
+                       size_t ws_bytes, void *stream, double *res_host, ecnt_info *info, Plan &p)
+{
+    ecnt_status rc = make_plan(p, A ? A->n : 0, m, S, T, o);
+    if (rc) return rc;
+    rc = check_common(A, probes, o, ws, p, ws_bytes);
+    if (rc) return rc;
+    for (int s = 0; s < S; ++s)
+        if (!isfinite(taus[s])) return fail(ECNT_EINVAL, "shift %d is not finite", s);
+    p.val_f32 = A->val_type == ECNT_F32;
+    char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    plan_layout(p, base);
+    hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        t_prof = g_prof_on;
+    }
+    enqueue(p, A, taus, probes, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return finish(p, st, res_host, info);
+}
+
+}  // namespace ecnt
+
+using namespace ecnt;
+
+extern "C" {
+
+size_t ecnt_workspace_bytes(int64_t n, int64_t m, int32_t nshift, const ecnt_prec *T,
+                            const ecnt_opts *opts)
+{
+    Plan p;
+    if (make_plan(p, n, m, nshift, T, opts) != ECNT_OK) return 0;
+    return p.bytes;
+}
+
+ecnt_status ecnt_count(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                       const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
+                       size_t ws_bytes, void *stream, double *estimate, double *variance,
+                       ecnt_info *info)
+{
+    g_err.clear();
+    if (!estimate || !variance) return fail(ECNT_EINVAL, "estimate/variance output is null");
+    if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
+    if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
+    const double taus[2] = {xi, eta};
+    double res[4 * kMaxShifts + 8];
+    Plan p;
+    ecnt_status rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p);
+    if (rc) return rc;
+    *estimate = res[2];
+    *variance = res[3];
+    if (info) {
+        info->neg_xi = res[0];
+        info->neg_eta = res[1];
+        info->min_abs_ritz = res[4];
+    }
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const double *taus,
+                           int32_t nshift, const void *probes, int64_t m, const ecnt_opts *opts,
+                           void *ws, size_t ws_bytes, void *stream, double *negcounts,
+                           double *counts, double *variances, ecnt_info *info)
+{
+    g_err.clear();
+    if (!taus || !negcounts) return fail(ECNT_EINVAL, "taus/negcounts is null");
+    if (nshift < 1 || nshift > kMaxShifts) return fail(ECNT_EINVAL, "nshift must be in 1..%d", kMaxShifts);
+    double res[4 * kMaxShifts + 8];
+    Plan p;
+    ecnt_status rc = run(A, T, taus, nshift, probes, m, opts, ws, ws_bytes, stream, res, info, p);
+    if (rc) return rc;
+    const int S = nshift;
+    for (int s = 0; s < S; ++s) negcounts[s] = res[s];
+    for (int t = 0; t + 1 < S; ++t) {
+        if (counts) counts[t] = res[S + t];
+        if (variances) variances[t] = res[2 * S - 1 + t];
+    }
+    if (info) {
+        info->neg_xi = res[0];
+        info->neg_eta = S > 1 ? res[1] : res[0];
+        info->min_abs_ritz = res[3 * S - 2];
+    }
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    if (g_prof_on) {
+        for (int f = 0; f < F_COUNT; ++f) {
+            memset(&g_stats[f], 0, sizeof g_stats[f]);
+            snprintf(g_stats[f].name, sizeof g_stats[f].name, "%s", kFamilyName[f]);
+        }
+    }
+    return ECNT_OK;
+}
+
+int32_t ecnt_profile_read(ecnt_kernel_stat *out, int32_t max)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    int32_t n = 0;
+    for (int f = 0; f < F_COUNT && n < max && out; ++f) out[n++] = g_stats[f];
+    return n;
+}
+
+const char *ecnt_last_error(void) { return g_err.c_str(); }
+
+const char *ecnt_version(void) { return "ecount-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

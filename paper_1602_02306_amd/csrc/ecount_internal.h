@@ -1,0 +1,82 @@
+// Internal interfaces of the eigenvalue-count library (not part of the ABI).
+//
+// Device data layout (all block vectors "probe-minor"):
+//   a block vector of the run is n rows x C columns, element (r, c) at r*C + c,
+//   with C = nshift * m columns: column c = s*m + j is probe j at shift s.
+//   basis: (k+1) slots of one block vector each.  Slot l holds the Lanczos
+//   vector q_{l+1} *unnormalized*; its per-column scale sig[l][c] (1/|v| for
+//   l = 0, 1/beta_{l+1} afterwards, 0 once the column has stopped) turns it
+//   into q_{l+1}.  Slot i first receives C q_i (operator output) and is then
+//   overwritten in place by the reorthogonalized residual.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ecnt {
+
+constexpr int kColTile = 64;       // columns per wavefront (one lane per column)
+constexpr int kBasisChunk = 32;    // basis vectors per reorthogonalization launch
+constexpr int kMaxShifts = 64;
+constexpr int kMaxK = 512;
+
+struct Plan {
+    int64_t n = 0;
+    int m = 0, S = 0, C = 0, k = 0;
+    int vec_f32 = 0;      // 0: FP64 vectors, 1: FP32 vectors
+    int val_f32 = 0;      // A values FP32
+    int prec_kind = 0;
+    int ndim = 0, dims[3] = {1, 1, 1};
+    int degree = 0;
+    double coef[17] = {0};
+    double s = 0, lo = 0, hi = 0;
+    int rule = 0;
+    double smooth_w = 0;
+    // reduction geometry
+    int nct = 0;          // column tiles of 64
+    int nchunk = 0;       // row chunks of the two-phase column reductions
+    int64_t rpc = 0;      // rows per chunk
+    // workspace carve (device pointers)
+    void *basis = nullptr;     // (k+1) * n * C elements
+    void *tmp[3] = {nullptr, nullptr, nullptr};
+    double *part = nullptr;    // nchunk * kBasisChunk * C
+    double *sig = nullptr;     // (k+1) * C
+    double *alpha = nullptr;   // k * C
+    double *beta = nullptr;    // (k+1) * C
+    double *cf = nullptr;      // kBasisChunk * C   (update coefficients g_l * sig_l)
+    double *kappa = nullptr;   // C                 (beta_i * sig_{i-2})
+    double *runmax = nullptr;  // C
+    double *nu = nullptr;      // C
+    double *taus = nullptr;    // S
+    double *s_out = nullptr;   // C   per-column quadrature s_c
+    double *minabs = nullptr;  // C
+    double *jac = nullptr;     // S * n (Jacobi scaling)
+    double *result = nullptr;  // 4*S + 8 small results
+    int32_t *active = nullptr; // C
+    int32_t *kused = nullptr;  // C
+    int32_t *flags = nullptr;  // 4 status flags
+    size_t bytes = 0;
+};
+
+size_t plan_layout(Plan &p, char *base);   // base == nullptr: size only
+
+// ---- launchers (all enqueue on `st`) ----
+void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
+                        const void *val, hipStream_t st);
+void launch_setup(const Plan &p, const void *probes, hipStream_t st);
+void launch_setup_fin(const Plan &p, hipStream_t st);
+// y = M (A - tau_c I) M x  for the Jacobi / no-preconditioner path (one fused sweep)
+void launch_csr_op(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                   const void *x, const double *xscale, const double *pre_post, void *y,
+                   hipStream_t st);
+// out = cx*xs*X + cb*B(ins*IN) - cz*Z  (one Chebyshev/Clenshaw sweep on the grid Laplacian)
+void launch_cheb_sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                       bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st);
+void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st);
+void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st);
+void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st);
+void launch_norm_fin(const Plan &p, int step, hipStream_t st);
+void launch_tridiag(const Plan &p, hipStream_t st);
+void launch_reduce(const Plan &p, hipStream_t st);
+
+}  // namespace ecnt

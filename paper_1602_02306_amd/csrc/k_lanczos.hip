@@ -1,0 +1,302 @@
+// Lanczos recurrence with full reorthogonalization on a block of independent
+// probe columns (Algorithm 1; Section 3.2, the probe loop of Algorithm 2 run
+// data-parallel over columns).
+//
+// Step i of Algorithm 1, per column c (q_l = sig_{l-1} * slot_{l-1}):
+//   y      = C q_i                                (operator kernels, into slot i)
+//   w      = y - beta_i q_{i-1}
+//   g_l    = q_l^T w,  l = 1..i;  alpha_i = g_i   (k_dots + k_dots_fin)
+//   w     <- w - sum_l g_l q_l                    (k_update, in place in slot i)
+//   beta_{i+1} = |w|; sig_i = 1/beta_{i+1}        (k_norm_fin)
+// The single Gram-Schmidt pass against q_1..q_i (including q_i) also removes
+// the alpha_i q_i component: the result differs from "alpha first, then
+// reorthogonalize" only by rounding, since q_l^T q_i = delta_li + O(eps).
+//
+// Column reductions are two-phase and deterministic: each workgroup writes
+// the partial sums of its row chunk, a finalize kernel adds them in chunk
+// order.  No floating-point atomics.
+#include <float.h>
+
+#include "device_common.h"
+#include "ecount_internal.h"
+
+namespace ecnt {
+
+// ---- probe setup: slot 0 = v (for every shift), partial |v|^2 ----
+template <typename T>
+__global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int nct, int64_t rpc,
+                                               const T *__restrict__ V, T *__restrict__ slot0,
+                                               double *__restrict__ part)
+{
+    __shared__ double red[4][kColTile];
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = ct * kColTile + lane;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double acc = 0.0;
+    if (c < C) {
+        const int j = c % m;
+        for (int64_t r = r0 + wv; r < r1; r += 4) {
+            const T v = V[(size_t)r * m + j];
+            slot0[(size_t)r * C + c] = v;
+            const double dv = static_cast<double>(v);
+            acc += dv * dv;
+        }
+    }
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && c < C)
+        part[(size_t)chunk * kBasisChunk * C + c] =
+            red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+__global__ void k_setup_fin(int C, int k, int nchunk, const double *__restrict__ part,
+                            double *__restrict__ nu, double *__restrict__ sig,
+                            double *__restrict__ kappa, double *__restrict__ runmax,
+                            double *__restrict__ beta, int32_t *__restrict__ active,
+                            int32_t *__restrict__ kused)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * kBasisChunk * C + c];
+    nu[c] = s;
+    const bool ok = s > 0.0;
+    sig[c] = ok ? 1.0 / sqrt(s) : 0.0;
+    kappa[c] = 0.0;
+    runmax[c] = 0.0;
+    beta[c] = 0.0;   // beta_1 = 0 (Algorithm 1, first step)
+    active[c] = ok ? 1 : 0;
+    kused[c] = ok ? k : 0;
+}
+
+// ---- reorthogonalization dots: part[chunk][l][c] = sum_rows slot_{l0+l} * w ----
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_dots(int64_t n, int C, int nct, int64_t rpc,
+                                              const T *__restrict__ basis, size_t ss, int slot_y,
+                                              int l0, int nb, int slot_m,
+                                              const double *__restrict__ kappa,
+                                              double *__restrict__ part)
+{
+    __shared__ double red[4][NB][kColTile];
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = ct * kColTile + lane;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double acc[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) acc[l] = 0.0;
+    if (c < C) {
+        const double kap = slot_m >= 0 ? kappa[c] : 0.0;
+        const T *Y = basis + (size_t)slot_y * ss;
+        const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
+        const T *Q0 = basis + (size_t)l0 * ss;
+        for (int64_t r = r0 + wv; r < r1; r += 4) {
+            const size_t e = (size_t)r * C + c;
+            double w = ld(Y, e);
+            if (slot_m >= 0) w -= kap * ld(Qm, e);
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (l < nb) acc[l] += ld(Q0 + (size_t)l * ss, e) * w;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < NB; ++l) red[wv][l][lane] = acc[l];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nb * kColTile; idx += 256) {
+        const int l = idx / kColTile, ln = idx % kColTile;
+        const int cc = ct * kColTile + ln;
+        if (cc < C)
+            part[((size_t)chunk * kBasisChunk + l) * C + cc] =
+                red[0][l][ln] + red[1][l][ln] + red[2][l][ln] + red[3][l][ln];
+    }
+}
+
+// g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
+__global__ void k_dots_fin(int C, int nchunk, int step, int l0, int nb,
+                           const double *__restrict__ part, const double *__restrict__ sig,
+                           const int32_t *__restrict__ active, double *__restrict__ cf,
+                           double *__restrict__ alpha)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nb * C) return;
+    const int l = idx / C, c = idx % C;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)ch * kBasisChunk + l) * C + c];
+    const double sg = sig[(size_t)(l0 + l) * C + c];
+    const double g = s * sg;
+    cf[(size_t)(l0 + l) * C + c] = g * sg;
+    if (l0 + l == step - 1) alpha[(size_t)(step - 1) * C + c] = active[c] ? g : 0.0;
+}
+
+// w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
+// slot_w; the last chunk also writes partial |w|^2 into part[chunk][0][c].
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_update(int64_t n, int C, int nct, int64_t rpc,
+                                                T *__restrict__ basis, size_t ss, int slot_w,
+                                                int l0, int nb, int slot_m,
+                                                const double *__restrict__ kappa,
+                                                const double *__restrict__ cf, int last,
+                                                double *__restrict__ part)
+{
+    __shared__ double red[4][kColTile];
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = ct * kColTile + lane;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double nrm = 0.0;
+    if (c < C) {
+        const double kap = slot_m >= 0 ? kappa[c] : 0.0;
+        double co[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) co[l] = l < nb ? cf[(size_t)(l0 + l) * C + c] : 0.0;
+        T *W = basis + (size_t)slot_w * ss;
+        const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
+        const T *Q0 = basis + (size_t)l0 * ss;
+        for (int64_t r = r0 + wv; r < r1; r += 4) {
+            const size_t e = (size_t)r * C + c;
+            double w = ld(W, e);
+            if (slot_m >= 0) w -= kap * ld(Qm, e);
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (l < nb) w -= co[l] * ld(Q0 + (size_t)l * ss, e);
+            const T wt = static_cast<T>(w);
+            W[e] = wt;
+            const double wd = static_cast<double>(wt);
+            nrm += wd * wd;
+        }
+    }
+    if (!last) return;
+    red[wv][lane] = nrm;
+    __syncthreads();
+    if (wv == 0 && c < C)
+        part[(size_t)chunk * kBasisChunk * C + c] =
+            red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// beta_{i+1} = |w|, breakdown test, next scales.
+__global__ void k_norm_fin(int C, int nchunk, int step, double eps_vec,
+                           const double *__restrict__ part, const double *__restrict__ alpha,
+                           double *__restrict__ beta, double *__restrict__ sig,
+                           double *__restrict__ kappa, double *__restrict__ runmax,
+                           int32_t *__restrict__ active, int32_t *__restrict__ kused)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int i = step;
+    double ss = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) ss += part[(size_t)ch * kBasisChunk * C + c];
+    const double b = sqrt(ss);
+    double rm = fmax(runmax[c], fabs(alpha[(size_t)(i - 1) * C + c]));
+    if (i > 1) rm = fmax(rm, beta[(size_t)(i - 1) * C + c]);
+    runmax[c] = rm;
+    if (active[c]) {
+        beta[(size_t)i * C + c] = b;
+        if (b <= 1e3 * eps_vec * rm) {
+            active[c] = 0;
+            kused[c] = i;
+            sig[(size_t)i * C + c] = 0.0;
+            kappa[c] = 0.0;
+        } else {
+            sig[(size_t)i * C + c] = 1.0 / b;
+            kappa[c] = b * sig[(size_t)(i - 1) * C + c];
+        }
+    } else {
+        beta[(size_t)i * C + c] = 0.0;
+        sig[(size_t)i * C + c] = 0.0;
+        kappa[c] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline dim3 red_grid(const Plan &p) { return dim3((unsigned)((int64_t)p.nchunk * p.nct)); }
+static inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C; }
+
+void launch_setup(const Plan &p, const void *probes, hipStream_t st)
+{
+    if (p.vec_f32)
+        k_setup<float><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.nct, p.rpc,
+                                                    (const float *)probes, (float *)p.basis, p.part);
+    else
+        k_setup<double><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.nct, p.rpc,
+                                                     (const double *)probes, (double *)p.basis,
+                                                     p.part);
+}
+
+void launch_setup_fin(const Plan &p, hipStream_t st)
+{
+    k_setup_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.k, p.nchunk, p.part, p.nu, p.sig,
+                                                   p.kappa, p.runmax, p.beta, p.active, p.kused);
+}
+
+template <typename T, int NB>
+static void dots_t(const Plan &p, int step, int l0, int nb, hipStream_t st)
+{
+    k_dots<T, NB><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.nct, p.rpc, (const T *)p.basis,
+                                               slot_elems(p), step, l0, nb, step >= 2 ? step - 2 : -1,
+                                               p.kappa, p.part);
+}
+
+template <typename T>
+static void dots_dispatch(const Plan &p, int step, int l0, int nb, hipStream_t st)
+{
+    if (nb <= 4) dots_t<T, 4>(p, step, l0, nb, st);
+    else if (nb <= 8) dots_t<T, 8>(p, step, l0, nb, st);
+    else if (nb <= 16) dots_t<T, 16>(p, step, l0, nb, st);
+    else dots_t<T, 32>(p, step, l0, nb, st);
+}
+
+void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
+{
+    if (p.vec_f32) dots_dispatch<float>(p, step, l0, nb, st);
+    else dots_dispatch<double>(p, step, l0, nb, st);
+}
+
+void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
+{
+    const int tot = nb * p.C;
+    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, l0, nb, p.part, p.sig,
+                                                  p.active, p.cf, p.alpha);
+}
+
+template <typename T, int NB>
+static void update_t(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
+{
+    k_update<T, NB><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.nct, p.rpc, (T *)p.basis,
+                                                 slot_elems(p), step, l0, nb,
+                                                 (first && step >= 2) ? step - 2 : -1, p.kappa,
+                                                 p.cf, last ? 1 : 0, p.part);
+}
+
+template <typename T>
+static void update_dispatch(const Plan &p, int step, int l0, int nb, bool first, bool last,
+                            hipStream_t st)
+{
+    if (nb <= 4) update_t<T, 4>(p, step, l0, nb, first, last, st);
+    else if (nb <= 8) update_t<T, 8>(p, step, l0, nb, first, last, st);
+    else if (nb <= 16) update_t<T, 16>(p, step, l0, nb, first, last, st);
+    else update_t<T, 32>(p, step, l0, nb, first, last, st);
+}
+
+void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
+{
+    if (p.vec_f32) update_dispatch<float>(p, step, l0, nb, first, last, st);
+    else update_dispatch<double>(p, step, l0, nb, first, last, st);
+}
+
+void launch_norm_fin(const Plan &p, int step, hipStream_t st)
+{
+    const double eps = p.vec_f32 ? (double)FLT_EPSILON : DBL_EPSILON;
+    k_norm_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, eps, p.part, p.alpha,
+                                                  p.beta, p.sig, p.kappa, p.runmax, p.active,
+                                                  p.kused);
+}
+
+}  // namespace ecnt

@@ -1,0 +1,221 @@
+// Quadrature kernels: batched symmetric tridiagonal eigensolve and the probe
+// average.
+//
+// Per column c (one lane each): the Lanczos matrix J_k (Section 3.1, eq. Tk),
+// or the generalized averaged matrix of Section 3.4 (eq. GA_Tk), is
+// diagonalized by implicit QR sweeps with Wilkinson shifts, accumulating only
+// the first row of the eigenvector matrix (its entries are the z_i(1) of
+// eq. gauss_quad).  Then
+//   s_c = |v|^2 * sum_i z_i(1)^2 h(theta_i)         (eq. gauss_quad, Algorithm 2)
+// and, over probes, the mean and sample variance of the per-probe values
+// (eq. rand_prec_quad; the interval count is the difference of two shifts).
+#include <float.h>
+
+#include "device_common.h"
+#include "ecount_internal.h"
+
+namespace ecnt {
+
+constexpr int kQuadLdsBytes = 48 * 1024;
+
+template <int KMAX>
+struct QuadGeom {
+    static constexpr int lanes = (kQuadLdsBytes / (24 * KMAX)) < 64 ? (kQuadLdsBytes / (24 * KMAX)) : 64;
+};
+
+__device__ __forceinline__ double step_fn(double th, double w)
+{
+    if (w > 0.0) return 0.5 * erfc(th / w);
+    return th < 0.0 ? 1.0 : 0.0;
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_tridiag(int C, int k, int rule, double smooth_w,
+                                                const double *__restrict__ alpha,
+                                                const double *__restrict__ beta,
+                                                const int32_t *__restrict__ kused,
+                                                const double *__restrict__ nu,
+                                                double *__restrict__ s_out,
+                                                double *__restrict__ minabs,
+                                                int32_t *__restrict__ flags)
+{
+    constexpr int LN = QuadGeom<KMAX>::lanes;
+    __shared__ double lds[3 * KMAX * LN];
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x * LN + lane;
+    if (c >= C) return;
+    double *a = lds + lane;
+    double *b = lds + KMAX * LN + lane;
+    double *z = lds + 2 * KMAX * LN + lane;
+#define A_(i) a[(i) * LN]
+#define B_(i) b[(i) * LN]
+#define Z_(i) z[(i) * LN]
+    const int ku = kused[c];
+    if (ku < 1) {
+        s_out[c] = 0.0;
+        minabs[c] = INFINITY;
+        return;
+    }
+    int N;
+    if (rule == 1 && ku == k && k >= 2) {
+        // eq. GA_Tk: diag (a_1..a_k, a_{k-1}..a_1), off (b_2..b_k, b_{k+1}, b_{k-1}..b_2)
+        N = 2 * k - 1;
+        for (int i = 0; i < k; ++i) A_(i) = alpha[(size_t)i * C + c];
+        for (int i = k; i < N; ++i) A_(i) = alpha[(size_t)(2 * k - 2 - i) * C + c];
+        for (int i = 0; i < k; ++i) B_(i) = beta[(size_t)(i + 1) * C + c];
+        for (int i = k; i < N - 1; ++i) B_(i) = beta[(size_t)(2 * k - 2 - i) * C + c];
+    } else {
+        N = ku;
+        for (int i = 0; i < N; ++i) A_(i) = alpha[(size_t)i * C + c];
+        for (int i = 0; i < N - 1; ++i) B_(i) = beta[(size_t)(i + 1) * C + c];
+    }
+    for (int i = 0; i < N; ++i) Z_(i) = i == 0 ? 1.0 : 0.0;
+
+    int hi = N - 1;
+    int iter = 0;
+    bool failed = false;
+    while (hi > 0) {
+        if (fabs(B_(hi - 1)) <= DBL_EPSILON * (fabs(A_(hi - 1)) + fabs(A_(hi))) ||
+            fabs(B_(hi - 1)) < DBL_MIN) {
+            B_(hi - 1) = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0) {
+            const double bl = fabs(B_(lo - 1));
+            if (bl <= DBL_EPSILON * (fabs(A_(lo - 1)) + fabs(A_(lo))) || bl < DBL_MIN) {
+                B_(lo - 1) = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (++iter > 60 * N) {
+            failed = true;
+            break;
+        }
+        // Wilkinson shift from the trailing 2x2 block of the active window
+        const double bb = B_(hi - 1);
+        const double d = 0.5 * (A_(hi - 1) - A_(hi));
+        const double den = d + copysign(hypot(d, bb), d);
+        const double mu = A_(hi) - (den != 0.0 ? bb * bb / den : 0.0);
+        double x = A_(lo) - mu, y = B_(lo);
+        for (int kk = lo; kk < hi; ++kk) {
+            const double r = hypot(x, y);
+            double cs = 1.0, sn = 0.0;
+            if (r > 0.0) {
+                cs = x / r;
+                sn = y / r;
+            }
+            if (kk > lo) B_(kk - 1) = r;
+            const double ak = A_(kk), ak1 = A_(kk + 1), bk = B_(kk);
+            A_(kk) = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            A_(kk + 1) = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
+            const double nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
+            B_(kk) = nbk;
+            if (kk + 1 < hi) {
+                const double bk1 = B_(kk + 1);
+                y = sn * bk1;
+                B_(kk + 1) = cs * bk1;
+                x = nbk;
+            }
+            const double z0 = Z_(kk), z1 = Z_(kk + 1);
+            Z_(kk) = cs * z0 + sn * z1;
+            Z_(kk + 1) = -sn * z0 + cs * z1;
+        }
+    }
+    double s = 0.0, mn = INFINITY;
+    for (int i = 0; i < N; ++i) {
+        const double th = A_(i);
+        const double zz = Z_(i);
+        s += zz * zz * step_fn(th, smooth_w);
+        mn = fmin(mn, fabs(th));
+    }
+    s_out[c] = nu[c] * s;
+    minabs[c] = mn;
+    if (failed) atomicOr(&flags[1], 1);
+#undef A_
+#undef B_
+#undef Z_
+}
+
+// Probe average.  res[s] = mean_j s_out[s*m + j]; for t < S-1:
+// res[S + t] = mean_j d_j, res[2S - 1 + t] = sum_j (d_j - mean)^2 / ((m-1) m),
+// d_j = s_out[(t+1)*m + j] - s_out[t*m + j]; res[3S - 2] = min over columns of minabs.
+// One 256-thread workgroup; fixed reduction order.
+__device__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__restrict__ s_out,
+                                                const double *__restrict__ minabs,
+                                                double *__restrict__ res)
+{
+    __shared__ double sh[256];
+    for (int s = 0; s < S; ++s) {
+        double acc = 0.0;
+        for (int j = threadIdx.x; j < m; j += 256) acc += s_out[(size_t)s * m + j];
+        const double tot = block_sum(acc, sh);
+        if (threadIdx.x == 0) res[s] = tot / m;
+    }
+    for (int t = 0; t + 1 < S; ++t) {
+        double acc = 0.0;
+        for (int j = threadIdx.x; j < m; j += 256)
+            acc += s_out[(size_t)(t + 1) * m + j] - s_out[(size_t)t * m + j];
+        const double mean = block_sum(acc, sh) / m;
+        double v = 0.0;
+        for (int j = threadIdx.x; j < m; j += 256) {
+            const double d = s_out[(size_t)(t + 1) * m + j] - s_out[(size_t)t * m + j] - mean;
+            v += d * d;
+        }
+        const double vs = block_sum(v, sh);
+        if (threadIdx.x == 0) {
+            res[S + t] = mean;
+            res[2 * S - 1 + t] = m > 1 ? vs / ((double)(m - 1) * m) : NAN;
+        }
+    }
+    double mn = INFINITY;
+    for (int c = threadIdx.x; c < S * m; c += 256) mn = fmin(mn, minabs[c]);
+    sh[threadIdx.x] = mn;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) res[3 * S - 2] = sh[0];
+}
+
+template <int KMAX>
+static void tridiag_t(const Plan &p, hipStream_t st)
+{
+    constexpr int LN = QuadGeom<KMAX>::lanes;
+    const int blocks = (p.C + LN - 1) / LN;
+    k_tridiag<KMAX><<<blocks, LN, 0, st>>>(p.C, p.k, p.rule, p.smooth_w, p.alpha, p.beta, p.kused,
+                                           p.nu, p.s_out, p.minabs, p.flags);
+}
+
+void launch_tridiag(const Plan &p, hipStream_t st)
+{
+    const int N = (p.rule == 1) ? 2 * p.k - 1 : p.k;
+    if (N <= 32) tridiag_t<32>(p, st);
+    else if (N <= 64) tridiag_t<64>(p, st);
+    else if (N <= 128) tridiag_t<128>(p, st);
+    else if (N <= 256) tridiag_t<256>(p, st);
+    else tridiag_t<512>(p, st);
+}
+
+void launch_reduce(const Plan &p, hipStream_t st)
+{
+    k_reduce<<<1, 256, 0, st>>>(p.S, p.m, p.s_out, p.minabs, p.result);
+}
+
+}  // namespace ecnt

@@ -1,0 +1,297 @@
+"""Python binding of libecount.so (the C ABI in include/ecount.h).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+kernels of the library.  PyTorch provides device memory (the CSR arrays, the
+probe block, the workspace, the optional per-probe outputs) and the current
+stream.  There is no CPU fallback: if the library is not built, or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libecount.so")
+
+ECNT_OK, ECNT_EINVAL, ECNT_ENOTHPD, ECNT_EWORKSPACE, ECNT_EDEVICE, ECNT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "ECNT_OK", -1: "ECNT_EINVAL", -2: "ECNT_ENOTHPD", -3: "ECNT_EWORKSPACE",
+                -4: "ECNT_EDEVICE", -5: "ECNT_EUNSUPPORTED"}
+DTYPES = {"f64": 0, "f32": 1}
+PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2}
+RULES = {"gauss": 0, "ga": 1}
+
+
+class EcntError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class CsrT(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("val_type", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PrecT(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int32 * 3),
+                ("degree", ctypes.c_int32), ("s", ctypes.c_double), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double), ("coef", ctypes.c_void_p)]
+
+
+class OptsT(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("vec_type", ctypes.c_int32), ("rule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("smooth_w", ctypes.c_double)]
+
+
+class InfoT(ctypes.Structure):
+    _fields_ = [("neg_xi", ctypes.c_double), ("neg_eta", ctypes.c_double),
+                ("min_abs_ritz", ctypes.c_double), ("per_probe", ctypes.c_void_p),
+                ("k_used", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
+
+
+class KernelStatT(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libecount.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libecount.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_1602_02306_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        lib.ecnt_workspace_bytes.restype = ctypes.c_size_t
+        lib.ecnt_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.POINTER(PrecT), ctypes.POINTER(OptsT)]
+        lib.ecnt_count.restype = ctypes.c_int32
+        lib.ecnt_count.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT), ctypes.c_double,
+                                   ctypes.c_double, P, ctypes.c_int64, ctypes.POINTER(OptsT), P,
+                                   ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(InfoT)]
+        lib.ecnt_negcounts.restype = ctypes.c_int32
+        lib.ecnt_negcounts.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT), P,
+                                       ctypes.c_int32, P, ctypes.c_int64, ctypes.POINTER(OptsT), P,
+                                       ctypes.c_size_t, P, P, P, P, ctypes.POINTER(InfoT)]
+        lib.ecnt_last_error.restype = ctypes.c_char_p
+        lib.ecnt_last_error.argtypes = []
+        lib.ecnt_version.restype = ctypes.c_char_p
+        lib.ecnt_version.argtypes = []
+        lib.ecnt_profile_enable.restype = ctypes.c_int32
+        lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
+        lib.ecnt_profile_read.restype = ctypes.c_int32
+        lib.ecnt_profile_read.argtypes = [ctypes.POINTER(KernelStatT), ctypes.c_int32]
+        _lib = lib
+    return _lib
+
+
+def last_error() -> str:
+    return load().ecnt_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != ECNT_OK:
+        raise EcntError(rc, last_error())
+
+
+# ---------------------------------------------------------------------------
+# Device-side inputs
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class DeviceCSR:
+    n: int
+    nnz: int
+    row_ptr: object   # torch int32 (device)
+    col_idx: object   # torch int32 (device)
+    val: object       # torch float64/float32 (device)
+
+    def struct(self) -> CsrT:
+        import torch
+        vt = DTYPES["f32"] if self.val.dtype == torch.float32 else DTYPES["f64"]
+        return CsrT(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                    self.val.data_ptr(), vt, 0)
+
+
+def upload_csr(A, val_dtype: str = "f64", device: str = "cuda") -> DeviceCSR:
+    """Copy a host CSR (workloads.CSR) to device memory."""
+    import torch
+    tdt = torch.float32 if val_dtype == "f32" else torch.float64
+    return DeviceCSR(int(A.n), int(A.nnz),
+                     torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(A.col_idx, dtype=np.int32)).to(device),
+                     torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device, tdt))
+
+
+def prec_struct(prec):
+    """ecnt_prec from a workloads.PrecSpec; returns (struct, keep-alive coef array)."""
+    kind = PREC_KINDS[prec.kind]
+    dims = (ctypes.c_int32 * 3)(0, 0, 0)
+    coef = np.zeros(1)
+    ndim = 0
+    if kind == 2:
+        ndim = len(prec.dims)
+        for a, d in enumerate(prec.dims):
+            dims[a] = int(d)
+        coef = np.ascontiguousarray(prec.coef, dtype=np.float64)
+    st = PrecT(kind, ndim, dims, max(len(coef) - 1, 0) if kind == 2 else 0, float(prec.s),
+               float(prec.lo), float(prec.hi), coef.ctypes.data if kind == 2 else None)
+    return st, coef
+
+
+def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0) -> OptsT:
+    return OptsT(int(k), DTYPES[vec], RULES[rule], 0, float(smooth_w))
+
+
+def workspace_bytes(n: int, m: int, nshift: int, prec, k: int, vec: str = "f64",
+                    rule: str = "gauss", smooth_w: float = 0.0) -> int:
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, vec, rule, smooth_w)
+    return int(load().ecnt_workspace_bytes(int(n), int(m), int(nshift), ctypes.byref(ps),
+                                           ctypes.byref(o)))
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Workspace:
+    """A reusable device workspace (torch uint8 buffer)."""
+
+    def __init__(self, nbytes: int, device: str = "cuda"):
+        import torch
+        self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+    @property
+    def nbytes(self) -> int:
+        return self.buf.numel()
+
+    def ensure(self, nbytes: int):
+        if self.nbytes < nbytes:
+            import torch
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.buf.device)
+        return self
+
+
+@dataclass
+class CountResult:
+    estimate: float
+    variance: float
+    neg_xi: float
+    neg_eta: float
+    min_abs_ritz: float
+    per_probe: object = None   # torch (2m,) float64: s_j(xi) then s_j(eta)
+    k_used: object = None      # torch (2m,) int32
+    alpha: object = None       # torch (k, 2m)
+    beta: object = None        # torch (k+1, 2m)
+
+
+def _info(C: int, k: int, want: bool, device):
+    import torch
+    if not want:
+        return InfoT(), {}
+    t = {"per_probe": torch.empty(C, dtype=torch.float64, device=device),
+         "k_used": torch.empty(C, dtype=torch.int32, device=device),
+         "alpha": torch.empty((k, C), dtype=torch.float64, device=device),
+         "beta": torch.empty((k + 1, C), dtype=torch.float64, device=device)}
+    info = InfoT(0.0, 0.0, 0.0, t["per_probe"].data_ptr(), t["k_used"].data_ptr(),
+                 t["alpha"].data_ptr(), t["beta"].data_ptr())
+    return info, t
+
+
+def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
+          rule: str = "gauss", smooth_w: float = 0.0, workspace: Workspace | None = None,
+          stream=None, details: bool = True) -> CountResult:
+    """Interval count on [xi, eta) (ecnt_count).  `probes`: torch device tensor
+    n x m (float64 for vec='f64', float32 for vec='f32')."""
+    lib = load()
+    n, m = probes.shape
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, vec, rule, smooth_w)
+    need = lib.ecnt_workspace_bytes(n, m, 2, ctypes.byref(ps), ctypes.byref(o))
+    if need == 0:
+        raise EcntError(ECNT_EINVAL, last_error())
+    ws = (workspace or Workspace(need, probes.device)).ensure(need)
+    info, keep = _info(2 * m, k, details, probes.device)
+    est, var = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    rc = lib.ecnt_count(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                        probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
+                        _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
+                        ctypes.byref(info))
+    _check(rc)
+    return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
+                       keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"),
+                       keep.get("beta"))
+
+
+@dataclass
+class NegcountsResult:
+    negcounts: np.ndarray
+    counts: np.ndarray
+    variances: np.ndarray
+    min_abs_ritz: float
+    per_probe: object = None
+    k_used: object = None
+    alpha: object = None
+    beta: object = None
+
+
+def negcounts(A: DeviceCSR, prec, taus, probes, k: int, vec: str = "f64", rule: str = "gauss",
+              smooth_w: float = 0.0, workspace: Workspace | None = None, stream=None,
+              details: bool = True) -> NegcountsResult:
+    """Algorithm 2 at several shifts on one probe block (ecnt_negcounts)."""
+    lib = load()
+    n, m = probes.shape
+    taus = np.ascontiguousarray(taus, dtype=np.float64)
+    S = len(taus)
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, vec, rule, smooth_w)
+    need = lib.ecnt_workspace_bytes(n, m, S, ctypes.byref(ps), ctypes.byref(o))
+    if need == 0:
+        raise EcntError(ECNT_EINVAL, last_error())
+    ws = (workspace or Workspace(need, probes.device)).ensure(need)
+    info, keep = _info(S * m, k, details, probes.device)
+    neg = np.zeros(S)
+    cnt = np.zeros(max(S - 1, 1))
+    var = np.zeros(max(S - 1, 1))
+    cs = A.struct()
+    rc = lib.ecnt_negcounts(ctypes.byref(cs), ctypes.byref(ps), taus.ctypes.data, S,
+                            probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
+                            _stream_handle(stream), neg.ctypes.data, cnt.ctypes.data,
+                            var.ctypes.data, ctypes.byref(info))
+    _check(rc)
+    return NegcountsResult(neg, cnt[:S - 1], var[:S - 1], info.min_abs_ritz,
+                           keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"),
+                           keep.get("beta"))
+
+
+def version() -> str:
+    return load().ecnt_version().decode()
+
+
+def profile_enable(on: bool = True):
+    """Start (and reset) or stop per-kernel-family HIP-event timing."""
+    _check(load().ecnt_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{family: {launches, ms, bytes}} accumulated since profile_enable(True)."""
+    arr = (KernelStatT * 16)()
+    n = load().ecnt_profile_read(arr, 16)
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].total_ms),
+                                   "bytes": float(arr[i].bytes)} for i in range(n)}
