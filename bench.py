@@ -98,6 +98,80 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
+FAMILY_OF = [("k_stencil", "op_cheb_sweep"), ("k_csr_op", "op_csr"), ("k_dots_fin", "lz_finalize"),
+             ("k_dots", "lz_dots"), ("k_update", "lz_update"), ("k_setup_fin", "lz_finalize"),
+             ("k_setup", "lz_setup"), ("k_norm_fin", "lz_finalize"), ("k_jacobi_diag", "lz_setup"),
+             ("k_tridiag", "quadrature"), ("k_reduce", "quadrature"), ("k_init", "lz_finalize"),
+             ("copyBuffer", "copy"), ("FillFunc", "fill")]
+
+
+def family(kernel_name: str) -> str:
+    for key, fam in FAMILY_OF:
+        if key in kernel_name:
+            return fam
+    return kernel_name[:48]
+
+
+def summarize(trace_dir: str, pmc_dir: str | None, command: str, workload: str):
+    """Markdown summary of rocprofv3 output: per kernel family, launches, total
+    and average duration (kernel trace), and, when counter runs are given,
+    calibrated HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (scaled by
+    what the same counters read for a plain device copy of known size)."""
+    import csv
+    import collections
+    import glob
+
+    def one(pattern):
+        files = glob.glob(os.path.join(pattern), recursive=True)
+        return files[0] if files else None
+
+    trace = one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    fams = collections.defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(trace)):
+        f = family(r["Kernel_Name"])
+        fams[f][0] += 1
+        fams[f][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    total = sum(v[1] for v in fams.values())
+    lines = ["# rocprofv3 summary: %s" % workload, "", "Command (from the repository root):", "",
+             "    " + command, "",
+             "| kernel family | launches | total ms | share | avg ms/launch |",
+             "|---|---:|---:|---:|---:|"]
+    for f, (n, ms) in sorted(fams.items(), key=lambda x: -x[1][1]):
+        lines.append("| %s | %d | %.3f | %.1f%% | %.4f |" % (f, n, ms, 100 * ms / total, ms / n))
+    counters = {}
+    if pmc_dir:
+        calib = {}
+        per = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            cf = one(os.path.join(pmc_dir, "pmc_copy_" + ctr, "**", "*counter_collection.csv"))
+            copies = [float(r["Counter_Value"]) for r in csv.DictReader(open(cf))
+                      if "copyBuffer" in r["Kernel_Name"]]
+            # each copy moves 1 GiB each way: KiB expected / KiB counted
+            calib[ctr] = (2 ** 20) / (sum(copies) / len(copies))
+            kf = one(os.path.join(pmc_dir, "pmc_" + ctr, "**", "*counter_collection.csv"))
+            acc = collections.defaultdict(lambda: [0, 0.0])
+            for r in csv.DictReader(open(kf)):
+                a = acc[family(r["Kernel_Name"])]
+                a[0] += 1
+                a[1] += float(r["Counter_Value"])
+            per[ctr] = acc
+        lines += ["", "Counter calibration (plain 1 GiB device copy): FETCH_SIZE x %.3f, "
+                      "WRITE_SIZE x %.3f" % (calib["FETCH_SIZE"], calib["WRITE_SIZE"]), "",
+                  "| kernel family | fetch GiB/launch | write GiB/launch | HBM GiB/launch (calibrated) |",
+                  "|---|---:|---:|---:|"]
+        for f in sorted(per["FETCH_SIZE"], key=lambda f: -per["FETCH_SIZE"][f][1]):
+            nf, vf = per["FETCH_SIZE"][f]
+            nw, vw = per["WRITE_SIZE"].get(f, [1, 0.0])
+            fg = vf / nf * calib["FETCH_SIZE"] / 2 ** 20
+            wg = vw / max(nw, 1) * calib["WRITE_SIZE"] / 2 ** 20
+            if fg + wg < 1e-3:
+                continue
+            counters[f] = {"fetch_bytes_per_launch": fg * 2 ** 30, "write_bytes_per_launch": wg * 2 ** 30,
+                           "hbm_bytes_per_launch": (fg + wg) * 2 ** 30}
+            lines.append("| %s | %.3f | %.3f | %.3f |" % (f, fg, wg, fg + wg))
+    return "\n".join(lines) + "\n", counters
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +181,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--summarize", metavar="TRACE_DIR",
+                    help="print a markdown summary of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--pmc-dir", help="with --summarize: directory holding the counter runs")
+    ap.add_argument("--command", default="", help="with --summarize: the profiled command")
+    ap.add_argument("--counters-json", help="with --summarize: write calibrated per-launch bytes here")
     args = ap.parse_args()
+
+    if args.summarize:
+        text, counters = summarize(args.summarize, args.pmc_dir, args.command, args.workload)
+        print(text)
+        if args.counters_json and counters:
+            json.dump({"source_sha": kernel_sources_sha(), "workload": args.workload,
+                       "command": args.command, "kernels": counters},
+                      open(args.counters_json, "w"), indent=1)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the estimator on a single "

@@ -87,11 +87,19 @@ typedef enum {
     ECNT_PREC_CHEB_LAPLACIAN = 2
 } ecnt_prec_kind;
 
+/* How M is evaluated (CHEB only).  Both compute the same polynomial in B. */
+typedef enum {
+    ECNT_EVAL_AUTO = 0,     /* product of real linear/quadratic factors from the roots of
+                               the series when they reproduce it to 1e-12, else Clenshaw */
+    ECNT_EVAL_CLENSHAW = 1  /* Clenshaw's recurrence on the series */
+} ecnt_eval;
+
 typedef struct {
     int32_t kind;        /* ecnt_prec_kind */
     int32_t ndim;        /* 1..3 (CHEB only) */
     int32_t dims[3];     /* grid extents, product == n (CHEB only) */
     int32_t degree;      /* 0..16 (CHEB only) */
+    int32_t eval;        /* ecnt_eval (CHEB only) */
     double s, lo, hi;    /* shift of L and the interval mapped to [-1, 1] (CHEB only) */
     const double *coef;  /* host, degree+1 entries, copied at call time (CHEB only) */
 } ecnt_prec;
@@ -109,7 +117,11 @@ typedef struct {
                            alpha/beta, every dot product and norm, and the tridiagonal
                            eigensolve are FP64 in both cases. */
     int32_t rule;       /* ecnt_rule */
-    int32_t reserved;   /* must be 0 */
+    int32_t max_cols;   /* 0: all nshift*m Lanczos columns run together.  > 0: the columns
+                           (column c = shift c/m, probe c%m) run in consecutive waves of at
+                           most max_cols, reusing one workspace: bounds the memory of the
+                           Lanczos basis ((k+1) x n x max_cols vectors) at the cost of more
+                           passes over A.  Results do not depend on it. */
     double smooth_w;    /* 0: the paper's step h (h(theta) = 1 iff theta < 0).
                            > 0: h replaced by erfc(theta / smooth_w) / 2. */
 } ecnt_opts;

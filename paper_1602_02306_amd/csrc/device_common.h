@@ -24,4 +24,56 @@ __device__ __forceinline__ double ld(const T *p, size_t i)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// VW consecutive columns per lane, moved as one vector load/store.
+template <typename T, int VW> struct VecT;
+template <> struct VecT<double, 1> { using type = double; };
+template <> struct VecT<double, 2> { using type = double2; };
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<float, 2> { using type = float2; };
+template <> struct VecT<float, 4> { using type = float4; };
+
+template <typename T, int VW>
+__device__ __forceinline__ void vload(const T *__restrict__ p, size_t e, double (&o)[VW])
+{
+    using V = typename VecT<T, VW>::type;
+    const V v = *reinterpret_cast<const V *>(p + e);
+    if constexpr (VW == 1) {
+        o[0] = static_cast<double>(v);
+    } else if constexpr (VW == 2) {
+        o[0] = static_cast<double>(v.x);
+        o[1] = static_cast<double>(v.y);
+    } else {
+        o[0] = static_cast<double>(v.x);
+        o[1] = static_cast<double>(v.y);
+        o[2] = static_cast<double>(v.z);
+        o[3] = static_cast<double>(v.w);
+    }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vstore(T *__restrict__ p, size_t e, const double (&o)[VW])
+{
+    using V = typename VecT<T, VW>::type;
+    V v;
+    if constexpr (VW == 1) {
+        v = static_cast<T>(o[0]);
+    } else if constexpr (VW == 2) {
+        v.x = static_cast<T>(o[0]);
+        v.y = static_cast<T>(o[1]);
+    } else {
+        v.x = static_cast<T>(o[0]);
+        v.y = static_cast<T>(o[1]);
+        v.z = static_cast<T>(o[2]);
+        v.w = static_cast<T>(o[3]);
+    }
+    *reinterpret_cast<V *>(p + e) = v;
+}
+
+// Value after rounding to the storage type T (what a later load returns).
+template <typename T>
+__device__ __forceinline__ double rounded(double x)
+{
+    return static_cast<double>(static_cast<T>(x));
+}
+
 }  // namespace ecnt

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <complex>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -94,6 +95,8 @@ static ecnt_status fail(ecnt_status st, const char *fmt, ...)
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+static void geometry(Plan &p);
+
 size_t plan_layout(Plan &p, char *base)
 {
     size_t off = 0;
@@ -104,12 +107,22 @@ size_t plan_layout(Plan &p, char *base)
         return ptr;
     };
     const size_t bv = p.vec_f32 ? 4 : 8;
-    const size_t blk = (size_t)p.n * p.C * bv;
-    const size_t C = p.C;
+    const size_t blk = (size_t)p.n * p.wave_cols * bv;
+    const size_t C = p.wave_cols;
+    const size_t Ct = p.Ct;
     p.basis = take(blk * (p.k + 1));
     const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : 0;
     for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;
-    p.part = (double *)take(sizeof(double) * (size_t)p.nchunk * kBasisChunk * C);
+    // partial sums: the largest of the full and the (narrower) last wave
+    size_t part_elems = 0;
+    for (int w = 0; w < 2; ++w) {
+        Plan q = p;
+        q.C = w == 0 ? p.wave_cols : (p.Ct - (p.Ct - 1) / p.wave_cols * p.wave_cols);
+        geometry(q);
+        const size_t e = (size_t)q.nchunk * kBasisChunk * q.C;
+        if (e > part_elems) part_elems = e;
+    }
+    p.part = (double *)take(sizeof(double) * part_elems);
     p.sig = (double *)take(sizeof(double) * (p.k + 1) * C);
     p.alpha = (double *)take(sizeof(double) * p.k * C);
     p.beta = (double *)take(sizeof(double) * (p.k + 1) * C);
@@ -118,27 +131,122 @@ size_t plan_layout(Plan &p, char *base)
     p.runmax = (double *)take(sizeof(double) * C);
     p.nu = (double *)take(sizeof(double) * C);
     p.taus = (double *)take(sizeof(double) * kMaxShifts);
-    p.s_out = (double *)take(sizeof(double) * C);
-    p.minabs = (double *)take(sizeof(double) * C);
+    p.s_out = (double *)take(sizeof(double) * Ct);
+    p.minabs = (double *)take(sizeof(double) * Ct);
     p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
     p.result = (double *)take(sizeof(double) * (4 * kMaxShifts + 8));
     p.active = (int32_t *)take(sizeof(int32_t) * C);
-    p.kused = (int32_t *)take(sizeof(int32_t) * C);
+    p.kused = (int32_t *)take(sizeof(int32_t) * Ct);
     p.flags = (int32_t *)take(sizeof(int32_t) * 4);
     p.bytes = align_up(off, 256) + 256;   // slack for aligning the caller's pointer
     return p.bytes;
 }
 
-static void reduction_geometry(Plan &p)
+static void geometry(Plan &p)
 {
+    // columns per lane: 16-byte accesses where the column count allows it
+    if (p.vec_f32) p.vw = (p.C % 4 == 0) ? 4 : (p.C % 2 == 0 ? 2 : 1);
+    else p.vw = (p.C % 2 == 0) ? 2 : 1;
     p.nct = (p.C + kColTile - 1) / kColTile;
-    // about 2048 workgroups of 4 waves for the column reductions
-    int64_t target = (2048 + p.nct - 1) / p.nct;
-    int64_t maxchunks = (p.n + 3) / 4;
+    // reductions: one wavefront per (row chunk, tile of 64 lanes); about 2048 of them
+    const int vwr = (p.vec_f32 && p.C % 2 == 0) ? 2 : 1;
+    const int nctr = (p.C + 64 * vwr - 1) / (64 * vwr);
+    int64_t target = (2048 + nctr - 1) / nctr;
+    const int64_t maxchunks = (p.n + 15) / 16;
     if (target > maxchunks) target = maxchunks;
     if (target < 1) target = 1;
     p.rpc = (p.n + target - 1) / target;
     p.nchunk = (int)((p.n + p.rpc - 1) / p.rpc);
+}
+
+// ---- product form of the preconditioner polynomial ----
+// p(t) = sum_j c_j T_j(t) and p'(t) by Clenshaw's recurrence (complex t).
+static std::complex<double> cheb_eval(const double *c, int d, std::complex<double> t,
+                                      std::complex<double> *dp)
+{
+    std::complex<double> b1 = 0, b2 = 0, d1 = 0, d2 = 0;
+    for (int j = d; j >= 1; --j) {
+        std::complex<double> b = c[j] + 2.0 * t * b1 - b2;
+        std::complex<double> db = 2.0 * b1 + 2.0 * t * d1 - d2;
+        b2 = b1;
+        b1 = b;
+        d2 = d1;
+        d1 = db;
+    }
+    if (dp) *dp = b1 + t * d1 - d2;
+    return c[0] + t * b1 - b2;
+}
+
+// Roots by the Aberth-Ehrlich simultaneous iteration, paired into real
+// linear / quadratic factors; accepted only if lead * prod (t - r) reproduces
+// p on [-1, 1] to 1e-12 relative.  Returns false otherwise (Clenshaw is used).
+static bool factorize(Plan &p)
+{
+    const int d = p.degree;
+    if (d < 2 || d > 16 || p.coef[d] == 0.0) return false;
+    typedef std::complex<double> cd;
+    cd z[16];
+    for (int i = 0; i < d; ++i) z[i] = std::polar(1.3, 2.0 * M_PI * (i + 0.25) / d);
+    for (int it = 0; it < 500; ++it) {
+        double maxstep = 0.0;
+        for (int i = 0; i < d; ++i) {
+            cd dp;
+            const cd pv = cheb_eval(p.coef, d, z[i], &dp);
+            if (std::abs(pv) == 0.0) continue;
+            const cd ratio = pv / dp;
+            cd sum = 0;
+            for (int j = 0; j < d; ++j)
+                if (j != i) sum += 1.0 / (z[i] - z[j]);
+            const cd step = ratio / (1.0 - ratio * sum);
+            z[i] -= step;
+            maxstep = fmax(maxstep, std::abs(step) / fmax(1.0, std::abs(z[i])));
+        }
+        if (maxstep < 1e-15) break;
+    }
+    bool used[16] = {false};
+    int nf = 0;
+    for (int i = 0; i < d; ++i) {
+        if (used[i]) continue;
+        used[i] = true;
+        if (fabs(z[i].imag()) <= 1e-10 * fmax(1.0, std::abs(z[i]))) {
+            p.fac_quad[nf] = 0;
+            p.fac_a[nf] = z[i].real();
+            p.fac_b[nf] = 0.0;
+            ++nf;
+            continue;
+        }
+        int best = -1;
+        double bd = 1e300;
+        for (int j = 0; j < d; ++j) {
+            if (used[j]) continue;
+            const double dd = std::abs(z[j] - std::conj(z[i]));
+            if (dd < bd) {
+                bd = dd;
+                best = j;
+            }
+        }
+        if (best < 0 || bd > 1e-8 * fmax(1.0, std::abs(z[i]))) return false;
+        used[best] = true;
+        const cd r = 0.5 * (z[i] + std::conj(z[best]));
+        p.fac_quad[nf] = 1;
+        p.fac_a[nf] = r.real();
+        p.fac_b[nf] = std::norm(r);
+        ++nf;
+    }
+    p.nfac = nf;
+    p.lead = p.coef[d] * ldexp(1.0, d - 1);
+    // validate on Chebyshev points of [-1, 1]
+    double maxp = 0.0, maxerr = 0.0;
+    for (int k = 0; k < 4 * d + 1; ++k) {
+        const double t = cos(M_PI * (k + 0.5) / (4 * d + 1));
+        const double pv = cheb_eval(p.coef, d, cd(t, 0.0), nullptr).real();
+        double q = p.lead;
+        for (int f = 0; f < nf; ++f)
+            q *= p.fac_quad[f] ? (t * t - 2.0 * p.fac_a[f] * t + p.fac_b[f]) : (t - p.fac_a[f]);
+        maxp = fmax(maxp, fabs(pv));
+        maxerr = fmax(maxerr, fabs(q - pv));
+    }
+    return maxerr <= 1e-12 * maxp;
 }
 
 static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_prec *T,
@@ -155,7 +263,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         return fail(ECNT_EINVAL, "vec_type must be ECNT_F64 or ECNT_F32");
     if (o->rule != ECNT_RULE_GAUSS && o->rule != ECNT_RULE_GA)
         return fail(ECNT_EINVAL, "unknown quadrature rule %d", o->rule);
-    if (o->reserved != 0) return fail(ECNT_EINVAL, "opts.reserved must be 0");
+    if (o->max_cols < 0) return fail(ECNT_EINVAL, "opts.max_cols must be >= 0");
     if (!(o->smooth_w >= 0.0) || !isfinite(o->smooth_w))
         return fail(ECNT_EINVAL, "smooth_w must be finite and >= 0");
     const int kmax = o->rule == ECNT_RULE_GA ? kMaxK / 2 : kMaxK;
@@ -163,7 +271,9 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     p.n = n;
     p.m = (int)m;
     p.S = S;
-    p.C = (int)(m * S);
+    p.Ct = (int)(m * S);
+    p.wave_cols = (o->max_cols > 0 && o->max_cols < p.Ct) ? o->max_cols : p.Ct;
+    p.C = p.wave_cols;
     p.k = o->k;
     p.vec_f32 = o->vec_type == ECNT_F32;
     p.rule = o->rule;
@@ -184,6 +294,8 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         }
         if (prod != n) return fail(ECNT_EINVAL, "prec grid (%lld points) does not match n", (long long)prod);
         if (T->degree < 0 || T->degree > 16) return fail(ECNT_EINVAL, "prec.degree must be 0..16");
+        if (T->eval != ECNT_EVAL_AUTO && T->eval != ECNT_EVAL_CLENSHAW)
+            return fail(ECNT_EINVAL, "prec.eval must be ECNT_EVAL_AUTO or ECNT_EVAL_CLENSHAW");
         if (!T->coef) return fail(ECNT_EINVAL, "prec.coef is null");
         if (!isfinite(T->s) || !isfinite(T->lo) || !isfinite(T->hi) || !(T->hi > T->lo))
             return fail(ECNT_EINVAL, "prec interval must be finite with hi > lo");
@@ -204,7 +316,9 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     default:
         return fail(ECNT_EINVAL, "unknown preconditioner kind %d", T->kind);
     }
-    reduction_geometry(p);
+    geometry(p);
+    if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && T->eval == ECNT_EVAL_AUTO)
+        p.product = factorize(p) ? 1 : 0;
     plan_layout(p, nullptr);
     return ECNT_OK;
 }
@@ -227,67 +341,131 @@ __global__ void k_init(InitArgs a, double *taus, int32_t *flags)
 // only where noted by the caller: here it must differ from both).
 static double block_bytes(const Plan &p) { return (double)p.n * p.C * (p.vec_f32 ? 4 : 8); }
 
-static void cheb_sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
-                       bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st)
+static void sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                  bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st)
 {
     // distinct block vectors read, plus the one written
     int nread = 1 + ((IN && IN != X) ? 1 : 0) + ((Z && Z != X && Z != IN) ? 1 : 0);
     Timed t(F_CHEB, (nread + 1) * block_bytes(p), st);
-    launch_cheb_sweep(p, X, xs, cx, IN, in_is_x, cb, Z, cz, out, st);
+    launch_stencil(p, X, xs, cx, IN, in_is_x, cb, Z, cz, out, st);
+}
+
+// M x in product form, x = xs .* X:  M = lead * prod_f F_f(B), applied factor by
+// factor; a quadratic factor (B^2 - 2aB + b) takes two sweeps,
+//   t = B x - 2a x ;  y = B t + b x.
+// Scratch: t0 (quadratic intermediate) and t1; `out` also serves as an
+// intermediate so that the last factor lands in it.
+static void apply_M_product(const Plan &p, const void *X, const double *xs, void *t0, void *t1,
+                            void *out, hipStream_t st)
+{
+    const void *in = X;
+    const double *insc = xs;
+    double scale = p.lead;
+    for (int f = 0; f < p.nfac; ++f) {
+        void *dst = ((p.nfac - 1 - f) % 2 == 0) ? out : t1;
+        const double a = p.fac_a[f];
+        if (!p.fac_quad[f]) {
+            sweep(p, in, insc, -a * scale, in, insc != nullptr, scale, nullptr, 0.0, dst, st);
+        } else {
+            sweep(p, in, insc, -2.0 * a * scale, in, insc != nullptr, scale, nullptr, 0.0, t0, st);
+            sweep(p, in, insc, p.fac_b[f] * scale, t0, false, 1.0, nullptr, 0.0, dst, st);
+        }
+        in = dst;
+        insc = nullptr;
+        scale = 1.0;
+    }
+}
+
+// M x by Clenshaw's recurrence, x = xs .* X:
+// b_{d+1} = b_{d+2} = 0; b_j = c_j x + 2 B b_{j+1} - b_{j+2}; M x = c_0 x + B b_1 - b_2.
+// Scratch t0, t1; `out` must differ from both.
+static void apply_M_clenshaw(const Plan &p, const void *X, const double *xs, void *t0, void *t1,
+                             void *out, hipStream_t st)
+{
+    const double *c = p.coef;
+    const int d = p.degree;
+    if (d == 0) {
+        sweep(p, X, xs, c[0], nullptr, false, 0.0, nullptr, 0.0, out, st);
+        return;
+    }
+    if (d == 1) {
+        sweep(p, X, xs, c[0], X, true, c[1], nullptr, 0.0, out, st);
+        return;
+    }
+    // b_{d-1} = c_{d-1} x + 2 c_d B x
+    void *bj1 = t0;   // b_{j+1}
+    sweep(p, X, xs, c[d - 1], X, true, 2.0 * c[d], nullptr, 0.0, bj1, st);
+    if (d == 2) {
+        // M x = c_0 x + B b_1 - b_2, b_2 = c_2 x
+        sweep(p, X, xs, c[0] - c[2], bj1, false, 1.0, nullptr, 0.0, out, st);
+        return;
+    }
+    // b_{d-2} = (c_{d-2} - c_d) x + 2 B b_{d-1}
+    void *bj = t1;
+    sweep(p, X, xs, c[d - 2] - c[d], bj1, false, 2.0, nullptr, 0.0, bj, st);
+    void *bj2 = bj1;  // b_{j+2}
+    bj1 = bj;
+    for (int j = d - 3; j >= 1; --j) {
+        // b_j = c_j x + 2 B b_{j+1} - b_{j+2}, written over b_{j+2} (read point-wise only)
+        sweep(p, X, xs, c[j], bj1, false, 2.0, bj2, 1.0, bj2, st);
+        void *tmp = bj2;
+        bj2 = bj1;
+        bj1 = tmp;
+    }
+    sweep(p, X, xs, c[0], bj1, false, 1.0, bj2, 1.0, out, st);
 }
 
 static void apply_M(const Plan &p, const void *X, const double *xs, void *t0, void *t1, void *out,
                     hipStream_t st)
 {
-    const double *c = p.coef;
-    const int d = p.degree;
-    if (d == 0) {
-        cheb_sweep(p, X, xs, c[0], nullptr, false, 0.0, nullptr, 0.0, out, st);
-        return;
-    }
-    if (d == 1) {
-        cheb_sweep(p, X, xs, c[0], X, true, c[1], nullptr, 0.0, out, st);
-        return;
-    }
-    // b_{d-1} = c_{d-1} x + 2 c_d B x
-    void *bj1 = t0;   // b_{j+1}
-    cheb_sweep(p, X, xs, c[d - 1], X, true, 2.0 * c[d], nullptr, 0.0, bj1, st);
-    if (d == 2) {
-        // M x = c_0 x + B b_1 - b_2, b_2 = c_2 x
-        cheb_sweep(p, X, xs, c[0] - c[2], bj1, false, 1.0, nullptr, 0.0, out, st);
-        return;
-    }
-    // b_{d-2} = (c_{d-2} - c_d) x + 2 B b_{d-1}
-    void *bj = t1;
-    cheb_sweep(p, X, xs, c[d - 2] - c[d], bj1, false, 2.0, nullptr, 0.0, bj, st);
-    void *bj2 = bj1;  // b_{j+2}
-    bj1 = bj;
-    for (int j = d - 3; j >= 1; --j) {
-        // b_j = c_j x + 2 B b_{j+1} - b_{j+2}, written over b_{j+2} (read point-wise only)
-        cheb_sweep(p, X, xs, c[j], bj1, false, 2.0, bj2, 1.0, bj2, st);
-        void *tmp = bj2;
-        bj2 = bj1;
-        bj1 = tmp;
-    }
-    cheb_sweep(p, X, xs, c[0], bj1, false, 1.0, bj2, 1.0, out, st);
+    if (p.product) apply_M_product(p, X, xs, t0, t1, out, st);
+    else apply_M_clenshaw(p, X, xs, t0, t1, out, st);
 }
 
+static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st);
+
 static void enqueue(const Plan &p, const ecnt_csr *A, const double *taus, const void *probes,
-                    hipStream_t st)
+                    ecnt_info *info, hipStream_t st)
 {
     InitArgs ia;
     memset(&ia, 0, sizeof ia);
     for (int s = 0; s < p.S; ++s) ia.taus[s] = taus[s];
     ia.S = p.S;
     k_init<<<1, 64, 0, st>>>(ia, p.taus, p.flags);
-    const double blk_b = block_bytes(p);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
     if (p.prec_kind == ECNT_PREC_JACOBI) {
         Timed t(F_SETUP, csr_b + 8.0 * p.S * p.n, st);
         launch_jacobi_diag(p, A->row_ptr, A->col_idx, A->val, st);
     }
+    for (int c_off = 0; c_off < p.Ct; c_off += p.wave_cols) {
+        Plan w = p;
+        w.c_off = c_off;
+        w.C = (p.Ct - c_off) < p.wave_cols ? (p.Ct - c_off) : p.wave_cols;
+        geometry(w);
+        w.s_out = p.s_out + c_off;
+        w.minabs = p.minabs + c_off;
+        w.kused = p.kused + c_off;
+        enqueue_wave(w, A, probes, st);
+        if (info && info->alpha)
+            (void)hipMemcpy2DAsync(info->alpha + c_off, sizeof(double) * p.Ct, w.alpha,
+                                   sizeof(double) * w.C, sizeof(double) * w.C, p.k,
+                                   hipMemcpyDeviceToDevice, st);
+        if (info && info->beta)
+            (void)hipMemcpy2DAsync(info->beta + c_off, sizeof(double) * p.Ct, w.beta,
+                                   sizeof(double) * w.C, sizeof(double) * w.C, p.k + 1,
+                                   hipMemcpyDeviceToDevice, st);
+    }
+    Timed t(F_QUAD, 0.0, st);
+    launch_reduce(p, st);
+}
+
+// One wave of columns: Algorithm 1 on every column, then the quadrature.
+static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st)
+{
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
     {
-        Timed t(F_SETUP, blk_b + (double)p.n * p.m * (p.vec_f32 ? 4 : 8), st);
+        Timed t(F_SETUP, blk_b + (double)p.n * p.C * (p.vec_f32 ? 4 : 8) / p.S, st);
         launch_setup(p, probes, st);
     }
     {
@@ -339,7 +517,6 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const double *taus, const 
     }
     Timed t(F_QUAD, 0.0, st);
     launch_tridiag(p, st);
-    launch_reduce(p, st);
 }
 
 static ecnt_status check_common(const ecnt_csr *A, const void *probes, const ecnt_opts *o,
@@ -366,15 +543,11 @@ static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_
     if (e == hipSuccess)
         e = hipMemcpyAsync(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && info) {
-        const size_t C = p.C;
+        const size_t C = p.Ct;
         if (info->per_probe)
             e = hipMemcpyAsync(info->per_probe, p.s_out, sizeof(double) * C, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess && info->k_used)
             e = hipMemcpyAsync(info->k_used, p.kused, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess && info->alpha)
-            e = hipMemcpyAsync(info->alpha, p.alpha, sizeof(double) * C * p.k, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess && info->beta)
-            e = hipMemcpyAsync(info->beta, p.beta, sizeof(double) * C * (p.k + 1), hipMemcpyDeviceToDevice, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
@@ -403,7 +576,7 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
         std::lock_guard<std::mutex> g(g_prof_mu);
         t_prof = g_prof_on;
     }
-    enqueue(p, A, taus, probes, st);
+    enqueue(p, A, taus, probes, info, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return finish(p, st, res_host, info);

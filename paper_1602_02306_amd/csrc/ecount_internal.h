@@ -22,7 +22,11 @@ constexpr int kMaxK = 512;
 
 struct Plan {
     int64_t n = 0;
-    int m = 0, S = 0, C = 0, k = 0;
+    int m = 0, S = 0, k = 0;
+    int Ct = 0;           // all Lanczos columns, m * S
+    int C = 0;            // columns of the current wave (block vector width)
+    int wave_cols = 0;    // columns per wave (== Ct unless bounded by opts.max_cols)
+    int c_off = 0;        // global index of the wave's first column
     int vec_f32 = 0;      // 0: FP64 vectors, 1: FP32 vectors
     int val_f32 = 0;      // A values FP32
     int prec_kind = 0;
@@ -32,8 +36,16 @@ struct Plan {
     double s = 0, lo = 0, hi = 0;
     int rule = 0;
     double smooth_w = 0;
-    // reduction geometry
-    int nct = 0;          // column tiles of 64
+    // M = lead * prod_f factor_f(B): linear (B - a) or quadratic (B^2 - 2aB + b),
+    // from the roots of the Chebyshev series (used when they reproduce it).
+    int product = 0;
+    int nfac = 0;
+    int fac_quad[16] = {0};
+    double fac_a[16] = {0}, fac_b[16] = {0};
+    double lead = 1.0;
+    // geometry
+    int vw = 1;           // columns per lane in the row-sweep kernels
+    int nct = 0;          // column tiles of 64 (setup kernel)
     int nchunk = 0;       // row chunks of the two-phase column reductions
     int64_t rpc = 0;      // rows per chunk
     // workspace carve (device pointers)
@@ -48,12 +60,12 @@ struct Plan {
     double *runmax = nullptr;  // C
     double *nu = nullptr;      // C
     double *taus = nullptr;    // S
-    double *s_out = nullptr;   // C   per-column quadrature s_c
-    double *minabs = nullptr;  // C
+    double *s_out = nullptr;   // Ct  per-column quadrature s_c (wave views are offset)
+    double *minabs = nullptr;  // Ct
     double *jac = nullptr;     // S * n (Jacobi scaling)
     double *result = nullptr;  // 4*S + 8 small results
     int32_t *active = nullptr; // C
-    int32_t *kused = nullptr;  // C
+    int32_t *kused = nullptr;  // Ct
     int32_t *flags = nullptr;  // 4 status flags
     size_t bytes = 0;
 };
@@ -69,9 +81,9 @@ void launch_setup_fin(const Plan &p, hipStream_t st);
 void launch_csr_op(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
                    const void *x, const double *xscale, const double *pre_post, void *y,
                    hipStream_t st);
-// out = cx*xs*X + cb*B(ins*IN) - cz*Z  (one Chebyshev/Clenshaw sweep on the grid Laplacian)
-void launch_cheb_sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
-                       bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st);
+// out = cx*xs*X + cb*B(ins*IN) - cz*Z  (one stencil sweep on the grid Laplacian)
+void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                    bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st);
 void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st);
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st);
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st);

@@ -24,9 +24,9 @@ namespace ecnt {
 
 // ---- probe setup: slot 0 = v (for every shift), partial |v|^2 ----
 template <typename T>
-__global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int nct, int64_t rpc,
-                                               const T *__restrict__ V, T *__restrict__ slot0,
-                                               double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int c_off, int nct,
+                                               int64_t rpc, const T *__restrict__ V,
+                                               T *__restrict__ slot0, double *__restrict__ part)
 {
     __shared__ double red[4][kColTile];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int nct,
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
     double acc = 0.0;
     if (c < C) {
-        const int j = c % m;
+        const int j = (c_off + c) % m;
         for (int64_t r = r0 + wv; r < r1; r += 4) {
             const T v = V[(size_t)r * m + j];
             slot0[(size_t)r * C + c] = v;
@@ -73,47 +73,52 @@ __global__ void k_setup_fin(int C, int k, int nchunk, const double *__restrict__
 }
 
 // ---- reorthogonalization dots: part[chunk][l][c] = sum_rows slot_{l0+l} * w ----
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_dots(int64_t n, int C, int nct, int64_t rpc,
-                                              const T *__restrict__ basis, size_t ss, int slot_y,
-                                              int l0, int nb, int slot_m,
-                                              const double *__restrict__ kappa,
-                                              double *__restrict__ part)
+// One wavefront per (row chunk, column tile); NB is the exact number of basis
+// vectors of the launch, so all NB + 2 row loads are issued back to back.
+template <typename T, int NB, int VW>
+__global__ __launch_bounds__(64) void k_dots(int64_t n, int C, int nct, int64_t rpc,
+                                             const T *__restrict__ basis, size_t ss, int slot_y,
+                                             int l0, int slot_m, const double *__restrict__ kappa,
+                                             double *__restrict__ part)
 {
-    __shared__ double red[4][NB][kColTile];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = (int)(L % nct);
     const int64_t chunk = L / nct;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int c = ct * kColTile + lane;
+    const int c0 = (ct * 64 + (int)threadIdx.x) * VW;
+    if (c0 >= C) return;
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
-    double acc[NB];
+    double acc[NB][VW];
 #pragma unroll
-    for (int l = 0; l < NB; ++l) acc[l] = 0.0;
-    if (c < C) {
-        const double kap = slot_m >= 0 ? kappa[c] : 0.0;
-        const T *Y = basis + (size_t)slot_y * ss;
-        const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
-        const T *Q0 = basis + (size_t)l0 * ss;
-        for (int64_t r = r0 + wv; r < r1; r += 4) {
-            const size_t e = (size_t)r * C + c;
-            double w = ld(Y, e);
-            if (slot_m >= 0) w -= kap * ld(Qm, e);
+    for (int l = 0; l < NB; ++l)
 #pragma unroll
-            for (int l = 0; l < NB; ++l)
-                if (l < nb) acc[l] += ld(Q0 + (size_t)l * ss, e) * w;
+        for (int v = 0; v < VW; ++v) acc[l][v] = 0.0;
+    double kap[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) kap[v] = slot_m >= 0 ? kappa[c0 + v] : 0.0;
+    const T *Y = basis + (size_t)slot_y * ss;
+    const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
+    const T *Q0 = basis + (size_t)l0 * ss;
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c0;
+        double y[VW], qm[VW], q[NB][VW];
+        vload<T, VW>(Y, e, y);
+        vload<T, VW>(Qm, e, qm);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) vload<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        // keep all NB + 2 loads of the row in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            const double w = y[v] - kap[v] * qm[v];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) acc[l][v] += q[l][v] * w;
         }
     }
 #pragma unroll
-    for (int l = 0; l < NB; ++l) red[wv][l][lane] = acc[l];
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nb * kColTile; idx += 256) {
-        const int l = idx / kColTile, ln = idx % kColTile;
-        const int cc = ct * kColTile + ln;
-        if (cc < C)
-            part[((size_t)chunk * kBasisChunk + l) * C + cc] =
-                red[0][l][ln] + red[1][l][ln] + red[2][l][ln] + red[3][l][ln];
-    }
+    for (int l = 0; l < NB; ++l)
+#pragma unroll
+        for (int v = 0; v < VW; ++v)
+            part[((size_t)chunk * kBasisChunk + l) * C + c0 + v] = acc[l][v];
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
@@ -134,50 +139,55 @@ __global__ void k_dots_fin(int C, int nchunk, int step, int l0, int nb,
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
-// slot_w; the last chunk also writes partial |w|^2 into part[chunk][0][c].
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_update(int64_t n, int C, int nct, int64_t rpc,
-                                                T *__restrict__ basis, size_t ss, int slot_w,
-                                                int l0, int nb, int slot_m,
-                                                const double *__restrict__ kappa,
-                                                const double *__restrict__ cf, int last,
-                                                double *__restrict__ part)
+// slot_w; the last chunk also writes partial |w|^2 into part[chunk][0][c]
+// (of the value as stored, i.e. after rounding to T).
+template <typename T, int NB, int VW>
+__global__ __launch_bounds__(64) void k_update(int64_t n, int C, int nct, int64_t rpc,
+                                               T *__restrict__ basis, size_t ss, int slot_w, int l0,
+                                               int slot_m, const double *__restrict__ kappa,
+                                               const double *__restrict__ cf, int last,
+                                               double *__restrict__ part)
 {
-    __shared__ double red[4][kColTile];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = (int)(L % nct);
     const int64_t chunk = L / nct;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int c = ct * kColTile + lane;
+    const int c0 = (ct * 64 + (int)threadIdx.x) * VW;
+    if (c0 >= C) return;
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
-    double nrm = 0.0;
-    if (c < C) {
-        const double kap = slot_m >= 0 ? kappa[c] : 0.0;
-        double co[NB];
+    double co[NB][VW], kap[VW], nrm[VW];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) co[l] = l < nb ? cf[(size_t)(l0 + l) * C + c] : 0.0;
-        T *W = basis + (size_t)slot_w * ss;
-        const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
-        const T *Q0 = basis + (size_t)l0 * ss;
-        for (int64_t r = r0 + wv; r < r1; r += 4) {
-            const size_t e = (size_t)r * C + c;
-            double w = ld(W, e);
-            if (slot_m >= 0) w -= kap * ld(Qm, e);
+    for (int v = 0; v < VW; ++v) {
+        kap[v] = slot_m >= 0 ? kappa[c0 + v] : 0.0;
+        nrm[v] = 0.0;
 #pragma unroll
-            for (int l = 0; l < NB; ++l)
-                if (l < nb) w -= co[l] * ld(Q0 + (size_t)l * ss, e);
-            const T wt = static_cast<T>(w);
-            W[e] = wt;
-            const double wd = static_cast<double>(wt);
-            nrm += wd * wd;
-        }
+        for (int l = 0; l < NB; ++l) co[l][v] = cf[(size_t)(l0 + l) * C + c0 + v];
     }
-    if (!last) return;
-    red[wv][lane] = nrm;
-    __syncthreads();
-    if (wv == 0 && c < C)
-        part[(size_t)chunk * kBasisChunk * C + c] =
-            red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    T *W = basis + (size_t)slot_w * ss;
+    const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
+    const T *Q0 = basis + (size_t)l0 * ss;
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c0;
+        double w[VW], qm[VW], q[NB][VW];
+        vload<T, VW>(W, e, w);
+        vload<T, VW>(Qm, e, qm);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) vload<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            double x = w[v] - kap[v] * qm[v];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) x -= co[l][v] * q[l][v];
+            w[v] = x;
+            const double xr = rounded<T>(x);
+            nrm[v] += xr * xr;
+        }
+        vstore<T, VW>(W, e, w);
+    }
+    if (last) {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) part[(size_t)chunk * kBasisChunk * C + c0 + v] = nrm[v];
+    }
 }
 
 // beta_{i+1} = |w|, breakdown test, next scales.
@@ -222,10 +232,10 @@ static inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C; }
 void launch_setup(const Plan &p, const void *probes, hipStream_t st)
 {
     if (p.vec_f32)
-        k_setup<float><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.nct, p.rpc,
+        k_setup<float><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.c_off, p.nct, p.rpc,
                                                     (const float *)probes, (float *)p.basis, p.part);
     else
-        k_setup<double><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.nct, p.rpc,
+        k_setup<double><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.c_off, p.nct, p.rpc,
                                                      (const double *)probes, (double *)p.basis,
                                                      p.part);
 }
@@ -236,27 +246,73 @@ void launch_setup_fin(const Plan &p, hipStream_t st)
                                                    p.kappa, p.runmax, p.beta, p.active, p.kused);
 }
 
-template <typename T, int NB>
-static void dots_t(const Plan &p, int step, int l0, int nb, hipStream_t st)
+template <typename T, int NB, int VW>
+static void dots_t(const Plan &p, int step, int l0, hipStream_t st)
 {
-    k_dots<T, NB><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.nct, p.rpc, (const T *)p.basis,
-                                               slot_elems(p), step, l0, nb, step >= 2 ? step - 2 : -1,
-                                               p.kappa, p.part);
+    const int nct = (p.C + 64 * VW - 1) / (64 * VW);
+    k_dots<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
+        p.n, p.C, nct, p.rpc, (const T *)p.basis, slot_elems(p), step, l0,
+        step >= 2 ? step - 2 : -1, p.kappa, p.part);
 }
 
-template <typename T>
-static void dots_dispatch(const Plan &p, int step, int l0, int nb, hipStream_t st)
+template <typename T, int NB, int VW>
+static void update_t(const Plan &p, int step, int l0, bool first, bool last, hipStream_t st)
 {
-    if (nb <= 4) dots_t<T, 4>(p, step, l0, nb, st);
-    else if (nb <= 8) dots_t<T, 8>(p, step, l0, nb, st);
-    else if (nb <= 16) dots_t<T, 16>(p, step, l0, nb, st);
-    else dots_t<T, 32>(p, step, l0, nb, st);
+    const int nct = (p.C + 64 * VW - 1) / (64 * VW);
+    k_update<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
+        p.n, p.C, nct, p.rpc, (T *)p.basis, slot_elems(p), step, l0,
+        (first && step >= 2) ? step - 2 : -1, p.kappa, p.cf, last ? 1 : 0, p.part);
 }
+
+// exact-NB dispatch (1..kBasisChunk)
+#define ECNT_NB_CASES(F)                                                                        \
+    F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)   \
+    F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30)     \
+    F(31) F(32)
+
+template <typename T, int VW>
+static void dots_nb(const Plan &p, int step, int l0, int nb, hipStream_t st)
+{
+    switch (nb) {
+#define ECNT_CASE(N) \
+    case N:          \
+        dots_t<T, N, VW>(p, step, l0, st); \
+        break;
+        ECNT_NB_CASES(ECNT_CASE)
+#undef ECNT_CASE
+    default:
+        break;
+    }
+}
+
+template <typename T, int VW>
+static void update_nb(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
+{
+    switch (nb) {
+#define ECNT_CASE(N) \
+    case N:          \
+        update_t<T, N, VW>(p, step, l0, first, last, st); \
+        break;
+        ECNT_NB_CASES(ECNT_CASE)
+#undef ECNT_CASE
+    default:
+        break;
+    }
+}
+
+// Columns per lane of the reduction kernels: FP32 pairs (8-byte loads) when the
+// wave width is even; FP64 one column per lane (the NB accumulators per column
+// already fill the register budget).  Must match the geometry of the plan.
+static inline int red_vw(const Plan &p) { return (p.vec_f32 && p.C % 2 == 0) ? 2 : 1; }
 
 void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
 {
-    if (p.vec_f32) dots_dispatch<float>(p, step, l0, nb, st);
-    else dots_dispatch<double>(p, step, l0, nb, st);
+    if (p.vec_f32) {
+        if (red_vw(p) == 2) dots_nb<float, 2>(p, step, l0, nb, st);
+        else dots_nb<float, 1>(p, step, l0, nb, st);
+    } else {
+        dots_nb<double, 1>(p, step, l0, nb, st);
+    }
 }
 
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
@@ -266,29 +322,14 @@ void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
                                                   p.active, p.cf, p.alpha);
 }
 
-template <typename T, int NB>
-static void update_t(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
-{
-    k_update<T, NB><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.nct, p.rpc, (T *)p.basis,
-                                                 slot_elems(p), step, l0, nb,
-                                                 (first && step >= 2) ? step - 2 : -1, p.kappa,
-                                                 p.cf, last ? 1 : 0, p.part);
-}
-
-template <typename T>
-static void update_dispatch(const Plan &p, int step, int l0, int nb, bool first, bool last,
-                            hipStream_t st)
-{
-    if (nb <= 4) update_t<T, 4>(p, step, l0, nb, first, last, st);
-    else if (nb <= 8) update_t<T, 8>(p, step, l0, nb, first, last, st);
-    else if (nb <= 16) update_t<T, 16>(p, step, l0, nb, first, last, st);
-    else update_t<T, 32>(p, step, l0, nb, first, last, st);
-}
-
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
 {
-    if (p.vec_f32) update_dispatch<float>(p, step, l0, nb, first, last, st);
-    else update_dispatch<double>(p, step, l0, nb, first, last, st);
+    if (p.vec_f32) {
+        if (red_vw(p) == 2) update_nb<float, 2>(p, step, l0, nb, first, last, st);
+        else update_nb<float, 1>(p, step, l0, nb, first, last, st);
+    } else {
+        update_nb<double, 1>(p, step, l0, nb, first, last, st);
+    }
 }
 
 void launch_norm_fin(const Plan &p, int step, hipStream_t st)

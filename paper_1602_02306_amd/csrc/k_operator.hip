@@ -1,17 +1,16 @@
 // Operator kernels: w = M (A - tau_c I) M^* x on a probe block
 // (Algorithm 1, step "w <- M(A - tau I)M^* q_i"; Section 2, eq. negi_T).
 //
-// Every column c of the block carries its own shift tau_{c / m}.  Rows are
-// processed by wavefronts (one lane per column, 64 columns per wave), so the
-// CSR row structure and the grid coordinates of a row are wave-uniform
-// (scalar loads), and every vector access is a contiguous 64-column segment.
+// Every column c of the block carries its own shift tau_{c / m}.  Each lane
+// owns VW consecutive columns (one 8- or 16-byte vector access per row), a
+// wavefront covers 64*VW columns of one row, so all vector accesses are
+// contiguous row segments.  Boundary handling is branch-free (clamped
+// addresses with zero weights) so that every load of a row is in flight at
+// once.
 #include "device_common.h"
 #include "ecount_internal.h"
 
 namespace ecnt {
-
-constexpr int kRowsPerWave = 4;
-constexpr int kRowsPerBlock = 4 * kRowsPerWave;   // 4 waves per 256-thread block
 
 // |a_rr - tau_s|^(-1/2) for the Jacobi preconditioner, per shift.
 template <typename VT>
@@ -34,9 +33,11 @@ __global__ __launch_bounds__(256) void k_jacobi_diag(int64_t n, int S, const int
 }
 
 // y(r, c) = xs_c * d_s(r) * ( sum_p a_{r,j_p} d_s(j_p) x(j_p, c) - tau_s d_s(r) x(r, c) )
-// with d_s the Jacobi scaling of shift s (or 1 without preconditioner).
-template <typename T, typename VT, bool JAC>
-__global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int nct,
+// with d_s the Jacobi scaling of shift s = c / m (or 1 without preconditioner).
+// One wavefront per row; the row's nonzeros are taken four at a time with
+// clamped indices so that four row segments are loaded together.
+template <typename T, typename VT, bool JAC, int VW>
+__global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_off, int ncg,
                                                 const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
                                                 const VT *__restrict__ val, const T *__restrict__ x,
@@ -45,84 +46,211 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int nct
                                                 const double *__restrict__ taus, T *__restrict__ y)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const int ct = (int)(L % nct);
-    const int64_t rg = L / nct;
+    const int cg = (int)(L % ncg);
+    const int64_t r = (L / ncg) * 4 + uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int wv = uniform(threadIdx.x >> 6);
-    const int c = ct * kColTile + lane;
-    if (c >= C) return;
-    const int s = c / m;
-    const double tau = taus[s];
-    const double xsc = xs ? xs[c] : 1.0;
-    const double *js = JAC ? jac + (size_t)s * n : nullptr;
-    for (int t = 0; t < kRowsPerWave; ++t) {
-        const int64_t r = rg * kRowsPerBlock + wv * kRowsPerWave + t;
-        if (r >= n) break;
-        const int p0 = rp[r], p1 = rp[r + 1];
-        double acc = 0.0;
-        for (int p = p0; p < p1; ++p) {
-            const int64_t j = ci[p];
-            double xv = ld(x, (size_t)j * C + c);
-            if (JAC) xv *= js[j];
-            acc += static_cast<double>(val[p]) * xv;
-        }
-        double xr = ld(x, (size_t)r * C + c);
-        if (JAC) xr *= js[r];
-        double out = acc - tau * xr;
-        if (JAC) out *= js[r];
-        y[(size_t)r * C + c] = static_cast<T>(out * xsc);
+    const int c0 = (cg * 64 + lane) * VW;
+    if (r >= n || c0 >= C) return;
+    double tau[VW], xsc[VW];
+    const double *js[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+        const int s = (c_off + c0 + v) / m;
+        tau[v] = taus[s];
+        xsc[v] = xs ? xs[c0 + v] : 1.0;
+        js[v] = JAC ? jac + (size_t)s * n : nullptr;
     }
+    const int p0 = rp[r], p1 = rp[r + 1];
+    double acc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = 0.0;
+    for (int p = p0; p < p1; p += 4) {
+        int j[4];
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int pp = min(p + q, p1 - 1);
+            j[q] = ci[pp];
+            a[q] = (p + q < p1) ? static_cast<double>(val[pp]) : 0.0;
+        }
+        double xv[4][VW];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vload<T, VW>(x, (size_t)j[q] * C + c0, xv[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                double xq = xv[q][v];
+                if (JAC) xq *= js[v][j[q]];
+                acc[v] += a[q] * xq;
+            }
+    }
+    double xr[VW], out[VW];
+    vload<T, VW>(x, (size_t)r * C + c0, xr);
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+        double xv = xr[v];
+        if (JAC) xv *= js[v][r];
+        double o = acc[v] - tau[v] * xv;
+        if (JAC) o *= js[v][r];
+        out[v] = o * xsc[v];
+    }
+    vstore<T, VW>(y, (size_t)r * C + c0, out);
 }
 
-// One Clenshaw sweep for M = sum_j c_j T_j(B), B = (2(L + sI) - (lo+hi)I)/(hi-lo):
-//   out = cx*xs_c*X + cb*B(u) - cz*Z,   u = (in_is_x ? xs_c : 1) * IN
-// with B u (r) = bd*u(r) - bo*sum_{grid neighbours} u.
-template <typename T>
-__global__ __launch_bounds__(256) void k_cheb_sweep(int64_t n, int C, int nct, int d0, int d1, int d2,
-                                                    const T *__restrict__ X,
-                                                    const double *__restrict__ xs, double cx,
-                                                    const T *__restrict__ IN, int in_is_x,
-                                                    double cbd, double cbo,
-                                                    const T *__restrict__ Z, double cz,
-                                                    T *__restrict__ out)
+// One stencil sweep on the grid Laplacian L (diagonal 2*ndim, neighbours -1):
+//   out = cx*xs_c*X + B(u) - cz*Z,   B u(r) = cbd*u(r) - cbo*sum_{grid neighbours} u,
+//   u = (in_is_x ? xs_c : 1) * IN
+// (cbd, cbo carry the scaling of B = (2(L + sI) - (lo+hi)I)/(hi-lo) and any
+// factor applied to it).
+//
+// Register tiling: one wavefront owns a TX x TY block of z-lines (grid
+// points (x, y, 0..d2-1)) for 64*VW columns and walks z, keeping the z-1, z
+// and z+1 values of all its lines in registers.  The lateral neighbours
+// inside the block come from registers as well; only the block's boundary
+// lines and the next z value of each line are loaded: (TX*TY + 2*TX + 2*TY)
+// row loads per TX*TY outputs instead of 5 per output.  Lines outside the
+// grid (ragged blocks, Dirichlet boundary) are loaded from a clamped address
+// with weight 0, so every load of a z step is issued together.
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
+__global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int d0, int d1, int d2, int nty,
+                                                 int ntiles, const T *__restrict__ X,
+                                                 const double *__restrict__ xs, double cx,
+                                                 const T *__restrict__ IN, int in_is_x, double cbd,
+                                                 double cbo, const T *__restrict__ Z, double cz,
+                                                 T *__restrict__ out)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const int ct = (int)(L % nct);
-    const int64_t rg = L / nct;
+    const int64_t gw = L * 4 + uniform(threadIdx.x >> 6);
+    const int cg = (int)(gw % ncg);
+    const int tile = (int)(gw / ncg);
     const int lane = threadIdx.x & 63;
-    const int wv = uniform(threadIdx.x >> 6);
-    const int c = ct * kColTile + lane;
-    if (c >= C) return;
-    const double xsc = xs ? xs[c] : 1.0;
-    const double isc = in_is_x ? xsc : 1.0;
-    const int64_t s1 = d2, s0 = (int64_t)d1 * d2;
-    for (int t = 0; t < kRowsPerWave; ++t) {
-        const int64_t r = rg * kRowsPerBlock + wv * kRowsPerWave + t;
-        if (r >= n) break;
-        const int64_t i2 = r % d2, q = r / d2;
-        const int64_t i1 = q % d1, i0 = q / d1;
-        const size_t e = (size_t)r * C + c;
-        double acc = 0.0;
-        double val = cx * xsc * ld(X, e);
-        if (IN) {
-            double nb = 0.0;
-            if (i2 > 0) nb += ld(IN, e - C);
-            if (i2 + 1 < d2) nb += ld(IN, e + C);
-            if (i1 > 0) nb += ld(IN, e - s1 * C);
-            if (i1 + 1 < d1) nb += ld(IN, e + s1 * C);
-            if (i0 > 0) nb += ld(IN, e - s0 * C);
-            if (i0 + 1 < d0) nb += ld(IN, e + s0 * C);
-            acc = isc * (cbd * ld(IN, e) - cbo * nb);
+    const int c0 = (cg * 64 + lane) * VW;
+    if (tile >= ntiles || c0 >= C) return;
+    const int x0 = (tile / nty) * TX, y0 = (tile % nty) * TY;
+    const size_t zs = (size_t)C;                       // element stride of z
+    const size_t ys = (size_t)d2 * C;                  // of y
+    const size_t xs_ = (size_t)d1 * d2 * C;            // of x
+    const size_t base = (size_t)x0 * xs_ + (size_t)y0 * ys + c0;
+    // tile lines and boundary lines: offset from `base` (clamped) and weight
+    size_t off[TX][TY];
+    double wt[TX][TY];
+    size_t offym[TX], offyp[TX], offxm[TY], offxp[TY];
+    double wym[TX], wyp[TX], wxm[TY], wxp[TY];
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+            const bool ok = x0 + a < d0 && y0 + b < d1;
+            off[a][b] = ok ? (size_t)a * xs_ + (size_t)b * ys : 0;
+            wt[a][b] = ok ? 1.0 : 0.0;
         }
-        val += acc;
-        if (Z) val -= cz * ld(Z, e);
-        out[e] = static_cast<T>(val);
+#pragma unroll
+    for (int a = 0; a < TX; ++a) {
+        const bool okx = x0 + a < d0;
+        const bool okm = okx && y0 > 0, okp = okx && y0 + TY < d1;
+        offym[a] = okm ? (size_t)a * xs_ - ys : 0;
+        offyp[a] = okp ? (size_t)a * xs_ + (size_t)TY * ys : 0;
+        wym[a] = okm ? 1.0 : 0.0;
+        wyp[a] = okp ? 1.0 : 0.0;
     }
-}
-
-static inline int64_t row_blocks(const Plan &p)
-{
-    return (p.n + kRowsPerBlock - 1) / kRowsPerBlock * p.nct;
+#pragma unroll
+    for (int b = 0; b < TY; ++b) {
+        const bool oky = y0 + b < d1;
+        const bool okm = oky && x0 > 0, okp = oky && x0 + TX < d0;
+        offxm[b] = okm ? (size_t)b * ys - xs_ : 0;
+        offxp[b] = okp ? (size_t)b * ys + (size_t)TX * xs_ : 0;
+        wxm[b] = okm ? 1.0 : 0.0;
+        wxp[b] = okp ? 1.0 : 0.0;
+    }
+    double xsc[VW], isc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+        xsc[v] = xs ? xs[c0 + v] : 1.0;
+        isc[v] = in_is_x ? xsc[v] : 1.0;
+    }
+    double prev[TX][TY][VW], cur[TX][TY][VW];
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+            double t[VW];
+            if (HASIN) vload<T, VW>(IN, base + off[a][b], t);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                prev[a][b][v] = 0.0;
+                cur[a][b][v] = HASIN ? wt[a][b] * t[v] : 0.0;
+            }
+        }
+    size_t ez = base;
+    for (int z = 0; z < d2; ++z, ez += zs) {
+        const bool hasn = z + 1 < d2;
+        const size_t en = hasn ? ez + zs : ez;
+        double nxt[TX][TY][VW], ym[TX][VW], yp[TX][VW], xm[TY][VW], xp[TY][VW];
+        double xv[TX][TY][VW], zv[TX][TY][VW];
+        if (HASIN) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TY; ++b) vload<T, VW>(IN, en + off[a][b], nxt[a][b]);
+#pragma unroll
+            for (int a = 0; a < TX; ++a) {
+                vload<T, VW>(IN, ez + offym[a], ym[a]);
+                vload<T, VW>(IN, ez + offyp[a], yp[a]);
+            }
+#pragma unroll
+            for (int b = 0; b < TY; ++b) {
+                vload<T, VW>(IN, ez + offxm[b], xm[b]);
+                vload<T, VW>(IN, ez + offxp[b], xp[b]);
+            }
+        }
+        if (XSEP) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TY; ++b) vload<T, VW>(X, ez + off[a][b], xv[a][b]);
+        }
+        if (HASZ) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TY; ++b) vload<T, VW>(Z, ez + off[a][b], zv[a][b]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const double zn = hasn ? 1.0 : 0.0;
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TY; ++b) {
+                double o[VW];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    double val = cx * xsc[v] * (XSEP ? xv[a][b][v] : cur[a][b][v]);
+                    if (HASIN) {
+                        const double nym = b > 0 ? cur[a][b - 1][v] : wym[a] * ym[a][v];
+                        const double nyp = b + 1 < TY ? cur[a][b + 1][v] : wyp[a] * yp[a][v];
+                        const double nxm = a > 0 ? cur[a - 1][b][v] : wxm[b] * xm[b][v];
+                        const double nxp = a + 1 < TX ? cur[a + 1][b][v] : wxp[b] * xp[b][v];
+                        const double nb = prev[a][b][v] + zn * nxt[a][b][v] + nym + nyp + nxm + nxp;
+                        val += isc[v] * (cbd * cur[a][b][v] - cbo * nb);
+                    }
+                    if (HASZ) val -= cz * zv[a][b][v];
+                    o[v] = val;
+                }
+                if (wt[a][b] != 0.0) vstore<T, VW>(out, ez + off[a][b], o);
+            }
+        if (HASIN) {
+#pragma unroll
+            for (int a = 0; a < TX; ++a)
+#pragma unroll
+                for (int b = 0; b < TY; ++b)
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) {
+                        prev[a][b][v] = cur[a][b][v];
+                        cur[a][b][v] = wt[a][b] * nxt[a][b][v];
+                    }
+        }
+    }
 }
 
 void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
@@ -137,49 +265,102 @@ void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *co
                                                     p.taus, p.jac, p.flags);
 }
 
-template <typename T, typename VT>
+template <typename T, typename VT, int VW>
 static void csr_op_t(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
                      const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
 {
-    dim3 grid((unsigned)row_blocks(p));
+    const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
+    dim3 grid((unsigned)(((p.n + 3) / 4) * ncg));
     if (jac)
-        k_csr_op<T, VT, true><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.nct, rp, ci, (const VT *)val,
-                                                    (const T *)x, xs, jac, p.taus, (T *)y);
+        k_csr_op<T, VT, true, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, rp, ci, (const VT *)val,
+                                                        (const T *)x, xs, jac, p.taus, (T *)y);
     else
-        k_csr_op<T, VT, false><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.nct, rp, ci, (const VT *)val,
-                                                     (const T *)x, xs, nullptr, p.taus, (T *)y);
+        k_csr_op<T, VT, false, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, rp, ci, (const VT *)val,
+                                                         (const T *)x, xs, nullptr, p.taus, (T *)y);
+}
+
+template <typename T, typename VT>
+static void csr_op_vw(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
+                      const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (p.vw == 4) {
+            csr_op_t<T, VT, 4>(p, rp, ci, val, x, xs, jac, y, st);
+            return;
+        }
+    }
+    if (p.vw == 2) csr_op_t<T, VT, 2>(p, rp, ci, val, x, xs, jac, y, st);
+    else csr_op_t<T, VT, 1>(p, rp, ci, val, x, xs, jac, y, st);
 }
 
 void launch_csr_op(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
                    const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
 {
     if (p.vec_f32) {
-        if (p.val_f32) csr_op_t<float, float>(p, rp, ci, val, x, xs, jac, y, st);
-        else csr_op_t<float, double>(p, rp, ci, val, x, xs, jac, y, st);
+        if (p.val_f32) csr_op_vw<float, float>(p, rp, ci, val, x, xs, jac, y, st);
+        else csr_op_vw<float, double>(p, rp, ci, val, x, xs, jac, y, st);
     } else {
-        if (p.val_f32) csr_op_t<double, float>(p, rp, ci, val, x, xs, jac, y, st);
-        else csr_op_t<double, double>(p, rp, ci, val, x, xs, jac, y, st);
+        if (p.val_f32) csr_op_vw<double, float>(p, rp, ci, val, x, xs, jac, y, st);
+        else csr_op_vw<double, double>(p, rp, ci, val, x, xs, jac, y, st);
     }
 }
 
-void launch_cheb_sweep(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
-                       bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st)
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
+static void stencil_t(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                      bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
+                      hipStream_t st)
 {
-    // B u = ((2*(2*ndim + s) - (lo + hi)) u - 2 * sum_nb u) / (hi - lo)
+    const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
+    const int ntx = (p.dims[0] + TX - 1) / TX, nty = (p.dims[1] + TY - 1) / TY;
+    const int ntiles = ntx * nty;
+    const int64_t waves = (int64_t)ntiles * ncg;
+    dim3 grid((unsigned)((waves + 3) / 4));
+    k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ><<<grid, 256, 0, st>>>(
+        p.C, ncg, p.dims[0], p.dims[1], p.dims[2], nty, ntiles, (const T *)X, xs, cx,
+        (const T *)IN, in_is_x ? 1 : 0, cbd, cbo, (const T *)Z, cz, (T *)out);
+}
+
+template <typename T, int VW, int TX, int TY>
+static void stencil_flags(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                          bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
+                          hipStream_t st)
+{
+    if (!IN) {
+        stencil_t<T, VW, TX, TY, false, true, false>(p, X, xs, cx, IN, false, 0, 0, nullptr, 0, out, st);
+    } else if (IN == X && !Z) {
+        stencil_t<T, VW, TX, TY, true, false, false>(p, X, xs, cx, IN, in_is_x, cbd, cbo, nullptr, 0, out, st);
+    } else if (!Z) {
+        stencil_t<T, VW, TX, TY, true, true, false>(p, X, xs, cx, IN, in_is_x, cbd, cbo, nullptr, 0, out, st);
+    } else {
+        stencil_t<T, VW, TX, TY, true, true, true>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
+    }
+}
+
+// line-block shape: 4 x 4 lines on 3D grids, 1 x 8 when the grid has a single x plane
+template <typename T, int VW>
+static void stencil_shape(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                          bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
+                          hipStream_t st)
+{
+    if (p.dims[0] >= 4) stencil_flags<T, VW, 4, 4>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
+    else stencil_flags<T, VW, 1, 8>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
+}
+
+void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
+                    bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st)
+{
+    // B u = ((2*(2*ndim + s) - (lo + hi)) u - 2 * sum_nb u) / (hi - lo), scaled by cb
     const double w = p.hi - p.lo;
-    const double bd = (2.0 * (2.0 * p.ndim + p.s) - (p.lo + p.hi)) / w;
-    const double bo = 2.0 / w;
-    dim3 grid((unsigned)row_blocks(p));
-    if (p.vec_f32)
-        k_cheb_sweep<float><<<grid, 256, 0, st>>>(p.n, p.C, p.nct, p.dims[0], p.dims[1], p.dims[2],
-                                                  (const float *)X, xs, cx, (const float *)IN,
-                                                  in_is_x ? 1 : 0, cb * bd, cb * bo,
-                                                  (const float *)Z, cz, (float *)out);
+    const double bd = cb * (2.0 * (2.0 * p.ndim + p.s) - (p.lo + p.hi)) / w;
+    const double bo = cb * 2.0 / w;
+    // one column per lane (FP64) / two (FP32, when the width is even): the
+    // register tile holds 3 z-values of TX*TY lines per column
+    if (p.vec_f32 && p.C % 2 == 0)
+        stencil_shape<float, 2>(p, X, xs, cx, IN, in_is_x, bd, bo, Z, cz, out, st);
+    else if (p.vec_f32)
+        stencil_shape<float, 1>(p, X, xs, cx, IN, in_is_x, bd, bo, Z, cz, out, st);
     else
-        k_cheb_sweep<double><<<grid, 256, 0, st>>>(p.n, p.C, p.nct, p.dims[0], p.dims[1], p.dims[2],
-                                                   (const double *)X, xs, cx, (const double *)IN,
-                                                   in_is_x ? 1 : 0, cb * bd, cb * bo,
-                                                   (const double *)Z, cz, (double *)out);
+        stencil_shape<double, 1>(p, X, xs, cx, IN, in_is_x, bd, bo, Z, cz, out, st);
 }
 
 }  // namespace ecnt

@@ -40,13 +40,13 @@ class CsrT(ctypes.Structure):
 
 class PrecT(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int32 * 3),
-                ("degree", ctypes.c_int32), ("s", ctypes.c_double), ("lo", ctypes.c_double),
-                ("hi", ctypes.c_double), ("coef", ctypes.c_void_p)]
+                ("degree", ctypes.c_int32), ("eval", ctypes.c_int32), ("s", ctypes.c_double),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("coef", ctypes.c_void_p)]
 
 
 class OptsT(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("vec_type", ctypes.c_int32), ("rule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("smooth_w", ctypes.c_double)]
+                ("max_cols", ctypes.c_int32), ("smooth_w", ctypes.c_double)]
 
 
 class InfoT(ctypes.Structure):
@@ -135,7 +135,10 @@ def upload_csr(A, val_dtype: str = "f64", device: str = "cuda") -> DeviceCSR:
                      torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device, tdt))
 
 
-def prec_struct(prec):
+EVALS = {"auto": 0, "clenshaw": 1}
+
+
+def prec_struct(prec, eval: str = "auto"):
     """ecnt_prec from a workloads.PrecSpec; returns (struct, keep-alive coef array)."""
     kind = PREC_KINDS[prec.kind]
     dims = (ctypes.c_int32 * 3)(0, 0, 0)
@@ -146,19 +149,20 @@ def prec_struct(prec):
         for a, d in enumerate(prec.dims):
             dims[a] = int(d)
         coef = np.ascontiguousarray(prec.coef, dtype=np.float64)
-    st = PrecT(kind, ndim, dims, max(len(coef) - 1, 0) if kind == 2 else 0, float(prec.s),
-               float(prec.lo), float(prec.hi), coef.ctypes.data if kind == 2 else None)
+    st = PrecT(kind, ndim, dims, max(len(coef) - 1, 0) if kind == 2 else 0, EVALS[eval],
+               float(prec.s), float(prec.lo), float(prec.hi), coef.ctypes.data if kind == 2 else None)
     return st, coef
 
 
-def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0) -> OptsT:
-    return OptsT(int(k), DTYPES[vec], RULES[rule], 0, float(smooth_w))
+def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
+                max_cols: int = 0) -> OptsT:
+    return OptsT(int(k), DTYPES[vec], RULES[rule], int(max_cols), float(smooth_w))
 
 
 def workspace_bytes(n: int, m: int, nshift: int, prec, k: int, vec: str = "f64",
-                    rule: str = "gauss", smooth_w: float = 0.0) -> int:
+                    rule: str = "gauss", smooth_w: float = 0.0, max_cols: int = 0) -> int:
     ps, _coef = prec_struct(prec)
-    o = opts_struct(k, vec, rule, smooth_w)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols)
     return int(load().ecnt_workspace_bytes(int(n), int(m), int(nshift), ctypes.byref(ps),
                                            ctypes.byref(o)))
 
@@ -215,13 +219,13 @@ def _info(C: int, k: int, want: bool, device):
 
 def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
           rule: str = "gauss", smooth_w: float = 0.0, workspace: Workspace | None = None,
-          stream=None, details: bool = True) -> CountResult:
+          stream=None, details: bool = True, eval: str = "auto", max_cols: int = 0) -> CountResult:
     """Interval count on [xi, eta) (ecnt_count).  `probes`: torch device tensor
     n x m (float64 for vec='f64', float32 for vec='f32')."""
     lib = load()
     n, m = probes.shape
-    ps, _coef = prec_struct(prec)
-    o = opts_struct(k, vec, rule, smooth_w)
+    ps, _coef = prec_struct(prec, eval)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols)
     need = lib.ecnt_workspace_bytes(n, m, 2, ctypes.byref(ps), ctypes.byref(o))
     if need == 0:
         raise EcntError(ECNT_EINVAL, last_error())
@@ -253,14 +257,14 @@ class NegcountsResult:
 
 def negcounts(A: DeviceCSR, prec, taus, probes, k: int, vec: str = "f64", rule: str = "gauss",
               smooth_w: float = 0.0, workspace: Workspace | None = None, stream=None,
-              details: bool = True) -> NegcountsResult:
+              details: bool = True, eval: str = "auto", max_cols: int = 0) -> NegcountsResult:
     """Algorithm 2 at several shifts on one probe block (ecnt_negcounts)."""
     lib = load()
     n, m = probes.shape
     taus = np.ascontiguousarray(taus, dtype=np.float64)
     S = len(taus)
-    ps, _coef = prec_struct(prec)
-    o = opts_struct(k, vec, rule, smooth_w)
+    ps, _coef = prec_struct(prec, eval)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols)
     need = lib.ecnt_workspace_bytes(n, m, S, ctypes.byref(ps), ctypes.byref(o))
     if need == 0:
         raise EcntError(ECNT_EINVAL, last_error())

@@ -91,7 +91,7 @@ def _call_count(A=True, prec=None, xi=0.0, eta=1.0, probes=0x1000, m=4, k=3, ws=
     (dict(prec=W.PrecSpec("cheb", (4, 4, 4), 1.0, 1.0, 13.0, np.array([1.0, np.nan]))), ec.ECNT_EINVAL),
     (dict(opts=ec.OptsT(3, 7, 0, 0, 0.0)), ec.ECNT_EINVAL),
     (dict(opts=ec.OptsT(3, 0, 5, 0, 0.0)), ec.ECNT_EINVAL),
-    (dict(opts=ec.OptsT(3, 0, 0, 1, 0.0)), ec.ECNT_EINVAL),
+    (dict(opts=ec.OptsT(3, 0, 0, -1, 0.0)), ec.ECNT_EINVAL),
     (dict(opts=ec.OptsT(3, 0, 0, 0, -1.0)), ec.ECNT_EINVAL),
 ])
 def test_invalid_calls_rejected_on_host(kw, code):

@@ -93,7 +93,7 @@ def run_workload(ec, name, **over):
     k = over.pop("k", wl.k)
     rule = over.pop("rule", "gauss")
     sw = over.pop("smooth_w", wl.smooth_w)
-    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, k, rule=rule, smooth_w=sw)
+    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, k, rule=rule, smooth_w=sw, **over)
     ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, k, rule=rule, smooth_w=sw)
     return r, ref, k
 
@@ -233,3 +233,49 @@ def test_bench_configuration_sampled(ec):
     assert rel(r.estimate, d.mean()) <= 1e-12
     exact = json.load(open(os.path.join(GOLDEN, "exact_counts.json"))).get("c2", {}).get("count")
     print("c2 estimate %.4f +- %.4f exact %s" % (r.estimate, math.sqrt(r.variance), exact), flush=True)
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c2_ragged"])
+def test_parity_clenshaw_evaluation(ec, name):
+    """M evaluated by Clenshaw's recurrence instead of the product of its
+    quadratic factors: same polynomial, same parity bar."""
+    r, ref, k = run_workload(ec, name, eval="clenshaw")
+    assert_parity(r, ref, k)
+
+
+@pytest.mark.parametrize("max_cols", [30, 37, 1])
+def test_parity_column_waves(ec, max_cols):
+    """Columns run in waves of at most max_cols (ragged last wave; odd widths
+    take the one-column-per-lane kernels); results equal the oracle's."""
+    r, ref, k = run_workload(ec, "c2_ragged", max_cols=max_cols)
+    assert_parity(r, ref, k)
+
+
+def test_parity_column_waves_jacobi(ec):
+    r, ref, k = run_workload(ec, "c1", max_cols=48)
+    assert_parity(r, ref, k)
+
+
+# FP32 storage form: A values, probes, Lanczos vectors and basis in FP32;
+# alpha/beta, every dot product and norm and the tridiagonal eigensolve in
+# FP64.  Parity with the FP64 oracle is not expected to 1e-10; the stated
+# bound is 1e-4 * max(|estimate|, 1) on the estimate and 1e-4 * |v_j|^2 on each
+# per-probe value.
+FP32_BOUND = 1e-4
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c2_ragged", "c1"])
+def test_fp32_form_within_stated_bound(ec, name):
+    wl = W.WORKLOADS[name]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec="f32", val="f32")
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    s = r.per_probe.cpu().numpy()
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    e_est = rel(r.estimate, ref.estimate)
+    e_probe = float(np.max(np.abs(s - s_ref) / nu))
+    print("fp32 %s: est %.10f oracle %.10f rel %.2e  max|ds|/nu %.2e" % (name, r.estimate, ref.estimate, e_est, e_probe), flush=True)
+    assert e_est <= FP32_BOUND
+    assert e_probe <= FP32_BOUND
