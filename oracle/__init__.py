@@ -3,8 +3,12 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the GPU library or its binding.
 """
-from .oracle import (CountResult, LanczosResult, build, count, dense_operator, host_threads,
-                     jacobi_matrix, lanczos, negcount, probe_quadrature, quadrature, step)
+from .oracle import (CountResult, LanczosResult, build, count, count_tangent, dense_operator,
+                     divided_difference, host_threads, jacobi_matrix, lanczos, lanczos_tangent,
+                     negcount, probe_quadrature, probe_quadrature_tangent, quadrature, step,
+                     step_deriv)
 
-__all__ = ["CountResult", "LanczosResult", "build", "count", "dense_operator", "host_threads",
-           "jacobi_matrix", "lanczos", "negcount", "probe_quadrature", "quadrature", "step"]
+__all__ = ["CountResult", "LanczosResult", "build", "count", "count_tangent", "dense_operator",
+           "divided_difference", "host_threads", "jacobi_matrix", "lanczos", "lanczos_tangent",
+           "negcount", "probe_quadrature", "probe_quadrature_tangent", "quadrature", "step",
+           "step_deriv"]

@@ -327,6 +327,155 @@ int oracle_dense_operator(int64_t n, const int32_t *row_ptr, const int32_t *col_
     return 0;
 }
 
+/*
+ * Forward-mode tangent of Algorithm 1 (used to check gradients of the
+ * smoothed estimator).  The matrix depends on a direction (du, dtau) as
+ * A - tau I -> A + t diag(du) - (tau + t dtau) I, with M independent of both
+ * (no preconditioner or the Laplacian polynomial), so
+ *   dC x = M (du .* (M x) - dtau * (M x)).
+ * Every line of Algorithm 1 is differentiated in its literal order; the
+ * outputs are alpha, beta as in oracle_lanczos and their derivatives
+ * dalpha (m x k), dbeta (m x (k+1)).
+ */
+static int lanczos_tangent_one(const op_t *P, const double *du, double dtau, const double *v, int k,
+                               double *alpha, double *beta, double *dalpha, double *dbeta,
+                               double *nu_out, double *Q, double *dQ, double *w, double *dw,
+                               double *h, double *work)
+{
+    int64_t n = P->n;
+    double *t = work + 5 * n, *u = work + 6 * n, *y2 = work + 7 * n;
+    double nu = dot(n, v, v);
+    *nu_out = nu;
+    double inv = 1.0 / sqrt(nu);
+    for (int64_t r = 0; r < n; ++r) {
+        Q[r] = v[r] * inv;
+        dQ[r] = 0.0;
+    }
+    beta[0] = 0.0;
+    dbeta[0] = 0.0;
+    double scale = 0.0;
+    for (int i = 1; i <= k; ++i) {
+        const double *qi = Q + (size_t)(i - 1) * n, *dqi = dQ + (size_t)(i - 1) * n;
+        /* w = C q_i ;  dw = dC q_i + C dq_i */
+        apply_C(P, qi, w, work);
+        apply_C(P, dqi, dw, work);
+        apply_M(P, qi, t, work + 2 * n);
+        for (int64_t r = 0; r < n; ++r) u[r] = du[r] * t[r] - dtau * t[r];
+        apply_M(P, u, y2, work + 2 * n);
+        for (int64_t r = 0; r < n; ++r) dw[r] += y2[r];
+        if (i > 1) {
+            const double *qm = Q + (size_t)(i - 2) * n, *dqm = dQ + (size_t)(i - 2) * n;
+            for (int64_t r = 0; r < n; ++r) {
+                w[r] -= beta[i - 1] * qm[r];
+                dw[r] -= dbeta[i - 1] * qm[r] + beta[i - 1] * dqm[r];
+            }
+        }
+        double a = dot(n, qi, w);
+        double da = dot(n, dqi, w) + dot(n, qi, dw);
+        alpha[i - 1] = a;
+        dalpha[i - 1] = da;
+        for (int64_t r = 0; r < n; ++r) {
+            w[r] -= a * qi[r];
+            dw[r] -= da * qi[r] + a * dqi[r];
+        }
+        /* one classical Gram-Schmidt pass: h = Q^T w, w -= Q h */
+        double *dh = h + (k + 1);
+        for (int l = 0; l < i; ++l) {
+            const double *ql = Q + (size_t)l * n, *dql = dQ + (size_t)l * n;
+            h[l] = dot(n, ql, w);
+            dh[l] = dot(n, dql, w) + dot(n, ql, dw);
+        }
+        for (int l = 0; l < i; ++l) {
+            const double *ql = Q + (size_t)l * n, *dql = dQ + (size_t)l * n;
+            for (int64_t r = 0; r < n; ++r) {
+                w[r] -= h[l] * ql[r];
+                dw[r] -= dh[l] * ql[r] + h[l] * dql[r];
+            }
+        }
+        double b = sqrt(dot(n, w, w));
+        double db = dot(n, w, dw) / b;
+        beta[i] = b;
+        dbeta[i] = db;
+        if (fabs(a) > scale) scale = fabs(a);
+        if (i > 1 && beta[i - 1] > scale) scale = beta[i - 1];
+        if (b <= 1e3 * DBL_EPSILON * scale) return i;
+        double *qn = Q + (size_t)i * n, *dqn = dQ + (size_t)i * n;
+        for (int64_t r = 0; r < n; ++r) {
+            qn[r] = w[r] / b;
+            dqn[r] = dw[r] / b - w[r] * db / (b * b);
+        }
+    }
+    return k;
+}
+
+int oracle_lanczos_tangent(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                           const double *val, int prec_kind, int ndim, const int32_t *dims,
+                           double s, double lo, double hi, int degree, const double *coef,
+                           double tau, const double *du, double dtau, const double *V, int64_t m,
+                           int k, int nthreads, double *alpha, double *beta, double *dalpha,
+                           double *dbeta, int32_t *k_used, double *nu)
+{
+    if (n < 1 || m < 1 || k < 1 || k > n) return -1;
+    if (prec_kind == 1) return -3; /* M would depend on diag(A) and tau */
+    op_t P;
+    memset(&P, 0, sizeof P);
+    P.n = n;
+    P.row_ptr = row_ptr;
+    P.col_idx = col_idx;
+    P.val = val;
+    P.prec_kind = prec_kind;
+    P.ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) P.dims[a] = dims[a];
+    P.s = s;
+    P.lo = lo;
+    P.hi = hi;
+    P.degree = degree;
+    P.coef = coef;
+    P.tau = tau;
+    memset(alpha, 0, (size_t)m * k * sizeof(double));
+    memset(beta, 0, (size_t)m * (k + 1) * sizeof(double));
+    memset(dalpha, 0, (size_t)m * k * sizeof(double));
+    memset(dbeta, 0, (size_t)m * (k + 1) * sizeof(double));
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *Q = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
+        double *dQ = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
+        double *w = (double *)malloc((size_t)n * sizeof(double));
+        double *dw = (double *)malloc((size_t)n * sizeof(double));
+        double *v = (double *)malloc((size_t)n * sizeof(double));
+        double *work = (double *)malloc((size_t)n * 8 * sizeof(double));
+        double *h = (double *)malloc((size_t)2 * (k + 1) * sizeof(double));
+        if (!Q || !dQ || !w || !dw || !v || !work || !h) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t j = 0; j < m; ++j) {
+                for (int64_t r = 0; r < n; ++r) v[r] = V[r * m + j];
+                k_used[j] = lanczos_tangent_one(&P, du, dtau, v, k, alpha + j * k,
+                                                beta + j * (k + 1), dalpha + j * k,
+                                                dbeta + j * (k + 1), nu + j, Q, dQ, w, dw, h, work);
+            }
+        }
+        free(Q);
+        free(dQ);
+        free(w);
+        free(dw);
+        free(v);
+        free(work);
+        free(h);
+    }
+    return failed ? -1 : 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

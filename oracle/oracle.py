@@ -74,6 +74,12 @@ def _load():
         lib.oracle_dense_operator.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int,
                                               P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                               ctypes.c_int, P, ctypes.c_double, P]
+        lib.oracle_lanczos_tangent.restype = ctypes.c_int
+        lib.oracle_lanczos_tangent.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int,
+                                               P, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, P, ctypes.c_double,
+                                               P, ctypes.c_double, P, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.c_int, P, P, P, P, P, P]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -241,3 +247,86 @@ def count(A, prec, xi, eta, V, k, rule="gauss", smooth_w=0.0, nthreads=None) -> 
     else:
         var = float("nan")
     return CountResult(est, var, _mean(s_xi), _mean(s_eta), s_xi, s_eta, min(mx, me), lx, le)
+
+
+# ---------------------------------------------------------------------------
+# Derivatives of the erf-smoothed estimator (forward mode)
+# ---------------------------------------------------------------------------
+
+
+def step_deriv(theta: np.ndarray, smooth_w: float) -> np.ndarray:
+    """d/dtheta of erfc(theta / w) / 2."""
+    return -np.exp(-(theta / smooth_w) ** 2) / (smooth_w * math.sqrt(math.pi))
+
+
+def divided_difference(theta: np.ndarray, smooth_w: float) -> np.ndarray:
+    """S[1](a, b) = (S(a) - S(b)) / (a - b), S'(a) on (near-)coincident pairs."""
+    S = step(theta, smooth_w)
+    ta, tb = theta[:, None], theta[None, :]
+    diff = ta - tb
+    close = np.abs(diff) < 1e-8 * (1.0 + np.abs(ta))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        D = (S[:, None] - S[None, :]) / diff
+    D[close] = step_deriv(0.5 * (ta + tb), smooth_w)[close]
+    return D
+
+
+@dataclass
+class TangentResult:
+    lan: LanczosResult
+    dalpha: np.ndarray
+    dbeta: np.ndarray
+
+
+def lanczos_tangent(A, prec, tau, V, k, du, dtau, nthreads=None) -> TangentResult:
+    """Algorithm 1 and its forward-mode derivative along A -> A + t diag(du),
+    tau -> tau + t dtau (M fixed)."""
+    lib = _load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n, m = V.shape
+    kind, nd, dims, coef = _prec_args(prec, n)
+    du = np.ascontiguousarray(du, dtype=np.float64)
+    alpha, beta = np.zeros((m, k)), np.zeros((m, k + 1))
+    dalpha, dbeta = np.zeros((m, k)), np.zeros((m, k + 1))
+    k_used = np.zeros(m, dtype=np.int32)
+    nu = np.zeros(m)
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    rc = lib.oracle_lanczos_tangent(n, _ptr(rp), _ptr(ci), _ptr(va), kind, nd, _ptr(dims),
+                                    float(prec.s), float(prec.lo), float(prec.hi), len(coef) - 1,
+                                    _ptr(coef), float(tau), _ptr(du), float(dtau), _ptr(V), m,
+                                    int(k), int(nthreads or host_threads()), _ptr(alpha),
+                                    _ptr(beta), _ptr(dalpha), _ptr(dbeta), _ptr(k_used), _ptr(nu))
+    if rc != 0:
+        raise ValueError("oracle_lanczos_tangent failed (%d)" % rc)
+    return TangentResult(LanczosResult(alpha, beta, k_used, nu), dalpha, dbeta)
+
+
+def probe_quadrature_tangent(alpha_j, beta_j, dalpha_j, dbeta_j, k_used, nu, smooth_w):
+    """(s_j, ds_j): s = nu e1^T S(J) e1 and its derivative
+    ds = nu sum_{a,b} z_a z_b S[1](theta_a, theta_b) (Z^T dJ Z)_{ab}
+    (Daleckii-Krein), z = first row of the eigenvector matrix Z of J."""
+    k = int(k_used)
+    J = jacobi_matrix(alpha_j, beta_j, k)
+    dJ = jacobi_matrix(dalpha_j, dbeta_j, k)
+    theta, Z = np.linalg.eigh(J)
+    z = Z[0, :]
+    s = nu * float(np.dot(z * z, step(theta, smooth_w)))
+    D = divided_difference(theta, smooth_w)
+    ds = nu * float(z @ (D * (Z.T @ dJ @ Z)) @ z)
+    return s, ds
+
+
+def count_tangent(A, prec, xi, eta, V, k, du, dxi=0.0, deta=0.0, smooth_w=0.05, nthreads=None):
+    """(estimate, directional derivative) of the smoothed interval count along
+    V -> V + t du, xi -> xi + t dxi, eta -> eta + t deta."""
+    m = V.shape[1]
+    out = []
+    for tau, dtau in ((xi, dxi), (eta, deta)):
+        T = lanczos_tangent(A, prec, tau, V, k, du, dtau, nthreads)
+        sd = [probe_quadrature_tangent(T.lan.alpha[j], T.lan.beta[j], T.dalpha[j], T.dbeta[j],
+                                       T.lan.k_used[j], T.lan.nu[j], smooth_w) for j in range(m)]
+        out.append(np.array(sd))
+    d = out[1] - out[0]
+    return _mean(d[:, 0]), _mean(d[:, 1])
