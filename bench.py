@@ -65,7 +65,8 @@ def cpu_baseline(P, V, wl, target_s: float):
     while done < m:
         s = min(batch, m - done)
         t0 = time.perf_counter()
-        oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads)
+        oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads,
+                     smooth_w=wl.smooth_w)
         dt = time.perf_counter() - t0
         t_tot += dt
         done += s
@@ -217,19 +218,42 @@ def main():
     wl = W.WORKLOADS[args.workload]
     log("building inputs", wl.name, "n=%d m=%d k=%d" % (wl.n, wl.m, wl.k))
     P = W.make_problem(wl)
-    V = W.make_probes(wl)
     vec = wl.vec
     tdt = torch.float32 if vec == "f32" else torch.float64
     A = ec.upload_csr(P.A, val_dtype=vec)
-    Vd = torch.from_numpy(V).to("cuda", tdt)
+    # probes generated in HBM (bitwise the same block as workloads.rademacher)
+    Vd = W.rademacher_torch(wl.n, wl.m, wl.probe_seed, device="cuda", dtype=tdt)
     S = 2
-    need = ec.workspace_bytes(wl.n, wl.m, S, P.prec, wl.k, vec=vec, smooth_w=wl.smooth_w)
+    grad = wl.smooth_w > 0.0
+    # FP32 128^3 form: one shift (m columns) per wave bounds the basis to 124 GiB
+    max_cols = wl.m if wl.name == "c3" else 0
+    if grad:
+        need = ec.smooth_workspace_bytes(wl.n, wl.m, P.prec, wl.k, wl.smooth_w)
+    else:
+        need = ec.workspace_bytes(wl.n, wl.m, S, P.prec, wl.k, vec=vec, smooth_w=wl.smooth_w,
+                                  max_cols=max_cols)
     ws = ec.Workspace(need)
     log("workspace %.2f GiB" % (need / 2 ** 30))
+    grad_times = {}
 
     def one():
-        return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
-                        workspace=ws, details=False)
+        if not grad:
+            return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
+                            workspace=ws, details=False, max_cols=max_cols)
+        # differentiated form: forward keeping the basis, then the backward
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        res, _ = ec.smooth_forward(A, P.prec, wl.xi, wl.eta, Vd, wl.k, wl.smooth_w, workspace=ws)
+        e1.record()
+        dV, dxi, deta = ec.smooth_backward(A, P.prec, wl.xi, wl.eta, Vd, wl.k, wl.smooth_w,
+                                           workspace=ws)
+        e2.record()
+        torch.cuda.synchronize()
+        grad_times.setdefault("fwd_ms", []).append(e0.elapsed_time(e1))
+        grad_times.setdefault("bwd_ms", []).append(e1.elapsed_time(e2))
+        grad_times["dxi"], grad_times["deta"] = dxi, deta
+        grad_times["dV_norm"] = float(torch.linalg.vector_norm(dV))
+        return res
 
     for i in range(args.warmup):
         r = one()
@@ -304,7 +328,30 @@ def main():
         "accuracy": accuracy,
         "kernel_sources_sha": kernel_sources_sha(),
     }
+    if grad:
+        # the same number of timed steps with the basis recomputed inside the backward
+        rec = []
+        for i in range(max(1, args.steps // 2)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ec.smooth_backward(A, P.prec, wl.xi, wl.eta, Vd, wl.k, wl.smooth_w, ckpt="recompute",
+                               workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            rec.append(e0.elapsed_time(e1))
+        f = grad_times["fwd_ms"][-args.steps:]
+        b = grad_times["bwd_ms"][-args.steps:]
+        out["differentiated"] = {
+            "step": "smoothed forward + backward (dV in R^n, dxi, deta), basis kept",
+            "fwd_ms": sum(f) / len(f), "bwd_keep_ms": sum(b) / len(b),
+            "bwd_recompute_ms": sum(rec) / len(rec),
+            "fwd_probe_steps_per_s": probe_steps / (sum(f) / len(f) / 1e3),
+            "dxi": grad_times["dxi"], "deta": grad_times["deta"], "dV_norm": grad_times["dV_norm"],
+            "workspace_gib": need / 2 ** 30}
+    if max_cols:
+        out["config"]["column_waves"] = "%d columns per wave" % max_cols
     if not args.no_cpu_baseline:
+        V = Vd.cpu().double().numpy()
         out["cpu_baseline"] = cpu_baseline(P, V, wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -176,6 +176,42 @@ ECNT_API ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const
                            void *ws, size_t ws_bytes, void *stream, double *negcounts,
                            double *counts, double *variances, ecnt_info *info);
 
+/* ---- Differentiated form: gradient of an erf-smoothed count ----
+ *
+ * With smooth_w = w > 0 the step h(theta) of eq. gauss_quad is replaced at the
+ * Ritz values by S_w(theta) = erfc(theta / w) / 2 (the rule only sees h at the
+ * Ritz values, Section 3.3), which makes the computed estimate a smooth
+ * function of A's diagonal and of the shifts.  The backward pass is the exact
+ * reverse-mode derivative of what the forward kernels compute (Algorithm 1
+ * with its one Gram-Schmidt pass, differentiated line by line in reverse; the
+ * tridiagonal step by the Daleckii-Krein formula).  Restrictions: FP64, Gauss
+ * rule, ECNT_PREC_CHEB_LAPLACIAN (M does not depend on A or tau), k <= 32,
+ * max_cols = 0; otherwise ECNT_EUNSUPPORTED.
+ *
+ * State kept between forward and backward (ECNT_CKPT_KEEP): the Lanczos basis,
+ * M q_i of every step and the Gram-Schmidt coefficients, in the workspace
+ * (sized by ecnt_smooth_workspace_bytes), which the caller must not touch
+ * between the two calls.  ECNT_CKPT_RECOMPUTE: the backward reruns the
+ * forward first, so the workspace may be reused in between. */
+typedef enum { ECNT_CKPT_KEEP = 0, ECNT_CKPT_RECOMPUTE = 1 } ecnt_ckpt;
+
+ECNT_API size_t ecnt_smooth_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T,
+                                            const ecnt_opts *opts);
+
+/* Smoothed interval count; same arguments and outputs as ecnt_count. */
+ECNT_API ecnt_status ecnt_smooth_fwd(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                                     const void *probes, int64_t m, const ecnt_opts *opts,
+                                     void *ws, size_t ws_bytes, void *stream, double *estimate,
+                                     double *variance, ecnt_info *info);
+
+/* Gradient of g_est * estimate with respect to A's diagonal (dV: device, n
+ * doubles, overwritten) and the endpoints (dxi, deta: host).  All other
+ * arguments must equal those of the forward call. */
+ECNT_API ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                                     const void *probes, int64_t m, const ecnt_opts *opts,
+                                     int32_t ckpt, double g_est, void *ws, size_t ws_bytes,
+                                     void *stream, double *dV, double *dxi, double *deta);
+
 /* Per-kernel-family timing, for measurement.  While enabled, every launch
  * made by ecnt_count / ecnt_negcounts is bracketed by two hipEvents recorded
  * on the caller's stream; elapsed times and the algorithmic bytes of each

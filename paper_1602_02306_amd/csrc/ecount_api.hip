@@ -17,9 +17,11 @@
 namespace ecnt {
 
 // ------------------------------------------------------------------ profiling
-enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_COUNT };
+enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
+              F_VGRAD, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
-                                           "lz_setup", "lz_finalize", "quadrature"};
+                                           "lz_setup", "lz_finalize", "quadrature", "bw_dots",
+                                           "bw_update", "bw_vgrad"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -119,7 +121,7 @@ size_t plan_layout(Plan &p, char *base)
         Plan q = p;
         q.C = w == 0 ? p.wave_cols : (p.Ct - (p.Ct - 1) / p.wave_cols * p.wave_cols);
         geometry(q);
-        const size_t e = (size_t)q.nchunk * kBasisChunk * q.C;
+        const size_t e = (size_t)q.nchunk * kPartRows * q.C;
         if (e > part_elems) part_elems = e;
     }
     p.part = (double *)take(sizeof(double) * part_elems);
@@ -138,6 +140,25 @@ size_t plan_layout(Plan &p, char *base)
     p.active = (int32_t *)take(sizeof(int32_t) * C);
     p.kused = (int32_t *)take(sizeof(int32_t) * Ct);
     p.flags = (int32_t *)take(sizeof(int32_t) * 4);
+    if (p.grad) {
+        const size_t k = p.k;
+        p.g_tslots = take(blk * k);
+        p.g_qbar = (double *)take(blk * k);
+        p.g_ybar = (double *)take(blk);
+        p.g_tbar = (double *)take(blk);
+        p.g_gall = (double *)take(sizeof(double) * k * k * C);
+        p.g_Z = (double *)take(sizeof(double) * k * k * C);
+        p.g_theta = (double *)take(sizeof(double) * k * C);
+        p.g_sval = (double *)take(sizeof(double) * k * C);
+        p.g_abar = (double *)take(sizeof(double) * k * C);
+        p.g_bbar = (double *)take(sizeof(double) * (k + 1) * C);
+        p.g_coef = (double *)take(sizeof(double) * 4 * 32 * C);
+        p.g_scal = (double *)take(sizeof(double) * 2 * C);
+        p.g_vpart = (double *)take(sizeof(double) * ((C + 63) / 64) * (size_t)p.n);
+        p.g_taubar = (double *)take(sizeof(double) * C);
+        p.g_w = (double *)p.tmp[0];
+        p.g_r = (double *)p.tmp[1];
+    }
     p.bytes = align_up(off, 256) + 256;   // slack for aligning the caller's pointer
     return p.bytes;
 }
@@ -353,22 +374,26 @@ static void sweep(const Plan &p, const void *X, const double *xs, double cx, con
 // M x in product form, x = xs .* X:  M = lead * prod_f F_f(B), applied factor by
 // factor; a quadratic factor (B^2 - 2aB + b) takes two sweeps,
 //   t = B x - 2a x ;  y = B t + b x.
-// Scratch: t0 (quadratic intermediate) and t1; `out` also serves as an
-// intermediate so that the last factor lands in it.
+// Scratch: t0 (quadratic intermediate); factor outputs alternate between t1
+// and t2 so that the last one lands in `out` (t2 may be `out` itself unless
+// accumulating).  accum: out += M x instead of out = M x.
 static void apply_M_product(const Plan &p, const void *X, const double *xs, void *t0, void *t1,
-                            void *out, hipStream_t st)
+                            void *t2, void *out, bool accum, hipStream_t st)
 {
     const void *in = X;
     const double *insc = xs;
     double scale = p.lead;
     for (int f = 0; f < p.nfac; ++f) {
-        void *dst = ((p.nfac - 1 - f) % 2 == 0) ? out : t1;
+        const bool last = f == p.nfac - 1;
+        void *dst = last ? out : (((p.nfac - 2 - f) % 2 == 0) ? t1 : t2);
+        const void *Z = (last && accum) ? out : nullptr;
+        const double cz = (last && accum) ? -1.0 : 0.0;
         const double a = p.fac_a[f];
         if (!p.fac_quad[f]) {
-            sweep(p, in, insc, -a * scale, in, insc != nullptr, scale, nullptr, 0.0, dst, st);
+            sweep(p, in, insc, -a * scale, in, insc != nullptr, scale, Z, cz, dst, st);
         } else {
             sweep(p, in, insc, -2.0 * a * scale, in, insc != nullptr, scale, nullptr, 0.0, t0, st);
-            sweep(p, in, insc, p.fac_b[f] * scale, t0, false, 1.0, nullptr, 0.0, dst, st);
+            sweep(p, in, insc, p.fac_b[f] * scale, t0, false, 1.0, Z, cz, dst, st);
         }
         in = dst;
         insc = nullptr;
@@ -415,11 +440,19 @@ static void apply_M_clenshaw(const Plan &p, const void *X, const double *xs, voi
     sweep(p, X, xs, c[0], bj1, false, 1.0, bj2, 1.0, out, st);
 }
 
-static void apply_M(const Plan &p, const void *X, const double *xs, void *t0, void *t1, void *out,
-                    hipStream_t st)
+// out = M x (or out += M x when accum).  Scratch t0, t1, t2, all distinct from
+// X; t2 may equal out when not accumulating.
+static void apply_M(const Plan &p, const void *X, const double *xs, void *t0, void *t1, void *t2,
+                    void *out, bool accum, hipStream_t st)
 {
-    if (p.product) apply_M_product(p, X, xs, t0, t1, out, st);
-    else apply_M_clenshaw(p, X, xs, t0, t1, out, st);
+    if (p.product) {
+        apply_M_product(p, X, xs, t0, t1, t2, out, accum, st);
+    } else if (!accum) {
+        apply_M_clenshaw(p, X, xs, t0, t1, out, st);
+    } else {
+        apply_M_clenshaw(p, X, xs, t0, t1, t2, st);
+        sweep(p, t2, nullptr, 1.0, nullptr, false, 0.0, out, -1.0, out, st);   // out += t2
+    }
 }
 
 static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st);
@@ -481,14 +514,14 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
         const double *xs = p.sig + (size_t)(i - 1) * p.C;
         if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
-            // t = M q ; u = (A - tau I) t ; y = M u
-            apply_M(p, x, xs, p.tmp[0], p.tmp[1], p.tmp[2], st);
+            // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
+            void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * blk : p.tmp[2];
+            apply_M(p, x, xs, p.tmp[0], p.tmp[1], t, t, false, st);
             {
-                Timed t(F_CSR, 2 * blk_b + csr_b, st);
-                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[2], nullptr, nullptr,
-                              p.tmp[0], st);
+                Timed tm(F_CSR, 2 * blk_b + csr_b, st);
+                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, t, nullptr, nullptr, p.tmp[0], st);
             }
-            apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, st);
+            apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
         } else {
             Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
             launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,
@@ -517,6 +550,56 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     }
     Timed t(F_QUAD, 0.0, st);
     launch_tridiag(p, st);
+}
+
+// Reverse sweep of the smoothed count (see k_backward.hip for the recurrences).
+static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, double *dV,
+                             hipStream_t st)
+{
+    const size_t blk = (size_t)p.n * p.C * 8;
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * 12;
+    {
+        Timed t(F_QUAD, 0.0, st);
+        launch_tridiag_bwd(p, g_out, st);
+    }
+    for (int i = p.k; i >= 1; --i) {
+        const bool last = i == p.k;
+        if (!last) {
+            Timed t(F_BDOTS, (i + 2) * blk_b, st);
+            launch_bdots(p, i, st);
+        }
+        {
+            Timed t(F_FIN, 0.0, st);
+            launch_bdots_fin(p, i, !last, st);
+        }
+        {
+            Timed t(F_BUPD, (i + 1 + (last ? 0 : 1) + 3) * blk_b, st);
+            launch_bupdate1(p, i, st);
+        }
+        {
+            Timed t(F_FIN, 0.0, st);
+            launch_bnorm_fin(p, i, st);
+        }
+        {
+            Timed t(F_BUPD, ((last ? i : 2 * i) + 3) * blk_b, st);
+            launch_bupdate2(p, i, last, st);
+        }
+        // qbar_i += C ybar:  tbar = M ybar ; u = (A - tau I) tbar ; qbar_i += M u
+        apply_M(p, p.g_ybar, nullptr, p.tmp[0], p.tmp[1], p.g_tbar, p.g_tbar, false, st);
+        {
+            Timed t(F_CSR, 2 * blk_b + csr_b, st);
+            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.g_tbar, nullptr, nullptr, p.tmp[2], st);
+        }
+        double *qbi = (double *)((char *)p.g_qbar + (size_t)(i - 1) * blk);
+        apply_M(p, p.tmp[2], nullptr, p.tmp[0], p.tmp[1], p.g_ybar, qbi, true, st);
+        {
+            Timed t(F_VGRAD, 2 * blk_b, st);
+            launch_vgrad(p, (const double *)((char *)p.g_tslots + (size_t)(i - 1) * blk), last, st);
+        }
+    }
+    Timed t(F_FIN, 0.0, st);
+    launch_grad_out(p, dV, st);
 }
 
 static ecnt_status check_common(const ecnt_csr *A, const void *probes, const ecnt_opts *o,
@@ -557,12 +640,38 @@ static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_
     return ECNT_OK;
 }
 
+// Restrictions of the differentiated form: FP64 Gauss rule with a smoothed
+// step, the Laplacian-polynomial preconditioner (M independent of V and tau),
+// one wave of columns, k <= 32.
+static ecnt_status grad_plan(Plan &p, int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *o)
+{
+    ecnt_status rc = make_plan(p, n, m, 2, T, o);
+    if (rc) return rc;
+    if (!(o->smooth_w > 0.0)) return fail(ECNT_EINVAL, "the smoothed count needs opts.smooth_w > 0");
+    if (o->vec_type != ECNT_F64) return fail(ECNT_EUNSUPPORTED, "gradients need FP64 vectors");
+    if (o->rule != ECNT_RULE_GAUSS) return fail(ECNT_EUNSUPPORTED, "gradients need the Gauss rule");
+    if (T->kind != ECNT_PREC_CHEB_LAPLACIAN)
+        return fail(ECNT_EUNSUPPORTED, "gradients need the Laplacian-polynomial preconditioner");
+    if (o->k > kBasisChunk) return fail(ECNT_EUNSUPPORTED, "gradients need k <= %d", kBasisChunk);
+    if (p.wave_cols != p.Ct) return fail(ECNT_EUNSUPPORTED, "gradients need a single column wave");
+    p.grad = 1;
+    plan_layout(p, nullptr);
+    return ECNT_OK;
+}
+
+// mode: 0 count, 1 forward keeping backward state, 2 backward on kept state,
+//       3 forward + backward (recompute).
 static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus, int S,
                        const void *probes, int64_t m, const ecnt_opts *o, void *ws,
-                       size_t ws_bytes, void *stream, double *res_host, ecnt_info *info, Plan &p)
+                       size_t ws_bytes, void *stream, double *res_host, ecnt_info *info, Plan &p,
+                       int mode = 0, double g_out = 0.0, double *dV = nullptr)
 {
-    ecnt_status rc = make_plan(p, A ? A->n : 0, m, S, T, o);
+    ecnt_status rc = mode == 0 ? make_plan(p, A ? A->n : 0, m, S, T, o)
+                               : grad_plan(p, A ? A->n : 0, m, T, o);
     if (rc) return rc;
+    if (mode >= 2 && !dV) return fail(ECNT_EINVAL, "dV is null");
+    if (mode >= 1 && A && A->val_type != ECNT_F64)
+        return fail(ECNT_EUNSUPPORTED, "gradients need FP64 matrix values");
     rc = check_common(A, probes, o, ws, p, ws_bytes);
     if (rc) return rc;
     for (int s = 0; s < S; ++s)
@@ -576,7 +685,8 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
         std::lock_guard<std::mutex> g(g_prof_mu);
         t_prof = g_prof_on;
     }
-    enqueue(p, A, taus, probes, info, st);
+    if (mode != 2) enqueue(p, A, taus, probes, info, st);
+    if (mode >= 2) enqueue_backward(p, A, g_out, dV, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return finish(p, st, res_host, info);
@@ -665,6 +775,67 @@ int32_t ecnt_profile_read(ecnt_kernel_stat *out, int32_t max)
     int32_t n = 0;
     for (int f = 0; f < F_COUNT && n < max && out; ++f) out[n++] = g_stats[f];
     return n;
+}
+
+size_t ecnt_smooth_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *opts)
+{
+    Plan p;
+    if (grad_plan(p, n, m, T, opts) != ECNT_OK) return 0;
+    return p.bytes;
+}
+
+static ecnt_status smooth_common_args(double xi, double eta)
+{
+    if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
+    if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_smooth_fwd(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                            const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
+                            size_t ws_bytes, void *stream, double *estimate, double *variance,
+                            ecnt_info *info)
+{
+    g_err.clear();
+    if (!estimate || !variance) return fail(ECNT_EINVAL, "estimate/variance output is null");
+    ecnt_status rc = smooth_common_args(xi, eta);
+    if (rc) return rc;
+    const double taus[2] = {xi, eta};
+    double res[4 * kMaxShifts + 8];
+    Plan p;
+    rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p, 1);
+    if (rc) return rc;
+    *estimate = res[2];
+    *variance = res[3];
+    if (info) {
+        info->neg_xi = res[0];
+        info->neg_eta = res[1];
+        info->min_abs_ritz = res[4];
+    }
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                            const void *probes, int64_t m, const ecnt_opts *opts, int32_t ckpt,
+                            double g_est, void *ws, size_t ws_bytes, void *stream, double *dV,
+                            double *dxi, double *deta)
+{
+    g_err.clear();
+    if (!dxi || !deta) return fail(ECNT_EINVAL, "dxi/deta output is null");
+    if (ckpt != ECNT_CKPT_KEEP && ckpt != ECNT_CKPT_RECOMPUTE)
+        return fail(ECNT_EINVAL, "ckpt must be ECNT_CKPT_KEEP or ECNT_CKPT_RECOMPUTE");
+    if (!isfinite(g_est)) return fail(ECNT_EINVAL, "g_est must be finite");
+    ecnt_status rc = smooth_common_args(xi, eta);
+    if (rc) return rc;
+    const double taus[2] = {xi, eta};
+    double res[4 * kMaxShifts + 8];
+    Plan p;
+    rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, nullptr, p,
+             ckpt == ECNT_CKPT_KEEP ? 2 : 3, g_est, dV);
+    if (rc) return rc;
+    *dxi = res[4 * kMaxShifts + 0];
+    *deta = res[4 * kMaxShifts + 1];
+    return ECNT_OK;
 }
 
 const char *ecnt_last_error(void) { return g_err.c_str(); }

@@ -67,8 +67,28 @@ struct Plan {
     int32_t *active = nullptr; // C
     int32_t *kused = nullptr;  // Ct
     int32_t *flags = nullptr;  // 4 status flags
+    // ---- differentiated form (smoothed count), single wave, FP64 ----
+    int grad = 0;
+    void *g_tslots = nullptr;  // k blocks: M q_i of every forward step
+    double *g_qbar = nullptr;  // k blocks: adjoints of q_1..q_k (slot-indexed)
+    double *g_ybar = nullptr;  // block: adjoint of C q_i
+    double *g_tbar = nullptr;  // block: M ybar
+    double *g_w = nullptr;     // block views of scratch used by the backward
+    double *g_r = nullptr;
+    double *g_gall = nullptr;  // k*k*C: Gram-Schmidt coefficients g_i[l] of every step
+    double *g_Z = nullptr;     // k*k*C: eigenvectors of J
+    double *g_theta = nullptr; // k*C
+    double *g_sval = nullptr;  // k*C
+    double *g_abar = nullptr;  // k*C
+    double *g_bbar = nullptr;  // (k+1)*C
+    double *g_coef = nullptr;  // 4*32*C
+    double *g_scal = nullptr;  // 2*C
+    double *g_vpart = nullptr; // ceil(C/64)*n
+    double *g_taubar = nullptr;// C
     size_t bytes = 0;
 };
+
+constexpr int kPartRows = 64;      // rows per chunk of the partial-sum buffer
 
 size_t plan_layout(Plan &p, char *base);   // base == nullptr: size only
 
@@ -90,5 +110,14 @@ void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool las
 void launch_norm_fin(const Plan &p, int step, hipStream_t st);
 void launch_tridiag(const Plan &p, hipStream_t st);
 void launch_reduce(const Plan &p, hipStream_t st);
+// backward of the smoothed count
+void launch_tridiag_bwd(const Plan &p, double g_out, hipStream_t st);
+void launch_bdots(const Plan &p, int i, hipStream_t st);
+void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st);
+void launch_bupdate1(const Plan &p, int i, hipStream_t st);
+void launch_bnorm_fin(const Plan &p, int i, hipStream_t st);
+void launch_bupdate2(const Plan &p, int i, bool first, hipStream_t st);
+void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st);
+void launch_grad_out(const Plan &p, double *dV, hipStream_t st);
 
 }  // namespace ecnt

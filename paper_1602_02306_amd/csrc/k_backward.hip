@@ -1,0 +1,523 @@
+// Reverse-mode derivative of the erf-smoothed estimator.
+//
+// Forward, per column (probe j at shift tau), as computed by the forward
+// kernels (q_l = sig_{l-1} * slot_{l-1}; Algorithm 1 with one fused
+// Gram-Schmidt pass):
+//   y_i = C q_i,  w_i = y_i - beta_i q_{i-1},  g_i = Q_i^T w_i (alpha_i = g_i[i]),
+//   r_i = w_i - Q_i g_i,  beta_{i+1} = |r_i|,  q_{i+1} = r_i / beta_{i+1},
+//   s = nu * e_1^T S_w(J_k) e_1,  S_w(x) = erfc(x / w) / 2,
+//   C = M (A - tau I) M,  A = L + diag(V),  M independent of V and tau.
+// Reverse, for i = k..1 (bars are adjoints; all sums over l run to i):
+//   rbar   = qbar_{i+1} / beta_{i+1} + betabar_{i+1} q_{i+1}
+//            (betabar_{i+1} first decreased by qbar_{i+1}^T q_{i+1} / beta_{i+1})
+//   gbar_l = -q_l^T rbar (+ alphabar_i for l = i)
+//   wbar   = rbar + sum_l gbar_l q_l
+//   qbar_l += gbar_l w_i - g_i[l] rbar,   qbar_{i-1} -= beta_i wbar,
+//   betabar_i -= wbar^T q_{i-1},  ybar = wbar,
+//   qbar_i += C ybar,  Vbar += (M ybar) .* (M q_i),  taubar -= (M ybar)^T (M q_i)
+// with alphabar, betabar of the tridiagonal step from Daleckii-Krein:
+//   Jbar = sbar * nu * Z (S[1] o z z^T) Z^T,  z = first row of Z.
+// M q_i is kept from the forward (one block vector per step).
+#include <float.h>
+
+#include "device_common.h"
+#include "ecount_internal.h"
+
+namespace ecnt {
+
+__device__ __forceinline__ double smooth_step(double th, double w) { return 0.5 * erfc(th / w); }
+__device__ __forceinline__ double smooth_step_d(double th, double w)
+{
+    return -exp(-(th / w) * (th / w)) / (w * 1.7724538509055160273);   // sqrt(pi)
+}
+
+// ---- tridiagonal adjoint: full eigendecomposition of J_ku, then alphabar, betabar ----
+// Z (k x k per column) lives in global scratch at Z[(a*k + b)*C + c].
+__global__ __launch_bounds__(64) void k_tridiag_bwd(int C, int k, int m, double smooth_w,
+                                                    double g_out,
+                                                    const double *__restrict__ alpha,
+                                                    const double *__restrict__ beta,
+                                                    const int32_t *__restrict__ kused,
+                                                    const double *__restrict__ nu,
+                                                    double *__restrict__ Zg, double *__restrict__ th,
+                                                    double *__restrict__ sv,
+                                                    double *__restrict__ abar,
+                                                    double *__restrict__ bbar,
+                                                    int32_t *__restrict__ flags)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+#define Z_(a, b) Zg[((size_t)(a) * k + (b)) * C + c]
+#define A_(i) th[(size_t)(i) * C + c]
+    // offdiagonal kept in bbar during the iteration, overwritten at the end
+#define B_(i) bbar[(size_t)(i) * C + c]
+    const int N = kused[c];
+    for (int i = 0; i <= k; ++i) B_(i) = 0.0;
+    for (int i = 0; i < k; ++i) abar[(size_t)i * C + c] = 0.0;
+    if (N < 1) return;
+    for (int i = 0; i < N; ++i) {
+        A_(i) = alpha[(size_t)i * C + c];
+        if (i + 1 < N) B_(i) = beta[(size_t)(i + 1) * C + c];
+        for (int j = 0; j < N; ++j) Z_(i, j) = i == j ? 1.0 : 0.0;
+    }
+    int hi = N - 1, iter = 0;
+    bool failed = false;
+    while (hi > 0) {
+        if (fabs(B_(hi - 1)) <= DBL_EPSILON * (fabs(A_(hi - 1)) + fabs(A_(hi))) ||
+            fabs(B_(hi - 1)) < DBL_MIN) {
+            B_(hi - 1) = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0) {
+            const double bl = fabs(B_(lo - 1));
+            if (bl <= DBL_EPSILON * (fabs(A_(lo - 1)) + fabs(A_(lo))) || bl < DBL_MIN) {
+                B_(lo - 1) = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (++iter > 60 * N) {
+            failed = true;
+            break;
+        }
+        const double bb = B_(hi - 1);
+        const double d = 0.5 * (A_(hi - 1) - A_(hi));
+        const double den = d + copysign(hypot(d, bb), d);
+        const double mu = A_(hi) - (den != 0.0 ? bb * bb / den : 0.0);
+        double x = A_(lo) - mu, y = B_(lo);
+        for (int kk = lo; kk < hi; ++kk) {
+            const double r = hypot(x, y);
+            double cs = 1.0, sn = 0.0;
+            if (r > 0.0) {
+                cs = x / r;
+                sn = y / r;
+            }
+            if (kk > lo) B_(kk - 1) = r;
+            const double ak = A_(kk), ak1 = A_(kk + 1), bk = B_(kk);
+            A_(kk) = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            A_(kk + 1) = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
+            const double nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
+            B_(kk) = nbk;
+            if (kk + 1 < hi) {
+                const double bk1 = B_(kk + 1);
+                y = sn * bk1;
+                B_(kk + 1) = cs * bk1;
+                x = nbk;
+            }
+            for (int rr = 0; rr < N; ++rr) {
+                const double z0 = Z_(rr, kk), z1 = Z_(rr, kk + 1);
+                Z_(rr, kk) = cs * z0 + sn * z1;
+                Z_(rr, kk + 1) = -sn * z0 + cs * z1;
+            }
+        }
+    }
+    if (failed) atomicOr(&flags[1], 1);
+    // seed: d estimate / d s_c = +-1/m (eta columns +, xi columns -)
+    const double sbar = g_out * ((c >= m) ? 1.0 : -1.0) / (double)m;
+    const double scale = sbar * nu[c];
+    for (int a = 0; a < N; ++a) sv[(size_t)a * C + c] = smooth_step(A_(a), smooth_w);
+    // u^(l)_a = sum_b F_ab Z[l][b],  F_ab = S[1](th_a, th_b) z_a z_b;  then
+    // abar_l = scale * Z[l] . u^(l),  bbar_{l+1} = 2 * scale * Z[l] . u^(l+1)
+    for (int i = 0; i <= k; ++i) B_(i) = 0.0;
+    for (int l = N - 1; l >= 0; --l) {
+        double diag = 0.0, off = 0.0;
+        for (int a = 0; a < N; ++a) {
+            const double ta = A_(a), za = Z_(0, a);
+            double ua = 0.0, uan = 0.0;
+            for (int b = 0; b < N; ++b) {
+                const double tb = A_(b);
+                double D;
+                if (fabs(ta - tb) < 1e-8 * (1.0 + fabs(ta)))
+                    D = smooth_step_d(0.5 * (ta + tb), smooth_w);
+                else
+                    D = (sv[(size_t)a * C + c] - sv[(size_t)b * C + c]) / (ta - tb);
+                const double F = D * za * Z_(0, b);
+                ua += F * Z_(l, b);
+                if (l + 1 < N) uan += F * Z_(l + 1, b);
+            }
+            diag += Z_(l, a) * ua;
+            off += Z_(l, a) * uan;
+        }
+        abar[(size_t)l * C + c] = scale * diag;
+        if (l + 1 < N) B_(l + 1) = 2.0 * scale * off;   // betabar_{l+2} (array index l+1)
+    }
+#undef Z_
+#undef A_
+#undef B_
+}
+
+// ---- backward dots: raw[s] = slot_s . qbar_{i+1} (s = 0..i), raw[i+1+s] = slot_s . slot_i (s < i)
+template <int NS>
+__global__ __launch_bounds__(64) void k_bdots(int64_t n, int C, int nct, int64_t rpc,
+                                              const double *__restrict__ basis,
+                                              const double *__restrict__ qbar, size_t ss, int i,
+                                              double *__restrict__ part)
+{
+    // NS = i + 1 slots (0..i)
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int c = ct * 64 + (int)threadIdx.x;
+    if (c >= C) return;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double accD[NS], accE[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) accD[s] = accE[s] = 0.0;
+    const double *QB = qbar + (size_t)i * ss;   // qbar_{i+1}
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c;
+        double q[NS];
+        const double qb = QB[e];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) q[s] = basis[(size_t)s * ss + e];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            accD[s] += q[s] * qb;
+            accE[s] += q[s] * q[NS - 1];
+        }
+    }
+    double *P = part + (size_t)chunk * 64 * C + c;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        P[(size_t)s * C] = accD[s];
+        if (s + 1 < NS) P[(size_t)(NS + s) * C] = accE[s];
+    }
+}
+
+// Per column: finish betabar_{i+1}, form the coefficients of rbar and gbar.
+// coef layout (each [32][C]): cA = gbar*sig (wbar), cW = g*sig (w), cG = gbar, cR = g;
+// scal[0][c] = a (qbar_{i+1} weight in rbar), scal[1][c] = b*sig_i (slot_i weight).
+__global__ void k_bdots_fin(int C, int k, int nchunk, int i, int have_dots,
+                            const double *__restrict__ part, const double *__restrict__ sig,
+                            const double *__restrict__ beta, const double *__restrict__ gall,
+                            const double *__restrict__ abar, double *__restrict__ bbar,
+                            const int32_t *__restrict__ kused, double *__restrict__ cA,
+                            double *__restrict__ cW, double *__restrict__ cG,
+                            double *__restrict__ cR, double *__restrict__ scal)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int ku = kused[c];
+    double a = 0.0, b = 0.0;
+    const double sgi = sig[(size_t)i * C + c];
+    auto raw = [&](int row) {
+        double t = 0.0;
+        for (int ch = 0; ch < nchunk; ++ch) t += part[((size_t)ch * 64 + row) * C + c];
+        return t;
+    };
+    if (have_dots && i < ku) {
+        const double bi1 = beta[(size_t)i * C + c];                  // beta_{i+1}
+        const double cc = sgi * raw(i);                              // qbar_{i+1}^T q_{i+1}
+        double bb = bbar[(size_t)i * C + c] - cc / bi1;              // betabar_{i+1}
+        bbar[(size_t)i * C + c] = bb;
+        a = 1.0 / bi1;
+        b = bb;
+    }
+    for (int s = 0; s < i; ++s) {
+        const double sg = sig[(size_t)s * C + c];
+        double gb = 0.0;
+        if (a != 0.0 || b != 0.0) gb = -(a * sg * raw(s) + b * sg * sgi * raw(i + 1 + s));
+        if (s == i - 1 && i <= ku) gb += abar[(size_t)(i - 1) * C + c];
+        const double g = gall[((size_t)(i - 1) * k + s) * C + c];
+        cA[(size_t)s * C + c] = gb * sg;
+        cW[(size_t)s * C + c] = g * sg;
+        cG[(size_t)s * C + c] = gb;
+        cR[(size_t)s * C + c] = g;
+    }
+    scal[c] = a;
+    scal[(size_t)C + c] = b * sgi;
+}
+
+// Pass 1: rbar, wbar (= ybar), w per row; partial wbar . slot_{i-2}.
+template <int NB, bool HASQ>
+__global__ __launch_bounds__(64) void k_bupdate1(int64_t n, int C, int nct, int64_t rpc,
+                                                 const double *__restrict__ basis,
+                                                 const double *__restrict__ qbar, size_t ss, int i,
+                                                 const double *__restrict__ cA,
+                                                 const double *__restrict__ cW,
+                                                 const double *__restrict__ scal,
+                                                 double *__restrict__ ybar, double *__restrict__ W,
+                                                 double *__restrict__ R, double *__restrict__ part)
+{
+    // NB = i (slots 0..i-1), plus slot i
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int c = ct * 64 + (int)threadIdx.x;
+    if (c >= C) return;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double ca[NB], cw[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+        ca[s] = cA[(size_t)s * C + c];
+        cw[s] = cW[(size_t)s * C + c];
+    }
+    const double a = scal[c], bq = scal[(size_t)C + c];
+    const double *QB = qbar + (size_t)i * ss;
+    const double *SI = basis + (size_t)i * ss;
+    const int sm = i >= 2 ? i - 2 : 0;
+    double dotm = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c;
+        double q[NB];
+        const double si = SI[e];
+        const double qb = HASQ ? QB[e] : 0.0;
+#pragma unroll
+        for (int s = 0; s < NB; ++s) q[s] = basis[(size_t)s * ss + e];
+        __builtin_amdgcn_sched_barrier(0);
+        const double rb = a * qb + bq * si;
+        double wb = rb, w = si;
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            wb += ca[s] * q[s];
+            w += cw[s] * q[s];
+        }
+        ybar[e] = wb;
+        W[e] = w;
+        R[e] = rb;
+        dotm += wb * q[sm];
+    }
+    part[(size_t)chunk * 64 * C + c] = dotm;
+}
+
+// betabar_i -= sig_{i-2} * sum_chunks (wbar . slot_{i-2})
+__global__ void k_bnorm_fin(int C, int nchunk, int i, const double *__restrict__ part,
+                            const double *__restrict__ sig, double *__restrict__ bbar)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C || i < 2) return;
+    double t = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) t += part[(size_t)ch * 64 * C + c];
+    bbar[(size_t)(i - 1) * C + c] -= sig[(size_t)(i - 2) * C + c] * t;
+}
+
+// Pass 2: qbar_s += cG_s w - cR_s rbar (s < i); qbar_{i-1} -= beta_i wbar.
+template <int NB, bool FIRST>
+__global__ __launch_bounds__(64) void k_bupdate2(int64_t n, int C, int nct, int64_t rpc,
+                                                 double *__restrict__ qbar, size_t ss, int i,
+                                                 const double *__restrict__ cG,
+                                                 const double *__restrict__ cR,
+                                                 const double *__restrict__ beta,
+                                                 const double *__restrict__ ybar,
+                                                 const double *__restrict__ W,
+                                                 const double *__restrict__ R)
+{
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int c = ct * 64 + (int)threadIdx.x;
+    if (c >= C) return;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double cg[NB], cr[NB];
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+        cg[s] = cG[(size_t)s * C + c];
+        cr[s] = cR[(size_t)s * C + c];
+    }
+    const double bi = i >= 2 ? beta[(size_t)(i - 1) * C + c] : 0.0;   // beta_i
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c;
+        const double w = W[e], rb = R[e], yb = ybar[e];
+        double qb[NB];
+#pragma unroll
+        for (int s = 0; s < NB; ++s) qb[s] = FIRST ? 0.0 : qbar[(size_t)s * ss + e];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            double v = qb[s] + cg[s] * w - cr[s] * rb;
+            if (s == i - 2) v -= bi * yb;
+            qbar[(size_t)s * ss + e] = v;
+        }
+    }
+}
+
+// Vbar and taubar contributions of step i: tb = M ybar_i, tq = M q_i.
+// vpart[ct][r] (+)= sum over the tile's columns of tb*tq (fixed-order lane
+// reduction); part[chunk][0][c] = sum over the chunk's rows of tb*tq.
+__global__ __launch_bounds__(64) void k_vgrad(int64_t n, int C, int nct, int64_t rpc,
+                                              const double *__restrict__ tb,
+                                              const double *__restrict__ tq, int first,
+                                              double *__restrict__ vpart,
+                                              double *__restrict__ part)
+{
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = (int)(L % nct);
+    const int64_t chunk = L / nct;
+    const int lane = threadIdx.x;
+    const int c = ct * 64 + lane;
+    const bool ok = c < C;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    double tacc = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c;
+        double p = ok ? tb[e] * tq[e] : 0.0;
+        tacc += p;
+        // fixed-order butterfly over the 64 lanes
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, 64);
+        if (lane == 0) {
+            double *dst = vpart + (size_t)ct * n + r;
+            *dst = first ? p : *dst + p;
+        }
+    }
+    if (ok) part[(size_t)chunk * 64 * C + c] = tacc;
+}
+
+__global__ void k_vgrad_fin(int C, int nchunk, const double *__restrict__ part,
+                            double *__restrict__ taubar, int first)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double t = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) t += part[(size_t)ch * 64 * C + c];
+    taubar[c] = (first ? 0.0 : taubar[c]) - t;
+}
+
+// dV[r] = sum_ct vpart[ct][r]
+__global__ void k_grad_v(int64_t n, int nct, const double *__restrict__ vpart, double *__restrict__ dV)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double t = 0.0;
+    for (int ct = 0; ct < nct; ++ct) t += vpart[(size_t)ct * n + r];
+    dV[r] = t;
+}
+
+// out[0] = sum of taubar over the xi columns, out[1] over the eta columns.
+__global__ __launch_bounds__(256) void k_grad_tau(int m, const double *__restrict__ taubar,
+                                                  double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    for (int s = 0; s < 2; ++s) {
+        double acc = 0.0;
+        for (int j = threadIdx.x; j < m; j += 256) acc += taubar[(size_t)s * m + j];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[s] = sh[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned red_blocks(const Plan &p)
+{
+    const int nct = (p.C + 63) / 64;
+    return (unsigned)((int64_t)p.nchunk * nct);
+}
+
+void launch_tridiag_bwd(const Plan &p, double g_out, hipStream_t st)
+{
+    k_tridiag_bwd<<<(p.C + 63) / 64, 64, 0, st>>>(p.C, p.k, p.m, p.smooth_w, g_out, p.alpha, p.beta,
+                                                   p.kused, p.nu, p.g_Z, p.g_theta, p.g_sval, p.g_abar,
+                                                   p.g_bbar, p.flags);
+}
+
+#define ECNT_NS_CASES(F)                                                                        \
+    F(1) F(2) F(3) F(4) F(5) F(6) F(7) F(8) F(9) F(10) F(11) F(12) F(13) F(14) F(15) F(16)   \
+    F(17) F(18) F(19) F(20) F(21) F(22) F(23) F(24) F(25) F(26) F(27) F(28) F(29) F(30)     \
+    F(31) F(32)
+
+void launch_bdots(const Plan &p, int i, hipStream_t st)
+{
+    const int nct = (p.C + 63) / 64;
+    const size_t ss = (size_t)p.n * p.C;
+    switch (i + 1) {
+#define ECNT_CASE(N)                                                                             \
+    case N:                                                                                      \
+        k_bdots<N><<<red_blocks(p), 64, 0, st>>>(p.n, p.C, nct, p.rpc, (const double *)p.basis, \
+                                                 p.g_qbar, ss, i, p.part);                       \
+        break;
+        ECNT_NS_CASES(ECNT_CASE)
+#undef ECNT_CASE
+    default:
+        break;
+    }
+}
+
+void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st)
+{
+    const size_t C = p.C;
+    k_bdots_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.k, p.nchunk, i, have_dots ? 1 : 0,
+                                                   p.part, p.sig, p.beta, p.g_gall, p.g_abar,
+                                                   p.g_bbar, p.kused, p.g_coef, p.g_coef + 32 * C,
+                                                   p.g_coef + 64 * C, p.g_coef + 96 * C, p.g_scal);
+}
+
+void launch_bupdate1(const Plan &p, int i, hipStream_t st)
+{
+    const int nct = (p.C + 63) / 64;
+    const size_t ss = (size_t)p.n * p.C;
+    const size_t C = p.C;
+    const bool hasq = i < p.k;
+    switch (i) {
+#define ECNT_CASE(N)                                                                              \
+    case N:                                                                                       \
+        if (hasq)                                                                                 \
+            k_bupdate1<N, true><<<red_blocks(p), 64, 0, st>>>(                                    \
+                p.n, p.C, nct, p.rpc, (const double *)p.basis, p.g_qbar, ss, i, p.g_coef,         \
+                p.g_coef + 32 * C, p.g_scal, p.g_ybar, p.g_w, p.g_r, p.part);                     \
+        else                                                                                      \
+            k_bupdate1<N, false><<<red_blocks(p), 64, 0, st>>>(                                   \
+                p.n, p.C, nct, p.rpc, (const double *)p.basis, p.g_qbar, ss, i, p.g_coef,         \
+                p.g_coef + 32 * C, p.g_scal, p.g_ybar, p.g_w, p.g_r, p.part);                     \
+        break;
+        ECNT_NS_CASES(ECNT_CASE)
+#undef ECNT_CASE
+    default:
+        break;
+    }
+}
+
+void launch_bnorm_fin(const Plan &p, int i, hipStream_t st)
+{
+    k_bnorm_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, i, p.part, p.sig, p.g_bbar);
+}
+
+void launch_bupdate2(const Plan &p, int i, bool first, hipStream_t st)
+{
+    const int nct = (p.C + 63) / 64;
+    const size_t ss = (size_t)p.n * p.C;
+    const size_t C = p.C;
+    switch (i) {
+#define ECNT_CASE(N)                                                                              \
+    case N:                                                                                       \
+        if (first)                                                                                \
+            k_bupdate2<N, true><<<red_blocks(p), 64, 0, st>>>(                                    \
+                p.n, p.C, nct, p.rpc, p.g_qbar, ss, i, p.g_coef + 64 * C, p.g_coef + 96 * C,      \
+                p.beta, p.g_ybar, p.g_w, p.g_r);                                                  \
+        else                                                                                      \
+            k_bupdate2<N, false><<<red_blocks(p), 64, 0, st>>>(                                   \
+                p.n, p.C, nct, p.rpc, p.g_qbar, ss, i, p.g_coef + 64 * C, p.g_coef + 96 * C,      \
+                p.beta, p.g_ybar, p.g_w, p.g_r);                                                  \
+        break;
+        ECNT_NS_CASES(ECNT_CASE)
+#undef ECNT_CASE
+    default:
+        break;
+    }
+}
+
+void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st)
+{
+    const int nct = (p.C + 63) / 64;
+    k_vgrad<<<red_blocks(p), 64, 0, st>>>(p.n, p.C, nct, p.rpc, p.g_tbar, tq, first ? 1 : 0,
+                                          p.g_vpart, p.part);
+    k_vgrad_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, p.part, p.g_taubar, first ? 1 : 0);
+}
+
+void launch_grad_out(const Plan &p, double *dV, hipStream_t st)
+{
+    const int nct = (p.C + 63) / 64;
+    k_grad_v<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(p.n, nct, p.g_vpart, dV);
+    k_grad_tau<<<1, 256, 0, st>>>(p.m, p.g_taubar, p.result + 4 * kMaxShifts);
+}
+
+}  // namespace ecnt

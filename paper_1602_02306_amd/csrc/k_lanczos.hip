@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int c_of
     red[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && c < C)
-        part[(size_t)chunk * kBasisChunk * C + c] =
+        part[(size_t)chunk * kPartRows * C + c] =
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
@@ -61,7 +61,7 @@ __global__ void k_setup_fin(int C, int k, int nchunk, const double *__restrict__
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * kBasisChunk * C + c];
+    for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * kPartRows * C + c];
     nu[c] = s;
     const bool ok = s > 0.0;
     sig[c] = ok ? 1.0 / sqrt(s) : 0.0;
@@ -118,24 +118,25 @@ __global__ __launch_bounds__(64) void k_dots(int64_t n, int C, int nct, int64_t 
     for (int l = 0; l < NB; ++l)
 #pragma unroll
         for (int v = 0; v < VW; ++v)
-            part[((size_t)chunk * kBasisChunk + l) * C + c0 + v] = acc[l][v];
+            part[((size_t)chunk * kPartRows + l) * C + c0 + v] = acc[l][v];
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
-__global__ void k_dots_fin(int C, int nchunk, int step, int l0, int nb,
+__global__ void k_dots_fin(int C, int nchunk, int step, int l0, int nb, int k,
                            const double *__restrict__ part, const double *__restrict__ sig,
                            const int32_t *__restrict__ active, double *__restrict__ cf,
-                           double *__restrict__ alpha)
+                           double *__restrict__ alpha, double *__restrict__ gall)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nb * C) return;
     const int l = idx / C, c = idx % C;
     double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)ch * kBasisChunk + l) * C + c];
+    for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)ch * kPartRows + l) * C + c];
     const double sg = sig[(size_t)(l0 + l) * C + c];
     const double g = s * sg;
     cf[(size_t)(l0 + l) * C + c] = g * sg;
     if (l0 + l == step - 1) alpha[(size_t)(step - 1) * C + c] = active[c] ? g : 0.0;
+    if (gall) gall[((size_t)(step - 1) * k + l0 + l) * C + c] = g;   // kept for the backward
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(64) void k_update(int64_t n, int C, int nct, int64_
     }
     if (last) {
 #pragma unroll
-        for (int v = 0; v < VW; ++v) part[(size_t)chunk * kBasisChunk * C + c0 + v] = nrm[v];
+        for (int v = 0; v < VW; ++v) part[(size_t)chunk * kPartRows * C + c0 + v] = nrm[v];
     }
 }
 
@@ -201,7 +202,7 @@ __global__ void k_norm_fin(int C, int nchunk, int step, double eps_vec,
     if (c >= C) return;
     const int i = step;
     double ss = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) ss += part[(size_t)ch * kBasisChunk * C + c];
+    for (int ch = 0; ch < nchunk; ++ch) ss += part[(size_t)ch * kPartRows * C + c];
     const double b = sqrt(ss);
     double rm = fmax(runmax[c], fabs(alpha[(size_t)(i - 1) * C + c]));
     if (i > 1) rm = fmax(rm, beta[(size_t)(i - 1) * C + c]);
@@ -318,8 +319,8 @@ void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
 {
     const int tot = nb * p.C;
-    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, l0, nb, p.part, p.sig,
-                                                  p.active, p.cf, p.alpha);
+    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, l0, nb, p.k, p.part, p.sig,
+                                                  p.active, p.cf, p.alpha, p.g_gall);
 }
 
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)

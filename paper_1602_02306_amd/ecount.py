@@ -88,6 +88,17 @@ def load():
         lib.ecnt_last_error.argtypes = []
         lib.ecnt_version.restype = ctypes.c_char_p
         lib.ecnt_version.argtypes = []
+        lib.ecnt_smooth_workspace_bytes.restype = ctypes.c_size_t
+        lib.ecnt_smooth_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64,
+                                                    ctypes.POINTER(PrecT), ctypes.POINTER(OptsT)]
+        lib.ecnt_smooth_fwd.restype = ctypes.c_int32
+        lib.ecnt_smooth_fwd.argtypes = lib.ecnt_count.argtypes
+        lib.ecnt_smooth_bwd.restype = ctypes.c_int32
+        lib.ecnt_smooth_bwd.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT), ctypes.c_double,
+                                        ctypes.c_double, P, ctypes.c_int64, ctypes.POINTER(OptsT),
+                                        ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t, P, P,
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
         lib.ecnt_profile_enable.restype = ctypes.c_int32
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
         lib.ecnt_profile_read.restype = ctypes.c_int32
@@ -227,12 +238,11 @@ def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = 
     ps, _coef = prec_struct(prec, eval)
     o = opts_struct(k, vec, rule, smooth_w, max_cols)
     need = lib.ecnt_workspace_bytes(n, m, 2, ctypes.byref(ps), ctypes.byref(o))
-    if need == 0:
-        raise EcntError(ECNT_EINVAL, last_error())
-    ws = (workspace or Workspace(need, probes.device)).ensure(need)
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
     info, keep = _info(2 * m, k, details, probes.device)
     est, var = ctypes.c_double(), ctypes.c_double()
     cs = A.struct()
+    # a request the library cannot size is passed on so that it reports its own status
     rc = lib.ecnt_count(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
                         probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
                         _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
@@ -266,9 +276,7 @@ def negcounts(A: DeviceCSR, prec, taus, probes, k: int, vec: str = "f64", rule: 
     ps, _coef = prec_struct(prec, eval)
     o = opts_struct(k, vec, rule, smooth_w, max_cols)
     need = lib.ecnt_workspace_bytes(n, m, S, ctypes.byref(ps), ctypes.byref(o))
-    if need == 0:
-        raise EcntError(ECNT_EINVAL, last_error())
-    ws = (workspace or Workspace(need, probes.device)).ensure(need)
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
     info, keep = _info(S * m, k, details, probes.device)
     neg = np.zeros(S)
     cnt = np.zeros(max(S - 1, 1))
@@ -299,3 +307,63 @@ def profile_read() -> dict:
     n = load().ecnt_profile_read(arr, 16)
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].total_ms),
                                    "bytes": float(arr[i].bytes)} for i in range(n)}
+
+
+# ---------------------------------------------------------------------------
+# Differentiated form (erf-smoothed count)
+# ---------------------------------------------------------------------------
+
+CKPT = {"keep": 0, "recompute": 1}
+
+
+def smooth_workspace_bytes(n: int, m: int, prec, k: int, smooth_w: float) -> int:
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, "f64", "gauss", smooth_w)
+    return int(load().ecnt_smooth_workspace_bytes(int(n), int(m), ctypes.byref(ps), ctypes.byref(o)))
+
+
+def smooth_forward(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, smooth_w: float,
+                   workspace: Workspace | None = None, stream=None, details: bool = False):
+    """Smoothed interval count (ecnt_smooth_fwd).  Returns (CountResult, workspace);
+    the workspace holds the state that smooth_backward(..., ckpt='keep') uses."""
+    lib = load()
+    n, m = probes.shape
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, "f64", "gauss", smooth_w)
+    need = lib.ecnt_smooth_workspace_bytes(n, m, ctypes.byref(ps), ctypes.byref(o))
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
+    info, keep = _info(2 * m, k, details, probes.device)
+    est, var = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    rc = lib.ecnt_smooth_fwd(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                             probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
+                             _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
+                             ctypes.byref(info))
+    _check(rc)
+    res = CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
+                      keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"), keep.get("beta"))
+    return res, ws
+
+
+def smooth_backward(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, smooth_w: float,
+                    g_est: float = 1.0, ckpt: str = "keep", workspace: Workspace | None = None,
+                    stream=None):
+    """Gradient of g_est * estimate: (dV (torch, device, n), dxi, deta)."""
+    import torch
+    lib = load()
+    n, m = probes.shape
+    ps, _coef = prec_struct(prec)
+    o = opts_struct(k, "f64", "gauss", smooth_w)
+    need = lib.ecnt_smooth_workspace_bytes(n, m, ctypes.byref(ps), ctypes.byref(o))
+    if need and ckpt == "keep" and (workspace is None or workspace.nbytes < need):
+        raise ValueError("ckpt='keep' needs the workspace returned by smooth_forward")
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
+    dV = torch.empty(n, dtype=torch.float64, device=probes.device)
+    dxi, deta = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    rc = lib.ecnt_smooth_bwd(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                             probes.data_ptr(), m, ctypes.byref(o), CKPT[ckpt], float(g_est),
+                             ws.buf.data_ptr(), ws.nbytes, _stream_handle(stream), dV.data_ptr(),
+                             ctypes.byref(dxi), ctypes.byref(deta))
+    _check(rc)
+    return dV, dxi.value, deta.value

@@ -175,6 +175,37 @@ def rademacher(n: int, m: int, seed: int, dtype=np.float64, row_block: int = 1 <
     return out
 
 
+def rademacher_torch(n: int, m: int, seed: int, device="cuda", dtype=None, row_block: int = 1 << 15):
+    """The same +-1 block as `rademacher`, generated with torch on `device`
+    (SplitMix64 in wrapping int64 arithmetic; logical shifts emulated by
+    masking).  Bitwise identical to the numpy version."""
+    import torch
+    dtype = dtype or torch.float64
+
+    def as_i64(u: int) -> int:
+        u &= (1 << 64) - 1
+        return u - (1 << 64) if u >= 1 << 63 else u
+
+    def lsr(x, sh):
+        return (x >> sh) & ((1 << (64 - sh)) - 1)
+
+    gamma, mix1, mix2 = as_i64(0x9E3779B97F4A7C15), as_i64(0xBF58476D1CE4E5B9), as_i64(0x94D049BB133111EB)
+    out = torch.empty((n, m), dtype=dtype, device=device)
+    j = torch.arange(m, dtype=torch.int64, device=device)[None, :]
+    seed_i = as_i64(seed)
+    for r0 in range(0, n, row_block):
+        r1 = min(n, r0 + row_block)
+        r = torch.arange(r0, r1, dtype=torch.int64, device=device)[:, None]
+        z = (j * n + r + 1) * gamma + seed_i
+        z = z ^ lsr(z, 30)
+        z = z * mix1
+        z = z ^ lsr(z, 27)
+        z = z * mix2
+        z = z ^ lsr(z, 31)
+        out[r0:r1] = torch.where(z >= 0, 1.0, -1.0).to(dtype)
+    return out
+
+
 def identity_probes(n: int) -> np.ndarray:
     """sqrt(n) * I: n probes with sum_j v_j v_j^T = n I and |v_j|^2 = n."""
     return np.sqrt(float(n)) * np.eye(n)

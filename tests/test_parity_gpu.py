@@ -279,3 +279,114 @@ def test_fp32_form_within_stated_bound(ec, name):
     print("fp32 %s: est %.10f oracle %.10f rel %.2e  max|ds|/nu %.2e" % (name, r.estimate, ref.estimate, e_est, e_probe), flush=True)
     assert e_est <= FP32_BOUND
     assert e_probe <= FP32_BOUND
+
+
+# ---------------------------------------------------------------------------
+# Differentiated form: gradient of the erf-smoothed count
+# ---------------------------------------------------------------------------
+
+GRAD_CASES = {
+    "wells6": W.Workload("wells6", (6, 6, 6), "wells", 1, -160.0, -120.0, "cheb", 6, 8),
+    "c2_small": W.WORKLOADS["c2_small"],
+    "ragged": W.Workload("ragged", (7, 5, 6), "wells", 4, -120.0, -60.0, "cheb", 9, 10),
+}
+
+
+def grad_setup(ec, name, w=0.05):
+    wl = GRAD_CASES[name]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    Ad = ec.upload_csr(P.A)
+    Vd = torch.from_numpy(V).cuda()
+    return wl, P, V, Ad, Vd
+
+
+@pytest.mark.parametrize("name", ["wells6", "c2_small", "ragged"])
+def test_smooth_gradient_matches_oracle_tangents(ec, name):
+    """<dV, u>, d/dxi and d/deta against the oracle's forward-mode tangents
+    (Algorithm 1 differentiated in its literal order), relative 1e-8."""
+    w = 0.05
+    wl, P, V, Ad, Vd = grad_setup(ec, name, w)
+    print("case grad", name, flush=True)
+    res, ws = ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w)
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, wl.k, smooth_w=w)
+    assert rel(res.estimate, ref.estimate) <= TOL
+    dV, dxi, deta = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, workspace=ws)
+    dV = dV.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for t in range(2):
+        u = rng.standard_normal(P.A.n)
+        _, d_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, u, 0.0, 0.0, w)
+        d_gpu = float(np.dot(dV, u))
+        print("  <dV,u> gpu %.12e oracle %.12e" % (d_gpu, d_ref), flush=True)
+        assert abs(d_gpu - d_ref) <= 1e-8 * max(abs(d_ref), 1e-12 * np.abs(dV).sum())
+    _, dxi_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, np.zeros(P.A.n), 1.0, 0.0, w)
+    _, deta_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, np.zeros(P.A.n), 0.0, 1.0, w)
+    print("  dxi %.12e / %.12e  deta %.12e / %.12e" % (dxi, dxi_ref, deta, deta_ref), flush=True)
+    assert abs(dxi - dxi_ref) <= 1e-8 * max(abs(dxi_ref), 1e-10)
+    assert abs(deta - deta_ref) <= 1e-8 * max(abs(deta_ref), 1e-10)
+
+
+def test_smooth_gradient_finite_differences_gpu(ec):
+    """Central differences of the GPU's own smoothed estimate."""
+    w = 0.05
+    wl, P, V, Ad, Vd = grad_setup(ec, "wells6", w)
+    _, ws = ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w)
+    dV, dxi, deta = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, workspace=ws)
+    u = np.random.default_rng(5).standard_normal(P.A.n)
+    h = 1e-4
+
+    def est(Vpot, xi, eta):
+        A2 = ec.upload_csr(W.laplacian_csr(wl.dims, Vpot))
+        return ec.smooth_forward(A2, P.prec, xi, eta, Vd, wl.k, w)[0].estimate
+
+    fd = (est(P.V + h * u, wl.xi, wl.eta) - est(P.V - h * u, wl.xi, wl.eta)) / (2 * h)
+    g = float(np.dot(dV.cpu().numpy(), u))
+    assert abs(fd - g) <= 1e-6 * abs(g) + 1e-8
+    fd = (est(P.V, wl.xi + h, wl.eta) - est(P.V, wl.xi - h, wl.eta)) / (2 * h)
+    assert abs(fd - dxi) <= 1e-6 * abs(dxi) + 1e-8
+    fd = (est(P.V, wl.xi, wl.eta + h) - est(P.V, wl.xi, wl.eta - h)) / (2 * h)
+    assert abs(fd - deta) <= 1e-6 * abs(deta) + 1e-8
+
+
+def test_smooth_keep_and_recompute_agree(ec):
+    w = 0.05
+    wl, P, V, Ad, Vd = grad_setup(ec, "c2_small", w)
+    res, ws = ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w)
+    cnt = ec.count(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, smooth_w=w)
+    assert res.estimate == cnt.estimate
+    a = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, workspace=ws)
+    b = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, ckpt="recompute")
+    assert torch.equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
+    c = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=1.0, ckpt="recompute")
+    assert torch.allclose(a[0], 2.0 * c[0], rtol=1e-14, atol=0)
+
+
+def test_smooth_autograd_function(ec):
+    from paper_1602_02306_amd.autograd import SmoothCount, SmoothProblem
+    w = 0.05
+    wl = GRAD_CASES["wells6"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    L = W.laplacian_csr(wl.dims)
+    pb = SmoothProblem.from_host(L, P.prec, V, wl.k, w)
+    Vt = torch.from_numpy(P.V).cuda().requires_grad_(True)
+    xi = torch.tensor(wl.xi, dtype=torch.float64, device="cuda", requires_grad=True)
+    eta = torch.tensor(wl.eta, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = SmoothCount.apply(Vt, xi, eta, pb)
+    (3.0 * out).backward()
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, wl.k, smooth_w=w)
+    assert rel(out.item(), ref.estimate) <= TOL
+    u = np.random.default_rng(2).standard_normal(P.A.n)
+    _, d_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, u, 0.0, 0.0, w)
+    assert abs(float(np.dot(Vt.grad.cpu().numpy(), u)) - 3.0 * d_ref) <= 1e-8 * abs(3.0 * d_ref)
+
+
+def test_smooth_rejects_unsupported(ec):
+    wl = W.WORKLOADS["c1"]
+    P = W.make_problem(wl)
+    Ad = ec.upload_csr(P.A)
+    Vd = torch.from_numpy(W.make_probes(wl)).cuda()
+    with pytest.raises(ec.EcntError) as e:
+        ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, 0.05)   # Jacobi M depends on A
+    assert e.value.status == ec.ECNT_EUNSUPPORTED
