@@ -156,6 +156,7 @@ size_t plan_layout(Plan &p, char *base)
         p.g_scal = (double *)take(sizeof(double) * 2 * C);
         p.g_vpart = (double *)take(sizeof(double) * ((C + 63) / 64) * (size_t)p.n);
         p.g_taubar = (double *)take(sizeof(double) * C);
+        p.g_sums = (double *)take(sizeof(double) * 64 * C);
         p.g_w = (double *)p.tmp[0];
         p.g_r = (double *)p.tmp[1];
     }

@@ -85,6 +85,7 @@ struct Plan {
     double *g_scal = nullptr;  // 2*C
     double *g_vpart = nullptr; // ceil(C/64)*n
     double *g_taubar = nullptr;// C
+    double *g_sums = nullptr;  // 64*C: chunk-summed backward dots
     size_t bytes = 0;
 };
 

@@ -187,6 +187,18 @@ __global__ __launch_bounds__(64) void k_bdots(int64_t n, int C, int nct, int64_t
     }
 }
 
+// sums[row][c] = sum over chunks of part[chunk][row][c], one thread per (row, c)
+__global__ void k_rowsum(int C, int nchunk, int nrows, const double *__restrict__ part,
+                         double *__restrict__ sums)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nrows * C) return;
+    const int row = idx / C, c = idx % C;
+    double t = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) t += part[((size_t)ch * 64 + row) * C + c];
+    sums[idx] = t;
+}
+
 // Per column: finish betabar_{i+1}, form the coefficients of rbar and gbar.
 // coef layout (each [32][C]): cA = gbar*sig (wbar), cW = g*sig (w), cG = gbar, cR = g;
 // scal[0][c] = a (qbar_{i+1} weight in rbar), scal[1][c] = b*sig_i (slot_i weight).
@@ -203,11 +215,9 @@ __global__ void k_bdots_fin(int C, int k, int nchunk, int i, int have_dots,
     const int ku = kused[c];
     double a = 0.0, b = 0.0;
     const double sgi = sig[(size_t)i * C + c];
-    auto raw = [&](int row) {
-        double t = 0.0;
-        for (int ch = 0; ch < nchunk; ++ch) t += part[((size_t)ch * 64 + row) * C + c];
-        return t;
-    };
+    // part holds the chunk-summed dots here (k_rowsum)
+    auto raw = [&](int row) { return part[(size_t)row * C + c]; };
+    (void)nchunk;
     if (have_dots && i < ku) {
         const double bi1 = beta[(size_t)i * C + c];                  // beta_{i+1}
         const double cc = sgi * raw(i);                              // qbar_{i+1}^T q_{i+1}
@@ -445,8 +455,12 @@ void launch_bdots(const Plan &p, int i, hipStream_t st)
 void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st)
 {
     const size_t C = p.C;
+    if (have_dots) {
+        const int rows = 2 * i + 1;
+        k_rowsum<<<(rows * p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, rows, p.part, p.g_sums);
+    }
     k_bdots_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.k, p.nchunk, i, have_dots ? 1 : 0,
-                                                   p.part, p.sig, p.beta, p.g_gall, p.g_abar,
+                                                   p.g_sums, p.sig, p.beta, p.g_gall, p.g_abar,
                                                    p.g_bbar, p.kused, p.g_coef, p.g_coef + 32 * C,
                                                    p.g_coef + 64 * C, p.g_coef + 96 * C, p.g_scal);
 }
