@@ -212,6 +212,77 @@ ECNT_API ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, doub
                                      int32_t ckpt, double g_est, void *ws, size_t ws_bytes,
                                      void *stream, double *dV, double *dxi, double *deta);
 
+/* ---- Batches of independent problems ----
+ *
+ * Many small problems (each its own A_b, shifts and probe block) run as one
+ * launch sequence: the batch is stored as one block-diagonal matrix whose
+ * rows are the problems' rows in order, and every reduction, Lanczos scalar
+ * and shift is kept per (problem, column), so the result for problem b is
+ * exactly what ecnt_negcounts returns for it alone (Algorithm 2 per problem,
+ * Section 3.2), up to the order of floating-point sums.
+ *
+ *   A         the block-diagonal matrix (rows and column indices global),
+ *             A.n = sum of items[b].n
+ *   items     host, nprob descriptions:
+ *               n      rows of problem b
+ *               dims   its grid (d0, d1, d2; d2 contiguous) for
+ *                      ECNT_PREC_CHEB_LAPLACIAN, where T.ndim must be 3 and
+ *                      the stencil of every problem is the 7-point one; with
+ *                      other preconditioners dims is ignored
+ *               taus   host, nshift finite shifts of problem b
+ *   T         one preconditioner description for all problems (T.dims is
+ *             ignored: each problem uses its own grid)
+ *   probes    device, A.n x m row-major (rows of problem b at its offset)
+ *   negcounts host, nprob x nshift; counts / variances nullable,
+ *             nprob x (nshift-1), as ecnt_negcounts
+ *   info      nullable; per_probe / k_used are nprob x (nshift*m); alpha and
+ *             beta are not written for batches
+ * Errors as ecnt_negcounts, plus EINVAL when a problem's grid does not match
+ * its n or k exceeds a problem's n.
+ *
+ * The call is split in three so that the middle one can be captured into a
+ * hipGraph and replayed: prepare (validates, carves the workspace, uploads the
+ * per-problem tables; synchronous), enqueue (kernel launches on `stream`
+ * only: no allocation, copy or host synchronization), results (copies the
+ * results back; synchronizes `stream`).  All three take the same arguments;
+ * the workspace must stay untouched between them.  ecnt_count_batched runs
+ * all three. */
+typedef struct {
+    int64_t n;
+    int32_t dims[3];
+    int32_t reserved;
+    const double *taus;
+} ecnt_batch_item;
+
+ECNT_API size_t ecnt_batch_workspace_bytes(const ecnt_batch_item *items, int32_t nprob,
+                                           int32_t nshift, int64_t m, const ecnt_prec *T,
+                                           const ecnt_opts *opts);
+
+ECNT_API ecnt_status ecnt_batch_prepare(const ecnt_csr *A, const ecnt_prec *T,
+                                        const ecnt_batch_item *items, int32_t nprob,
+                                        int32_t nshift, const void *probes, int64_t m,
+                                        const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                        void *stream);
+
+ECNT_API ecnt_status ecnt_batch_enqueue(const ecnt_csr *A, const ecnt_prec *T,
+                                        const ecnt_batch_item *items, int32_t nprob,
+                                        int32_t nshift, const void *probes, int64_t m,
+                                        const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                        void *stream);
+
+ECNT_API ecnt_status ecnt_batch_results(const ecnt_batch_item *items, int32_t nprob,
+                                        int32_t nshift, int64_t m, const ecnt_prec *T,
+                                        const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                        void *stream, double *negcounts, double *counts,
+                                        double *variances, ecnt_info *info);
+
+ECNT_API ecnt_status ecnt_count_batched(const ecnt_csr *A, const ecnt_prec *T,
+                                        const ecnt_batch_item *items, int32_t nprob,
+                                        int32_t nshift, const void *probes, int64_t m,
+                                        const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                        void *stream, double *negcounts, double *counts,
+                                        double *variances, ecnt_info *info);
+
 /* Per-kernel-family timing, for measurement.  While enabled, every launch
  * made by ecnt_count / ecnt_negcounts is bracketed by two hipEvents recorded
  * on the caller's stream; elapsed times and the algorithmic bytes of each

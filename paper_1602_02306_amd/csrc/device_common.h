@@ -24,6 +24,18 @@ __device__ __forceinline__ double ld(const T *p, size_t i)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Segment holding x: off[b] <= x < off[b+1] (off ascending, off[0] = 0).
+__device__ __forceinline__ int find_seg(const int64_t *__restrict__ off, int nseg, int64_t x)
+{
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // VW consecutive columns per lane, moved as one vector load/store.
 template <typename T, int VW> struct VecT;
 template <> struct VecT<double, 1> { using type = double; };

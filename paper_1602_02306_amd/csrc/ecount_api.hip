@@ -97,7 +97,7 @@ static ecnt_status fail(ecnt_status st, const char *fmt, ...)
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-static void geometry(Plan &p);
+static void col_geometry(Plan &p);
 
 size_t plan_layout(Plan &p, char *base)
 {
@@ -110,38 +110,33 @@ size_t plan_layout(Plan &p, char *base)
     };
     const size_t bv = p.vec_f32 ? 4 : 8;
     const size_t blk = (size_t)p.n * p.wave_cols * bv;
-    const size_t C = p.wave_cols;
-    const size_t Ct = p.Ct;
+    const size_t NC = (size_t)p.nseg * p.wave_cols;   // virtual columns of one wave
+    const size_t NCt = (size_t)p.nseg * p.Ct;         // of the whole run
     p.basis = take(blk * (p.k + 1));
     const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : 0;
     for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;
-    // partial sums: the largest of the full and the (narrower) last wave
-    size_t part_elems = 0;
-    for (int w = 0; w < 2; ++w) {
-        Plan q = p;
-        q.C = w == 0 ? p.wave_cols : (p.Ct - (p.Ct - 1) / p.wave_cols * p.wave_cols);
-        geometry(q);
-        const size_t e = (size_t)q.nchunk * kPartRows * q.C;
-        if (e > part_elems) part_elems = e;
-    }
-    p.part = (double *)take(sizeof(double) * part_elems);
-    p.sig = (double *)take(sizeof(double) * (p.k + 1) * C);
-    p.alpha = (double *)take(sizeof(double) * p.k * C);
-    p.beta = (double *)take(sizeof(double) * (p.k + 1) * C);
-    p.cf = (double *)take(sizeof(double) * (p.k + 1) * C);
-    p.kappa = (double *)take(sizeof(double) * C);
-    p.runmax = (double *)take(sizeof(double) * C);
-    p.nu = (double *)take(sizeof(double) * C);
-    p.taus = (double *)take(sizeof(double) * kMaxShifts);
-    p.s_out = (double *)take(sizeof(double) * Ct);
-    p.minabs = (double *)take(sizeof(double) * Ct);
+    p.part = (double *)take(sizeof(double) * (size_t)p.nchunk * kPartRows * p.wave_cols);
+    p.sig = (double *)take(sizeof(double) * (p.k + 1) * NC);
+    p.alpha = (double *)take(sizeof(double) * p.k * NC);
+    p.beta = (double *)take(sizeof(double) * (p.k + 1) * NC);
+    p.cf = (double *)take(sizeof(double) * (p.k + 1) * NC);
+    p.kappa = (double *)take(sizeof(double) * NC);
+    p.runmax = (double *)take(sizeof(double) * NC);
+    p.nu = (double *)take(sizeof(double) * NC);
+    p.s_out = (double *)take(sizeof(double) * NCt);
+    p.minabs = (double *)take(sizeof(double) * NCt);
     p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
-    p.result = (double *)take(sizeof(double) * (4 * kMaxShifts + 8));
-    p.active = (int32_t *)take(sizeof(int32_t) * C);
-    p.kused = (int32_t *)take(sizeof(int32_t) * Ct);
+    p.result = (double *)take(sizeof(double) * kResStride * p.nseg);
+    p.active = (int32_t *)take(sizeof(int32_t) * NC);
+    p.kused = (int32_t *)take(sizeof(int32_t) * NCt);
     p.flags = (int32_t *)take(sizeof(int32_t) * 4);
+    p.seg_row = (int64_t *)take(sizeof(int64_t) * (p.nseg + 1));
+    p.seg_chunk = (int64_t *)take(sizeof(int64_t) * (p.nseg + 1));
+    p.seg_tile = (int64_t *)take(sizeof(int64_t) * (p.nseg + 1));
+    p.seg_dims = (int32_t *)take(sizeof(int32_t) * 3 * p.nseg);
+    p.seg_taus = (double *)take(sizeof(double) * p.S * p.nseg);
     if (p.grad) {
-        const size_t k = p.k;
+        const size_t k = p.k, C = p.wave_cols;
         p.g_tslots = take(blk * k);
         p.g_qbar = (double *)take(blk * k);
         p.g_ybar = (double *)take(blk);
@@ -164,21 +159,42 @@ size_t plan_layout(Plan &p, char *base)
     return p.bytes;
 }
 
-static void geometry(Plan &p)
+// Column geometry of a wave of width p.C.
+static void col_geometry(Plan &p)
 {
     // columns per lane: 16-byte accesses where the column count allows it
     if (p.vec_f32) p.vw = (p.C % 4 == 0) ? 4 : (p.C % 2 == 0 ? 2 : 1);
     else p.vw = (p.C % 2 == 0) ? 2 : 1;
     p.nct = (p.C + kColTile - 1) / kColTile;
+}
+
+// Row geometry (once per run): rows per reduction chunk, chunk and stencil
+// line-block offsets of every segment.  `sh.row` and `sh.dims` must be set.
+static void row_geometry(Plan &p, SegHost &sh)
+{
     // reductions: one wavefront per (row chunk, tile of 64 lanes); about 2048 of them
-    const int vwr = (p.vec_f32 && p.C % 2 == 0) ? 2 : 1;
-    const int nctr = (p.C + 64 * vwr - 1) / (64 * vwr);
+    const int vwr = (p.vec_f32 && p.wave_cols % 2 == 0) ? 2 : 1;
+    const int nctr = (p.wave_cols + 64 * vwr - 1) / (64 * vwr);
     int64_t target = (2048 + nctr - 1) / nctr;
     const int64_t maxchunks = (p.n + 15) / 16;
     if (target > maxchunks) target = maxchunks;
     if (target < 1) target = 1;
     p.rpc = (p.n + target - 1) / target;
-    p.nchunk = (int)((p.n + p.rpc - 1) / p.rpc);
+    sh.chunk.assign(p.nseg + 1, 0);
+    sh.tile.assign(p.nseg + 1, 0);
+    bool thin = false;
+    for (int b = 0; b < p.nseg; ++b) thin = thin || sh.dims[3 * b] < 4;
+    p.tx = thin ? 1 : 4;
+    p.ty = thin ? 8 : 4;
+    for (int b = 0; b < p.nseg; ++b) {
+        const int64_t nb = sh.row[b + 1] - sh.row[b];
+        sh.chunk[b + 1] = sh.chunk[b] + (nb + p.rpc - 1) / p.rpc;
+        const int64_t tiles = (int64_t)((sh.dims[3 * b] + p.tx - 1) / p.tx) *
+                              ((sh.dims[3 * b + 1] + p.ty - 1) / p.ty);
+        sh.tile[b + 1] = sh.tile[b] + tiles;
+    }
+    p.nchunk = (int)sh.chunk[p.nseg];
+    p.ntiles = sh.tile[p.nseg];
 }
 
 // ---- product form of the preconditioner polynomial ----
@@ -338,23 +354,63 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     default:
         return fail(ECNT_EINVAL, "unknown preconditioner kind %d", T->kind);
     }
-    geometry(p);
     if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && T->eval == ECNT_EVAL_AUTO)
         p.product = factorize(p) ? 1 : 0;
+    return ECNT_OK;
+}
+
+// Segment tables: nseg problems of ns[b] rows (grids dims[3b..3b+2], d2
+// contiguous) and shifts taus[b*S..]; then geometry and workspace size.
+static ecnt_status set_segments(Plan &p, SegHost &sh, int nseg, const int64_t *ns,
+                                const int32_t *dims, const double *taus)
+{
+    p.nseg = nseg;
+    sh.row.assign(nseg + 1, 0);
+    sh.dims.assign(3 * (size_t)nseg, 1);
+    sh.taus.assign((size_t)nseg * p.S, 0.0);
+    for (int b = 0; b < nseg; ++b) {
+        if (ns[b] < 1) return fail(ECNT_EINVAL, "problem %d has no rows", b);
+        if (p.k > ns[b]) return fail(ECNT_EINVAL, "k = %d exceeds the size of problem %d", p.k, b);
+        sh.row[b + 1] = sh.row[b] + ns[b];
+        int64_t prod = 1;
+        for (int a = 0; a < 3; ++a) {
+            const int32_t d = dims ? dims[3 * b + a] : (a == 2 ? (int32_t)ns[b] : 1);
+            if (d < 1) return fail(ECNT_EINVAL, "grid extents of problem %d must be >= 1", b);
+            sh.dims[3 * b + a] = d;
+            prod *= d;
+        }
+        if (prod != ns[b])
+            return fail(ECNT_EINVAL, "grid of problem %d (%lld points) does not match its %lld rows", b,
+                        (long long)prod, (long long)ns[b]);
+        for (int t = 0; t < p.S; ++t) {
+            const double tau = taus[(size_t)b * p.S + t];
+            if (!isfinite(tau)) return fail(ECNT_EINVAL, "shift %d of problem %d is not finite", t, b);
+            sh.taus[(size_t)b * p.S + t] = tau;
+        }
+    }
+    if (sh.row[nseg] != p.n) return fail(ECNT_EINVAL, "problem sizes do not add up to n");
+    col_geometry(p);
+    row_geometry(p, sh);
     plan_layout(p, nullptr);
     return ECNT_OK;
 }
 
-struct InitArgs {
-    double taus[kMaxShifts];
-    int S;
-};
-
-__global__ void k_init(InitArgs a, double *taus, int32_t *flags)
+// One problem: one segment, grid from the preconditioner (a single line otherwise).
+static ecnt_status single_segment(Plan &p, SegHost &sh, const double *taus)
 {
-    const int t = threadIdx.x;
-    if (t < a.S) taus[t] = a.taus[t];
-    if (t < 4) flags[t] = 0;
+    const int64_t n = p.n;
+    int32_t d[3] = {1, 1, (int32_t)n};
+    if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
+        d[0] = p.dims[0];
+        d[1] = p.dims[1];
+        d[2] = p.dims[2];
+    }
+    return set_segments(p, sh, 1, &n, d, taus);
+}
+
+__global__ void k_init(int32_t *flags)
+{
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0;
 }
 
 // M x by Clenshaw's recurrence (R of degree d), with x = xs .* X.
@@ -458,14 +514,10 @@ static void apply_M(const Plan &p, const void *X, const double *xs, void *t0, vo
 
 static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st);
 
-static void enqueue(const Plan &p, const ecnt_csr *A, const double *taus, const void *probes,
-                    ecnt_info *info, hipStream_t st)
+static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_info *info,
+                    hipStream_t st)
 {
-    InitArgs ia;
-    memset(&ia, 0, sizeof ia);
-    for (int s = 0; s < p.S; ++s) ia.taus[s] = taus[s];
-    ia.S = p.S;
-    k_init<<<1, 64, 0, st>>>(ia, p.taus, p.flags);
+    k_init<<<1, 64, 0, st>>>(p.flags);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
     if (p.prec_kind == ECNT_PREC_JACOBI) {
         Timed t(F_SETUP, csr_b + 8.0 * p.S * p.n, st);
@@ -475,16 +527,14 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const double *taus, const 
         Plan w = p;
         w.c_off = c_off;
         w.C = (p.Ct - c_off) < p.wave_cols ? (p.Ct - c_off) : p.wave_cols;
-        geometry(w);
-        w.s_out = p.s_out + c_off;
-        w.minabs = p.minabs + c_off;
-        w.kused = p.kused + c_off;
+        col_geometry(w);
         enqueue_wave(w, A, probes, st);
-        if (info && info->alpha)
+        // diagnostics of a single problem: alpha/beta of this wave into the caller's arrays
+        if (p.nseg == 1 && info && info->alpha)
             (void)hipMemcpy2DAsync(info->alpha + c_off, sizeof(double) * p.Ct, w.alpha,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k,
                                    hipMemcpyDeviceToDevice, st);
-        if (info && info->beta)
+        if (p.nseg == 1 && info && info->beta)
             (void)hipMemcpy2DAsync(info->beta + c_off, sizeof(double) * p.Ct, w.beta,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k + 1,
                                    hipMemcpyDeviceToDevice, st);
@@ -513,7 +563,7 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     for (int i = 1; i <= p.k; ++i) {
         void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
-        const double *xs = p.sig + (size_t)(i - 1) * p.C;
+        const double *xs = p.sig + (size_t)(i - 1) * p.nseg * p.C;
         if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
             // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
             void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * blk : p.tmp[2];
@@ -619,19 +669,42 @@ static ecnt_status check_common(const ecnt_csr *A, const void *probes, const ecn
     return ECNT_OK;
 }
 
+static ecnt_status upload_tables(const Plan &p, const SegHost &sh, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(p.seg_row, sh.row.data(), sizeof(int64_t) * (p.nseg + 1),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p.seg_chunk, sh.chunk.data(), sizeof(int64_t) * (p.nseg + 1),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p.seg_tile, sh.tile.data(), sizeof(int64_t) * (p.nseg + 1),
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p.seg_dims, sh.dims.data(), sizeof(int32_t) * 3 * p.nseg,
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p.seg_taus, sh.taus.data(), sizeof(double) * p.S * p.nseg,
+                           hipMemcpyHostToDevice, st);
+    // the host tables are locals of the caller: complete the copies before returning
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+    return ECNT_OK;
+}
+
+// Copy results (nseg * kResStride doubles) and flags back; synchronizes the stream.
 static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_info *info)
 {
     int32_t flags[4] = {0, 0, 0, 0};
-    hipError_t e = hipMemcpyAsync(res_host, p.result, sizeof(double) * (4 * kMaxShifts + 8),
+    hipError_t e = hipMemcpyAsync(res_host, p.result, sizeof(double) * kResStride * p.nseg,
                                   hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(flags, p.flags, sizeof flags, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && info) {
-        const size_t C = p.Ct;
+        const size_t NCt = (size_t)p.nseg * p.Ct;
         if (info->per_probe)
-            e = hipMemcpyAsync(info->per_probe, p.s_out, sizeof(double) * C, hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(info->per_probe, p.s_out, sizeof(double) * NCt, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess && info->k_used)
-            e = hipMemcpyAsync(info->k_used, p.kused, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, st);
+            e = hipMemcpyAsync(info->k_used, p.kused, sizeof(int32_t) * NCt, hipMemcpyDeviceToDevice, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
@@ -644,7 +717,8 @@ static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_
 // Restrictions of the differentiated form: FP64 Gauss rule with a smoothed
 // step, the Laplacian-polynomial preconditioner (M independent of V and tau),
 // one wave of columns, k <= 32.
-static ecnt_status grad_plan(Plan &p, int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *o)
+static ecnt_status grad_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, const ecnt_prec *T,
+                             const ecnt_opts *o, const double *taus)
 {
     ecnt_status rc = make_plan(p, n, m, 2, T, o);
     if (rc) return rc;
@@ -656,8 +730,14 @@ static ecnt_status grad_plan(Plan &p, int64_t n, int64_t m, const ecnt_prec *T, 
     if (o->k > kBasisChunk) return fail(ECNT_EUNSUPPORTED, "gradients need k <= %d", kBasisChunk);
     if (p.wave_cols != p.Ct) return fail(ECNT_EUNSUPPORTED, "gradients need a single column wave");
     p.grad = 1;
-    plan_layout(p, nullptr);
-    return ECNT_OK;
+    return single_segment(p, sh, taus);
+}
+
+static void begin_launches()
+{
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    t_prof = g_prof_on;
 }
 
 // mode: 0 count, 1 forward keeping backward state, 2 backward on kept state,
@@ -667,30 +747,70 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
                        size_t ws_bytes, void *stream, double *res_host, ecnt_info *info, Plan &p,
                        int mode = 0, double g_out = 0.0, double *dV = nullptr)
 {
-    ecnt_status rc = mode == 0 ? make_plan(p, A ? A->n : 0, m, S, T, o)
-                               : grad_plan(p, A ? A->n : 0, m, T, o);
+    SegHost sh;
+    ecnt_status rc;
+    if (mode == 0) {
+        rc = make_plan(p, A ? A->n : 0, m, S, T, o);
+        if (!rc) rc = single_segment(p, sh, taus);
+    } else {
+        rc = grad_plan(p, sh, A ? A->n : 0, m, T, o, taus);
+    }
     if (rc) return rc;
     if (mode >= 2 && !dV) return fail(ECNT_EINVAL, "dV is null");
     if (mode >= 1 && A && A->val_type != ECNT_F64)
         return fail(ECNT_EUNSUPPORTED, "gradients need FP64 matrix values");
     rc = check_common(A, probes, o, ws, p, ws_bytes);
     if (rc) return rc;
-    for (int s = 0; s < S; ++s)
-        if (!isfinite(taus[s])) return fail(ECNT_EINVAL, "shift %d is not finite", s);
     p.val_f32 = A->val_type == ECNT_F32;
     char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     plan_layout(p, base);
     hipStream_t st = (hipStream_t)stream;
-    (void)hipGetLastError();
-    {
-        std::lock_guard<std::mutex> g(g_prof_mu);
-        t_prof = g_prof_on;
-    }
-    if (mode != 2) enqueue(p, A, taus, probes, info, st);
+    rc = upload_tables(p, sh, st);
+    if (rc) return rc;
+    begin_launches();
+    if (mode != 2) enqueue(p, A, probes, info, st);
     if (mode >= 2) enqueue_backward(p, A, g_out, dV, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return finish(p, st, res_host, info);
+}
+
+// ---- batches of independent problems (block-diagonal A) ----
+static ecnt_status batch_plan(Plan &p, SegHost &sh, const ecnt_batch_item *items, int32_t nprob,
+                              int32_t nshift, int64_t m, const ecnt_prec *T, const ecnt_opts *o)
+{
+    if (!items || nprob < 1) return fail(ECNT_EINVAL, "need at least one problem");
+    if (nprob > (1 << 20)) return fail(ECNT_EUNSUPPORTED, "too many problems");
+    if (nshift < 1 || nshift > kMaxShifts) return fail(ECNT_EINVAL, "nshift must be in 1..%d", kMaxShifts);
+    int64_t n = 0;
+    std::vector<int64_t> ns(nprob);
+    std::vector<int32_t> dims(3 * (size_t)nprob);
+    std::vector<double> taus((size_t)nprob * (nshift > 0 ? nshift : 1));
+    for (int b = 0; b < nprob; ++b) {
+        ns[b] = items[b].n;
+        if (ns[b] < 1) return fail(ECNT_EINVAL, "problem %d has no rows", b);
+        n += ns[b];
+        if (!items[b].taus) return fail(ECNT_EINVAL, "shifts of problem %d are null", b);
+        for (int a = 0; a < 3; ++a)   // the grid matters to the stencil preconditioner only
+            dims[3 * b + a] = T && T->kind == ECNT_PREC_CHEB_LAPLACIAN
+                                  ? items[b].dims[a]
+                                  : (a == 2 ? (int32_t)(ns[b] < INT32_MAX ? ns[b] : INT32_MAX) : 1);
+        for (int t = 0; t < nshift; ++t) taus[(size_t)b * nshift + t] = items[b].taus[t];
+    }
+    if (!T) return fail(ECNT_EINVAL, "null preconditioner");
+    if (T->kind == ECNT_PREC_CHEB_LAPLACIAN && T->ndim != 3)
+        return fail(ECNT_EINVAL, "batches with the Laplacian preconditioner need prec.ndim = 3");
+    ecnt_prec Tb = *T;
+    if (Tb.kind == ECNT_PREC_CHEB_LAPLACIAN) {   // per-problem grids come from the items
+        Tb.ndim = 3;
+        Tb.dims[0] = 1;
+        Tb.dims[1] = 1;
+        Tb.dims[2] = (int32_t)(n < INT32_MAX ? n : INT32_MAX);
+    }
+    ecnt_status rc = make_plan(p, n, m, nshift, &Tb, o);
+    if (rc) return rc;
+    p.ndim = T->ndim;
+    return set_segments(p, sh, nprob, ns.data(), dims.data(), taus.data());
 }
 
 }  // namespace ecnt
@@ -703,7 +823,10 @@ size_t ecnt_workspace_bytes(int64_t n, int64_t m, int32_t nshift, const ecnt_pre
                             const ecnt_opts *opts)
 {
     Plan p;
+    SegHost sh;
     if (make_plan(p, n, m, nshift, T, opts) != ECNT_OK) return 0;
+    std::vector<double> taus((size_t)nshift, 0.0);   // values do not affect the size
+    if (single_segment(p, sh, taus.data()) != ECNT_OK) return 0;
     return p.bytes;
 }
 
@@ -717,7 +840,7 @@ ecnt_status ecnt_count(const ecnt_csr *A, const ecnt_prec *T, double xi, double 
     if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
     if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
     const double taus[2] = {xi, eta};
-    double res[4 * kMaxShifts + 8];
+    double res[kResStride];
     Plan p;
     ecnt_status rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p);
     if (rc) return rc;
@@ -739,7 +862,7 @@ ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const double *
     g_err.clear();
     if (!taus || !negcounts) return fail(ECNT_EINVAL, "taus/negcounts is null");
     if (nshift < 1 || nshift > kMaxShifts) return fail(ECNT_EINVAL, "nshift must be in 1..%d", kMaxShifts);
-    double res[4 * kMaxShifts + 8];
+    double res[kResStride];
     Plan p;
     ecnt_status rc = run(A, T, taus, nshift, probes, m, opts, ws, ws_bytes, stream, res, info, p);
     if (rc) return rc;
@@ -781,8 +904,108 @@ int32_t ecnt_profile_read(ecnt_kernel_stat *out, int32_t max)
 size_t ecnt_smooth_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *opts)
 {
     Plan p;
-    if (grad_plan(p, n, m, T, opts) != ECNT_OK) return 0;
+    SegHost sh;
+    const double taus[2] = {0.0, 1.0};
+    if (grad_plan(p, sh, n, m, T, opts, taus) != ECNT_OK) return 0;
     return p.bytes;
+}
+
+size_t ecnt_batch_workspace_bytes(const ecnt_batch_item *items, int32_t nprob, int32_t nshift,
+                                  int64_t m, const ecnt_prec *T, const ecnt_opts *opts)
+{
+    Plan p;
+    SegHost sh;
+    if (batch_plan(p, sh, items, nprob, nshift, m, T, opts) != ECNT_OK) return 0;
+    return p.bytes;
+}
+
+// prepare: validate, carve, upload the segment tables (synchronous)
+ecnt_status ecnt_batch_prepare(const ecnt_csr *A, const ecnt_prec *T, const ecnt_batch_item *items,
+                               int32_t nprob, int32_t nshift, const void *probes, int64_t m,
+                               const ecnt_opts *opts, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Plan p;
+    SegHost sh;
+    ecnt_status rc = batch_plan(p, sh, items, nprob, nshift, m, T, opts);
+    if (rc) return rc;
+    if (A && A->n != p.n) return fail(ECNT_EINVAL, "A has %lld rows, the problems %lld",
+                                      (long long)A->n, (long long)p.n);
+    rc = check_common(A, probes, opts, ws, p, ws_bytes);
+    if (rc) return rc;
+    char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    plan_layout(p, base);
+    return upload_tables(p, sh, (hipStream_t)stream);
+}
+
+// enqueue: kernel launches only (no host synchronization, no copies): may be
+// captured into a hipGraph and replayed; results stay in the workspace.
+ecnt_status ecnt_batch_enqueue(const ecnt_csr *A, const ecnt_prec *T, const ecnt_batch_item *items,
+                               int32_t nprob, int32_t nshift, const void *probes, int64_t m,
+                               const ecnt_opts *opts, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Plan p;
+    SegHost sh;
+    ecnt_status rc = batch_plan(p, sh, items, nprob, nshift, m, T, opts);
+    if (rc) return rc;
+    rc = check_common(A, probes, opts, ws, p, ws_bytes);
+    if (rc) return rc;
+    p.val_f32 = A->val_type == ECNT_F32;
+    char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    plan_layout(p, base);
+    begin_launches();
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+        t_prof = false;   // no timing events inside a captured graph
+    enqueue(p, A, probes, nullptr, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return ECNT_OK;
+}
+
+// results: copy the per-problem results back (synchronizes the stream)
+ecnt_status ecnt_batch_results(const ecnt_batch_item *items, int32_t nprob, int32_t nshift,
+                               int64_t m, const ecnt_prec *T, const ecnt_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream, double *negcounts, double *counts,
+                               double *variances, ecnt_info *info)
+{
+    g_err.clear();
+    Plan p;
+    SegHost sh;
+    ecnt_status rc = batch_plan(p, sh, items, nprob, nshift, m, T, opts);
+    if (rc) return rc;
+    if (!ws || ws_bytes < p.bytes) return fail(ECNT_EWORKSPACE, "workspace missing or too small");
+    if (!negcounts) return fail(ECNT_EINVAL, "negcounts is null");
+    char *base = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    plan_layout(p, base);
+    std::vector<double> res((size_t)kResStride * nprob);
+    rc = finish(p, (hipStream_t)stream, res.data(), info);
+    if (rc) return rc;
+    const int S = nshift;
+    for (int b = 0; b < nprob; ++b) {
+        const double *r = res.data() + (size_t)b * kResStride;
+        for (int s = 0; s < S; ++s) negcounts[(size_t)b * S + s] = r[s];
+        for (int t = 0; t + 1 < S; ++t) {
+            if (counts) counts[(size_t)b * (S - 1) + t] = r[S + t];
+            if (variances) variances[(size_t)b * (S - 1) + t] = r[2 * S - 1 + t];
+        }
+    }
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_count_batched(const ecnt_csr *A, const ecnt_prec *T, const ecnt_batch_item *items,
+                               int32_t nprob, int32_t nshift, const void *probes, int64_t m,
+                               const ecnt_opts *opts, void *ws, size_t ws_bytes, void *stream,
+                               double *negcounts, double *counts, double *variances,
+                               ecnt_info *info)
+{
+    ecnt_status rc = ecnt_batch_prepare(A, T, items, nprob, nshift, probes, m, opts, ws, ws_bytes, stream);
+    if (rc) return rc;
+    rc = ecnt_batch_enqueue(A, T, items, nprob, nshift, probes, m, opts, ws, ws_bytes, stream);
+    if (rc) return rc;
+    return ecnt_batch_results(items, nprob, nshift, m, T, opts, ws, ws_bytes, stream, negcounts,
+                              counts, variances, info);
 }
 
 static ecnt_status smooth_common_args(double xi, double eta)
@@ -802,7 +1025,7 @@ ecnt_status ecnt_smooth_fwd(const ecnt_csr *A, const ecnt_prec *T, double xi, do
     ecnt_status rc = smooth_common_args(xi, eta);
     if (rc) return rc;
     const double taus[2] = {xi, eta};
-    double res[4 * kMaxShifts + 8];
+    double res[kResStride];
     Plan p;
     rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p, 1);
     if (rc) return rc;
@@ -829,7 +1052,7 @@ ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, double xi, do
     ecnt_status rc = smooth_common_args(xi, eta);
     if (rc) return rc;
     const double taus[2] = {xi, eta};
-    double res[4 * kMaxShifts + 8];
+    double res[kResStride];
     Plan p;
     rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, nullptr, p,
              ckpt == ECNT_CKPT_KEEP ? 2 : 3, g_est, dV);

@@ -8,10 +8,19 @@
 //   l = 0, 1/beta_{l+1} afterwards, 0 once the column has stopped) turns it
 //   into q_{l+1}.  Slot i first receives C q_i (operator output) and is then
 //   overwritten in place by the reorthogonalized residual.
+//
+// Segments: a batch of independent problems is stored block-diagonally, the
+// rows of problem b (a "segment") at [seg_row[b], seg_row[b+1]).  Every
+// column-wise scalar (nu, alpha, beta, sig, kappa, ...) is kept per
+// (segment, column), "virtual column" vc = b*C + c, and every reduction runs
+// over the rows of one segment only (row chunks never straddle segments), so
+// the batch is exactly nseg independent runs.  A single problem is nseg = 1.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
 
 namespace ecnt {
 
@@ -46,8 +55,17 @@ struct Plan {
     // geometry
     int vw = 1;           // columns per lane in the row-sweep kernels
     int nct = 0;          // column tiles of 64 (setup kernel)
-    int nchunk = 0;       // row chunks of the two-phase column reductions
+    int nchunk = 0;       // row chunks of the two-phase column reductions (all segments)
     int64_t rpc = 0;      // rows per chunk
+    // segments
+    int nseg = 1;
+    int tx = 4, ty = 4;   // stencil line-block shape
+    int64_t ntiles = 0;   // stencil line blocks over all segments
+    int64_t *seg_row = nullptr;    // device, nseg+1
+    int64_t *seg_chunk = nullptr;  // device, nseg+1
+    int64_t *seg_tile = nullptr;   // device, nseg+1
+    int32_t *seg_dims = nullptr;   // device, 3*nseg (d0, d1, d2; d2 contiguous)
+    double *seg_taus = nullptr;    // device, nseg*S
     // workspace carve (device pointers)
     void *basis = nullptr;     // (k+1) * n * C elements
     void *tmp[3] = {nullptr, nullptr, nullptr};
@@ -59,7 +77,7 @@ struct Plan {
     double *kappa = nullptr;   // C                 (beta_i * sig_{i-2})
     double *runmax = nullptr;  // C
     double *nu = nullptr;      // C
-    double *taus = nullptr;    // S
+
     double *s_out = nullptr;   // Ct  per-column quadrature s_c (wave views are offset)
     double *minabs = nullptr;  // Ct
     double *jac = nullptr;     // S * n (Jacobi scaling)
@@ -90,6 +108,14 @@ struct Plan {
 };
 
 constexpr int kPartRows = 64;      // rows per chunk of the partial-sum buffer
+constexpr int kResStride = 4 * kMaxShifts + 8;   // result doubles per segment
+
+// Host copy of the segment tables.
+struct SegHost {
+    std::vector<int64_t> row, chunk, tile;
+    std::vector<int32_t> dims;
+    std::vector<double> taus;
+};
 
 size_t plan_layout(Plan &p, char *base);   // base == nullptr: size only
 

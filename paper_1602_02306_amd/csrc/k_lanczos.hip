@@ -23,10 +23,24 @@
 namespace ecnt {
 
 // ---- probe setup: slot 0 = v (for every shift), partial |v|^2 ----
+// Rows of chunk `chunk`: chunks are numbered segment by segment and never
+// straddle a segment.
+__device__ __forceinline__ void chunk_rows(const int64_t *__restrict__ seg_row,
+                                           const int64_t *__restrict__ seg_chunk, int nseg,
+                                           int64_t rpc, int64_t chunk, int &seg, int64_t &r0,
+                                           int64_t &r1)
+{
+    seg = find_seg(seg_chunk, nseg, chunk);
+    r0 = seg_row[seg] + (chunk - seg_chunk[seg]) * rpc;
+    r1 = min(seg_row[seg + 1], r0 + rpc);
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int c_off, int nct,
-                                               int64_t rpc, const T *__restrict__ V,
-                                               T *__restrict__ slot0, double *__restrict__ part)
+__global__ __launch_bounds__(256) void k_setup(int C, int m, int c_off, int nct, int64_t rpc,
+                                               int nseg, const int64_t *__restrict__ seg_row,
+                                               const int64_t *__restrict__ seg_chunk,
+                                               const T *__restrict__ V, T *__restrict__ slot0,
+                                               double *__restrict__ part)
 {
     __shared__ double red[4][kColTile];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -34,7 +48,9 @@ __global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int c_of
     const int64_t chunk = L / nct;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int c = ct * kColTile + lane;
-    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    int seg;
+    int64_t r0, r1;
+    chunk_rows(seg_row, seg_chunk, nseg, rpc, chunk, seg, r0, r1);
     double acc = 0.0;
     if (c < C) {
         const int j = (c_off + c) % m;
@@ -52,33 +68,39 @@ __global__ __launch_bounds__(256) void k_setup(int64_t n, int C, int m, int c_of
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
-__global__ void k_setup_fin(int C, int k, int nchunk, const double *__restrict__ part,
-                            double *__restrict__ nu, double *__restrict__ sig,
-                            double *__restrict__ kappa, double *__restrict__ runmax,
-                            double *__restrict__ beta, int32_t *__restrict__ active,
-                            int32_t *__restrict__ kused)
+// Per virtual column vc = seg*C + c.  kused is global: kused[seg*ku_ld + ku_off + c].
+__global__ void k_setup_fin(int C, int nseg, int k, const int64_t *__restrict__ seg_chunk,
+                            const double *__restrict__ part, double *__restrict__ nu,
+                            double *__restrict__ sig, double *__restrict__ kappa,
+                            double *__restrict__ runmax, double *__restrict__ beta,
+                            int32_t *__restrict__ active, int32_t *__restrict__ kused, int ku_ld,
+                            int ku_off)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (vc >= nseg * C) return;
+    const int seg = vc / C, c = vc - seg * C;
     double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)ch * kPartRows * C + c];
-    nu[c] = s;
+    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
+        s += part[(size_t)ch * kPartRows * C + c];
+    nu[vc] = s;
     const bool ok = s > 0.0;
-    sig[c] = ok ? 1.0 / sqrt(s) : 0.0;
-    kappa[c] = 0.0;
-    runmax[c] = 0.0;
-    beta[c] = 0.0;   // beta_1 = 0 (Algorithm 1, first step)
-    active[c] = ok ? 1 : 0;
-    kused[c] = ok ? k : 0;
+    sig[vc] = ok ? 1.0 / sqrt(s) : 0.0;
+    kappa[vc] = 0.0;
+    runmax[vc] = 0.0;
+    beta[vc] = 0.0;   // beta_1 = 0 (Algorithm 1, first step)
+    active[vc] = ok ? 1 : 0;
+    kused[(size_t)seg * ku_ld + ku_off + c] = ok ? k : 0;
 }
 
 // ---- reorthogonalization dots: part[chunk][l][c] = sum_rows slot_{l0+l} * w ----
 // One wavefront per (row chunk, column tile); NB is the exact number of basis
 // vectors of the launch, so all NB + 2 row loads are issued back to back.
 template <typename T, int NB, int VW>
-__global__ __launch_bounds__(64) void k_dots(int64_t n, int C, int nct, int64_t rpc,
+__global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int nseg,
+                                             const int64_t *__restrict__ seg_row,
+                                             const int64_t *__restrict__ seg_chunk,
                                              const T *__restrict__ basis, size_t ss, int slot_y,
-                                             int l0, int slot_m, const double *__restrict__ kappa,
+                                             int l0, int slot_m, const double *__restrict__ kappa_all,
                                              double *__restrict__ part)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -86,7 +108,10 @@ __global__ __launch_bounds__(64) void k_dots(int64_t n, int C, int nct, int64_t 
     const int64_t chunk = L / nct;
     const int c0 = (ct * 64 + (int)threadIdx.x) * VW;
     if (c0 >= C) return;
-    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    int seg;
+    int64_t r0, r1;
+    chunk_rows(seg_row, seg_chunk, nseg, rpc, chunk, seg, r0, r1);
+    const double *kappa = kappa_all + (size_t)seg * C;
     double acc[NB][VW];
 #pragma unroll
     for (int l = 0; l < NB; ++l)
@@ -122,30 +147,37 @@ __global__ __launch_bounds__(64) void k_dots(int64_t n, int C, int nct, int64_t 
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
-__global__ void k_dots_fin(int C, int nchunk, int step, int l0, int nb, int k,
-                           const double *__restrict__ part, const double *__restrict__ sig,
-                           const int32_t *__restrict__ active, double *__restrict__ cf,
-                           double *__restrict__ alpha, double *__restrict__ gall)
+// One thread per (l, vc); arrays indexed [row][nseg*C].
+__global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
+                           const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
+                           const double *__restrict__ sig, const int32_t *__restrict__ active,
+                           double *__restrict__ cf, double *__restrict__ alpha,
+                           double *__restrict__ gall)
 {
+    const int NC = nseg * C;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nb * C) return;
-    const int l = idx / C, c = idx % C;
+    if (idx >= nb * NC) return;
+    const int l = idx / NC, vc = idx - l * NC;
+    const int seg = vc / C, c = vc - seg * C;
     double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[((size_t)ch * kPartRows + l) * C + c];
-    const double sg = sig[(size_t)(l0 + l) * C + c];
+    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
+        s += part[((size_t)ch * kPartRows + l) * C + c];
+    const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = s * sg;
-    cf[(size_t)(l0 + l) * C + c] = g * sg;
-    if (l0 + l == step - 1) alpha[(size_t)(step - 1) * C + c] = active[c] ? g : 0.0;
-    if (gall) gall[((size_t)(step - 1) * k + l0 + l) * C + c] = g;   // kept for the backward
+    cf[(size_t)(l0 + l) * NC + vc] = g * sg;
+    if (l0 + l == step - 1) alpha[(size_t)(step - 1) * NC + vc] = active[vc] ? g : 0.0;
+    if (gall) gall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = g;   // kept for the backward
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
 // slot_w; the last chunk also writes partial |w|^2 into part[chunk][0][c]
 // (of the value as stored, i.e. after rounding to T).
 template <typename T, int NB, int VW>
-__global__ __launch_bounds__(64) void k_update(int64_t n, int C, int nct, int64_t rpc,
+__global__ __launch_bounds__(64) void k_update(int C, int nct, int64_t rpc, int nseg,
+                                               const int64_t *__restrict__ seg_row,
+                                               const int64_t *__restrict__ seg_chunk,
                                                T *__restrict__ basis, size_t ss, int slot_w, int l0,
-                                               int slot_m, const double *__restrict__ kappa,
+                                               int slot_m, const double *__restrict__ kappa_all,
                                                const double *__restrict__ cf, int last,
                                                double *__restrict__ part)
 {
@@ -154,14 +186,17 @@ __global__ __launch_bounds__(64) void k_update(int64_t n, int C, int nct, int64_
     const int64_t chunk = L / nct;
     const int c0 = (ct * 64 + (int)threadIdx.x) * VW;
     if (c0 >= C) return;
-    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
+    int seg;
+    int64_t r0, r1;
+    chunk_rows(seg_row, seg_chunk, nseg, rpc, chunk, seg, r0, r1);
+    const size_t NC = (size_t)nseg * C, vc0 = (size_t)seg * C + c0;
     double co[NB][VW], kap[VW], nrm[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) {
-        kap[v] = slot_m >= 0 ? kappa[c0 + v] : 0.0;
+        kap[v] = slot_m >= 0 ? kappa_all[vc0 + v] : 0.0;
         nrm[v] = 0.0;
 #pragma unroll
-        for (int l = 0; l < NB; ++l) co[l][v] = cf[(size_t)(l0 + l) * C + c0 + v];
+        for (int l = 0; l < NB; ++l) co[l][v] = cf[(size_t)(l0 + l) * NC + vc0 + v];
     }
     T *W = basis + (size_t)slot_w * ss;
     const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
@@ -192,35 +227,41 @@ __global__ __launch_bounds__(64) void k_update(int64_t n, int C, int nct, int64_
 }
 
 // beta_{i+1} = |w|, breakdown test, next scales.
-__global__ void k_norm_fin(int C, int nchunk, int step, double eps_vec,
-                           const double *__restrict__ part, const double *__restrict__ alpha,
-                           double *__restrict__ beta, double *__restrict__ sig,
-                           double *__restrict__ kappa, double *__restrict__ runmax,
-                           int32_t *__restrict__ active, int32_t *__restrict__ kused)
+__global__ void k_norm_fin(int C, int nseg, int step, double eps_vec,
+                           const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
+                           const double *__restrict__ alpha, double *__restrict__ beta,
+                           double *__restrict__ sig, double *__restrict__ kappa,
+                           double *__restrict__ runmax, int32_t *__restrict__ active,
+                           int32_t *__restrict__ kused, int ku_ld, int ku_off)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
+    const int NC = nseg * C;
+    if (vc >= NC) return;
+    const int seg = vc / C, cc = vc - seg * C;
     const int i = step;
     double ss = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) ss += part[(size_t)ch * kPartRows * C + c];
+    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
+        ss += part[(size_t)ch * kPartRows * C + cc];
+    const int c = vc;   // per-virtual-column arrays below
+    const size_t C_ = NC;
     const double b = sqrt(ss);
-    double rm = fmax(runmax[c], fabs(alpha[(size_t)(i - 1) * C + c]));
-    if (i > 1) rm = fmax(rm, beta[(size_t)(i - 1) * C + c]);
+    double rm = fmax(runmax[c], fabs(alpha[(size_t)(i - 1) * C_ + c]));
+    if (i > 1) rm = fmax(rm, beta[(size_t)(i - 1) * C_ + c]);
     runmax[c] = rm;
     if (active[c]) {
-        beta[(size_t)i * C + c] = b;
+        beta[(size_t)i * C_ + c] = b;
         if (b <= 1e3 * eps_vec * rm) {
             active[c] = 0;
-            kused[c] = i;
-            sig[(size_t)i * C + c] = 0.0;
+            kused[(size_t)seg * ku_ld + ku_off + cc] = i;
+            sig[(size_t)i * C_ + c] = 0.0;
             kappa[c] = 0.0;
         } else {
-            sig[(size_t)i * C + c] = 1.0 / b;
-            kappa[c] = b * sig[(size_t)(i - 1) * C + c];
+            sig[(size_t)i * C_ + c] = 1.0 / b;
+            kappa[c] = b * sig[(size_t)(i - 1) * C_ + c];
         }
     } else {
-        beta[(size_t)i * C + c] = 0.0;
-        sig[(size_t)i * C + c] = 0.0;
+        beta[(size_t)i * C_ + c] = 0.0;
+        sig[(size_t)i * C_ + c] = 0.0;
         kappa[c] = 0.0;
     }
 }
@@ -233,18 +274,21 @@ static inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C; }
 void launch_setup(const Plan &p, const void *probes, hipStream_t st)
 {
     if (p.vec_f32)
-        k_setup<float><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.c_off, p.nct, p.rpc,
-                                                    (const float *)probes, (float *)p.basis, p.part);
+        k_setup<float><<<red_grid(p), 256, 0, st>>>(p.C, p.m, p.c_off, p.nct, p.rpc, p.nseg,
+                                                    p.seg_row, p.seg_chunk, (const float *)probes,
+                                                    (float *)p.basis, p.part);
     else
-        k_setup<double><<<red_grid(p), 256, 0, st>>>(p.n, p.C, p.m, p.c_off, p.nct, p.rpc,
-                                                     (const double *)probes, (double *)p.basis,
-                                                     p.part);
+        k_setup<double><<<red_grid(p), 256, 0, st>>>(p.C, p.m, p.c_off, p.nct, p.rpc, p.nseg,
+                                                     p.seg_row, p.seg_chunk, (const double *)probes,
+                                                     (double *)p.basis, p.part);
 }
 
 void launch_setup_fin(const Plan &p, hipStream_t st)
 {
-    k_setup_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.k, p.nchunk, p.part, p.nu, p.sig,
-                                                   p.kappa, p.runmax, p.beta, p.active, p.kused);
+    const int NC = p.nseg * p.C;
+    k_setup_fin<<<(NC + 255) / 256, 256, 0, st>>>(p.C, p.nseg, p.k, p.seg_chunk, p.part, p.nu, p.sig,
+                                                  p.kappa, p.runmax, p.beta, p.active, p.kused,
+                                                  p.Ct, p.c_off);
 }
 
 template <typename T, int NB, int VW>
@@ -252,8 +296,8 @@ static void dots_t(const Plan &p, int step, int l0, hipStream_t st)
 {
     const int nct = (p.C + 64 * VW - 1) / (64 * VW);
     k_dots<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
-        p.n, p.C, nct, p.rpc, (const T *)p.basis, slot_elems(p), step, l0,
-        step >= 2 ? step - 2 : -1, p.kappa, p.part);
+        p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk, (const T *)p.basis, slot_elems(p), step,
+        l0, step >= 2 ? step - 2 : -1, p.kappa, p.part);
 }
 
 template <typename T, int NB, int VW>
@@ -261,7 +305,7 @@ static void update_t(const Plan &p, int step, int l0, bool first, bool last, hip
 {
     const int nct = (p.C + 64 * VW - 1) / (64 * VW);
     k_update<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
-        p.n, p.C, nct, p.rpc, (T *)p.basis, slot_elems(p), step, l0,
+        p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk, (T *)p.basis, slot_elems(p), step, l0,
         (first && step >= 2) ? step - 2 : -1, p.kappa, p.cf, last ? 1 : 0, p.part);
 }
 
@@ -318,9 +362,9 @@ void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
 
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
 {
-    const int tot = nb * p.C;
-    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, l0, nb, p.k, p.part, p.sig,
-                                                  p.active, p.cf, p.alpha, p.g_gall);
+    const int tot = nb * p.nseg * p.C;
+    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part,
+                                                  p.sig, p.active, p.cf, p.alpha, p.g_gall);
 }
 
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
@@ -336,9 +380,10 @@ void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool las
 void launch_norm_fin(const Plan &p, int step, hipStream_t st)
 {
     const double eps = p.vec_f32 ? (double)FLT_EPSILON : DBL_EPSILON;
-    k_norm_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, step, eps, p.part, p.alpha,
-                                                  p.beta, p.sig, p.kappa, p.runmax, p.active,
-                                                  p.kused);
+    const int NC = p.nseg * p.C;
+    k_norm_fin<<<(NC + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, eps, p.seg_chunk, p.part, p.alpha,
+                                                 p.beta, p.sig, p.kappa, p.runmax, p.active, p.kused,
+                                                 p.Ct, p.c_off);
 }
 
 }  // namespace ecnt

@@ -14,14 +14,17 @@ namespace ecnt {
 
 // |a_rr - tau_s|^(-1/2) for the Jacobi preconditioner, per shift.
 template <typename VT>
-__global__ __launch_bounds__(256) void k_jacobi_diag(int64_t n, int S, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(256) void k_jacobi_diag(int64_t n, int S, int nseg,
+                                                     const int64_t *__restrict__ seg_row,
+                                                     const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci,
                                                      const VT *__restrict__ val,
-                                                     const double *__restrict__ taus,
+                                                     const double *__restrict__ seg_taus,
                                                      double *__restrict__ jac, int32_t *flags)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
+    const double *taus = seg_taus + (size_t)find_seg(seg_row, nseg, r) * S;
     double arr = 0.0;
     for (int p = rp[r]; p < rp[r + 1]; ++p)
         if (ci[p] == r) arr = static_cast<double>(val[p]);
@@ -37,13 +40,14 @@ __global__ __launch_bounds__(256) void k_jacobi_diag(int64_t n, int S, const int
 // One wavefront per row; the row's nonzeros are taken four at a time with
 // clamped indices so that four row segments are loaded together.
 template <typename T, typename VT, bool JAC, int VW>
-__global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_off, int ncg,
+__global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_off, int ncg, int S,
+                                                int nseg, const int64_t *__restrict__ seg_row,
                                                 const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
                                                 const VT *__restrict__ val, const T *__restrict__ x,
                                                 const double *__restrict__ xs,
                                                 const double *__restrict__ jac,
-                                                const double *__restrict__ taus, T *__restrict__ y)
+                                                const double *__restrict__ seg_taus, T *__restrict__ y)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int cg = (int)(L % ncg);
@@ -51,13 +55,15 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
     const int lane = threadIdx.x & 63;
     const int c0 = (cg * 64 + lane) * VW;
     if (r >= n || c0 >= C) return;
+    const int seg = find_seg(seg_row, nseg, r);
+    const double *taus = seg_taus + (size_t)seg * S;
     double tau[VW], xsc[VW];
     const double *js[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) {
         const int s = (c_off + c0 + v) / m;
         tau[v] = taus[s];
-        xsc[v] = xs ? xs[c0 + v] : 1.0;
+        xsc[v] = xs ? xs[(size_t)seg * C + c0 + v] : 1.0;
         js[v] = JAC ? jac + (size_t)s * n : nullptr;
     }
     const int p0 = rp[r], p1 = rp[r + 1];
@@ -113,9 +119,12 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
 // grid (ragged blocks, Dirichlet boundary) are loaded from a clamped address
 // with weight 0, so every load of a z step is issued together.
 template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
-__global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int d0, int d1, int d2, int nty,
-                                                 int ntiles, const T *__restrict__ X,
-                                                 const double *__restrict__ xs, double cx,
+__global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
+                                                 const int64_t *__restrict__ seg_row,
+                                                 const int64_t *__restrict__ seg_tile,
+                                                 const int32_t *__restrict__ seg_dims,
+                                                 int64_t ntiles, const T *__restrict__ X,
+                                                 const double *__restrict__ xs_all, double cx,
                                                  const T *__restrict__ IN, int in_is_x, double cbd,
                                                  double cbo, const T *__restrict__ Z, double cz,
                                                  T *__restrict__ out)
@@ -123,15 +132,21 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int d0, int d1,
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t gw = L * 4 + uniform(threadIdx.x >> 6);
     const int cg = (int)(gw % ncg);
-    const int tile = (int)(gw / ncg);
+    const int64_t tile = gw / ncg;
     const int lane = threadIdx.x & 63;
     const int c0 = (cg * 64 + lane) * VW;
     if (tile >= ntiles || c0 >= C) return;
-    const int x0 = (tile / nty) * TX, y0 = (tile % nty) * TY;
+    // the line block's segment (problem) and its grid
+    const int seg = find_seg(seg_tile, nseg, tile);
+    const int d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int nty = (d1 + TY - 1) / TY;
+    const int lt = (int)(tile - seg_tile[seg]);
+    const int x0 = (lt / nty) * TX, y0 = (lt % nty) * TY;
+    const double *xs = xs_all ? xs_all + (size_t)seg * C : nullptr;
     const size_t zs = (size_t)C;                       // element stride of z
     const size_t ys = (size_t)d2 * C;                  // of y
     const size_t xs_ = (size_t)d1 * d2 * C;            // of x
-    const size_t base = (size_t)x0 * xs_ + (size_t)y0 * ys + c0;
+    const size_t base = (size_t)seg_row[seg] * C + (size_t)x0 * xs_ + (size_t)y0 * ys + c0;
     // tile lines and boundary lines: offset from `base` (clamped) and weight
     size_t off[TX][TY];
     double wt[TX][TY];
@@ -258,11 +273,11 @@ void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *co
 {
     dim3 grid((unsigned)((p.n + 255) / 256));
     if (p.val_f32)
-        k_jacobi_diag<float><<<grid, 256, 0, st>>>(p.n, p.S, row_ptr, col_idx, (const float *)val,
-                                                   p.taus, p.jac, p.flags);
+        k_jacobi_diag<float><<<grid, 256, 0, st>>>(p.n, p.S, p.nseg, p.seg_row, row_ptr, col_idx,
+                                                   (const float *)val, p.seg_taus, p.jac, p.flags);
     else
-        k_jacobi_diag<double><<<grid, 256, 0, st>>>(p.n, p.S, row_ptr, col_idx, (const double *)val,
-                                                    p.taus, p.jac, p.flags);
+        k_jacobi_diag<double><<<grid, 256, 0, st>>>(p.n, p.S, p.nseg, p.seg_row, row_ptr, col_idx,
+                                                    (const double *)val, p.seg_taus, p.jac, p.flags);
 }
 
 template <typename T, typename VT, int VW>
@@ -272,11 +287,13 @@ static void csr_op_t(const Plan &p, const int32_t *rp, const int32_t *ci, const 
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
     dim3 grid((unsigned)(((p.n + 3) / 4) * ncg));
     if (jac)
-        k_csr_op<T, VT, true, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, rp, ci, (const VT *)val,
-                                                        (const T *)x, xs, jac, p.taus, (T *)y);
+        k_csr_op<T, VT, true, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg,
+                                                        p.seg_row, rp, ci, (const VT *)val,
+                                                        (const T *)x, xs, jac, p.seg_taus, (T *)y);
     else
-        k_csr_op<T, VT, false, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, rp, ci, (const VT *)val,
-                                                         (const T *)x, xs, nullptr, p.taus, (T *)y);
+        k_csr_op<T, VT, false, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg,
+                                                         p.seg_row, rp, ci, (const VT *)val,
+                                                         (const T *)x, xs, nullptr, p.seg_taus, (T *)y);
 }
 
 template <typename T, typename VT>
@@ -311,12 +328,10 @@ static void stencil_t(const Plan &p, const void *X, const double *xs, double cx,
                       hipStream_t st)
 {
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
-    const int ntx = (p.dims[0] + TX - 1) / TX, nty = (p.dims[1] + TY - 1) / TY;
-    const int ntiles = ntx * nty;
-    const int64_t waves = (int64_t)ntiles * ncg;
+    const int64_t waves = p.ntiles * ncg;
     dim3 grid((unsigned)((waves + 3) / 4));
     k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ><<<grid, 256, 0, st>>>(
-        p.C, ncg, p.dims[0], p.dims[1], p.dims[2], nty, ntiles, (const T *)X, xs, cx,
+        p.C, ncg, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles, (const T *)X, xs, cx,
         (const T *)IN, in_is_x ? 1 : 0, cbd, cbo, (const T *)Z, cz, (T *)out);
 }
 
@@ -342,7 +357,7 @@ static void stencil_shape(const Plan &p, const void *X, const double *xs, double
                           bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
                           hipStream_t st)
 {
-    if (p.dims[0] >= 4) stencil_flags<T, VW, 4, 4>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
+    if (p.tx == 4) stencil_flags<T, VW, 4, 4>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
     else stencil_flags<T, VW, 1, 8>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
 }
 

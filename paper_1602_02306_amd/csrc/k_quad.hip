@@ -29,31 +29,38 @@ __device__ __forceinline__ double step_fn(double th, double w)
     return th < 0.0 ? 1.0 : 0.0;
 }
 
+// One lane per virtual column vc = seg*C + c (alpha, beta, nu indexed [row][NC]);
+// kused, s_out and minabs are global: [seg*ld + off + c].
 template <int KMAX>
-__global__ __launch_bounds__(64) void k_tridiag(int C, int k, int rule, double smooth_w,
+__global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, int k, int rule,
+                                                double smooth_w,
                                                 const double *__restrict__ alpha,
                                                 const double *__restrict__ beta,
-                                                const int32_t *__restrict__ kused,
+                                                const int32_t *__restrict__ kused_all,
                                                 const double *__restrict__ nu,
-                                                double *__restrict__ s_out,
-                                                double *__restrict__ minabs,
+                                                double *__restrict__ s_all,
+                                                double *__restrict__ minabs_all,
                                                 int32_t *__restrict__ flags)
 {
     constexpr int LN = QuadGeom<KMAX>::lanes;
     __shared__ double lds[3 * KMAX * LN];
     const int lane = threadIdx.x;
-    const int c = blockIdx.x * LN + lane;
-    if (c >= C) return;
+    const int vc = blockIdx.x * LN + lane;
+    if (vc >= NC) return;
+    const int seg = vc / C;
+    const size_t gidx = (size_t)seg * ld + off + (vc - seg * C);
+    const int c = vc;
+    C = NC;   // alpha, beta, nu below are indexed [row][NC] by the virtual column
     double *a = lds + lane;
     double *b = lds + KMAX * LN + lane;
     double *z = lds + 2 * KMAX * LN + lane;
 #define A_(i) a[(i) * LN]
 #define B_(i) b[(i) * LN]
 #define Z_(i) z[(i) * LN]
-    const int ku = kused[c];
+    const int ku = kused_all[gidx];
     if (ku < 1) {
-        s_out[c] = 0.0;
-        minabs[c] = INFINITY;
+        s_all[gidx] = 0.0;
+        minabs_all[gidx] = INFINITY;
         return;
     }
     int N;
@@ -131,8 +138,8 @@ __global__ __launch_bounds__(64) void k_tridiag(int C, int k, int rule, double s
         s += zz * zz * step_fn(th, smooth_w);
         mn = fmin(mn, fabs(th));
     }
-    s_out[c] = nu[c] * s;
-    minabs[c] = mn;
+    s_all[gidx] = nu[c] * s;
+    minabs_all[gidx] = mn;
     if (failed) atomicOr(&flags[1], 1);
 #undef A_
 #undef B_
@@ -156,11 +163,15 @@ __device__ double block_sum(double v, double *sh)
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__restrict__ s_out,
-                                                const double *__restrict__ minabs,
-                                                double *__restrict__ res)
+// One workgroup per segment (problem): s_out, minabs at seg*S*m, results at seg*kResStride.
+__global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__restrict__ s_all,
+                                                const double *__restrict__ minabs_all,
+                                                double *__restrict__ res_all)
 {
     __shared__ double sh[256];
+    const double *s_out = s_all + (size_t)blockIdx.x * S * m;
+    const double *minabs = minabs_all + (size_t)blockIdx.x * S * m;
+    double *res = res_all + (size_t)blockIdx.x * kResStride;
     for (int s = 0; s < S; ++s) {
         double acc = 0.0;
         for (int j = threadIdx.x; j < m; j += 256) acc += s_out[(size_t)s * m + j];
@@ -198,9 +209,10 @@ template <int KMAX>
 static void tridiag_t(const Plan &p, hipStream_t st)
 {
     constexpr int LN = QuadGeom<KMAX>::lanes;
-    const int blocks = (p.C + LN - 1) / LN;
-    k_tridiag<KMAX><<<blocks, LN, 0, st>>>(p.C, p.k, p.rule, p.smooth_w, p.alpha, p.beta, p.kused,
-                                           p.nu, p.s_out, p.minabs, p.flags);
+    const int NC = p.nseg * p.C;
+    const int blocks = (NC + LN - 1) / LN;
+    k_tridiag<KMAX><<<blocks, LN, 0, st>>>(NC, p.C, p.Ct, p.c_off, p.k, p.rule, p.smooth_w, p.alpha,
+                                           p.beta, p.kused, p.nu, p.s_out, p.minabs, p.flags);
 }
 
 void launch_tridiag(const Plan &p, hipStream_t st)
@@ -215,7 +227,7 @@ void launch_tridiag(const Plan &p, hipStream_t st)
 
 void launch_reduce(const Plan &p, hipStream_t st)
 {
-    k_reduce<<<1, 256, 0, st>>>(p.S, p.m, p.s_out, p.minabs, p.result);
+    k_reduce<<<p.nseg, 256, 0, st>>>(p.S, p.m, p.s_out, p.minabs, p.result);
 }
 
 }  // namespace ecnt

@@ -55,6 +55,11 @@ class InfoT(ctypes.Structure):
                 ("k_used", ctypes.c_void_p), ("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p)]
 
 
+class BatchItemT(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dims", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+                ("taus", ctypes.c_void_p)]
+
+
 class KernelStatT(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -99,6 +104,21 @@ def load():
                                         ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t, P, P,
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]
+        BI = ctypes.POINTER(BatchItemT)
+        lib.ecnt_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.ecnt_batch_workspace_bytes.argtypes = [BI, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                                   ctypes.POINTER(PrecT), ctypes.POINTER(OptsT)]
+        batch_args = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT), BI, ctypes.c_int32,
+                      ctypes.c_int32, P, ctypes.c_int64, ctypes.POINTER(OptsT), P, ctypes.c_size_t, P]
+        for name in ("ecnt_batch_prepare", "ecnt_batch_enqueue"):
+            getattr(lib, name).restype = ctypes.c_int32
+            getattr(lib, name).argtypes = batch_args
+        lib.ecnt_batch_results.restype = ctypes.c_int32
+        lib.ecnt_batch_results.argtypes = [BI, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.POINTER(PrecT), ctypes.POINTER(OptsT), P,
+                                           ctypes.c_size_t, P, P, P, P, ctypes.POINTER(InfoT)]
+        lib.ecnt_count_batched.restype = ctypes.c_int32
+        lib.ecnt_count_batched.argtypes = batch_args + [P, P, P, ctypes.POINTER(InfoT)]
         lib.ecnt_profile_enable.restype = ctypes.c_int32
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
         lib.ecnt_profile_read.restype = ctypes.c_int32
@@ -367,3 +387,119 @@ def smooth_backward(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, s
                              ctypes.byref(dxi), ctypes.byref(deta))
     _check(rc)
     return dV, dxi.value, deta.value
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent problems (block-diagonal A)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class BatchResult:
+    negcounts: np.ndarray      # (nprob, nshift)
+    counts: np.ndarray         # (nprob, nshift - 1)
+    variances: np.ndarray      # (nprob, nshift - 1)
+    per_probe: object = None   # torch (nprob, nshift * m) float64
+    k_used: object = None      # torch (nprob, nshift * m) int32
+
+
+class Batch:
+    """A batch of independent problems run as one launch sequence
+    (ecnt_batch_prepare / ecnt_batch_enqueue / ecnt_batch_results).
+
+    A: DeviceCSR of the block-diagonal matrix (workloads.block_diag_csr);
+    sizes: rows per problem; taus: (nprob, nshift) shifts; dims: per-problem
+    grids (needed with the Laplacian preconditioner); probes: torch device
+    tensor A.n x m.  `enqueue` only launches kernels, so it can be captured
+    in a torch.cuda.CUDAGraph (see `capture`)."""
+
+    def __init__(self, A: DeviceCSR, prec, sizes, taus, probes, k: int, dims=None,
+                 vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
+                 max_cols: int = 0, eval: str = "auto", workspace: Workspace | None = None,
+                 stream=None, details: bool = False):
+        self.lib = load()
+        self.A, self.probes = A, probes
+        self.n, self.m = probes.shape
+        taus = np.ascontiguousarray(np.atleast_2d(taus), dtype=np.float64)
+        self.nprob, self.nshift = taus.shape
+        if len(sizes) != self.nprob:
+            raise ValueError("sizes and taus disagree on the number of problems")
+        self._taus = taus
+        self._items = (BatchItemT * self.nprob)()
+        for b in range(self.nprob):
+            d = dims[b] if dims is not None else (1, 1, int(sizes[b]))
+            d = tuple(int(x) for x in d)
+            d = (1,) * (3 - len(d)) + d
+            self._items[b] = BatchItemT(int(sizes[b]), (ctypes.c_int32 * 3)(*d), 0,
+                                        taus[b].ctypes.data)
+        self._ps, self._coef = prec_struct(prec, eval)
+        if self._ps.kind == PREC_KINDS["cheb"]:
+            self._ps.ndim = 3
+        self._o = opts_struct(k, vec, rule, smooth_w, max_cols)
+        self._cs = A.struct()
+        need = self.lib.ecnt_batch_workspace_bytes(self._items, self.nprob, self.nshift, self.m,
+                                                   ctypes.byref(self._ps), ctypes.byref(self._o))
+        self.ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
+        self.details = details
+        self._keep = {}
+        if details:
+            import torch
+            C = self.nshift * self.m
+            self._keep = {"per_probe": torch.empty((self.nprob, C), dtype=torch.float64,
+                                                   device=probes.device),
+                          "k_used": torch.empty((self.nprob, C), dtype=torch.int32,
+                                                device=probes.device)}
+        self.prepare(stream)
+
+    def _args(self, stream):
+        return (ctypes.byref(self._cs), ctypes.byref(self._ps), self._items, self.nprob,
+                self.nshift, self.probes.data_ptr(), self.m, ctypes.byref(self._o),
+                self.ws.buf.data_ptr(), self.ws.nbytes, _stream_handle(stream))
+
+    def prepare(self, stream=None):
+        _check(self.lib.ecnt_batch_prepare(*self._args(stream)))
+
+    def enqueue(self, stream=None):
+        _check(self.lib.ecnt_batch_enqueue(*self._args(stream)))
+
+    def results(self, stream=None) -> BatchResult:
+        S = self.nshift
+        neg = np.zeros((self.nprob, S))
+        cnt = np.zeros((self.nprob, max(S - 1, 1)))
+        var = np.zeros((self.nprob, max(S - 1, 1)))
+        info = InfoT()
+        if self.details:
+            info = InfoT(0.0, 0.0, 0.0, self._keep["per_probe"].data_ptr(),
+                         self._keep["k_used"].data_ptr(), None, None)
+        _check(self.lib.ecnt_batch_results(self._items, self.nprob, S, self.m,
+                                           ctypes.byref(self._ps), ctypes.byref(self._o),
+                                           self.ws.buf.data_ptr(), self.ws.nbytes,
+                                           _stream_handle(stream), neg.ctypes.data,
+                                           cnt.ctypes.data, var.ctypes.data, ctypes.byref(info)))
+        return BatchResult(neg, cnt[:, :S - 1], var[:, :S - 1],
+                           self._keep["per_probe"].clone() if self.details else None,
+                           self._keep["k_used"].clone() if self.details else None)
+
+    def run(self, stream=None) -> BatchResult:
+        self.enqueue(stream)
+        return self.results(stream)
+
+    def capture(self):
+        """Capture `enqueue` into a torch.cuda.CUDAGraph (returned); replay it and
+        then call `results`."""
+        import torch
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue(s)   # warm-up outside the capture (first-launch code-object loads)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            self.enqueue()
+        return g
+
+
+def count_batched(A: DeviceCSR, prec, sizes, taus, probes, k: int, dims=None, **kw) -> BatchResult:
+    """One-shot batched run (prepare + enqueue + results)."""
+    return Batch(A, prec, sizes, taus, probes, k, dims=dims, **kw).run(kw.get("stream"))

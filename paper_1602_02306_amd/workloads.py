@@ -361,6 +361,28 @@ class BatchItem:
     shifts: np.ndarray      # 4 sorted endpoints -> 3 contiguous intervals
 
 
+def block_diag_csr(mats: Sequence[CSR]) -> CSR:
+    """The block-diagonal matrix diag(mats[0], mats[1], ...) in CSR form (rows
+    and column indices of block b offset by the sizes of the blocks before
+    it): how a batch of independent problems is handed over as one matrix."""
+    n = sum(int(a.n) for a in mats)
+    nnz = sum(a.nnz for a in mats)
+    if n >= 2 ** 31 or nnz >= 2 ** 31:
+        raise ValueError("block-diagonal matrix exceeds int32 indexing")
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col_idx = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    r = 0
+    e = 0
+    for a in mats:
+        row_ptr[r + 1:r + a.n + 1] = e + a.row_ptr[1:].astype(np.int64)
+        col_idx[e:e + a.nnz] = a.col_idx.astype(np.int64) + r
+        val[e:e + a.nnz] = a.val
+        r += int(a.n)
+        e += a.nnz
+    return CSR(n, row_ptr.astype(np.int32), col_idx, val)
+
+
 def batched_item(b: int, nmin: int = 16, nmax: int = 64, base_seed: int = 1000,
                  lo: float = -8.0, hi: float = -2.0, nshift: int = 4) -> BatchItem:
     """Problem b of the batched family: rng = default_rng(base_seed + b); draw

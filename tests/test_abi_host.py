@@ -112,3 +112,62 @@ def test_negcounts_rejects_bad_shift_counts():
                                 ctypes.byref(o), 0x2000, 1 << 40, None, out.ctypes.data, None,
                                 None, None)
         assert rc == code, ec.last_error()
+
+
+def _items(sizes, dims, taus):
+    arr = (ec.BatchItemT * len(sizes))()
+    for b, (n, d) in enumerate(zip(sizes, dims)):
+        arr[b] = ec.BatchItemT(n, (ctypes.c_int32 * 3)(*d), 0, taus[b].ctypes.data)
+    return arr
+
+
+def test_batch_workspace_bytes():
+    lib = ec.load()
+    prec = W.cheb_invsqrt_prec((4, 4, 4))
+    ps, keep = ec.prec_struct(prec)
+    o = ec.opts_struct(5)
+    taus = np.tile(np.array([-3.0, -2.0, -1.0]), (3, 1))
+    sizes, dims = [64, 125, 60], [(4, 4, 4), (5, 5, 5), (3, 4, 5)]
+    it = _items(sizes, dims, taus)
+    b = lib.ecnt_batch_workspace_bytes(it, 3, 3, 8, ctypes.byref(ps), ctypes.byref(o))
+    # basis (k+1 blocks) and 3 scratch blocks of 249 rows x 24 columns, FP64
+    assert b >= 9 * 249 * 24 * 8
+    # a grid that does not match its problem's rows, k above a problem's size,
+    # no problems, too many shifts: size 0
+    bad = _items(sizes, [(4, 4, 4), (5, 5, 4), (3, 4, 5)], taus)
+    assert lib.ecnt_batch_workspace_bytes(bad, 3, 3, 8, ctypes.byref(ps), ctypes.byref(o)) == 0
+    o70 = ec.opts_struct(61)
+    assert lib.ecnt_batch_workspace_bytes(it, 3, 3, 8, ctypes.byref(ps), ctypes.byref(o70)) == 0
+    assert lib.ecnt_batch_workspace_bytes(it, 0, 3, 8, ctypes.byref(ps), ctypes.byref(o)) == 0
+    assert lib.ecnt_batch_workspace_bytes(it, 3, 65, 8, ctypes.byref(ps), ctypes.byref(o)) == 0
+    # without the stencil preconditioner the grids are ignored
+    pj, keepj = ec.prec_struct(W.PrecSpec("jacobi", ()))
+    assert lib.ecnt_batch_workspace_bytes(bad, 3, 3, 8, ctypes.byref(pj), ctypes.byref(o)) > 0
+
+
+def test_batch_rejects_invalid_calls_on_host():
+    lib = ec.load()
+    ps, keep = ec.prec_struct(W.PrecSpec("none", ()))
+    o = ec.opts_struct(3)
+    taus = np.tile(np.array([0.0, 1.0]), (2, 1))
+    it = _items([32, 32], [(1, 1, 32)] * 2, taus)
+    out = np.zeros(4)
+    cases = [(ec.CsrT(65, 320, 0x3000, 0x4000, 0x5000, 0, 0), it, 2, ec.ECNT_EINVAL),   # A.n != sum n
+             (ec.CsrT(64, 320, 0x3000, 0x4000, 0x5000, 0, 0), None, 2, ec.ECNT_EINVAL),
+             (ec.CsrT(64, 320, 0x3000, 0x4000, 0x5000, 0, 0), it, 0, ec.ECNT_EINVAL)]
+    for cs, items, nshift, code in cases:
+        rc = lib.ecnt_count_batched(ctypes.byref(cs), ctypes.byref(ps), items, 2, nshift, 0x1000, 4,
+                                    ctypes.byref(o), 0x2000, 1 << 40, None, out.ctypes.data, None,
+                                    None, None)
+        assert rc == code, ec.last_error()
+    cs = ec.CsrT(64, 320, 0x3000, 0x4000, 0x5000, 0, 0)
+    rc = lib.ecnt_count_batched(ctypes.byref(cs), ctypes.byref(ps), it, 2, 2, 0x1000, 4,
+                                ctypes.byref(o), 0x2000, 1024, None, out.ctypes.data, None, None,
+                                None)
+    assert rc == ec.ECNT_EWORKSPACE
+    taus_nan = np.array([[0.0, np.nan], [0.0, 1.0]])
+    it2 = _items([32, 32], [(1, 1, 32)] * 2, taus_nan)
+    rc = lib.ecnt_count_batched(ctypes.byref(cs), ctypes.byref(ps), it2, 2, 2, 0x1000, 4,
+                                ctypes.byref(o), 0x2000, 1 << 40, None, out.ctypes.data, None,
+                                None, None)
+    assert rc == ec.ECNT_EINVAL

@@ -1,0 +1,191 @@
+"""GPU parity of the batched path: a batch of independent problems, run as one
+block-diagonal launch sequence, against the oracle run on each problem alone
+(same probe rows), and against the single-problem GPU call.
+
+Tolerances as for the single-problem parity tests: per-shift means and every
+per-probe quadrature value within 1e-10 * |v_j|^2 (FP64).  The batched and the
+single-problem GPU runs differ only in the row chunking of the column sums.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02306_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ec():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_02306_amd import ecount
+    ecount.load()
+    return ecount
+
+
+class Problems:
+    """Host side of a batch: per-problem A, grids, shifts, and the block-diagonal A."""
+
+    def __init__(self, dims_list, nshift=4, seed=0, lo=-8.0, hi=-2.0):
+        rng = np.random.default_rng(seed)
+        self.dims = [tuple(d) for d in dims_list]
+        self.A = []
+        self.taus = np.zeros((len(dims_list), nshift))
+        for b, d in enumerate(self.dims):
+            V = W.gaussian_wells(d, rng)
+            self.A.append(W.laplacian_csr(d, V))
+            self.taus[b] = np.sort(rng.uniform(lo, hi, size=nshift))
+        self.sizes = [a.n for a in self.A]
+        self.off = np.concatenate([[0], np.cumsum(self.sizes)])
+        self.Abd = W.block_diag_csr(self.A)
+        self.prec = W.cheb_invsqrt_prec((1, 1, 1))   # the same series for every 3-D grid
+
+    def prec_for(self, kind, b):
+        if kind == "cheb":
+            return W.cheb_invsqrt_prec(self.dims[b])
+        return W.PrecSpec(kind, ())
+
+    def batch_prec(self, kind):
+        return self.prec if kind == "cheb" else W.PrecSpec(kind, ())
+
+
+def run_batch(ec, P, V, k, prec_kind="cheb", vec="f64", **kw):
+    Ad = ec.upload_csr(P.Abd, val_dtype=kw.pop("val", "f64"))
+    Vd = torch.from_numpy(V).to("cuda", torch.float32 if vec == "f32" else torch.float64)
+    bt = ec.Batch(Ad, P.batch_prec(prec_kind), P.sizes, P.taus, Vd, k, dims=P.dims, vec=vec,
+                  details=True, **kw)
+    return bt.run(), bt
+
+
+def check_against_oracle(P, r, V, k, prec_kind="cheb", rule="gauss", smooth_w=0.0, tol=TOL):
+    m = V.shape[1]
+    S = P.taus.shape[1]
+    s_gpu = r.per_probe.cpu().numpy().reshape(len(P.sizes), S, m)
+    worst = 0.0
+    for b in range(len(P.sizes)):
+        Vb = np.ascontiguousarray(V[P.off[b]:P.off[b + 1]])
+        nu = float(P.sizes[b])   # Rademacher: |v|^2 = n
+        for t in range(S):
+            mean, s, _, _ = oracle.negcount(P.A[b], P.prec_for(prec_kind, b), P.taus[b, t], Vb, k,
+                                            rule=rule, smooth_w=smooth_w)
+            d = np.max(np.abs(s_gpu[b, t] - s)) / nu
+            worst = max(worst, d, abs(r.negcounts[b, t] - mean) / nu)
+            assert abs(r.negcounts[b, t] - mean) <= tol * nu, (b, t, r.negcounts[b, t], mean)
+            assert d <= tol, (b, t, d)
+        for t in range(S - 1):
+            dd = s_gpu[b, t + 1] - s_gpu[b, t]
+            assert abs(r.counts[b, t] - dd.mean()) <= 1e-12 * max(1.0, abs(dd.mean()))
+    print("max deviation / |v|^2: %.2e" % worst)
+
+
+def test_batch_matches_oracle_per_problem(ec):
+    P = Problems([(5, 5, 5), (7, 7, 7), (6, 6, 6), (9, 9, 9), (5, 5, 5)], seed=1)
+    V = W.rademacher(P.Abd.n, 12, 4242)
+    r, _ = run_batch(ec, P, V, 8)
+    check_against_oracle(P, r, V, 8)
+
+
+def test_batch_ragged_grids_thin_tiles(ec):
+    """Non-cubic grids, one with d0 < 4 (the 1 x 8 line-block shape), m not a
+    multiple of the vector width."""
+    P = Problems([(3, 5, 7), (4, 6, 5), (2, 9, 4), (6, 3, 3)], nshift=3, seed=2)
+    V = W.rademacher(P.Abd.n, 7, 99)
+    r, _ = run_batch(ec, P, V, 6)
+    check_against_oracle(P, r, V, 6)
+
+
+@pytest.mark.parametrize("prec_kind", ["jacobi", "none"])
+def test_batch_csr_preconditioners(ec, prec_kind):
+    P = Problems([(4, 4, 4), (5, 6, 7), (3, 3, 3)], nshift=4, seed=3)
+    V = W.rademacher(P.Abd.n, 10, 7)
+    r, _ = run_batch(ec, P, V, 9, prec_kind=prec_kind)
+    check_against_oracle(P, r, V, 9, prec_kind=prec_kind)
+
+
+def test_batch_options(ec):
+    """Clenshaw evaluation, the GA rule, the smoothed step, column waves."""
+    P = Problems([(5, 5, 5), (6, 6, 6), (4, 5, 6)], nshift=2, seed=4)
+    V = W.rademacher(P.Abd.n, 9, 11)
+    r, _ = run_batch(ec, P, V, 7, eval="clenshaw")
+    check_against_oracle(P, r, V, 7)
+    r, _ = run_batch(ec, P, V, 7, rule="ga")
+    check_against_oracle(P, r, V, 7, rule="ga")
+    r, _ = run_batch(ec, P, V, 7, smooth_w=0.05)
+    check_against_oracle(P, r, V, 7, smooth_w=0.05)
+    r, _ = run_batch(ec, P, V, 7, max_cols=5)
+    check_against_oracle(P, r, V, 7)
+
+
+def test_batch_equals_single_problem_calls(ec):
+    P = Problems([(6, 6, 6), (8, 8, 8), (5, 7, 6)], nshift=4, seed=5)
+    V = W.rademacher(P.Abd.n, 16, 5)
+    r, _ = run_batch(ec, P, V, 10)
+    s_b = r.per_probe.cpu().numpy().reshape(3, 4, 16)
+    for b in range(3):
+        Ad = ec.upload_csr(P.A[b])
+        Vd = torch.from_numpy(np.ascontiguousarray(V[P.off[b]:P.off[b + 1]])).cuda()
+        one = ec.negcounts(Ad, P.prec_for("cheb", b), P.taus[b], Vd, 10)
+        s1 = one.per_probe.cpu().numpy().reshape(4, 16)
+        assert np.max(np.abs(s1 - s_b[b])) <= TOL * P.sizes[b]
+        assert np.max(np.abs(one.negcounts - r.negcounts[b])) <= TOL * P.sizes[b]
+
+
+def test_batch_fp32_vectors(ec):
+    """FP32 vectors and matrix values against the FP64 oracle: the bound of
+    the single-problem FP32 test."""
+    P = Problems([(6, 6, 6), (5, 5, 5)], nshift=2, seed=6)
+    V = W.rademacher(P.Abd.n, 8, 3)
+    r, _ = run_batch(ec, P, V, 8, vec="f32", val="f32")
+    check_against_oracle(P, r, V, 8, tol=1e-4)
+
+
+def test_batch_k_above_a_problem_size_rejected(ec):
+    P = Problems([(2, 2, 2), (4, 4, 4)], nshift=2, seed=7)
+    V = W.rademacher(P.Abd.n, 4, 1)
+    with pytest.raises(ec.EcntError) as e:
+        run_batch(ec, P, V, 9)
+    assert e.value.status == ec.ECNT_EINVAL
+
+
+def test_batch_graph_replay(ec):
+    """The enqueue step captured in a graph: every replay, with unrelated eager
+    work in between, reproduces the eager results bitwise."""
+    P = Problems([(5, 5, 5), (7, 6, 5), (6, 6, 6)], nshift=4, seed=8)
+    V = W.rademacher(P.Abd.n, 8, 21)
+    r0, bt = run_batch(ec, P, V, 8)
+    g = bt.capture()
+    other = Problems([(4, 4, 4)], nshift=2, seed=9)
+    Vo = torch.from_numpy(W.rademacher(other.Abd.n, 4, 1)).cuda()
+    Ao = ec.upload_csr(other.Abd)
+    for rep in range(3):
+        g.replay()
+        r = bt.results()
+        assert np.array_equal(r.negcounts, r0.negcounts), rep
+        assert np.array_equal(r.counts, r0.counts), rep
+        assert torch.equal(r.per_probe, r0.per_probe), rep
+        # eager work between replays: another problem, and torch kernels
+        ec.negcounts(Ao, other.prec_for("cheb", 0), other.taus[0], Vo, 4)
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+        torch.cuda.synchronize()
+
+
+def test_batch_bench_family_sampled(ec):
+    """Problems of the batched benchmark family at their real sizes (N up to
+    64), a few of them, checked against the oracle on 3 probes."""
+    items = [W.batched_item(b) for b in range(3)]
+    dims = [it.dims for it in items]
+    P = Problems.__new__(Problems)
+    P.dims = dims
+    P.A = [it.A for it in items]
+    P.taus = np.stack([it.shifts for it in items])
+    P.sizes = [a.n for a in P.A]
+    P.off = np.concatenate([[0], np.cumsum(P.sizes)])
+    P.Abd = W.block_diag_csr(P.A)
+    P.prec = items[0].prec
+    V = W.rademacher(P.Abd.n, 3, 12345)
+    r, _ = run_batch(ec, P, V, 25)
+    check_against_oracle(P, r, V, 25)
