@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -30,7 +32,11 @@ WORKLOAD_TEXT = {
     "c2": "3D 7-pt 64^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=256, k=30, FP64",
     "c3": "3D 7-pt 128^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=512, k=30, FP32 vectors",
     "c5": "3D 7-pt 96^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M, erf-smoothed count w=0.05, [-8,-2], m=128, k=30",
+    "c4": "64 independent 3D 7-pt Gaussian-well Hamiltonians, N^3 grids with N~U{16..64} (seeds 1000+b), "
+          "4 sorted shifts ~U[-8,-2] each (3 intervals), Chebyshev M=c4(L+I), m=64, k=25, one "
+          "block-diagonal launch sequence replayed from a captured graph",
 }
+BATCH = {"c4": "f64", "c4_f32": "f32"}
 
 
 def log(*a):
@@ -79,6 +85,130 @@ def cpu_baseline(P, V, wl, target_s: float):
     return {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
             "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
                       % (done, m, wl.k, steps, t_tot)}
+
+
+def cpu_baseline_batch(items, V, off, k: int, target_s: float, m_total: int):
+    """The oracle on a bounded sample of the batch: problems in order, all
+    shifts, the first few probes of each, until about target_s seconds."""
+    import oracle
+    threads = oracle.host_threads()
+    m = V.shape[1]
+    mp = min(m, threads)
+    steps, t_tot, nprob = 0, 0.0, 0
+    for b, it in enumerate(items):
+        Vb = np.ascontiguousarray(V[off[b]:off[b + 1], :mp])
+        t0 = time.perf_counter()
+        for tau in it.shifts:
+            oracle.negcount(it.A, it.prec, float(tau), Vb, k, nthreads=threads)
+        t_tot += time.perf_counter() - t0
+        steps += len(it.shifts) * mp * k
+        nprob += 1
+        log("cpu oracle: problem %d (n=%d) done, total %.1f s" % (b, it.A.n, t_tot))
+        if t_tot >= target_s:
+            break
+    return {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "problems 0..%d of %d, all %d shifts, first %d of %d probes, k=%d "
+                      "(%d probe-steps, %.1f s)" % (nprob - 1, len(items), len(items[0].shifts), mp,
+                                                   m_total, k, steps, t_tot)}
+
+
+def bench_batched(args, name: str):
+    """The batched form: 64 problems of uneven size in one launch sequence,
+    captured once into a graph and replayed; one step = one whole batch."""
+    import torch
+    from paper_1602_02306_amd import autotune
+    from paper_1602_02306_amd import ecount as ec
+    from paper_1602_02306_amd import workloads as W
+    vec = BATCH[name]
+    nprob, m, k = 64, 64, 25
+    t0 = time.perf_counter()
+    items = [W.batched_item(b) for b in range(nprob)]
+    sizes = [it.A.n for it in items]
+    dims = [it.dims for it in items]
+    taus = np.stack([it.shifts for it in items])
+    S = taus.shape[1]
+    Abd = W.block_diag_csr([it.A for it in items])
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    log("built %d problems, %d rows, %d nonzeros in %.1f s" % (nprob, Abd.n, Abd.nnz,
+                                                              time.perf_counter() - t0))
+    prec = items[0].prec
+    A = ec.upload_csr(Abd, val_dtype=vec)
+    del Abd
+    tdt = torch.float32 if vec == "f32" else torch.float64
+    Vd = W.rademacher_torch(int(off[-1]), m, 4242, device="cuda", dtype=tdt)
+    free, _total = torch.cuda.mem_get_info()
+    budget = free - (16 << 30)
+    cfg = autotune.tune_batch(A, prec, sizes, taus, Vd, k, dims=dims, vec=vec, mem_bytes=budget,
+                              retune=args.retune, log=log)
+    log("launch shape (%s): %s" % (cfg["source"], {x: cfg[x] for x in ("max_cols", "tile",
+                                                                      "red_waves", "csr_vw")}))
+    Ct = S * m
+    tune = {x: cfg[x] for x in autotune.DEFAULTS}
+    max_cols = 0 if cfg["max_cols"] == Ct else cfg["max_cols"]
+    bt = ec.Batch(A, prec, sizes, taus, Vd, k, dims=dims, vec=vec, max_cols=max_cols, tune=tune)
+    log("workspace %.2f GiB" % (bt.ws.nbytes / 2 ** 30))
+    for i in range(args.warmup):
+        r = bt.run()
+        log("warmup %d: sum of negcounts %.6f" % (i, float(r.negcounts.sum())))
+    g = bt.capture()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        g.replay()
+        r = bt.results()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    ms = max((w1 - w0) * 1e3 / args.steps, ev0.elapsed_time(ev1) / args.steps)
+    probe_steps = nprob * S * m * k
+    value = probe_steps / (ms / 1e3)
+    log("timed %d graph replays: %.3f ms/batch, %.0f probe-steps/s" % (args.steps, ms, value))
+    # per-family event timings from one eager run of the same launches
+    ec.profile_enable(True)
+    r2 = bt.run()
+    ec.profile_enable(False)
+    assert np.array_equal(r2.negcounts, r.negcounts)
+    fams = {f: v for f, v in ec.profile_read().items() if v["launches"] > 0}
+    total_kernel_ms = sum(v["ms"] for v in fams.values())
+    dom = max(fams, key=lambda f: fams[f]["ms"])
+    d = fams[dom]
+    per_launch_bytes = d["bytes"] / d["launches"]
+    per_launch_ms = d["ms"] / d["launches"]
+    achieved = per_launch_bytes / (per_launch_ms / 1e3) / 1e9
+    algo_bytes = sum(v["bytes"] for v in fams.values())
+    out = {
+        "metric": "Lanczos probe-steps/s + HBM GB/s at fixed count error vs LDLᵀ inertia",
+        "value": value, "unit": "probe-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if vec == "f64" else "f32-storage/f64-accumulate",
+        "data": "synthetic",
+        "config": {"workload": name + ": " + WORKLOAD_TEXT["c4"], "problems": nprob,
+                   "rows": int(off[-1]), "probes": m, "shifts": S, "columns_per_problem": Ct,
+                   "k": k, "probe_steps_per_step": probe_steps,
+                   "launch_shape": {x: cfg[x] for x in ("max_cols", "tile", "red_waves", "csr_vw")},
+                   "tuned": cfg["source"]},
+        "hbm_gbs_algorithmic": algo_bytes / (total_kernel_ms / 1e3) / 1e9 if total_kernel_ms else None,
+        "algorithmic_bytes_per_probe_step": algo_bytes / probe_steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "avg_launch_ms": per_launch_ms},
+        "kernels": {f: {"launches_per_step": v["launches"], "ms_per_step": v["ms"],
+                        "share": v["ms"] / total_kernel_ms,
+                        "gbs": (v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["bytes"] > 0 else None}
+                    for f, v in fams.items()},
+        "eager_kernel_ms": total_kernel_ms,
+        "result": {"sum_negcounts": float(r.negcounts.sum()),
+                   "counts_first_problem": [float(x) for x in r.counts[0]]},
+        "kernel_sources_sha": kernel_sources_sha(),
+    }
+    if not args.no_cpu_baseline:
+        V = Vd[:, :16].cpu().double().numpy()
+        out["cpu_baseline"] = cpu_baseline_batch(items, V, off, k, args.cpu_seconds, m)
+    print(json.dumps(out), flush=True)
 
 
 def traffic_from_profiles(family: str, per_launch_algo: float):
@@ -187,6 +317,8 @@ def main():
     ap.add_argument("--pmc-dir", help="with --summarize: directory holding the counter runs")
     ap.add_argument("--command", default="", help="with --summarize: the profiled command")
     ap.add_argument("--counters-json", help="with --summarize: write calibrated per-launch bytes here")
+    ap.add_argument("--retune", action="store_true", help="batched workloads: search launch shapes "
+                    "again instead of using the tuning cache")
     args = ap.parse_args()
 
     if args.summarize:
@@ -204,12 +336,15 @@ def main():
               "end, which is not built); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     if args.copy_calib:
         copy_calib()
+        return
+
+    if args.workload in BATCH:
+        bench_batched(args, args.workload)
         return
 
     from paper_1602_02306_amd import ecount as ec

@@ -124,6 +124,16 @@ typedef struct {
                            passes over A.  Results do not depend on it. */
     double smooth_w;    /* 0: the paper's step h (h(theta) = 1 iff theta < 0).
                            > 0: h replaced by erfc(theta / smooth_w) / 2. */
+    /* Launch-shape tunables (0 = built-in default).  They change how the
+       work is cut into workgroups, not what is computed: results move at
+       most by the order of floating-point sums. */
+    int32_t tile;       /* stencil line block: 1 = 4x4 lines, 2 = 2x4, 3 = 1x8 (0: 4x4,
+                           or 1x8 when some grid has fewer than 4 x-planes) */
+    int32_t red_waves;  /* target wavefronts of a column-reduction launch, 64..65536
+                           (sets the rows per chunk of the two-phase sums; 0: 2048) */
+    int32_t csr_vw;     /* columns per lane of the CSR sweep: 1, 2 (or 4 with FP32
+                           vectors); used when it divides the wave's width (0: widest) */
+    int32_t reserved;   /* must be 0 */
 } ecnt_opts;
 
 /* Optional outputs.  Device arrays may be NULL. */

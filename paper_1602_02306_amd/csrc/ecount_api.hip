@@ -165,6 +165,7 @@ static void col_geometry(Plan &p)
     // columns per lane: 16-byte accesses where the column count allows it
     if (p.vec_f32) p.vw = (p.C % 4 == 0) ? 4 : (p.C % 2 == 0 ? 2 : 1);
     else p.vw = (p.C % 2 == 0) ? 2 : 1;
+    if (p.req_vw > 0 && p.req_vw <= p.vw && p.C % p.req_vw == 0) p.vw = p.req_vw;
     p.nct = (p.C + kColTile - 1) / kColTile;
 }
 
@@ -175,7 +176,8 @@ static void row_geometry(Plan &p, SegHost &sh)
     // reductions: one wavefront per (row chunk, tile of 64 lanes); about 2048 of them
     const int vwr = (p.vec_f32 && p.wave_cols % 2 == 0) ? 2 : 1;
     const int nctr = (p.wave_cols + 64 * vwr - 1) / (64 * vwr);
-    int64_t target = (2048 + nctr - 1) / nctr;
+    const int waves = p.req_red_waves > 0 ? p.req_red_waves : 2048;
+    int64_t target = (waves + nctr - 1) / nctr;
     const int64_t maxchunks = (p.n + 15) / 16;
     if (target > maxchunks) target = maxchunks;
     if (target < 1) target = 1;
@@ -184,8 +186,9 @@ static void row_geometry(Plan &p, SegHost &sh)
     sh.tile.assign(p.nseg + 1, 0);
     bool thin = false;
     for (int b = 0; b < p.nseg; ++b) thin = thin || sh.dims[3 * b] < 4;
-    p.tx = thin ? 1 : 4;
-    p.ty = thin ? 8 : 4;
+    const int shape = p.req_tile > 0 ? p.req_tile : (thin ? 3 : 1);
+    p.tx = shape == 1 ? 4 : (shape == 2 ? 2 : 1);
+    p.ty = shape == 3 ? 8 : 4;
     for (int b = 0; b < p.nseg; ++b) {
         const int64_t nb = sh.row[b + 1] - sh.row[b];
         sh.chunk[b + 1] = sh.chunk[b] + (nb + p.rpc - 1) / p.rpc;
@@ -304,6 +307,12 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     if (o->max_cols < 0) return fail(ECNT_EINVAL, "opts.max_cols must be >= 0");
     if (!(o->smooth_w >= 0.0) || !isfinite(o->smooth_w))
         return fail(ECNT_EINVAL, "smooth_w must be finite and >= 0");
+    if (o->tile < 0 || o->tile > 3) return fail(ECNT_EINVAL, "opts.tile must be 0..3");
+    if (o->red_waves != 0 && (o->red_waves < 64 || o->red_waves > 65536))
+        return fail(ECNT_EINVAL, "opts.red_waves must be 0 or 64..65536");
+    if (o->csr_vw != 0 && o->csr_vw != 1 && o->csr_vw != 2 && o->csr_vw != 4)
+        return fail(ECNT_EINVAL, "opts.csr_vw must be 0, 1, 2 or 4");
+    if (o->reserved != 0) return fail(ECNT_EINVAL, "opts.reserved must be 0");
     const int kmax = o->rule == ECNT_RULE_GA ? kMaxK / 2 : kMaxK;
     if (o->k > kmax) return fail(ECNT_EUNSUPPORTED, "k above %d is not supported", kmax);
     p.n = n;
@@ -316,6 +325,9 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     p.vec_f32 = o->vec_type == ECNT_F32;
     p.rule = o->rule;
     p.smooth_w = o->smooth_w;
+    p.req_tile = o->tile;
+    p.req_red_waves = o->red_waves;
+    p.req_vw = o->csr_vw;
     p.prec_kind = T->kind;
     switch (T->kind) {
     case ECNT_PREC_NONE:

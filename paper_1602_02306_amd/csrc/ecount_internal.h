@@ -53,13 +53,14 @@ struct Plan {
     double fac_a[16] = {0}, fac_b[16] = {0};
     double lead = 1.0;
     // geometry
-    int vw = 1;           // columns per lane in the row-sweep kernels
+    int vw = 1;           // columns per lane in the CSR sweep
+    int req_tile = 0, req_red_waves = 0, req_vw = 0;   // launch-shape requests (0: default)
     int nct = 0;          // column tiles of 64 (setup kernel)
     int nchunk = 0;       // row chunks of the two-phase column reductions (all segments)
     int64_t rpc = 0;      // rows per chunk
     // segments
     int nseg = 1;
-    int tx = 4, ty = 4;   // stencil line-block shape
+    int tx = 4, ty = 4;   // stencil line-block shape (4x4, 2x4 or 1x8)
     int64_t ntiles = 0;   // stencil line blocks over all segments
     int64_t *seg_row = nullptr;    // device, nseg+1
     int64_t *seg_chunk = nullptr;  // device, nseg+1

@@ -351,13 +351,14 @@ static void stencil_flags(const Plan &p, const void *X, const double *xs, double
     }
 }
 
-// line-block shape: 4 x 4 lines on 3D grids, 1 x 8 when the grid has a single x plane
+// line-block shape (x lines by y lines): 4 x 4, 2 x 4 or 1 x 8
 template <typename T, int VW>
 static void stencil_shape(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
                           bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
                           hipStream_t st)
 {
     if (p.tx == 4) stencil_flags<T, VW, 4, 4>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
+    else if (p.tx == 2) stencil_flags<T, VW, 2, 4>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
     else stencil_flags<T, VW, 1, 8>(p, X, xs, cx, IN, in_is_x, cbd, cbo, Z, cz, out, st);
 }
 

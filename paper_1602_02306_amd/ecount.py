@@ -46,7 +46,12 @@ class PrecT(ctypes.Structure):
 
 class OptsT(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("vec_type", ctypes.c_int32), ("rule", ctypes.c_int32),
-                ("max_cols", ctypes.c_int32), ("smooth_w", ctypes.c_double)]
+                ("max_cols", ctypes.c_int32), ("smooth_w", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("red_waves", ctypes.c_int32), ("csr_vw", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+TILES = {"auto": 0, "4x4": 1, "2x4": 2, "1x8": 3}
 
 
 class InfoT(ctypes.Structure):
@@ -186,14 +191,19 @@ def prec_struct(prec, eval: str = "auto"):
 
 
 def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
-                max_cols: int = 0) -> OptsT:
-    return OptsT(int(k), DTYPES[vec], RULES[rule], int(max_cols), float(smooth_w))
+                max_cols: int = 0, tune: dict | None = None) -> OptsT:
+    """ecnt_opts; `tune` holds optional launch-shape tunables:
+    {"tile": "4x4"|"2x4"|"1x8", "red_waves": int, "csr_vw": int}."""
+    t = tune or {}
+    return OptsT(int(k), DTYPES[vec], RULES[rule], int(max_cols), float(smooth_w),
+                 TILES[t.get("tile", "auto")], int(t.get("red_waves", 0)), int(t.get("csr_vw", 0)), 0)
 
 
 def workspace_bytes(n: int, m: int, nshift: int, prec, k: int, vec: str = "f64",
-                    rule: str = "gauss", smooth_w: float = 0.0, max_cols: int = 0) -> int:
+                    rule: str = "gauss", smooth_w: float = 0.0, max_cols: int = 0,
+                    tune: dict | None = None) -> int:
     ps, _coef = prec_struct(prec)
-    o = opts_struct(k, vec, rule, smooth_w, max_cols)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     return int(load().ecnt_workspace_bytes(int(n), int(m), int(nshift), ctypes.byref(ps),
                                            ctypes.byref(o)))
 
@@ -250,13 +260,14 @@ def _info(C: int, k: int, want: bool, device):
 
 def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
           rule: str = "gauss", smooth_w: float = 0.0, workspace: Workspace | None = None,
-          stream=None, details: bool = True, eval: str = "auto", max_cols: int = 0) -> CountResult:
+          stream=None, details: bool = True, eval: str = "auto", max_cols: int = 0,
+          tune: dict | None = None) -> CountResult:
     """Interval count on [xi, eta) (ecnt_count).  `probes`: torch device tensor
     n x m (float64 for vec='f64', float32 for vec='f32')."""
     lib = load()
     n, m = probes.shape
     ps, _coef = prec_struct(prec, eval)
-    o = opts_struct(k, vec, rule, smooth_w, max_cols)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     need = lib.ecnt_workspace_bytes(n, m, 2, ctypes.byref(ps), ctypes.byref(o))
     ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
     info, keep = _info(2 * m, k, details, probes.device)
@@ -287,14 +298,15 @@ class NegcountsResult:
 
 def negcounts(A: DeviceCSR, prec, taus, probes, k: int, vec: str = "f64", rule: str = "gauss",
               smooth_w: float = 0.0, workspace: Workspace | None = None, stream=None,
-              details: bool = True, eval: str = "auto", max_cols: int = 0) -> NegcountsResult:
+              details: bool = True, eval: str = "auto", max_cols: int = 0,
+              tune: dict | None = None) -> NegcountsResult:
     """Algorithm 2 at several shifts on one probe block (ecnt_negcounts)."""
     lib = load()
     n, m = probes.shape
     taus = np.ascontiguousarray(taus, dtype=np.float64)
     S = len(taus)
     ps, _coef = prec_struct(prec, eval)
-    o = opts_struct(k, vec, rule, smooth_w, max_cols)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     need = lib.ecnt_workspace_bytes(n, m, S, ctypes.byref(ps), ctypes.byref(o))
     ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
     info, keep = _info(S * m, k, details, probes.device)
@@ -416,7 +428,7 @@ class Batch:
     def __init__(self, A: DeviceCSR, prec, sizes, taus, probes, k: int, dims=None,
                  vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
                  max_cols: int = 0, eval: str = "auto", workspace: Workspace | None = None,
-                 stream=None, details: bool = False):
+                 stream=None, details: bool = False, tune: dict | None = None):
         self.lib = load()
         self.A, self.probes = A, probes
         self.n, self.m = probes.shape
@@ -435,7 +447,7 @@ class Batch:
         self._ps, self._coef = prec_struct(prec, eval)
         if self._ps.kind == PREC_KINDS["cheb"]:
             self._ps.ndim = 3
-        self._o = opts_struct(k, vec, rule, smooth_w, max_cols)
+        self._o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
         self._cs = A.struct()
         need = self.lib.ecnt_batch_workspace_bytes(self._items, self.nprob, self.nshift, self.m,
                                                    ctypes.byref(self._ps), ctypes.byref(self._o))
@@ -498,6 +510,24 @@ class Batch:
         with torch.cuda.graph(g):
             self.enqueue()
         return g
+
+
+def batch_workspace_bytes(sizes, dims, nshift: int, m: int, prec, k: int, vec: str = "f64",
+                          rule: str = "gauss", smooth_w: float = 0.0, max_cols: int = 0,
+                          tune: dict | None = None) -> int:
+    """Workspace bytes of a batch (ecnt_batch_workspace_bytes); 0 if invalid."""
+    taus = np.zeros((len(sizes), nshift))
+    items = (BatchItemT * len(sizes))()
+    for b, n in enumerate(sizes):
+        d = tuple(int(x) for x in (dims[b] if dims is not None else (1, 1, n)))
+        d = (1,) * (3 - len(d)) + d
+        items[b] = BatchItemT(int(n), (ctypes.c_int32 * 3)(*d), 0, taus[b].ctypes.data)
+    ps, _coef = prec_struct(prec)
+    if ps.kind == PREC_KINDS["cheb"]:
+        ps.ndim = 3
+    o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
+    return int(load().ecnt_batch_workspace_bytes(items, len(sizes), int(nshift), int(m),
+                                                 ctypes.byref(ps), ctypes.byref(o)))
 
 
 def count_batched(A: DeviceCSR, prec, sizes, taus, probes, k: int, dims=None, **kw) -> BatchResult:

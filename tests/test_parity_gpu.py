@@ -256,6 +256,30 @@ def test_parity_column_waves_jacobi(ec):
     assert_parity(r, ref, k)
 
 
+@pytest.mark.parametrize("tune", [{"tile": "2x4"}, {"tile": "1x8"}, {"tile": "4x4"},
+                                  {"red_waves": 64}, {"red_waves": 65536}, {"csr_vw": 1},
+                                  {"tile": "2x4", "red_waves": 8192, "csr_vw": 1}])
+def test_parity_launch_shapes(ec, tune):
+    """Every launch shape the autotuner may pick gives the oracle's results."""
+    r, ref, k = run_workload(ec, "c2_ragged", tune=tune)
+    assert_parity(r, ref, k)
+    r, ref, k = run_workload(ec, "c2_small", tune=tune)
+    assert_parity(r, ref, k)
+
+
+def test_stencil_tile_shapes_bitwise(ec):
+    """The stencil computes each grid point the same way whatever the line
+    block, so the tile shape alone changes no bit of the result."""
+    wl = W.WORKLOADS["c2_ragged"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    outs = [gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": t})
+            for t in ("4x4", "2x4", "1x8")]
+    for o in outs[1:]:
+        assert o.estimate == outs[0].estimate
+        assert torch.equal(o.per_probe, outs[0].per_probe)
+
+
 # FP32 storage form: A values, probes, Lanczos vectors and basis in FP32;
 # alpha/beta, every dot product and norm and the tridiagonal eigensolve in
 # FP64.  Parity with the FP64 oracle is not expected to 1e-10; the stated
