@@ -18,10 +18,10 @@ namespace ecnt {
 
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
-              F_VGRAD, F_COUNT };
+              F_VGRAD, F_CHEB2, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
-                                           "bw_update", "bw_vgrad"};
+                                           "bw_update", "bw_vgrad", "op_cheb_quad"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -187,8 +187,9 @@ static void row_geometry(Plan &p, SegHost &sh)
     bool thin = false;
     for (int b = 0; b < p.nseg; ++b) thin = thin || sh.dims[3 * b] < 4;
     const int shape = p.req_tile > 0 ? p.req_tile : (thin ? 3 : 1);
-    p.tx = shape == 1 ? 4 : (shape == 2 ? 2 : 1);
+    p.tx = (shape == 1 || shape == 4) ? 4 : (shape == 2 ? 2 : 1);
     p.ty = shape == 3 ? 8 : 4;
+    p.no_fuse = shape == 4 ? 1 : 0;
     for (int b = 0; b < p.nseg; ++b) {
         const int64_t nb = sh.row[b + 1] - sh.row[b];
         sh.chunk[b + 1] = sh.chunk[b] + (nb + p.rpc - 1) / p.rpc;
@@ -307,7 +308,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     if (o->max_cols < 0) return fail(ECNT_EINVAL, "opts.max_cols must be >= 0");
     if (!(o->smooth_w >= 0.0) || !isfinite(o->smooth_w))
         return fail(ECNT_EINVAL, "smooth_w must be finite and >= 0");
-    if (o->tile < 0 || o->tile > 3) return fail(ECNT_EINVAL, "opts.tile must be 0..3");
+    if (o->tile < 0 || o->tile > 4) return fail(ECNT_EINVAL, "opts.tile must be 0..4");
     if (o->red_waves != 0 && (o->red_waves < 64 || o->red_waves > 65536))
         return fail(ECNT_EINVAL, "opts.red_waves must be 0 or 64..65536");
     if (o->csr_vw != 0 && o->csr_vw != 1 && o->csr_vw != 2 && o->csr_vw != 4)
@@ -460,6 +461,9 @@ static void apply_M_product(const Plan &p, const void *X, const double *xs, void
         const double a = p.fac_a[f];
         if (!p.fac_quad[f]) {
             sweep(p, in, insc, -a * scale, in, insc != nullptr, scale, Z, cz, dst, st);
+        } else if (quad_sweep_supported(p)) {
+            Timed t(F_CHEB2, (Z ? 3 : 2) * block_bytes(p), st);
+            launch_quad_sweep(p, in, insc, -2.0 * a * scale, scale, p.fac_b[f] * scale, Z, cz, dst, st);
         } else {
             sweep(p, in, insc, -2.0 * a * scale, in, insc != nullptr, scale, nullptr, 0.0, t0, st);
             sweep(p, in, insc, p.fac_b[f] * scale, t0, false, 1.0, Z, cz, dst, st);

@@ -61,6 +61,7 @@ struct Plan {
     // segments
     int nseg = 1;
     int tx = 4, ty = 4;   // stencil line-block shape (4x4, 2x4 or 1x8)
+    int no_fuse = 0;      // 1: quadratic factors as two plain sweeps
     int64_t ntiles = 0;   // stencil line blocks over all segments
     int64_t *seg_row = nullptr;    // device, nseg+1
     int64_t *seg_chunk = nullptr;  // device, nseg+1
@@ -132,6 +133,11 @@ void launch_csr_op(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx
 // out = cx*xs*X + cb*B(ins*IN) - cz*Z  (one stencil sweep on the grid Laplacian)
 void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
                     bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st);
+// One quadratic factor in one sweep: t = c1*u + cb*B(u), out = B(t) + c2*u - cz*Z,
+// u = xs .* X (Z may be null).  Needs the 4 x 4 line-block geometry.
+bool quad_sweep_supported(const Plan &p);
+void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1, double cb,
+                       double c2, const void *Z, double cz, void *out, hipStream_t st);
 void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st);
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st);
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st);

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
 // row loads per TX*TY outputs instead of 5 per output.  Lines outside the
 // grid (ragged blocks, Dirichlet boundary) are loaded from a clamped address
 // with weight 0, so every load of a z step is issued together.
-template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ, bool PF>
 __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                                                  const int64_t *__restrict__ seg_row,
                                                  const int64_t *__restrict__ seg_tile,
@@ -197,42 +197,47 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                 cur[a][b][v] = HASIN ? wt[a][b] * t[v] : 0.0;
             }
         }
-    size_t ez = base;
-    for (int z = 0; z < d2; ++z, ez += zs) {
-        const bool hasn = z + 1 < d2;
-        const size_t en = hasn ? ez + zs : ez;
+    // Loads of one z step: the next z value of the block's lines, this z
+    // value of the boundary lines, and X, Z at this z.
+    struct StepLoads {
         double nxt[TX][TY][VW], ym[TX][VW], yp[TX][VW], xm[TY][VW], xp[TY][VW];
         double xv[TX][TY][VW], zv[TX][TY][VW];
+    };
+    auto issue = [&](StepLoads &L, int z) {
+        const size_t ez = base + (size_t)z * zs;
+        const size_t en = z + 1 < d2 ? ez + zs : ez;
         if (HASIN) {
 #pragma unroll
             for (int a = 0; a < TX; ++a)
 #pragma unroll
-                for (int b = 0; b < TY; ++b) vload<T, VW>(IN, en + off[a][b], nxt[a][b]);
+                for (int b = 0; b < TY; ++b) vload<T, VW>(IN, en + off[a][b], L.nxt[a][b]);
 #pragma unroll
             for (int a = 0; a < TX; ++a) {
-                vload<T, VW>(IN, ez + offym[a], ym[a]);
-                vload<T, VW>(IN, ez + offyp[a], yp[a]);
+                vload<T, VW>(IN, ez + offym[a], L.ym[a]);
+                vload<T, VW>(IN, ez + offyp[a], L.yp[a]);
             }
 #pragma unroll
             for (int b = 0; b < TY; ++b) {
-                vload<T, VW>(IN, ez + offxm[b], xm[b]);
-                vload<T, VW>(IN, ez + offxp[b], xp[b]);
+                vload<T, VW>(IN, ez + offxm[b], L.xm[b]);
+                vload<T, VW>(IN, ez + offxp[b], L.xp[b]);
             }
         }
         if (XSEP) {
 #pragma unroll
             for (int a = 0; a < TX; ++a)
 #pragma unroll
-                for (int b = 0; b < TY; ++b) vload<T, VW>(X, ez + off[a][b], xv[a][b]);
+                for (int b = 0; b < TY; ++b) vload<T, VW>(X, ez + off[a][b], L.xv[a][b]);
         }
         if (HASZ) {
 #pragma unroll
             for (int a = 0; a < TX; ++a)
 #pragma unroll
-                for (int b = 0; b < TY; ++b) vload<T, VW>(Z, ez + off[a][b], zv[a][b]);
+                for (int b = 0; b < TY; ++b) vload<T, VW>(Z, ez + off[a][b], L.zv[a][b]);
         }
-        __builtin_amdgcn_sched_barrier(0);
-        const double zn = hasn ? 1.0 : 0.0;
+    };
+    auto compute = [&](const StepLoads &L, int z) {
+        const size_t ez = base + (size_t)z * zs;
+        const double zn = z + 1 < d2 ? 1.0 : 0.0;
 #pragma unroll
         for (int a = 0; a < TX; ++a)
 #pragma unroll
@@ -240,16 +245,16 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                 double o[VW];
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
-                    double val = cx * xsc[v] * (XSEP ? xv[a][b][v] : cur[a][b][v]);
+                    double val = cx * xsc[v] * (XSEP ? L.xv[a][b][v] : cur[a][b][v]);
                     if (HASIN) {
-                        const double nym = b > 0 ? cur[a][b - 1][v] : wym[a] * ym[a][v];
-                        const double nyp = b + 1 < TY ? cur[a][b + 1][v] : wyp[a] * yp[a][v];
-                        const double nxm = a > 0 ? cur[a - 1][b][v] : wxm[b] * xm[b][v];
-                        const double nxp = a + 1 < TX ? cur[a + 1][b][v] : wxp[b] * xp[b][v];
-                        const double nb = prev[a][b][v] + zn * nxt[a][b][v] + nym + nyp + nxm + nxp;
+                        const double nym = b > 0 ? cur[a][b - 1][v] : wym[a] * L.ym[a][v];
+                        const double nyp = b + 1 < TY ? cur[a][b + 1][v] : wyp[a] * L.yp[a][v];
+                        const double nxm = a > 0 ? cur[a - 1][b][v] : wxm[b] * L.xm[b][v];
+                        const double nxp = a + 1 < TX ? cur[a + 1][b][v] : wxp[b] * L.xp[b][v];
+                        const double nb = prev[a][b][v] + zn * L.nxt[a][b][v] + nym + nyp + nxm + nxp;
                         val += isc[v] * (cbd * cur[a][b][v] - cbo * nb);
                     }
-                    if (HASZ) val -= cz * zv[a][b][v];
+                    if (HASZ) val -= cz * L.zv[a][b][v];
                     o[v] = val;
                 }
                 if (wt[a][b] != 0.0) vstore<T, VW>(out, ez + off[a][b], o);
@@ -262,8 +267,201 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
 #pragma unroll
                     for (int v = 0; v < VW; ++v) {
                         prev[a][b][v] = cur[a][b][v];
-                        cur[a][b][v] = wt[a][b] * nxt[a][b][v];
+                        cur[a][b][v] = wt[a][b] * L.nxt[a][b][v];
                     }
+        }
+    };
+    if constexpr (!PF) {
+        // all loads of a step issued together, then the step computed
+        for (int z = 0; z < d2; ++z) {
+            StepLoads L;
+            issue(L, z);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(L, z);
+        }
+    } else {
+        // software pipeline: the loads of step z+1 are in flight while step z
+        // is computed and stored
+        StepLoads A;
+        issue(A, 0);
+        for (int z = 0; z < d2; ++z) {
+            const StepLoads L = A;
+            if (z + 1 < d2) issue(A, z + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(L, z);
+        }
+    }
+}
+
+// ---- one quadratic factor of the preconditioner in a single sweep ----
+//   t = c1*u + cb*B(u),  out = B(t) + c2*u - cz*Z,   u = xs_c * X
+// which is (B^2 + (c1/cb... ) ) applied as the two sweeps above would apply
+// it, with t never written to memory: 1 read and 1 write of a block vector
+// instead of 3 reads and 2 writes.  t is rounded to the storage type as the
+// two-sweep form stores it, and every value is summed in the same order.
+//
+// A workgroup owns a 4 x 4 block of z-lines (the line blocks of the plain
+// sweep with the 4 x 4 shape) for 64*VW columns; each of its four wavefronts
+// owns a 2 x 2 quadrant and walks z.  It needs t on its lines and on the ring
+// of lines at distance 1 (for the lateral neighbours of B t), hence u on the
+// lines at distance <= 2.  Line table: 0..3 the quadrant, 4..11 distance 1,
+// 12..23 distance 2; (i, j) steps along the first and second grid axes.
+namespace quad {
+constexpr int LI[24] = {0, 0, 1, 1, -1, -1, 2, 2, 0, 1, 0, 1, -2, -2, 3, 3, 0, 1, 0, 1, -1, -1, 2, 2};
+constexpr int LJ[24] = {0, 1, 0, 1, 0, 1, 0, 1, -1, -1, 2, 2, 0, 1, 0, 1, -2, -2, 3, 3, -1, 2, -1, 2};
+// lateral neighbours of lines 0..11: (i, j-1), (i, j+1), (i-1, j), (i+1, j)
+constexpr int NYM[12] = {8, 0, 9, 2, 20, 4, 22, 6, 16, 17, 1, 3};
+constexpr int NYP[12] = {1, 10, 3, 11, 5, 21, 7, 23, 0, 2, 18, 19};
+constexpr int NXM[12] = {4, 5, 0, 1, 12, 13, 2, 3, 20, 8, 21, 10};
+constexpr int NXP[12] = {2, 3, 6, 7, 0, 1, 14, 15, 9, 22, 11, 23};
+}  // namespace quad
+
+template <typename T, int VW, bool HASZ>
+__global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
+                                                    const int64_t *__restrict__ seg_row,
+                                                    const int64_t *__restrict__ seg_tile,
+                                                    const int32_t *__restrict__ seg_dims,
+                                                    int64_t ntiles, const T *__restrict__ X,
+                                                    const double *__restrict__ xs_all, double c1,
+                                                    double bd1, double bo1, double c2, double bd2,
+                                                    double bo2, const T *__restrict__ Z, double cz,
+                                                    T *__restrict__ out)
+{
+    using namespace quad;
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int cg = (int)(L % ncg);
+    const int64_t tile = L / ncg;
+    const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int c0 = (cg * 64 + lane) * VW;
+    if (tile >= ntiles || c0 >= C) return;
+    const int seg = find_seg(seg_tile, nseg, tile);
+    const int d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int nty = (d1 + 3) / 4;
+    const int lt = (int)(tile - seg_tile[seg]);
+    const int tx0 = (lt / nty) * 4, ty0 = (lt % nty) * 4;       // the 4 x 4 block
+    const int bx = tx0 + 2 * (wv >> 1), by = ty0 + 2 * (wv & 1);  // this quadrant
+    const double *xs = xs_all ? xs_all + (size_t)seg * C : nullptr;
+    const int64_t zs = C, ys = (int64_t)d2 * C, xst = (int64_t)d1 * d2 * C;
+    // the block's first line is always inside the grid: clamp targets
+    const int64_t base = (int64_t)seg_row[seg] * C + (int64_t)tx0 * xst + (int64_t)ty0 * ys + c0;
+    int64_t off[24];
+    double w[24];
+#pragma unroll
+    for (int q = 0; q < 24; ++q) {
+        const int gi = bx + LI[q], gj = by + LJ[q];
+        const bool ok = gi >= 0 && gi < d0 && gj >= 0 && gj < d1;
+        off[q] = ok ? (int64_t)(gi - tx0) * xst + (int64_t)(gj - ty0) * ys : 0;
+        w[q] = ok ? 1.0 : 0.0;
+    }
+    double xsc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) xsc[v] = xs ? xs[c0 + v] : 1.0;
+    // values are kept in the storage type (u as loaded, t as the two-sweep
+    // form stores it) and widened to double for the arithmetic
+    auto ldT = [&](const T *P, int64_t e, T (&o)[VW]) {
+        using V = typename VecT<T, VW>::type;
+        const V x = *reinterpret_cast<const V *>(P + e);
+        if constexpr (VW == 1) {
+            o[0] = x;
+        } else {
+            o[0] = x.x;
+            o[1] = x.y;
+        }
+    };
+    const T zero = T(0);
+    // u (weighted by the line's inside-grid flag) on lines 0..11 at z-1, z,
+    // z+1 and on lines 12..23 at z; t on lines 0..3 at z-2, z-1 and on lines
+    // 4..11 at z-1
+    T um[12][VW], u0[12][VW], tm2[4][VW], tm1[4][VW], r1[8][VW];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        T a[VW];
+        ldT(X, base + off[q], a);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            um[q][v] = zero;
+            u0[q][v] = w[q] != 0.0 ? a[v] : zero;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) tm2[q][v] = tm1[q][v] = zero;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) r1[q][v] = zero;
+    for (int z = 0; z <= d2; ++z) {
+        const int64_t ez = base + (int64_t)z * zs;
+        const bool has_t = z < d2;                 // t at plane z exists
+        const bool has_n = z + 1 < d2;             // u at plane z+1 exists
+        const int64_t en = has_n ? ez + zs : base; // clamped
+        const int64_t ec = has_t ? ez : base;
+        const int64_t ep = z >= 1 ? ez - zs : base;
+        T un[12][VW], u2[12][VW], zv[4][VW];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) ldT(X, en + off[q], un[q]);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) ldT(X, ec + off[12 + q], u2[q]);
+        if (HASZ) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ldT(Z, ep + off[q], zv[q]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const double zn = has_n ? 1.0 : 0.0;
+        const double tz = has_t ? 1.0 : 0.0;
+        // t at plane z on lines 0..11 (zero outside the grid and past the last plane)
+        T tn[12][VW];
+#pragma unroll
+        for (int q = 0; q < 12; ++q)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                auto uat = [&](int r) -> double {
+                    return r < 12 ? (double)u0[r][v] : w[r] * (double)u2[r - 12][v];
+                };
+                const double cu = u0[q][v];
+                const double nb = (double)um[q][v] + zn * (double)un[q][v] + uat(NYM[q]) +
+                                  uat(NYP[q]) + uat(NXM[q]) + uat(NXP[q]);
+                double t = c1 * xsc[v] * cu;
+                t += xsc[v] * (bd1 * cu - bo1 * nb);
+                tn[q][v] = (tz != 0.0 && w[q] != 0.0) ? static_cast<T>(t) : zero;
+            }
+        // out at plane z-1 on lines 0..3
+        if (z >= 1) {
+            const double znt = has_t ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double o[VW];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    auto tat = [&](int r) -> double {
+                        return r < 4 ? (double)tm1[r][v] : (double)r1[r - 4][v];
+                    };
+                    const double nb = (double)tm2[q][v] + znt * (double)tn[q][v] + tat(NYM[q]) +
+                                      tat(NYP[q]) + tat(NXM[q]) + tat(NXP[q]);
+                    double val = c2 * xsc[v] * (double)um[q][v];
+                    val += 1.0 * (bd2 * (double)tm1[q][v] - bo2 * nb);
+                    if (HASZ) val -= cz * (double)zv[q][v];
+                    o[v] = val;
+                }
+                if (w[q] != 0.0) vstore<T, VW>(out, ep + off[q], o);
+            }
+        }
+        // advance one plane
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                tm2[q][v] = tm1[q][v];
+                tm1[q][v] = tn[q][v];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r1[q][v] = tn[4 + q][v];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                um[q][v] = u0[q][v];
+                u0[q][v] = w[q] != 0.0 ? un[q][v] : zero;
+            }
         }
     }
 }
@@ -322,7 +520,7 @@ void launch_csr_op(const Plan &p, const int32_t *rp, const int32_t *ci, const vo
     }
 }
 
-template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ, bool PF = false>
 static void stencil_t(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
                       bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
                       hipStream_t st)
@@ -330,7 +528,7 @@ static void stencil_t(const Plan &p, const void *X, const double *xs, double cx,
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
     const int64_t waves = p.ntiles * ncg;
     dim3 grid((unsigned)((waves + 3) / 4));
-    k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ><<<grid, 256, 0, st>>>(
+    k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ, PF><<<grid, 256, 0, st>>>(
         p.C, ncg, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles, (const T *)X, xs, cx,
         (const T *)IN, in_is_x ? 1 : 0, cbd, cbo, (const T *)Z, cz, (T *)out);
 }
@@ -377,6 +575,44 @@ void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, c
         stencil_shape<float, 1>(p, X, xs, cx, IN, in_is_x, bd, bo, Z, cz, out, st);
     else
         stencil_shape<double, 1>(p, X, xs, cx, IN, in_is_x, bd, bo, Z, cz, out, st);
+}
+
+}  // namespace ecnt
+
+namespace ecnt {
+
+template <typename T, int VW, bool HASZ>
+static void quad_t(const Plan &p, const void *X, const double *xs, double c1, double bd1,
+                   double bo1, double c2, double bd2, double bo2, const void *Z, double cz,
+                   void *out, hipStream_t st)
+{
+    const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
+    dim3 grid((unsigned)(p.ntiles * ncg));
+    k_quad_sweep<T, VW, HASZ><<<grid, 256, 0, st>>>(p.C, ncg, p.nseg, p.seg_row, p.seg_tile,
+                                                    p.seg_dims, p.ntiles, (const T *)X, xs, c1,
+                                                    bd1, bo1, c2, bd2, bo2, (const T *)Z, cz,
+                                                    (T *)out);
+}
+
+bool quad_sweep_supported(const Plan &p) { return p.tx == 4 && p.ty == 4 && !p.no_fuse; }
+
+void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1, double cb,
+                       double c2, const void *Z, double cz, void *out, hipStream_t st)
+{
+    const double w = p.hi - p.lo;
+    const double bd = (2.0 * (2.0 * p.ndim + p.s) - (p.lo + p.hi)) / w;
+    const double bo = 2.0 / w;
+    const double bd1 = cb * bd, bo1 = cb * 2.0 / w;
+    if (p.vec_f32 && p.C % 2 == 0) {
+        if (Z) quad_t<float, 2, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_t<float, 2, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+    } else if (p.vec_f32) {
+        if (Z) quad_t<float, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_t<float, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+    } else {
+        if (Z) quad_t<double, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_t<double, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+    }
 }
 
 }  // namespace ecnt

@@ -257,6 +257,7 @@ def test_parity_column_waves_jacobi(ec):
 
 
 @pytest.mark.parametrize("tune", [{"tile": "2x4"}, {"tile": "1x8"}, {"tile": "4x4"},
+                                  {"tile": "4x4-unfused"},
                                   {"red_waves": 64}, {"red_waves": 65536}, {"csr_vw": 1},
                                   {"tile": "2x4", "red_waves": 8192, "csr_vw": 1}])
 def test_parity_launch_shapes(ec, tune):
@@ -268,16 +269,31 @@ def test_parity_launch_shapes(ec, tune):
 
 
 def test_stencil_tile_shapes_bitwise(ec):
-    """The stencil computes each grid point the same way whatever the line
-    block, so the tile shape alone changes no bit of the result."""
+    """The plain stencil sweep computes each grid point the same way whatever
+    the line block, so the tile shape alone changes no bit of the result."""
     wl = W.WORKLOADS["c2_ragged"]
     P = W.make_problem(wl)
     V = W.make_probes(wl)
     outs = [gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": t})
-            for t in ("4x4", "2x4", "1x8")]
+            for t in ("4x4-unfused", "2x4", "1x8")]
     for o in outs[1:]:
         assert o.estimate == outs[0].estimate
         assert torch.equal(o.per_probe, outs[0].per_probe)
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c2_ragged"])
+def test_fused_quadratic_sweep_matches_two_sweeps(ec, name):
+    """Each quadratic factor of the preconditioner in one fused sweep against
+    the same factor as two plain sweeps: the same values up to rounding (the
+    fused form sums in the same order; only FMA contraction may differ)."""
+    wl = W.WORKLOADS[name]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    a = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": "4x4"})
+    b = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": "4x4-unfused"})
+    nu = float(P.A.n)
+    assert abs(a.estimate - b.estimate) <= 1e-12 * max(1.0, abs(b.estimate))
+    assert float((a.per_probe - b.per_probe).abs().max()) <= 1e-12 * nu
 
 
 # FP32 storage form: A values, probes, Lanczos vectors and basis in FP32;
