@@ -138,8 +138,16 @@ def bench_batched(args, name: str):
     Vd = W.rademacher_torch(int(off[-1]), m, 4242, device="cuda", dtype=tdt)
     free, _total = torch.cuda.mem_get_info()
     budget = free - (16 << 30)
-    cfg = autotune.tune_batch(A, prec, sizes, taus, Vd, k, dims=dims, vec=vec, mem_bytes=budget,
-                              retune=args.retune, log=log)
+    if args.tune == "off":
+        Ct = S * m
+        w = Ct
+        while w > 32 and ec.batch_workspace_bytes(sizes, dims, S, m, prec, k, vec=vec,
+                                                  max_cols=0 if w == Ct else w) > budget:
+            w //= 2
+        cfg = {"max_cols": w, "tile": "auto", "red_waves": 0, "csr_vw": 0, "source": "defaults"}
+    else:
+        cfg = autotune.tune_batch(A, prec, sizes, taus, Vd, k, dims=dims, vec=vec,
+                                  mem_bytes=budget, retune=args.tune == "search", log=log)
     log("launch shape (%s): %s" % (cfg["source"], {x: cfg[x] for x in ("max_cols", "tile",
                                                                       "red_waves", "csr_vw")}))
     Ct = S * m
@@ -317,8 +325,10 @@ def main():
     ap.add_argument("--pmc-dir", help="with --summarize: directory holding the counter runs")
     ap.add_argument("--command", default="", help="with --summarize: the profiled command")
     ap.add_argument("--counters-json", help="with --summarize: write calibrated per-launch bytes here")
-    ap.add_argument("--retune", action="store_true", help="batched workloads: search launch shapes "
-                    "again instead of using the tuning cache")
+    ap.add_argument("--tune", choices=["auto", "off", "search"], default="auto",
+                    help="launch shapes: auto = tuned table (user cache, then the shipped one) or "
+                    "a search if the size class is in neither; off = built-in defaults; search = "
+                    "search again")
     args = ap.parse_args()
 
     if args.summarize:
@@ -362,6 +372,17 @@ def main():
     grad = wl.smooth_w > 0.0
     # FP32 128^3 form: one shift (m columns) per wave bounds the basis to 124 GiB
     max_cols = wl.m if wl.name == "c3" else 0
+    tune, tuned = None, None
+    if not grad and args.tune != "off":
+        from paper_1602_02306_amd import autotune
+        free, _total = torch.cuda.mem_get_info()
+        cfg = autotune.tune_count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec,
+                                  mem_bytes=free - (16 << 30), retune=args.tune == "search",
+                                  log=log)
+        max_cols = 0 if cfg["max_cols"] == S * wl.m else cfg["max_cols"]
+        tune = {x: cfg[x] for x in autotune.DEFAULTS}
+        tuned = {"source": cfg["source"], "max_cols": cfg["max_cols"], **tune}
+        log("launch shape (%s): %s" % (cfg["source"], tuned))
     if grad:
         need = ec.smooth_workspace_bytes(wl.n, wl.m, P.prec, wl.k, wl.smooth_w)
     else:
@@ -374,7 +395,7 @@ def main():
     def one():
         if not grad:
             return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
-                            workspace=ws, details=False, max_cols=max_cols)
+                            workspace=ws, details=False, max_cols=max_cols, tune=tune)
         # differentiated form: forward keeping the basis, then the backward
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
@@ -485,6 +506,8 @@ def main():
             "workspace_gib": need / 2 ** 30}
     if max_cols:
         out["config"]["column_waves"] = "%d columns per wave" % max_cols
+    if tuned:
+        out["config"]["launch_shape"] = tuned
     if not args.no_cpu_baseline:
         V = Vd.cpu().double().numpy()
         out["cpu_baseline"] = cpu_baseline(P, V, wl, args.cpu_seconds)

@@ -26,9 +26,24 @@ from typing import Callable
 DEFAULTS = {"tile": "auto", "red_waves": 0, "csr_vw": 0}
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
 def cache_path() -> str:
     return os.environ.get("ECNT_TUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache", "ecount", "tune.json"))
+
+
+def lookup(key: str, cache: str | None = None):
+    """Tuned entry for a size class: the user cache first, then the table
+    shipped with the package (measured on an MI355X); None if neither has it."""
+    for path, src in ((cache or cache_path(), "cache"), (SHIPPED, "shipped")):
+        e = load_cache(path).get(key)
+        if e:
+            e = dict(e)
+            e["source"] = src
+            return e
+    return None
 
 
 def size_class(n: int, nprob: int, cols: int, k: int, vec: str, prec_kind: str) -> str:
@@ -102,7 +117,6 @@ def tune_batch(A, prec, sizes, taus, probes, k: int, dims=None, vec: str = "f64"
     mem_bytes bounds the workspace of the full-k run (column waves are
     narrowed until it fits)."""
     import numpy as np
-    import torch
     from . import ecount as ec
 
     taus = np.atleast_2d(taus)
@@ -110,17 +124,35 @@ def tune_batch(A, prec, sizes, taus, probes, k: int, dims=None, vec: str = "f64"
     m = probes.shape[1]
     Ct = S * m
     key = size_class(int(probes.shape[0]), nprob, Ct, k, vec, prec.kind)
-    entries = load_cache(cache)
-    if key in entries and not retune:
-        e = dict(entries[key])
-        e["source"] = "cache"
-        return e
+    if not retune:
+        e = lookup(key, cache)
+        if e:
+            return e
+    kt = max(2, min(k, k_tune))
+
+    def need_bytes(kk, w):
+        return ec.batch_workspace_bytes(sizes, dims, S, m, prec, kk, vec=vec,
+                                        max_cols=0 if w == Ct else w)
+
+    def make_run(ws):
+        def run_ms(cfg):
+            tune = {x: cfg[x] for x in DEFAULTS}
+            bt = ec.Batch(A, prec, sizes, taus, probes, kt, dims=dims, vec=vec, workspace=ws,
+                          max_cols=0 if cfg["max_cols"] == Ct else cfg["max_cols"], tune=tune)
+            return _timed(lambda: bt.run(), reps) * k / kt
+        return run_ms
+
+    return _search(key, Ct, k, kt, vec, need_bytes, make_run, mem_bytes, probes.device, cache, log)
+
+
+def _search(key, Ct, k, kt, vec, need_bytes, make_run, mem_bytes, device, cache, log):
+    import torch
+    from . import ecount as ec
     # column-wave widths whose full-k workspace fits
     widths = []
     w = Ct
     while w >= 32:
-        need = ec.batch_workspace_bytes(sizes, dims, S, m, prec, k, vec=vec,
-                                        max_cols=0 if w == Ct else w)
+        need = need_bytes(k, w)
         if need and (mem_bytes is None or need <= mem_bytes):
             widths.append(w)
         if len(widths) == 3:
@@ -128,24 +160,14 @@ def tune_batch(A, prec, sizes, taus, probes, k: int, dims=None, vec: str = "f64"
         w //= 2
     if not widths:
         raise RuntimeError("no column-wave width fits the memory budget")
-    kt = max(2, min(k, k_tune))
-    need = max(ec.batch_workspace_bytes(sizes, dims, S, m, prec, kt, vec=vec,
-                                        max_cols=0 if w == Ct else w) for w in widths)
-    ws = ec.Workspace(max(need, 1), probes.device)
-
-    def run_ms(cfg):
-        tune = {x: cfg[x] for x in DEFAULTS}
-        bt = ec.Batch(A, prec, sizes, taus, probes, kt, dims=dims, vec=vec, workspace=ws,
-                      max_cols=0 if cfg["max_cols"] == Ct else cfg["max_cols"], tune=tune)
-        return _timed(lambda: bt.run(), reps) * k / kt
-
+    ws = ec.Workspace(max(max(need_bytes(kt, w) for w in widths), 1), device)
     space = {"max_cols": widths,
-             "tile": ["4x4", "2x4", "1x8"],
+             "tile": ["4x4", "4x4-unfused", "2x4", "1x8"],
              "red_waves": [1024, 2048, 4096, 8192],
              "csr_vw": [1, 2] + ([4] if vec == "f32" else [])}
     start = {"max_cols": widths[0], "tile": "auto", "red_waves": 0, "csr_vw": 0}
     t0 = time.perf_counter()
-    best, best_ms, trials = coordinate_search(run_ms, space, start, log=log)
+    best, best_ms, trials = coordinate_search(make_run(ws), space, start, log=log)
     del ws
     torch.cuda.empty_cache()
     entry = dict(best)
@@ -160,3 +182,32 @@ def tune_batch(A, prec, sizes, taus, probes, k: int, dims=None, vec: str = "f64"
     entry = dict(entry)
     entry["source"] = "search"
     return entry
+
+
+def tune_count(A, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
+               mem_bytes: int | None = None, k_tune: int = 8, reps: int = 3,
+               cache: str | None = None, retune: bool = False, log=None) -> dict:
+    """Best launch shape for an interval count (ecount.count arguments), as
+    tune_batch for a single problem."""
+    from . import ecount as ec
+    n, m = probes.shape
+    Ct = 2 * m
+    key = size_class(int(n), 1, Ct, k, vec, prec.kind)
+    if not retune:
+        e = lookup(key, cache)
+        if e:
+            return e
+    kt = max(2, min(k, k_tune))
+
+    def need_bytes(kk, w):
+        return ec.workspace_bytes(n, m, 2, prec, kk, vec=vec, max_cols=0 if w == Ct else w)
+
+    def make_run(ws):
+        def run_ms(cfg):
+            tune = {x: cfg[x] for x in DEFAULTS}
+            mc = 0 if cfg["max_cols"] == Ct else cfg["max_cols"]
+            return _timed(lambda: ec.count(A, prec, xi, eta, probes, kt, vec=vec, workspace=ws,
+                                           details=False, max_cols=mc, tune=tune), reps) * k / kt
+        return run_ms
+
+    return _search(key, Ct, k, kt, vec, need_bytes, make_run, mem_bytes, probes.device, cache, log)

@@ -37,9 +37,14 @@ __global__ __launch_bounds__(256) void k_jacobi_diag(int64_t n, int S, int nseg,
 
 // y(r, c) = xs_c * d_s(r) * ( sum_p a_{r,j_p} d_s(j_p) x(j_p, c) - tau_s d_s(r) x(r, c) )
 // with d_s the Jacobi scaling of shift s = c / m (or 1 without preconditioner).
-// One wavefront per row; the row's nonzeros are taken four at a time with
-// clamped indices so that four row segments are loaded together.
-template <typename T, typename VT, bool JAC, int VW>
+// One wavefront per group of RPW consecutive rows; the nonzeros of all the
+// group's rows are taken NZ per row at a time with clamped indices, so that
+// NZ*RPW row segments are loaded together (with NZ = 8 a 7-point stencil row
+// in one pass).  Each row sums its nonzeros in CSR order.  Block order:
+// column groups fastest; `remap` spreads contiguous row ranges over the XCDs
+// (each XCD's L2 then sees its own rows' neighbours), otherwise all XCDs walk
+// the rows together and rows a grid plane apart meet in the shared cache.
+template <typename T, typename VT, bool JAC, int VW, int RPW, int NZ>
 __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_off, int ncg, int S,
                                                 int nseg, const int64_t *__restrict__ seg_row,
                                                 const int32_t *__restrict__ rp,
@@ -47,61 +52,87 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
                                                 const VT *__restrict__ val, const T *__restrict__ x,
                                                 const double *__restrict__ xs,
                                                 const double *__restrict__ jac,
-                                                const double *__restrict__ seg_taus, T *__restrict__ y)
+                                                const double *__restrict__ seg_taus, T *__restrict__ y,
+                                                int remap)
 {
-    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t L = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int cg = (int)(L % ncg);
-    const int64_t r = (L / ncg) * 4 + uniform(threadIdx.x >> 6);
+    const int64_t r0 = ((L / ncg) * 4 + uniform(threadIdx.x >> 6)) * RPW;
     const int lane = threadIdx.x & 63;
     const int c0 = (cg * 64 + lane) * VW;
-    if (r >= n || c0 >= C) return;
-    const int seg = find_seg(seg_row, nseg, r);
-    const double *taus = seg_taus + (size_t)seg * S;
-    double tau[VW], xsc[VW];
+    if (r0 >= n || c0 >= C) return;
+    int64_t row[RPW];
+    int p0[RPW], len[RPW], maxlen = 0;
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        row[i] = min(r0 + i, n - 1);   // rows past the end repeat the last one (not stored)
+        p0[i] = rp[row[i]];
+        len[i] = rp[row[i] + 1] - p0[i];
+        maxlen = max(maxlen, len[i]);
+    }
+    // an index inside the longest row: where the loads of shorter rows are clamped
+    int safe = p0[0];
+#pragma unroll
+    for (int i = RPW - 1; i >= 0; --i)
+        if (len[i] == maxlen) safe = p0[i];
+    double acc[RPW][VW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[i][v] = 0.0;
     const double *js[VW];
+    int sh[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) {
-        const int s = (c_off + c0 + v) / m;
-        tau[v] = taus[s];
-        xsc[v] = xs ? xs[(size_t)seg * C + c0 + v] : 1.0;
-        js[v] = JAC ? jac + (size_t)s * n : nullptr;
+        sh[v] = (c_off + c0 + v) / m;
+        js[v] = JAC ? jac + (size_t)sh[v] * n : nullptr;
     }
-    const int p0 = rp[r], p1 = rp[r + 1];
-    double acc[VW];
+    for (int p = 0; p < maxlen; p += NZ) {
+        int j[RPW][NZ];
+        double a[RPW][NZ];
 #pragma unroll
-    for (int v = 0; v < VW; ++v) acc[v] = 0.0;
-    for (int p = p0; p < p1; p += 4) {
-        int j[4];
-        double a[4];
+        for (int i = 0; i < RPW; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int pp = min(p + q, p1 - 1);
-            j[q] = ci[pp];
-            a[q] = (p + q < p1) ? static_cast<double>(val[pp]) : 0.0;
-        }
-        double xv[4][VW];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) vload<T, VW>(x, (size_t)j[q] * C + c0, xv[q]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < VW; ++v) {
-                double xq = xv[q][v];
-                if (JAC) xq *= js[v][j[q]];
-                acc[v] += a[q] * xq;
+            for (int q = 0; q < NZ; ++q) {
+                const bool ok = p + q < len[i];
+                const int pp = ok ? p0[i] + p + q : safe;
+                j[i][q] = ci[pp];
+                a[i][q] = ok ? static_cast<double>(val[pp]) : 0.0;
             }
-    }
-    double xr[VW], out[VW];
-    vload<T, VW>(x, (size_t)r * C + c0, xr);
+        double xv[RPW][NZ][VW];
 #pragma unroll
-    for (int v = 0; v < VW; ++v) {
-        double xv = xr[v];
-        if (JAC) xv *= js[v][r];
-        double o = acc[v] - tau[v] * xv;
-        if (JAC) o *= js[v][r];
-        out[v] = o * xsc[v];
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int q = 0; q < NZ; ++q) vload<T, VW>(x, (size_t)j[i][q] * C + c0, xv[i][q]);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int q = 0; q < NZ; ++q)
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    double xq = xv[i][q][v];
+                    if (JAC) xq *= js[v][j[i][q]];
+                    acc[i][v] += a[i][q] * xq;
+                }
     }
-    vstore<T, VW>(y, (size_t)r * C + c0, out);
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int64_t r = row[i];
+        const int seg = find_seg(seg_row, nseg, r);
+        const double *taus = seg_taus + (size_t)seg * S;
+        double xr[VW], out[VW];
+        vload<T, VW>(x, (size_t)r * C + c0, xr);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            double xv = xr[v];
+            if (JAC) xv *= js[v][r];
+            double o = acc[i][v] - taus[sh[v]] * xv;
+            if (JAC) o *= js[v][r];
+            const double xsc = xs ? xs[(size_t)seg * C + c0 + v] : 1.0;
+            out[v] = o * xsc;
+        }
+        if (r0 + i < n) vstore<T, VW>(y, (size_t)r * C + c0, out);
+    }
 }
 
 // One stencil sweep on the grid Laplacian L (diagonal 2*ndim, neighbours -1):
@@ -118,7 +149,7 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
 // row loads per TX*TY outputs instead of 5 per output.  Lines outside the
 // grid (ragged blocks, Dirichlet boundary) are loaded from a clamped address
 // with weight 0, so every load of a z step is issued together.
-template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ, bool PF>
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
 __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                                                  const int64_t *__restrict__ seg_row,
                                                  const int64_t *__restrict__ seg_tile,
@@ -130,9 +161,13 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                                                  T *__restrict__ out)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    // column-group-major: the waves of a workgroup and consecutive workgroups
+    // take neighbouring line blocks of one column group, so that boundary
+    // lines loaded by one block are still in cache for its neighbours
     const int64_t gw = L * 4 + uniform(threadIdx.x >> 6);
-    const int cg = (int)(gw % ncg);
-    const int64_t tile = gw / ncg;
+    const int cg = (int)(gw / ntiles);
+    const int64_t tile = gw % ntiles;
+    if (cg >= ncg) return;
     const int lane = threadIdx.x & 63;
     const int c0 = (cg * 64 + lane) * VW;
     if (tile >= ntiles || c0 >= C) return;
@@ -271,33 +306,21 @@ __global__ __launch_bounds__(256) void k_stencil(int C, int ncg, int nseg,
                     }
         }
     };
-    if constexpr (!PF) {
-        // all loads of a step issued together, then the step computed
-        for (int z = 0; z < d2; ++z) {
-            StepLoads L;
-            issue(L, z);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(L, z);
-        }
-    } else {
-        // software pipeline: the loads of step z+1 are in flight while step z
-        // is computed and stored
-        StepLoads A;
-        issue(A, 0);
-        for (int z = 0; z < d2; ++z) {
-            const StepLoads L = A;
-            if (z + 1 < d2) issue(A, z + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            compute(L, z);
-        }
+    // all loads of a step issued together, then the step computed
+    for (int z = 0; z < d2; ++z) {
+        StepLoads L;
+        issue(L, z);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(L, z);
     }
 }
 
 // ---- one quadratic factor of the preconditioner in a single sweep ----
 //   t = c1*u + cb*B(u),  out = B(t) + c2*u - cz*Z,   u = xs_c * X
-// which is (B^2 + (c1/cb... ) ) applied as the two sweeps above would apply
-// it, with t never written to memory: 1 read and 1 write of a block vector
-// instead of 3 reads and 2 writes.  t is rounded to the storage type as the
+// i.e. the factor cb*(B^2 - 2a B + b) of the product form (c1 = -2a*cb,
+// c2 = b*cb) computed as the two plain sweeps compute it, with t never
+// written to memory: 1 read and 1 write of a block vector instead of 3 reads
+// and 2 writes.  t is rounded to the storage type as the
 // two-sweep form stores it, and every value is summed in the same order.
 //
 // A workgroup owns a 4 x 4 block of z-lines (the line blocks of the plain
@@ -329,8 +352,8 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
 {
     using namespace quad;
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const int cg = (int)(L % ncg);
-    const int64_t tile = L / ncg;
+    const int cg = (int)(L / ntiles);   // column-group-major, as in the plain sweep
+    const int64_t tile = L % ntiles;
     const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int c0 = (cg * 64 + lane) * VW;
     if (tile >= ntiles || c0 >= C) return;
@@ -391,25 +414,29 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
     for (int q = 0; q < 8; ++q)
 #pragma unroll
         for (int v = 0; v < VW; ++v) r1[q][v] = zero;
-    for (int z = 0; z <= d2; ++z) {
-        const int64_t ez = base + (int64_t)z * zs;
-        const bool has_t = z < d2;                 // t at plane z exists
-        const bool has_n = z + 1 < d2;             // u at plane z+1 exists
-        const int64_t en = has_n ? ez + zs : base; // clamped
-        const int64_t ec = has_t ? ez : base;
-        const int64_t ep = z >= 1 ? ez - zs : base;
+    // loads of iteration z: u at z+1 on lines 0..11, u at z on lines 12..23,
+    // Z at z-1 on lines 0..3 (addresses clamped past the ends)
+    struct StepLoads {
         T un[12][VW], u2[12][VW], zv[4][VW];
+    };
+    auto issue = [&](StepLoads &S, int z) {
+        const int64_t ez = base + (int64_t)z * zs;
+        const int64_t en = z + 1 < d2 ? ez + zs : base;
+        const int64_t ec = z < d2 ? ez : base;
+        const int64_t ep = z >= 1 ? ez - zs : base;
 #pragma unroll
-        for (int q = 0; q < 12; ++q) ldT(X, en + off[q], un[q]);
+        for (int q = 0; q < 12; ++q) ldT(X, en + off[q], S.un[q]);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) ldT(X, ec + off[12 + q], u2[q]);
+        for (int q = 0; q < 12; ++q) ldT(X, ec + off[12 + q], S.u2[q]);
         if (HASZ) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ldT(Z, ep + off[q], zv[q]);
+            for (int q = 0; q < 4; ++q) ldT(Z, ep + off[q], S.zv[q]);
         }
-        __builtin_amdgcn_sched_barrier(0);
-        const double zn = has_n ? 1.0 : 0.0;
-        const double tz = has_t ? 1.0 : 0.0;
+    };
+    auto compute = [&](const StepLoads &S, int z) {
+        const int64_t ep = z >= 1 ? base + (int64_t)(z - 1) * zs : base;
+        const bool has_t = z < d2;                 // t at plane z exists
+        const double zn = z + 1 < d2 ? 1.0 : 0.0;  // u at plane z+1 exists
         // t at plane z on lines 0..11 (zero outside the grid and past the last plane)
         T tn[12][VW];
 #pragma unroll
@@ -417,14 +444,14 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
                 auto uat = [&](int r) -> double {
-                    return r < 12 ? (double)u0[r][v] : w[r] * (double)u2[r - 12][v];
+                    return r < 12 ? (double)u0[r][v] : w[r] * (double)S.u2[r - 12][v];
                 };
                 const double cu = u0[q][v];
-                const double nb = (double)um[q][v] + zn * (double)un[q][v] + uat(NYM[q]) +
+                const double nb = (double)um[q][v] + zn * (double)S.un[q][v] + uat(NYM[q]) +
                                   uat(NYP[q]) + uat(NXM[q]) + uat(NXP[q]);
                 double t = c1 * xsc[v] * cu;
                 t += xsc[v] * (bd1 * cu - bo1 * nb);
-                tn[q][v] = (tz != 0.0 && w[q] != 0.0) ? static_cast<T>(t) : zero;
+                tn[q][v] = (has_t && w[q] != 0.0) ? static_cast<T>(t) : zero;
             }
         // out at plane z-1 on lines 0..3
         if (z >= 1) {
@@ -441,7 +468,7 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
                                       tat(NYP[q]) + tat(NXM[q]) + tat(NXP[q]);
                     double val = c2 * xsc[v] * (double)um[q][v];
                     val += 1.0 * (bd2 * (double)tm1[q][v] - bo2 * nb);
-                    if (HASZ) val -= cz * (double)zv[q][v];
+                    if (HASZ) val -= cz * (double)S.zv[q][v];
                     o[v] = val;
                 }
                 if (w[q] != 0.0) vstore<T, VW>(out, ep + off[q], o);
@@ -460,9 +487,15 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
                 um[q][v] = u0[q][v];
-                u0[q][v] = w[q] != 0.0 ? un[q][v] : zero;
+                u0[q][v] = w[q] != 0.0 ? S.un[q][v] : zero;
             }
         }
+    };
+    for (int z = 0; z <= d2; ++z) {
+        StepLoads S;
+        issue(S, z);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(S, z);
     }
 }
 
@@ -478,20 +511,24 @@ void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *co
                                                     (const double *)val, p.seg_taus, p.jac, p.flags);
 }
 
-template <typename T, typename VT, int VW>
+// Measured shapes: 8-byte columns two per lane, two rows per wave, 8-nonzero
+// chunks, linear block order; 4-byte columns four per lane, one row per wave,
+// 4-nonzero chunks, XCD-remapped order.
+template <typename T, typename VT, int VW, int RPW = (VW == 4 ? 1 : 2), int NZ = (VW == 4 ? 4 : 8)>
 static void csr_op_t(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
-                     const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
+                     const void *x, const double *xs, const double *jac, void *y, hipStream_t st,
+                     int remap = (VW == 4 ? 1 : 0))
 {
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
-    dim3 grid((unsigned)(((p.n + 3) / 4) * ncg));
+    dim3 grid((unsigned)(((p.n + 4 * RPW - 1) / (4 * RPW)) * ncg));
     if (jac)
-        k_csr_op<T, VT, true, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg,
-                                                        p.seg_row, rp, ci, (const VT *)val,
-                                                        (const T *)x, xs, jac, p.seg_taus, (T *)y);
+        k_csr_op<T, VT, true, VW, RPW, NZ><<<grid, 256, 0, st>>>(
+            p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, rp, ci, (const VT *)val,
+            (const T *)x, xs, jac, p.seg_taus, (T *)y, remap);
     else
-        k_csr_op<T, VT, false, VW><<<grid, 256, 0, st>>>(p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg,
-                                                         p.seg_row, rp, ci, (const VT *)val,
-                                                         (const T *)x, xs, nullptr, p.seg_taus, (T *)y);
+        k_csr_op<T, VT, false, VW, RPW, NZ><<<grid, 256, 0, st>>>(
+            p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, rp, ci, (const VT *)val,
+            (const T *)x, xs, nullptr, p.seg_taus, (T *)y, remap);
 }
 
 template <typename T, typename VT>
@@ -520,7 +557,7 @@ void launch_csr_op(const Plan &p, const int32_t *rp, const int32_t *ci, const vo
     }
 }
 
-template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ, bool PF = false>
+template <typename T, int VW, int TX, int TY, bool HASIN, bool XSEP, bool HASZ>
 static void stencil_t(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
                       bool in_is_x, double cbd, double cbo, const void *Z, double cz, void *out,
                       hipStream_t st)
@@ -528,7 +565,7 @@ static void stencil_t(const Plan &p, const void *X, const double *xs, double cx,
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
     const int64_t waves = p.ntiles * ncg;
     dim3 grid((unsigned)((waves + 3) / 4));
-    k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ, PF><<<grid, 256, 0, st>>>(
+    k_stencil<T, VW, TX, TY, HASIN, XSEP, HASZ><<<grid, 256, 0, st>>>(
         p.C, ncg, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles, (const T *)X, xs, cx,
         (const T *)IN, in_is_x ? 1 : 0, cbd, cbo, (const T *)Z, cz, (T *)out);
 }
@@ -582,7 +619,7 @@ void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, c
 namespace ecnt {
 
 template <typename T, int VW, bool HASZ>
-static void quad_t(const Plan &p, const void *X, const double *xs, double c1, double bd1,
+static void quad_sweep_t(const Plan &p, const void *X, const double *xs, double c1, double bd1,
                    double bo1, double c2, double bd2, double bo2, const void *Z, double cz,
                    void *out, hipStream_t st)
 {
@@ -604,14 +641,14 @@ void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1
     const double bo = 2.0 / w;
     const double bd1 = cb * bd, bo1 = cb * 2.0 / w;
     if (p.vec_f32 && p.C % 2 == 0) {
-        if (Z) quad_t<float, 2, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
-        else quad_t<float, 2, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        if (Z) quad_sweep_t<float, 2, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_sweep_t<float, 2, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
     } else if (p.vec_f32) {
-        if (Z) quad_t<float, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
-        else quad_t<float, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        if (Z) quad_sweep_t<float, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_sweep_t<float, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
     } else {
-        if (Z) quad_t<double, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
-        else quad_t<double, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        if (Z) quad_sweep_t<double, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        else quad_sweep_t<double, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
     }
 }
 
