@@ -237,7 +237,10 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
-FAMILY_OF = [("k_stencil", "op_cheb_sweep"), ("k_csr_op", "op_csr"), ("k_dots_fin", "lz_finalize"),
+FAMILY_OF = [("k_quad_sweep", "op_cheb_quad"), ("k_bdots_fin", "lz_finalize"),
+             ("k_bnorm_fin", "lz_finalize"), ("k_rowsum", "lz_finalize"), ("k_vgrad", "bw_vgrad"),
+             ("k_bdots", "bw_dots"), ("k_bupdate", "bw_update"), ("k_grad_", "lz_finalize"),
+             ("k_stencil", "op_cheb_sweep"), ("k_csr_op", "op_csr"), ("k_dots_fin", "lz_finalize"),
              ("k_dots", "lz_dots"), ("k_update", "lz_update"), ("k_setup_fin", "lz_finalize"),
              ("k_setup", "lz_setup"), ("k_norm_fin", "lz_finalize"), ("k_jacobi_diag", "lz_setup"),
              ("k_tridiag", "quadrature"), ("k_reduce", "quadrature"), ("k_init", "lz_finalize"),
