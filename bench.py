@@ -31,6 +31,7 @@ WORKLOAD_TEXT = {
     "c1": "2D 5-pt 30x30 + V~U[0,1] (seed 0), CSR, Jacobi M per shift, [0.5,1.5], m=40, k=20, FP64",
     "c2": "3D 7-pt 64^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=256, k=30, FP64",
     "c3": "3D 7-pt 128^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=512, k=30, FP32 vectors",
+    "c2_f32": "the 64^3 problem of c2 with A values and all Lanczos vectors in FP32 (FP64 alpha/beta, dots, eigensolve)",
     "c5": "3D 7-pt 96^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M, erf-smoothed count w=0.05, [-8,-2], m=128, k=30",
     "c4": "64 independent 3D 7-pt Gaussian-well Hamiltonians, N^3 grids with N~U{16..64} (seeds 1000+b), "
           "4 sorted shifts ~U[-8,-2] each (3 intervals), Chebyshev M=c4(L+I), m=64, k=25, one "
@@ -63,17 +64,24 @@ def copy_calib(nbytes: int = 1 << 30):
     print(json.dumps({"copy_calib_bytes_each_way": nbytes, "launches": 3}), flush=True)
 
 
-def cpu_baseline(P, V, wl, target_s: float):
+def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
+    """The oracle timed on a bounded sample of the probes (whole probes, both
+    shifts).  With the GPU's per-probe values of the same run, also how far
+    they are from the oracle's on the sampled probes (relative to |v|^2 = n)."""
     import oracle
     threads = oracle.host_threads()
     m = V.shape[1]
     done, t_tot, batch = 0, 0.0, max(1, min(threads, m))
+    worst = 0.0
     while done < m:
         s = min(batch, m - done)
         t0 = time.perf_counter()
-        oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads,
-                     smooth_w=wl.smooth_w)
+        ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads,
+                           smooth_w=wl.smooth_w)
         dt = time.perf_counter() - t0
+        if gpu_per_probe is not None:
+            gx, ge = gpu_per_probe[done:done + s], gpu_per_probe[m + done:m + done + s]
+            worst = max(worst, float(np.max(np.abs(gx - ref.s_xi))), float(np.max(np.abs(ge - ref.s_eta))))
         t_tot += dt
         done += s
         log("cpu oracle: %d probes in %.1f s (total %.1f s)" % (s, dt, t_tot))
@@ -82,9 +90,12 @@ def cpu_baseline(P, V, wl, target_s: float):
         per = t_tot / done
         batch = max(1, min(m - done, int((target_s - t_tot) / per) + 1, 4 * threads))
     steps = 2 * done * wl.k
-    return {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
-                      % (done, m, wl.k, steps, t_tot)}
+    out = {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
+           "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
+                     % (done, m, wl.k, steps, t_tot)}
+    if gpu_per_probe is not None:
+        out["gpu_vs_oracle_max_abs_per_probe_over_n"] = worst / wl.n
+    return out
 
 
 def cpu_baseline_batch(items, V, off, k: int, target_s: float, m_total: int):
@@ -181,7 +192,7 @@ def bench_batched(args, name: str):
     assert np.array_equal(r2.negcounts, r.negcounts)
     fams = {f: v for f, v in ec.profile_read().items() if v["launches"] > 0}
     total_kernel_ms = sum(v["ms"] for v in fams.values())
-    dom = max(fams, key=lambda f: fams[f]["ms"])
+    dom = max((f for f in fams if fams[f]["bytes"] > 0), key=lambda f: fams[f]["ms"])
     d = fams[dom]
     per_launch_bytes = d["bytes"] / d["launches"]
     per_launch_ms = d["ms"] / d["launches"]
@@ -440,12 +451,13 @@ def main():
     fams = {k: v for k, v in prof.items() if v["launches"] > 0}
     total_kernel_ms = sum(v["ms"] for v in fams.values())
     algo_bytes = sum(v["bytes"] for v in fams.values()) / args.steps
-    dom = max(fams, key=lambda f: fams[f]["ms"])
+    # the dominant kernel: most time among the families that stream block vectors
+    dom = max((f for f in fams if fams[f]["bytes"] > 0), key=lambda f: fams[f]["ms"])
     d = fams[dom]
     per_launch_bytes = d["bytes"] / d["launches"]
     per_launch_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (per_launch_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(dom, per_launch_bytes)
+    traffic = traffic_from_profiles(dom, per_launch_bytes) if wl.name == "c2" else None
     kernels = {f: {"launches_per_step": v["launches"] / args.steps,
                    "ms_per_step": v["ms"] / args.steps,
                    "share": v["ms"] / total_kernel_ms if total_kernel_ms else None,
@@ -455,7 +467,9 @@ def main():
     exact = None
     gpath = os.path.join(ROOT, "tests", "golden", "exact_counts.json")
     if os.path.exists(gpath):
-        exact = json.load(open(gpath)).get(wl.name, {}).get("count")
+        golden = json.load(open(gpath))
+        # the FP32 storage form of a problem has the problem's exact count
+        exact = golden.get(wl.name, golden.get(wl.name.replace("_f32", ""), {})).get("count")
     accuracy = {"estimate": r.estimate, "std_error": math.sqrt(r.variance) if r.variance == r.variance else None,
                 "exact_count": exact, "method_exact": "LDL^T Sylvester inertia" if exact is not None else None,
                 "abs_error": abs(r.estimate - exact) if exact is not None else None,
@@ -511,9 +525,36 @@ def main():
         out["config"]["column_waves"] = "%d columns per wave" % max_cols
     if tuned:
         out["config"]["launch_shape"] = tuned
+    gpu_pp = None
+    if not grad:
+        # one more run with per-probe outputs (untimed): sampled parity against
+        # the oracle below, and the FP32 form against the FP64 path
+        rd = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws, details=True,
+                      max_cols=max_cols, tune=tune)
+        gpu_pp = rd.per_probe.cpu().numpy()
+        if vec == "f32":
+            del ws
+            torch.cuda.empty_cache()
+            A64 = ec.upload_csr(P.A, val_dtype="f64")
+            V64 = Vd.double()
+            free, _total = torch.cuda.mem_get_info()
+            w64 = 2 * wl.m
+            while w64 > 16 and ec.workspace_bytes(wl.n, wl.m, 2, P.prec, wl.k,
+                                                  max_cols=0 if w64 == 2 * wl.m else w64) > free - (8 << 30):
+                w64 //= 2
+            r64 = ec.count(A64, P.prec, wl.xi, wl.eta, V64, wl.k, details=True,
+                           max_cols=0 if w64 == 2 * wl.m else w64)
+            pp64 = r64.per_probe.cpu().numpy()
+            accuracy["fp64_path_estimate"] = r64.estimate
+            accuracy["fp32_minus_fp64_estimate"] = r.estimate - r64.estimate
+            accuracy["fp32_minus_fp64_max_abs_per_probe_over_n"] = float(np.max(np.abs(gpu_pp - pp64))) / wl.n
+            if exact is not None:
+                accuracy["fp64_path_abs_error"] = abs(r64.estimate - exact)
+            log("FP64 path on the same probes: %.6f (FP32 %.6f)" % (r64.estimate, r.estimate))
+            del A64, V64
     if not args.no_cpu_baseline:
         V = Vd.cpu().double().numpy()
-        out["cpu_baseline"] = cpu_baseline(P, V, wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(P, V, wl, args.cpu_seconds, gpu_pp)
     print(json.dumps(out), flush=True)
 
 

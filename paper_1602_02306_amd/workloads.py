@@ -300,6 +300,8 @@ WORKLOADS = {
     "c2": Workload("c2", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb", 256, 30),
     # 128^3, FP32 storage, 512 probes
     "c3": Workload("c3", (128, 128, 128), "wells", 1, -8.0, -2.0, "cheb", 512, 30, vec="f32"),
+    # the 64^3 problem in the FP32 storage form (its exact count is known)
+    "c2_f32": Workload("c2_f32", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb", 256, 30, vec="f32"),
     # 96^3, erf-smoothed count of width 0.05, 128 probes
     "c5": Workload("c5", (96, 96, 96), "wells", 1, -8.0, -2.0, "cheb", 128, 30, smooth_w=0.05),
     # small cases that the oracle finishes in seconds
