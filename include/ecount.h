@@ -127,11 +127,14 @@ typedef struct {
     /* Launch-shape tunables (0 = built-in default).  They change how the
        work is cut into workgroups, not what is computed: results move at
        most by the order of floating-point sums. */
-    int32_t tile;       /* stencil line block: 1 = 4x4 lines, 2 = 2x4, 3 = 1x8 (0: 4x4,
-                           or 1x8 when some grid has fewer than 4 x-planes).  With 4x4
+    int32_t tile;       /* stencil line block: 1 = 4x4 lines, 2 = 2x4, 3 = 1x8 (0: 1x8 when
+                           some grid has fewer than 4 x-planes, else 5 when it applies,
+                           else 4x4).  With 4x4
                            blocks each quadratic factor of the product-form
                            preconditioner runs as one fused sweep; 4 = 4x4 blocks with
-                           two plain sweeps per quadratic factor. */
+                           two plain sweeps per quadratic factor; 5 = 8x8 blocks, one
+                           workgroup of 16 wavefronts per block sharing lines through
+                           LDS (when every factor is quadratic; otherwise as 1). */
     int32_t red_waves;  /* target wavefronts of a column-reduction launch, 64..65536
                            (sets the rows per chunk of the two-phase sums; 0: 2048) */
     int32_t csr_vw;     /* columns per lane of the CSR sweep: 1, 2 (or 4 with FP32

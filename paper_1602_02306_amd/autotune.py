@@ -162,7 +162,7 @@ def _search(key, Ct, k, kt, vec, need_bytes, make_run, mem_bytes, device, cache,
         raise RuntimeError("no column-wave width fits the memory budget")
     ws = ec.Workspace(max(max(need_bytes(kt, w) for w in widths), 1), device)
     space = {"max_cols": widths,
-             "tile": ["4x4", "4x4-unfused", "2x4", "1x8"],
+             "tile": ["4x4", "8x8-wg", "4x4-unfused", "2x4", "1x8"],
              "red_waves": [1024, 2048, 4096, 8192],
              "csr_vw": [1, 2] + ([4] if vec == "f32" else [])}
     start = {"max_cols": widths[0], "tile": "auto", "red_waves": 0, "csr_vw": 0}

@@ -186,9 +186,14 @@ static void row_geometry(Plan &p, SegHost &sh)
     sh.tile.assign(p.nseg + 1, 0);
     bool thin = false;
     for (int b = 0; b < p.nseg; ++b) thin = thin || sh.dims[3 * b] < 4;
-    const int shape = p.req_tile > 0 ? p.req_tile : (thin ? 3 : 1);
-    p.tx = (shape == 1 || shape == 4) ? 4 : (shape == 2 ? 2 : 1);
-    p.ty = shape == 3 ? 8 : 4;
+    // 8 x 8 workgroup blocks serve the fused quadratic sweep only: every factor
+    // of the preconditioner must be quadratic
+    bool all_quad = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && p.product && p.nfac > 0;
+    for (int f = 0; f < p.nfac; ++f) all_quad = all_quad && p.fac_quad[f];
+    int shape = p.req_tile > 0 ? p.req_tile : (thin ? 3 : (all_quad ? 5 : 1));
+    if (shape == 5 && !all_quad) shape = 1;
+    p.tx = (shape == 1 || shape == 4) ? 4 : (shape == 2 ? 2 : (shape == 5 ? 8 : 1));
+    p.ty = (shape == 3 || shape == 5) ? 8 : 4;
     p.no_fuse = shape == 4 ? 1 : 0;
     for (int b = 0; b < p.nseg; ++b) {
         const int64_t nb = sh.row[b + 1] - sh.row[b];
@@ -308,7 +313,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     if (o->max_cols < 0) return fail(ECNT_EINVAL, "opts.max_cols must be >= 0");
     if (!(o->smooth_w >= 0.0) || !isfinite(o->smooth_w))
         return fail(ECNT_EINVAL, "smooth_w must be finite and >= 0");
-    if (o->tile < 0 || o->tile > 4) return fail(ECNT_EINVAL, "opts.tile must be 0..4");
+    if (o->tile < 0 || o->tile > 5) return fail(ECNT_EINVAL, "opts.tile must be 0..5");
     if (o->red_waves != 0 && (o->red_waves < 64 || o->red_waves > 65536))
         return fail(ECNT_EINVAL, "opts.red_waves must be 0 or 64..65536");
     if (o->csr_vw != 0 && o->csr_vw != 1 && o->csr_vw != 2 && o->csr_vw != 4)

@@ -499,6 +499,260 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
     }
 }
 
+// ---- the same quadratic factor, workgroup-cooperative ----
+// Sixteen wavefronts share one 8 x 8 block of z-lines for 64*VW columns: each
+// owns a 2 x 2 quadrant of output lines, and the quadrants on the block's
+// edge also own the adjacent lines of the distance-1 ring (where t is
+// needed).  Per z value the block's u on every line within distance 2
+// (132 lines) and its t on the block and ring (96 lines) pass through LDS,
+// so every u line is loaded from memory once per workgroup instead of once
+// per neighbouring quadrant.  Two barriers per z value; every wavefront runs
+// the same number of iterations and reaches every barrier.
+namespace quadwg {
+// the 36 lines at distance 2 from the 8 x 8 block, shared out round-robin
+constexpr int R2I[36] = {-2, -2, -2, -2, -2, -2, -2, -2, 9, 9, 9, 9, 9, 9, 9, 9, 0, 1,
+                         2,  3,  4,  5,  6,  7,  0,  1, 2, 3, 4, 5, 6, 7, -1, -1, 8, 8};
+constexpr int R2J[36] = {0, 1, 2, 3, 4,  5,  6,  7,  0,  1,  2,  3,  4, 5, 6, 7, -2, -2,
+                         -2, -2, -2, -2, -2, -2, 9, 9, 9, 9, 9, 9, 9, 9, -1, 8, -1, 8};
+constexpr int UW = 12;   // u plane: (i, j) in [-2, 10)^2 at (i + 2) * UW + (j + 2)
+constexpr int TW = 10;   // t plane: (i, j) in [-1, 9)^2 at (i + 1) * TW + (j + 1)
+}  // namespace quadwg
+
+template <typename T, int VW, bool HASZ>
+__global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg,
+                                                        const int64_t *__restrict__ seg_row,
+                                                        const int64_t *__restrict__ seg_tile,
+                                                        const int32_t *__restrict__ seg_dims,
+                                                        int64_t ntiles, const T *__restrict__ X,
+                                                        const double *__restrict__ xs_all,
+                                                        double c1, double bd1, double bo1, double c2,
+                                                        double bd2, double bo2,
+                                                        const T *__restrict__ Z, double cz,
+                                                        T *__restrict__ out)
+{
+    using namespace quadwg;
+    using V = typename VecT<T, VW>::type;
+    __shared__ V su[UW * UW * 64];
+    __shared__ V stp[TW * TW * 64];
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int cg = (int)(L / ntiles);   // column-group-major
+    const int64_t tile = L % ntiles;
+    const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    // lanes past the last column load column 0 and store nothing, and take
+    // part in every barrier
+    const int craw = (cg * 64 + lane) * VW;
+    const bool colok = craw < C;
+    const int c0 = colok ? craw : 0;
+    const int seg = find_seg(seg_tile, nseg, tile);
+    const int d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int nty = (d1 + 7) / 8;
+    const int lt = (int)(tile - seg_tile[seg]);
+    const int bx = (lt / nty) * 8, by = (lt % nty) * 8;   // block origin (inside the grid)
+    const double *xs = xs_all ? xs_all + (size_t)seg * C : nullptr;
+    const int64_t zs = C, ys = (int64_t)d2 * C, xst = (int64_t)d1 * d2 * C;
+    const int64_t base = (int64_t)seg_row[seg] * C + (int64_t)bx * xst + (int64_t)by * ys + c0;
+    auto inside = [&](int i, int j) { return bx + i < d0 && by + j < d1 && bx + i >= 0 && by + j >= 0; };
+    auto offset = [&](int i, int j) -> int64_t {
+        return inside(i, j) ? (int64_t)i * xst + (int64_t)j * ys : 0;
+    };
+    auto ldT = [&](int64_t e, T (&o)[VW]) {
+        const V x = *reinterpret_cast<const V *>(X + e);
+        if constexpr (VW == 1) {
+            o[0] = x;
+        } else {
+            o[0] = x.x;
+            o[1] = x.y;
+        }
+    };
+    auto toV = [](const T (&a)[VW]) {
+        V v;
+        if constexpr (VW == 1) {
+            v = a[0];
+        } else {
+            v.x = a[0];
+            v.y = a[1];
+        }
+        return v;
+    };
+    auto fromV = [](const V &v, int e) -> double {
+        if constexpr (VW == 1) {
+            (void)e;
+            return (double)v;
+        } else {
+            return (double)(e == 0 ? v.x : v.y);
+        }
+    };
+    const T zero = T(0);
+    // this wavefront's lines: 0..3 its quadrant, 4..5 the ring beside it in x,
+    // 6..7 the ring beside it in y (present on the block's edges only)
+    const int qx = wv >> 2, qy = wv & 3;
+    const bool hasX = qx == 0 || qx == 3, hasY = qy == 0 || qy == 3;
+    int LI[8], LJ[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        LI[q] = 2 * qx + (q >> 1);
+        LJ[q] = 2 * qy + (q & 1);
+    }
+    LI[4] = LI[5] = qx == 0 ? -1 : 8;
+    LJ[4] = 2 * qy;
+    LJ[5] = 2 * qy + 1;
+    LI[6] = 2 * qx;
+    LI[7] = 2 * qx + 1;
+    LJ[6] = LJ[7] = qy == 0 ? -1 : 8;
+    bool own[8];
+    int64_t off[8];
+    double w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        own[q] = q < 4 || (q < 6 ? hasX : hasY);
+        off[q] = own[q] ? offset(LI[q], LJ[q]) : 0;
+        w[q] = own[q] && inside(LI[q], LJ[q]) ? 1.0 : 0.0;
+    }
+    // ring-2 share
+    int64_t off2[3];
+    double w2[3];
+    int slot2[3];
+    bool has2[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int r = wv + 16 * s;
+        has2[s] = r < 36;
+        const int i = has2[s] ? R2I[r] : 0, j = has2[s] ? R2J[r] : 0;
+        off2[s] = has2[s] ? offset(i, j) : 0;
+        w2[s] = has2[s] && inside(i, j) ? 1.0 : 0.0;
+        slot2[s] = (i + 2) * UW + (j + 2);
+    }
+    double xsc[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) xsc[v] = xs ? xs[c0 + v] : 1.0;
+    T um[8][VW], u0[8][VW], r2[3][VW], tm2[4][VW], tm1[4][VW];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        T a[VW];
+        ldT(base + off[q], a);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            um[q][v] = zero;
+            u0[q][v] = w[q] != 0.0 ? a[v] : zero;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        T a[VW];
+        ldT(base + off2[s], a);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) r2[s][v] = w2[s] != 0.0 ? a[v] : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) tm2[q][v] = tm1[q][v] = zero;
+    for (int z = 0; z <= d2; ++z) {
+        const bool has_t = z < d2, has_n = z + 1 < d2;
+        const int64_t en = has_n ? (int64_t)(z + 1) * zs : 0;
+        const int64_t ep = z >= 1 ? (int64_t)(z - 1) * zs : 0;
+        // loads for the next z value (in flight during this one)
+        T un[8][VW], r2n[3][VW], zv[4][VW];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ldT(base + en + off[q], un[q]);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) ldT(base + en + off2[s], r2n[s]);
+        if (HASZ) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const V zz = *reinterpret_cast<const V *>(Z + base + ep + off[q]);
+                if constexpr (VW == 1) {
+                    zv[q][0] = zz;
+                } else {
+                    zv[q][0] = zz.x;
+                    zv[q][1] = zz.y;
+                }
+            }
+        }
+        // u at z into the shared plane
+        if (has_t) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (own[q]) su[((LI[q] + 2) * UW + (LJ[q] + 2)) * 64 + lane] = toV(u0[q]);
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                if (has2[s]) su[slot2[s] * 64 + lane] = toV(r2[s]);
+        }
+        __syncthreads();
+        // t at z on this wavefront's lines
+        const double zn = has_n ? 1.0 : 0.0;
+        T tn[8][VW];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!own[q] || !has_t) {
+#pragma unroll
+                for (int v = 0; v < VW; ++v) tn[q][v] = zero;
+                continue;
+            }
+            const int i = LI[q], j = LJ[q];
+            const V vym = su[((i + 2) * UW + (j + 1)) * 64 + lane];
+            const V vyp = su[((i + 2) * UW + (j + 3)) * 64 + lane];
+            const V vxm = su[((i + 1) * UW + (j + 2)) * 64 + lane];
+            const V vxp = su[((i + 3) * UW + (j + 2)) * 64 + lane];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                const double cu = u0[q][v];
+                const double nb = (double)um[q][v] + zn * (double)un[q][v] + fromV(vym, v) +
+                                  fromV(vyp, v) + fromV(vxm, v) + fromV(vxp, v);
+                double t = c1 * xsc[v] * cu;
+                t += xsc[v] * (bd1 * cu - bo1 * nb);
+                tn[q][v] = w[q] != 0.0 ? static_cast<T>(t) : zero;
+            }
+        }
+        // out at z-1 on the quadrant (t at z-1 of the neighbours from the shared plane)
+        if (z >= 1) {
+            const double znt = has_t ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = LI[q], j = LJ[q];
+                const V tym = stp[((i + 1) * TW + j) * 64 + lane];
+                const V typ = stp[((i + 1) * TW + (j + 2)) * 64 + lane];
+                const V txm = stp[(i * TW + (j + 1)) * 64 + lane];
+                const V txp = stp[((i + 2) * TW + (j + 1)) * 64 + lane];
+                double o[VW];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const double nb = (double)tm2[q][v] + znt * (double)tn[q][v] + fromV(tym, v) +
+                                      fromV(typ, v) + fromV(txm, v) + fromV(txp, v);
+                    double val = c2 * xsc[v] * (double)um[q][v];
+                    val += 1.0 * (bd2 * (double)tm1[q][v] - bo2 * nb);
+                    if (HASZ) val -= cz * (double)zv[q][v];
+                    o[v] = val;
+                }
+                if (w[q] != 0.0 && colok) vstore<T, VW>(out, base + ep + off[q], o);
+            }
+        }
+        __syncthreads();
+        // t at z into the shared plane
+        if (has_t) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (own[q]) stp[((LI[q] + 1) * TW + (LJ[q] + 1)) * 64 + lane] = toV(tn[q]);
+        }
+        // advance one z value
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                tm2[q][v] = tm1[q][v];
+                tm1[q][v] = tn[q][v];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                um[q][v] = u0[q][v];
+                u0[q][v] = (w[q] != 0.0 && has_n) ? un[q][v] : zero;
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) r2[s][v] = (w2[s] != 0.0 && has_n) ? r2n[s][v] : zero;
+        }
+    }
+}
+
 void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
                         const void *val, hipStream_t st)
 {
@@ -631,7 +885,23 @@ static void quad_sweep_t(const Plan &p, const void *X, const double *xs, double 
                                                     (T *)out);
 }
 
-bool quad_sweep_supported(const Plan &p) { return p.tx == 4 && p.ty == 4 && !p.no_fuse; }
+template <typename T, int VW, bool HASZ>
+static void quad_sweep_wg_t(const Plan &p, const void *X, const double *xs, double c1, double bd1,
+                            double bo1, double c2, double bd2, double bo2, const void *Z, double cz,
+                            void *out, hipStream_t st)
+{
+    const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
+    dim3 grid((unsigned)(p.ntiles * ncg));
+    k_quad_sweep_wg<T, VW, HASZ><<<grid, 1024, 0, st>>>(p.C, ncg, p.nseg, p.seg_row, p.seg_tile,
+                                                        p.seg_dims, p.ntiles, (const T *)X, xs, c1,
+                                                        bd1, bo1, c2, bd2, bo2, (const T *)Z, cz,
+                                                        (T *)out);
+}
+
+bool quad_sweep_supported(const Plan &p)
+{
+    return ((p.tx == 4 && p.ty == 4) || (p.tx == 8 && p.ty == 8)) && !p.no_fuse;
+}
 
 void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1, double cb,
                        double c2, const void *Z, double cz, void *out, hipStream_t st)
@@ -640,6 +910,16 @@ void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1
     const double bd = (2.0 * (2.0 * p.ndim + p.s) - (p.lo + p.hi)) / w;
     const double bo = 2.0 / w;
     const double bd1 = cb * bd, bo1 = cb * 2.0 / w;
+    if (p.tx == 8) {   // workgroup-cooperative form on 8 x 8 line blocks, one column per lane
+        if (p.vec_f32) {
+            if (Z) quad_sweep_wg_t<float, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+            else quad_sweep_wg_t<float, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        } else {
+            if (Z) quad_sweep_wg_t<double, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+            else quad_sweep_wg_t<double, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        }
+        return;
+    }
     if (p.vec_f32 && p.C % 2 == 0) {
         if (Z) quad_sweep_t<float, 2, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
         else quad_sweep_t<float, 2, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);

@@ -51,7 +51,7 @@ class OptsT(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-TILES = {"auto": 0, "4x4": 1, "2x4": 2, "1x8": 3, "4x4-unfused": 4}
+TILES = {"auto": 0, "4x4": 1, "2x4": 2, "1x8": 3, "4x4-unfused": 4, "8x8-wg": 5}
 
 
 class InfoT(ctypes.Structure):

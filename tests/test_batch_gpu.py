@@ -118,6 +118,8 @@ def test_batch_options(ec):
     check_against_oracle(P, r, V, 7, smooth_w=0.05)
     r, _ = run_batch(ec, P, V, 7, max_cols=5)
     check_against_oracle(P, r, V, 7)
+    r, _ = run_batch(ec, P, V, 7, tune={"tile": "8x8-wg"})
+    check_against_oracle(P, r, V, 7)
 
 
 def test_batch_equals_single_problem_calls(ec):

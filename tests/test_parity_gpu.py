@@ -257,7 +257,7 @@ def test_parity_column_waves_jacobi(ec):
 
 
 @pytest.mark.parametrize("tune", [{"tile": "2x4"}, {"tile": "1x8"}, {"tile": "4x4"},
-                                  {"tile": "4x4-unfused"},
+                                  {"tile": "4x4-unfused"}, {"tile": "8x8-wg"},
                                   {"red_waves": 64}, {"red_waves": 65536}, {"csr_vw": 1},
                                   {"tile": "2x4", "red_waves": 8192, "csr_vw": 1}])
 def test_parity_launch_shapes(ec, tune):
@@ -281,15 +281,16 @@ def test_stencil_tile_shapes_bitwise(ec):
         assert torch.equal(o.per_probe, outs[0].per_probe)
 
 
+@pytest.mark.parametrize("tile", ["4x4", "8x8-wg"])
 @pytest.mark.parametrize("name", ["c2_small", "c2_ragged"])
-def test_fused_quadratic_sweep_matches_two_sweeps(ec, name):
+def test_fused_quadratic_sweep_matches_two_sweeps(ec, name, tile):
     """Each quadratic factor of the preconditioner in one fused sweep against
     the same factor as two plain sweeps: the same values up to rounding (the
     fused form sums in the same order; only FMA contraction may differ)."""
     wl = W.WORKLOADS[name]
     P = W.make_problem(wl)
     V = W.make_probes(wl)
-    a = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": "4x4"})
+    a = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": tile})
     b = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, tune={"tile": "4x4-unfused"})
     nu = float(P.A.n)
     assert abs(a.estimate - b.estimate) <= 1e-12 * max(1.0, abs(b.estimate))
