@@ -3,12 +3,14 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the GPU library or its binding.
 """
-from .oracle import (CountResult, LanczosResult, build, count, count_tangent, dense_operator,
+from .oracle import (ArnoldiResult, CountResult, LanczosResult, arnoldi, arnoldi_quadrature,
+                     build, count, count_arnoldi, count_tangent, dense_operator,
                      divided_difference, host_threads, jacobi_matrix, lanczos, lanczos_tangent,
                      negcount, probe_quadrature, probe_quadrature_tangent, quadrature, step,
                      step_deriv)
 
-__all__ = ["CountResult", "LanczosResult", "build", "count", "count_tangent", "dense_operator",
+__all__ = ["ArnoldiResult", "CountResult", "LanczosResult", "arnoldi", "arnoldi_quadrature",
+           "build", "count", "count_arnoldi", "count_tangent", "dense_operator",
            "divided_difference", "host_threads", "jacobi_matrix", "lanczos", "lanczos_tangent",
            "negcount", "probe_quadrature", "probe_quadrature_tangent", "quadrature", "step",
            "step_deriv"]

@@ -476,6 +476,144 @@ int oracle_lanczos_tangent(int64_t n, const int32_t *row_ptr, const int32_t *col
     return failed ? -1 : 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Arnoldi estimator for an unfactored preconditioner (Section 4, Algorithms
+ * 3 and 4).  The operator is C = T (A - tau I) with
+ *   kind 0: T = I,
+ *   kind 1: T = |diag(A) - tau|^(-1) (the square of the Jacobi M above),
+ *   kind 2: T = sum_j c_j T_j(B), the series given (Clenshaw, as apply_M).
+ * Per probe, Algorithm 3 with modified Gram-Schmidt:
+ *   q_1 = v/|v|; for j = 1..k: w = C q_j; for i = 1..j: h_ij = q_i^T w,
+ *   w = w - h_ij q_i; h_{j+1,j} = |w|; q_{j+1} = w / h_{j+1,j}.
+ * The quadrature (eigendecomposition of H_k) is done by the Python half.
+ * Breakdown: when h_{j+1,j} <= 1e3 * eps * max |h_il| so far, the Krylov
+ * space is invariant; the run stops with k_used = j.
+ * ------------------------------------------------------------------------ */
+
+/* y = T x (see above); work: 3 vectors of n */
+static void apply_T(const op_t *P, const double *x, double *y, double *work)
+{
+    if (P->prec_kind == 1) {
+        for (int64_t r = 0; r < P->n; ++r) y[r] = P->jac[r] * P->jac[r] * x[r];
+        return;
+    }
+    apply_M(P, x, y, work); /* kind 0: copy; kind 2: the series */
+}
+
+/* H: (k+1) x k row-major, row i column l holds h_{i+1,l+1} */
+static int arnoldi_one(const op_t *P, const double *v, int k, double *H, double *nu_out,
+                       double *Q, double *w, double *u, double *work)
+{
+    int64_t n = P->n;
+    double nu = dot(n, v, v);
+    *nu_out = nu;
+    double inv = 1.0 / sqrt(nu);
+    for (int64_t r = 0; r < n; ++r) Q[r] = v[r] * inv;
+    double scale = 0.0;
+    for (int j = 1; j <= k; ++j) {
+        const double *qj = Q + (size_t)(j - 1) * n;
+        shifted_matvec(P, qj, u);
+        apply_T(P, u, w, work);
+        for (int i = 1; i <= j; ++i) {
+            const double *qi = Q + (size_t)(i - 1) * n;
+            double h = dot(n, qi, w);
+            H[(size_t)(i - 1) * k + (j - 1)] = h;
+            for (int64_t r = 0; r < n; ++r) w[r] -= h * qi[r];
+            if (fabs(h) > scale) scale = fabs(h);
+        }
+        double b = sqrt(dot(n, w, w));
+        H[(size_t)j * k + (j - 1)] = b;
+        if (b <= 1e3 * DBL_EPSILON * scale) return j;
+        if (b > scale) scale = b;
+        double *qn = Q + (size_t)j * n;
+        for (int64_t r = 0; r < n; ++r) qn[r] = w[r] / b;
+    }
+    return k;
+}
+
+/*
+ * Algorithm 3 for every probe j = 0..m-1 at shift tau.
+ *   V      n x m row-major probe block
+ *   H      m x (k+1) x k (per probe as in arnoldi_one; unused entries 0)
+ *   k_used m, nu m (|v_j|^2)
+ * Returns 0, -1 on bad arguments / allocation failure, -2 if kind 1 is
+ * singular (a_rr = tau).
+ */
+int oracle_arnoldi(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                   int prec_kind, int ndim, const int32_t *dims, double s, double lo, double hi,
+                   int degree, const double *coef, double tau, const double *V, int64_t m, int k,
+                   int nthreads, double *H, int32_t *k_used, double *nu)
+{
+    if (n < 1 || m < 1 || k < 1 || k > n) return -1;
+    op_t P;
+    memset(&P, 0, sizeof P);
+    P.n = n;
+    P.row_ptr = row_ptr;
+    P.col_idx = col_idx;
+    P.val = val;
+    P.prec_kind = prec_kind;
+    P.ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) P.dims[a] = dims[a];
+    P.s = s;
+    P.lo = lo;
+    P.hi = hi;
+    P.degree = degree;
+    P.coef = coef;
+    P.tau = tau;
+    double *jac = NULL;
+    if (prec_kind == 1) {
+        jac = (double *)malloc((size_t)n * sizeof(double));
+        if (!jac) return -1;
+        for (int64_t r = 0; r < n; ++r) {
+            double arr = 0.0;
+            for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p)
+                if (col_idx[p] == r) arr = val[p];
+            double d = fabs(arr - tau);
+            if (d == 0.0) {
+                free(jac);
+                return -2;
+            }
+            jac[r] = 1.0 / sqrt(d);
+        }
+        P.jac = jac;
+    }
+    memset(H, 0, (size_t)m * (k + 1) * k * sizeof(double));
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *Q = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
+        double *w = (double *)malloc((size_t)n * sizeof(double));
+        double *u = (double *)malloc((size_t)n * sizeof(double));
+        double *v = (double *)malloc((size_t)n * sizeof(double));
+        double *work = (double *)malloc((size_t)n * 3 * sizeof(double));
+        if (!Q || !w || !u || !v || !work) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t j = 0; j < m; ++j) {
+                for (int64_t r = 0; r < n; ++r) v[r] = V[r * m + j];
+                k_used[j] = arnoldi_one(&P, v, k, H + (size_t)j * (k + 1) * k, nu + j, Q, w, u,
+                                        work);
+            }
+        }
+        free(Q);
+        free(w);
+        free(u);
+        free(v);
+        free(work);
+    }
+    free(jac);
+    return failed ? -1 : 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP
