@@ -228,6 +228,32 @@ ECNT_API ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, doub
                                      int32_t ckpt, double g_est, void *ws, size_t ws_bytes,
                                      void *stream, double *dV, double *dxi, double *deta);
 
+/* ---- Arnoldi estimator for an unfactored preconditioner (Section 4) ----
+ *
+ * When T is not available as M*M, the estimator runs on C = T (A - tau I)
+ * (Algorithm 4): k Arnoldi steps per probe give an upper Hessenberg H_k
+ * (Algorithm 3; here two classical Gram-Schmidt passes per step, equal to its
+ * modified Gram-Schmidt loop in exact arithmetic), and
+ *   s_j(tau) = |v_j|^2 e_1^T h(H_k) e_1      (eq. arnoldi_quad),
+ * h = 1 on the open left half-plane, evaluated through the matrix sign
+ * function of H_k (real arithmetic).  T here IS the preconditioner:
+ * ECNT_PREC_NONE (T = I) or ECNT_PREC_CHEB_LAPLACIAN (T = the series, which
+ * must be positive on the spectrum of its argument); ECNT_PREC_JACOBI is
+ * ECNT_EUNSUPPORTED.  Same arguments and outputs as ecnt_count, with
+ * opts.rule = ECNT_RULE_GAUSS, opts.smooth_w = 0 and k <= 64 (otherwise
+ * ECNT_EUNSUPPORTED); info->alpha / info->beta are not written and
+ * info->min_abs_ritz is +inf (the eigenvalues of H_k are not formed).
+ * EDEVICE if the sign iteration fails (an eigenvalue of H_k on the imaginary
+ * axis). */
+ECNT_API size_t ecnt_arnoldi_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T,
+                                             const ecnt_opts *opts);
+
+ECNT_API ecnt_status ecnt_count_arnoldi(const ecnt_csr *A, const ecnt_prec *T, double xi,
+                                        double eta, const void *probes, int64_t m,
+                                        const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                        void *stream, double *estimate, double *variance,
+                                        ecnt_info *info);
+
 /* ---- Batches of independent problems ----
  *
  * Many small problems (each its own A_b, shifts and probe block) run as one

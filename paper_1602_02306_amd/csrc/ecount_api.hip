@@ -135,6 +135,11 @@ size_t plan_layout(Plan &p, char *base)
     p.seg_tile = (int64_t *)take(sizeof(int64_t) * (p.nseg + 1));
     p.seg_dims = (int32_t *)take(sizeof(int32_t) * 3 * p.nseg);
     p.seg_taus = (double *)take(sizeof(double) * p.S * p.nseg);
+    if (p.arnoldi) {
+        const size_t k = p.k;
+        p.H = (double *)take(sizeof(double) * k * (k + 1) * NC);
+        p.sgn = (double *)take(sizeof(double) * 3 * k * k * NC);
+    }
     if (p.grad) {
         const size_t k = p.k, C = p.wave_cols;
         p.g_tslots = take(blk * k);
@@ -551,11 +556,11 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
         col_geometry(w);
         enqueue_wave(w, A, probes, st);
         // diagnostics of a single problem: alpha/beta of this wave into the caller's arrays
-        if (p.nseg == 1 && info && info->alpha)
+        if (p.nseg == 1 && !p.arnoldi && info && info->alpha)
             (void)hipMemcpy2DAsync(info->alpha + c_off, sizeof(double) * p.Ct, w.alpha,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k,
                                    hipMemcpyDeviceToDevice, st);
-        if (p.nseg == 1 && info && info->beta)
+        if (p.nseg == 1 && !p.arnoldi && info && info->beta)
             (void)hipMemcpy2DAsync(info->beta + c_off, sizeof(double) * p.Ct, w.beta,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k + 1,
                                    hipMemcpyDeviceToDevice, st);
@@ -564,9 +569,68 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
     launch_reduce(p, st);
 }
 
+// One wave of columns for the Arnoldi estimator (Algorithms 3 and 4):
+// w = T (A - tau I) q_j, two classical Gram-Schmidt passes building column j
+// of H, h_{j+1,j} = |w|; then the quadrature of every column.
+static void enqueue_wave_arnoldi(const Plan &p, const ecnt_csr *A, const void *probes,
+                                 hipStream_t st)
+{
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
+    {
+        Timed t(F_SETUP, blk_b + (double)p.n * p.C * (p.vec_f32 ? 4 : 8) / p.S, st);
+        launch_setup(p, probes, st);
+    }
+    {
+        Timed t(F_FIN, 0.0, st);
+        launch_setup_fin(p, st);
+    }
+    const size_t blk = (size_t)p.n * p.C * (p.vec_f32 ? 4 : 8);
+    char *basis = (char *)p.basis;
+    for (int j = 1; j <= p.k; ++j) {
+        void *x = basis + (size_t)(j - 1) * blk;   // slot j-1 holds q_j (unnormalized)
+        void *y = basis + (size_t)j * blk;         // slot j receives C q_j
+        const double *xs = p.sig + (size_t)(j - 1) * p.nseg * p.C;
+        if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
+            {
+                Timed t(F_CSR, 2 * blk_b + csr_b, st);
+                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs, nullptr, p.tmp[0], st);
+            }
+            apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);   // T u
+        } else {
+            Timed t(F_CSR, 2 * blk_b + csr_b, st);
+            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs, nullptr, y, st);
+        }
+        for (int pass = 1; pass <= 2; ++pass) {
+            for (int l0 = 0; l0 < j; l0 += kBasisChunk) {
+                const int nb = (j - l0) < kBasisChunk ? (j - l0) : kBasisChunk;
+                {
+                    Timed t(F_DOTS, (nb + 1) * blk_b, st);
+                    launch_dots(p, j, l0, nb, st);
+                }
+                Timed t(F_FIN, 0.0, st);
+                launch_arn_fin(p, j, l0, nb, pass, st);
+            }
+            for (int l0 = 0; l0 < j; l0 += kBasisChunk) {
+                const int nb = (j - l0) < kBasisChunk ? (j - l0) : kBasisChunk;
+                Timed t(F_UPDATE, (nb + 2) * blk_b, st);
+                launch_update(p, j, l0, nb, false, pass == 2 && l0 + kBasisChunk >= j, st);
+            }
+        }
+        Timed t(F_FIN, 0.0, st);
+        launch_arn_norm_fin(p, j, st);
+    }
+    Timed t(F_QUAD, 0.0, st);
+    launch_arn_quad(p, st);
+}
+
 // One wave of columns: Algorithm 1 on every column, then the quadrature.
 static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st)
 {
+    if (p.arnoldi) {
+        enqueue_wave_arnoldi(p, A, probes, st);
+        return;
+    }
     const double blk_b = block_bytes(p);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
     {
@@ -754,6 +818,22 @@ static ecnt_status grad_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, const e
     return single_segment(p, sh, taus);
 }
 
+// The Arnoldi estimator: T itself is the preconditioner description (not a
+// factor of it); one problem, the paper's step h, no GA rule.
+static ecnt_status arnoldi_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, const ecnt_prec *T,
+                                const ecnt_opts *o, const double *taus)
+{
+    ecnt_status rc = make_plan(p, n, m, 2, T, o);
+    if (rc) return rc;
+    if (T->kind == ECNT_PREC_JACOBI)
+        return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator takes T = I or a Laplacian polynomial");
+    if (o->rule != ECNT_RULE_GAUSS) return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator has no GA rule");
+    if (o->smooth_w != 0.0) return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator uses the step h");
+    if (o->k > 64) return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator needs k <= 64");
+    p.arnoldi = 1;
+    return single_segment(p, sh, taus);
+}
+
 static void begin_launches()
 {
     (void)hipGetLastError();
@@ -762,7 +842,7 @@ static void begin_launches()
 }
 
 // mode: 0 count, 1 forward keeping backward state, 2 backward on kept state,
-//       3 forward + backward (recompute).
+//       3 forward + backward (recompute), 4 Arnoldi count.
 static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus, int S,
                        const void *probes, int64_t m, const ecnt_opts *o, void *ws,
                        size_t ws_bytes, void *stream, double *res_host, ecnt_info *info, Plan &p,
@@ -773,12 +853,14 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
     if (mode == 0) {
         rc = make_plan(p, A ? A->n : 0, m, S, T, o);
         if (!rc) rc = single_segment(p, sh, taus);
+    } else if (mode == 4) {
+        rc = arnoldi_plan(p, sh, A ? A->n : 0, m, T, o, taus);
     } else {
         rc = grad_plan(p, sh, A ? A->n : 0, m, T, o, taus);
     }
     if (rc) return rc;
-    if (mode >= 2 && !dV) return fail(ECNT_EINVAL, "dV is null");
-    if (mode >= 1 && A && A->val_type != ECNT_F64)
+    if ((mode == 2 || mode == 3) && !dV) return fail(ECNT_EINVAL, "dV is null");
+    if (mode >= 1 && mode <= 3 && A && A->val_type != ECNT_F64)
         return fail(ECNT_EUNSUPPORTED, "gradients need FP64 matrix values");
     rc = check_common(A, probes, o, ws, p, ws_bytes);
     if (rc) return rc;
@@ -790,7 +872,7 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
     if (rc) return rc;
     begin_launches();
     if (mode != 2) enqueue(p, A, probes, info, st);
-    if (mode >= 2) enqueue_backward(p, A, g_out, dV, st);
+    if (mode == 2 || mode == 3) enqueue_backward(p, A, g_out, dV, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return finish(p, st, res_host, info);
@@ -897,6 +979,39 @@ ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const double *
         info->neg_xi = res[0];
         info->neg_eta = S > 1 ? res[1] : res[0];
         info->min_abs_ritz = res[3 * S - 2];
+    }
+    return ECNT_OK;
+}
+
+size_t ecnt_arnoldi_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *opts)
+{
+    Plan p;
+    SegHost sh;
+    const double taus[2] = {0.0, 1.0};
+    if (arnoldi_plan(p, sh, n, m, T, opts, taus) != ECNT_OK) return 0;
+    return p.bytes;
+}
+
+ecnt_status ecnt_count_arnoldi(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                               const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream, double *estimate, double *variance,
+                               ecnt_info *info)
+{
+    g_err.clear();
+    if (!estimate || !variance) return fail(ECNT_EINVAL, "estimate/variance output is null");
+    if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
+    if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
+    const double taus[2] = {xi, eta};
+    double res[kResStride];
+    Plan p;
+    ecnt_status rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p, 4);
+    if (rc) return rc;
+    *estimate = res[2];
+    *variance = res[3];
+    if (info) {
+        info->neg_xi = res[0];
+        info->neg_eta = res[1];
+        info->min_abs_ritz = INFINITY;
     }
     return ECNT_OK;
 }

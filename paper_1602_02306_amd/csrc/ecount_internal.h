@@ -87,6 +87,10 @@ struct Plan {
     int32_t *active = nullptr; // C
     int32_t *kused = nullptr;  // Ct
     int32_t *flags = nullptr;  // 4 status flags
+    // ---- Arnoldi estimator for an unfactored T (one problem) ----
+    int arnoldi = 0;
+    double *H = nullptr;       // k x (k+1) x NC: H[(l*(k+1) + i)*NC + vc] = h_{i+1,l+1}
+    double *sgn = nullptr;     // 3 x k x k x NC: scratch of the matrix sign iteration
     // ---- differentiated form (smoothed count), single wave, FP64 ----
     int grad = 0;
     void *g_tslots = nullptr;  // k blocks: M q_i of every forward step
@@ -144,6 +148,10 @@ void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool las
 void launch_norm_fin(const Plan &p, int step, hipStream_t st);
 void launch_tridiag(const Plan &p, hipStream_t st);
 void launch_reduce(const Plan &p, hipStream_t st);
+// Arnoldi estimator
+void launch_arn_fin(const Plan &p, int step, int l0, int nb, int pass, hipStream_t st);
+void launch_arn_norm_fin(const Plan &p, int step, hipStream_t st);
+void launch_arn_quad(const Plan &p, hipStream_t st);
 // backward of the smoothed count
 void launch_tridiag_bwd(const Plan &p, double g_out, hipStream_t st);
 void launch_bdots(const Plan &p, int i, hipStream_t st);

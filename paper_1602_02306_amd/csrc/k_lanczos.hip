@@ -297,7 +297,7 @@ static void dots_t(const Plan &p, int step, int l0, hipStream_t st)
     const int nct = (p.C + 64 * VW - 1) / (64 * VW);
     k_dots<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
         p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk, (const T *)p.basis, slot_elems(p), step,
-        l0, step >= 2 ? step - 2 : -1, p.kappa, p.part);
+        l0, (step >= 2 && !p.arnoldi) ? step - 2 : -1, p.kappa, p.part);
 }
 
 template <typename T, int NB, int VW>

@@ -124,6 +124,10 @@ def load():
                                            ctypes.c_size_t, P, P, P, P, ctypes.POINTER(InfoT)]
         lib.ecnt_count_batched.restype = ctypes.c_int32
         lib.ecnt_count_batched.argtypes = batch_args + [P, P, P, ctypes.POINTER(InfoT)]
+        lib.ecnt_arnoldi_workspace_bytes.restype = ctypes.c_size_t
+        lib.ecnt_arnoldi_workspace_bytes.argtypes = lib.ecnt_smooth_workspace_bytes.argtypes
+        lib.ecnt_count_arnoldi.restype = ctypes.c_int32
+        lib.ecnt_count_arnoldi.argtypes = lib.ecnt_count.argtypes
         lib.ecnt_profile_enable.restype = ctypes.c_int32
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
         lib.ecnt_profile_read.restype = ctypes.c_int32
@@ -282,6 +286,40 @@ def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = 
     return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
                        keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"),
                        keep.get("beta"))
+
+
+def arnoldi_workspace_bytes(n: int, m: int, T, k: int, vec: str = "f64", max_cols: int = 0,
+                            tune: dict | None = None) -> int:
+    ps, _coef = prec_struct(T)
+    o = opts_struct(k, vec, "gauss", 0.0, max_cols, tune)
+    return int(load().ecnt_arnoldi_workspace_bytes(int(n), int(m), ctypes.byref(ps), ctypes.byref(o)))
+
+
+def count_arnoldi(A: DeviceCSR, T, xi: float, eta: float, probes, k: int, vec: str = "f64",
+                  workspace: Workspace | None = None, stream=None, details: bool = True,
+                  max_cols: int = 0, tune: dict | None = None) -> CountResult:
+    """Interval count with the Arnoldi estimator on T (A - tau I)
+    (ecnt_count_arnoldi); `T` is the preconditioner itself (PrecSpec "none"
+    or "cheb")."""
+    lib = load()
+    n, m = probes.shape
+    ps, _coef = prec_struct(T)
+    o = opts_struct(k, vec, "gauss", 0.0, max_cols, tune)
+    need = lib.ecnt_arnoldi_workspace_bytes(n, m, ctypes.byref(ps), ctypes.byref(o))
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
+    info, keep = _info(2 * m, k, details, probes.device)
+    if details:
+        info.alpha = None
+        info.beta = None
+    est, var = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    rc = lib.ecnt_count_arnoldi(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                                probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
+                                _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
+                                ctypes.byref(info))
+    _check(rc)
+    return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
+                       keep.get("per_probe"), keep.get("k_used"))
 
 
 @dataclass
