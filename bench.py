@@ -32,6 +32,8 @@ WORKLOAD_TEXT = {
     "c2": "3D 7-pt 64^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=256, k=30, FP64",
     "c3": "3D 7-pt 128^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M=c4(L+I), [-8,-2], m=512, k=30, FP32 vectors",
     "c2_f32": "the 64^3 problem of c2 with A values and all Lanczos vectors in FP32 (FP64 alpha/beta, dots, eigensolve)",
+    "c2_arn": "the 64^3 problem of c2 with the unfactored T = degree-8 Chebyshev approximation of (L+I)^-1 "
+              "and the Arnoldi estimator (Algorithm 4), m=256, k=30, FP64",
     "c5": "3D 7-pt 96^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M, erf-smoothed count w=0.05, [-8,-2], m=128, k=30",
     "c4": "64 independent 3D 7-pt Gaussian-well Hamiltonians, N^3 grids with N~U{16..64} (seeds 1000+b), "
           "4 sorted shifts ~U[-8,-2] each (3 intervals), Chebyshev M=c4(L+I), m=64, k=25, one "
@@ -76,8 +78,12 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
     while done < m:
         s = min(batch, m - done)
         t0 = time.perf_counter()
-        ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k, nthreads=threads,
-                           smooth_w=wl.smooth_w)
+        if wl.method == "arnoldi":
+            ref = oracle.count_arnoldi(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
+                                       nthreads=threads)
+        else:
+            ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
+                               nthreads=threads, smooth_w=wl.smooth_w)
         dt = time.perf_counter() - t0
         if gpu_per_probe is not None:
             gx, ge = gpu_per_probe[done:done + s], gpu_per_probe[m + done:m + done + s]
@@ -387,7 +393,8 @@ def main():
     # FP32 128^3 form: one shift (m columns) per wave bounds the basis to 124 GiB
     max_cols = wl.m if wl.name == "c3" else 0
     tune, tuned = None, None
-    if not grad and args.tune != "off":
+    arn = wl.method == "arnoldi"
+    if not grad and not arn and args.tune != "off":
         from paper_1602_02306_amd import autotune
         free, _total = torch.cuda.mem_get_info()
         cfg = autotune.tune_count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec,
@@ -399,6 +406,8 @@ def main():
         log("launch shape (%s): %s" % (cfg["source"], tuned))
     if grad:
         need = ec.smooth_workspace_bytes(wl.n, wl.m, P.prec, wl.k, wl.smooth_w)
+    elif arn:
+        need = ec.arnoldi_workspace_bytes(wl.n, wl.m, P.prec, wl.k, vec=vec, max_cols=max_cols)
     else:
         need = ec.workspace_bytes(wl.n, wl.m, S, P.prec, wl.k, vec=vec, smooth_w=wl.smooth_w,
                                   max_cols=max_cols)
@@ -407,6 +416,9 @@ def main():
     grad_times = {}
 
     def one():
+        if arn:
+            return ec.count_arnoldi(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws,
+                                    details=False, max_cols=max_cols)
         if not grad:
             return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
                             workspace=ws, details=False, max_cols=max_cols, tune=tune)
@@ -469,7 +481,8 @@ def main():
     if os.path.exists(gpath):
         golden = json.load(open(gpath))
         # the FP32 storage form of a problem has the problem's exact count
-        exact = golden.get(wl.name, golden.get(wl.name.replace("_f32", ""), {})).get("count")
+        base = wl.name.replace("_f32", "").replace("_arn", "")
+        exact = golden.get(wl.name, golden.get(base, {})).get("count")
     accuracy = {"estimate": r.estimate, "std_error": math.sqrt(r.variance) if r.variance == r.variance else None,
                 "exact_count": exact, "method_exact": "LDL^T Sylvester inertia" if exact is not None else None,
                 "abs_error": abs(r.estimate - exact) if exact is not None else None,
@@ -529,8 +542,12 @@ def main():
     if not grad:
         # one more run with per-probe outputs (untimed): sampled parity against
         # the oracle below, and the FP32 form against the FP64 path
-        rd = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws, details=True,
-                      max_cols=max_cols, tune=tune)
+        if arn:
+            rd = ec.count_arnoldi(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws,
+                                  details=True, max_cols=max_cols)
+        else:
+            rd = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws, details=True,
+                          max_cols=max_cols, tune=tune)
         gpu_pp = rd.per_probe.cpu().numpy()
         if vec == "f32":
             del ws

@@ -138,7 +138,6 @@ size_t plan_layout(Plan &p, char *base)
     if (p.arnoldi) {
         const size_t k = p.k;
         p.H = (double *)take(sizeof(double) * k * (k + 1) * NC);
-        p.sgn = (double *)take(sizeof(double) * 3 * k * k * NC);
     }
     if (p.grad) {
         const size_t k = p.k, C = p.wave_cols;

@@ -90,7 +90,6 @@ struct Plan {
     // ---- Arnoldi estimator for an unfactored T (one problem) ----
     int arnoldi = 0;
     double *H = nullptr;       // k x (k+1) x NC: H[(l*(k+1) + i)*NC + vc] = h_{i+1,l+1}
-    double *sgn = nullptr;     // 3 x k x k x NC: scratch of the matrix sign iteration
     // ---- differentiated form (smoothed count), single wave, FP64 ----
     int grad = 0;
     void *g_tslots = nullptr;  // k blocks: M q_i of every forward step

@@ -15,7 +15,8 @@
 // per column by the Newton iteration for the matrix sign function
 // (X <- (mu X + (mu X)^{-1}) / 2, determinant scaling mu = |det X|^{-1/N}
 // until the steps are small, then unscaled), which needs no complex
-// arithmetic: sign(H_k) is real for real H_k.
+// arithmetic: sign(H_k) is real for real H_k.  One wavefront per column, the
+// matrices in LDS.
 #include <float.h>
 #include <math.h>
 
@@ -83,105 +84,128 @@ __global__ void k_arn_norm_fin(int C, int nseg, int step, int k, double eps_vec,
     runmax[vc] = rm;
 }
 
-// One lane per column: s_c = nu_c (1 - sign(H_N)_{11}) / 2, N = k_used.
-// Scratch: three N x N matrices per column at sgn[(m*k*k + a*k + b)*NC + vc].
-__global__ __launch_bounds__(64) void k_arn_quad(int NC, int C, int ld, int off, int k,
+// One wavefront per column: s_c = nu_c (1 - sign(H_N)_{11}) / 2, N = k_used.
+// X, W (work copy) and Y = X^{-1} live in LDS, lane a holding row a; each
+// Gauss-Jordan pivot is found by a fixed-order wave reduction (ties to the
+// lower row), row swaps and scalings go column-parallel, eliminations
+// row-parallel.
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_arn_quad(int C, int ld, int off, int k,
                                                  const double *__restrict__ H,
                                                  const int32_t *__restrict__ kused_all,
                                                  const double *__restrict__ nu,
-                                                 double *__restrict__ sgn,
                                                  double *__restrict__ s_all,
                                                  double *__restrict__ minabs_all,
                                                  int32_t *__restrict__ flags)
 {
-    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (vc >= NC) return;
+    constexpr int LDK = KMAX + 1;
+    __shared__ double X[KMAX * LDK], W[KMAX * LDK], Y[KMAX * LDK];
+    const int NC = gridDim.x;
+    const int vc = blockIdx.x;
+    const int lane = threadIdx.x;
     const int seg = vc / C;
     const size_t gidx = (size_t)seg * ld + off + (vc - seg * C);
     const int N = kused_all[gidx];
-    minabs_all[gidx] = INFINITY;   // eigenvalues are not formed
-    if (N < 1) {
-        s_all[gidx] = 0.0;
+    if (N < 1) {   // uniform over the block
+        if (lane == 0) {
+            s_all[gidx] = 0.0;
+            minabs_all[gidx] = INFINITY;
+        }
         return;
     }
-    const size_t kk = (size_t)k * k;
-#define X_(a, b) sgn[((size_t)(a) * k + (b)) * NC + vc]
-#define W_(a, b) sgn[(kk + (size_t)(a) * k + (b)) * NC + vc]
-#define Y_(a, b) sgn[(2 * kk + (size_t)(a) * k + (b)) * NC + vc]
-    for (int a = 0; a < N; ++a)
-        for (int b = 0; b < N; ++b)
-            X_(a, b) = (a <= b + 1) ? H[((size_t)b * (k + 1) + a) * NC + vc] : 0.0;
+    for (int e = lane; e < N * N; e += 64) {
+        const int a = e / N, b = e % N;
+        X[a * LDK + b] = (a <= b + 1) ? H[((size_t)b * (k + 1) + a) * NC + vc] : 0.0;
+    }
+    __syncthreads();
     bool scaled = true, done = false, failed = false;
-    for (int it = 0; it < 100 && !done; ++it) {
-        // Y = X^{-1} by Gauss-Jordan elimination with partial pivoting on W
+    for (int it = 0; it < 100 && !done && !failed; ++it) {
+        for (int e = lane; e < N * N; e += 64) {
+            const int a = e / N, b = e % N;
+            W[a * LDK + b] = X[a * LDK + b];
+            Y[a * LDK + b] = a == b ? 1.0 : 0.0;
+        }
+        __syncthreads();
         double logdet = 0.0;
-        for (int a = 0; a < N; ++a)
-            for (int b = 0; b < N; ++b) {
-                W_(a, b) = X_(a, b);
-                Y_(a, b) = a == b ? 1.0 : 0.0;
-            }
-        for (int col = 0; col < N && !failed; ++col) {
-            int piv = col;
-            double pv = fabs(W_(col, col));
-            for (int r = col + 1; r < N; ++r)
-                if (fabs(W_(r, col)) > pv) {
-                    pv = fabs(W_(r, col));
-                    piv = r;
+        for (int col = 0; col < N; ++col) {
+            // pivot: largest |W[a][col]|, a >= col, lowest row on ties
+            double pv = (lane >= col && lane < N) ? fabs(W[lane * LDK + col]) : -1.0;
+            int pr = lane;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double qv = __shfl_xor(pv, o, 64);
+                const int qr = __shfl_xor(pr, o, 64);
+                if (qv > pv || (qv == pv && qr < pr)) {
+                    pv = qv;
+                    pr = qr;
                 }
-            if (!(pv > 0.0) || !isfinite(pv)) {
+            }
+            if (!(pv > 0.0) || !isfinite(pv)) {   // uniform: every lane holds the same pair
                 failed = true;
                 break;
             }
-            if (piv != col)
-                for (int b = 0; b < N; ++b) {
-                    double t = W_(col, b);
-                    W_(col, b) = W_(piv, b);
-                    W_(piv, b) = t;
-                    t = Y_(col, b);
-                    Y_(col, b) = Y_(piv, b);
-                    Y_(piv, b) = t;
-                }
-            const double d = W_(col, col);
+            if (pr != col && lane < N) {   // column-parallel row swap
+                double t = W[col * LDK + lane];
+                W[col * LDK + lane] = W[pr * LDK + lane];
+                W[pr * LDK + lane] = t;
+                t = Y[col * LDK + lane];
+                Y[col * LDK + lane] = Y[pr * LDK + lane];
+                Y[pr * LDK + lane] = t;
+            }
+            __syncthreads();
+            const double d = W[col * LDK + col];
             logdet += log(fabs(d));
-            const double inv = 1.0 / d;
-            for (int b = 0; b < N; ++b) {
-                W_(col, b) *= inv;
-                Y_(col, b) *= inv;
+            __syncthreads();
+            if (lane < N) {
+                const double inv = 1.0 / d;
+                W[col * LDK + lane] *= inv;
+                Y[col * LDK + lane] *= inv;
             }
-            for (int r = 0; r < N; ++r) {
-                if (r == col) continue;
-                const double f = W_(r, col);
-                if (f == 0.0) continue;
-                for (int b = 0; b < N; ++b) {
-                    W_(r, b) -= f * W_(col, b);
-                    Y_(r, b) -= f * Y_(col, b);
-                }
+            __syncthreads();
+            if (lane < N && lane != col) {   // row-parallel elimination
+                const double f = W[lane * LDK + col];
+                if (f != 0.0)
+                    for (int b = 0; b < N; ++b) {
+                        W[lane * LDK + b] -= f * W[col * LDK + b];
+                        Y[lane * LDK + b] -= f * Y[col * LDK + b];
+                    }
             }
+            __syncthreads();
         }
         if (failed) break;
         const double mu = scaled ? exp(-logdet / N) : 1.0;
         double num = 0.0, den = 0.0;
-        for (int a = 0; a < N; ++a)
+        if (lane < N)
             for (int b = 0; b < N; ++b) {
-                const double xn = 0.5 * (mu * X_(a, b) + Y_(a, b) / mu);
-                const double dd = xn - X_(a, b);
-                num += dd * dd;
+                const double xo = X[lane * LDK + b];
+                const double xn = 0.5 * (mu * xo + Y[lane * LDK + b] / mu);
+                num += (xn - xo) * (xn - xo);
                 den += xn * xn;
-                X_(a, b) = xn;
+                X[lane * LDK + b] = xn;
             }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            num += __shfl_xor(num, o, 64);
+            den += __shfl_xor(den, o, 64);
+        }
+        // the lanes' sums may differ in the last bit: take lane 0's, so that
+        // every lane takes the same branch below
+        num = __shfl(num, 0, 64);
+        den = __shfl(den, 0, 64);
+        __syncthreads();
         const double rel = sqrt(num / den);
         if (rel < 1e-2) scaled = false;
         if (!scaled && rel < 1e-13) done = true;
     }
-    if (!done || failed) {
-        atomicOr(&flags[1], 1);
-        s_all[gidx] = NAN;
-        return;
+    if (lane == 0) {
+        minabs_all[gidx] = INFINITY;   // the eigenvalues of H_N are not formed
+        if (!done || failed) {
+            atomicOr(&flags[1], 1);
+            s_all[gidx] = NAN;
+        } else {
+            s_all[gidx] = nu[vc] * 0.5 * (1.0 - X[0]);
+        }
     }
-    s_all[gidx] = nu[vc] * 0.5 * (1.0 - X_(0, 0));
-#undef X_
-#undef W_
-#undef Y_
 }
 
 void launch_arn_fin(const Plan &p, int step, int l0, int nb, int pass, hipStream_t st)
@@ -203,8 +227,12 @@ void launch_arn_norm_fin(const Plan &p, int step, hipStream_t st)
 void launch_arn_quad(const Plan &p, hipStream_t st)
 {
     const int NC = p.nseg * p.C;
-    k_arn_quad<<<(NC + 63) / 64, 64, 0, st>>>(NC, p.C, p.Ct, p.c_off, p.k, p.H, p.kused, p.nu,
-                                              p.sgn, p.s_out, p.minabs, p.flags);
+    if (p.k <= 32)
+        k_arn_quad<32><<<NC, 64, 0, st>>>(p.C, p.Ct, p.c_off, p.k, p.H, p.kused, p.nu, p.s_out,
+                                          p.minabs, p.flags);
+    else
+        k_arn_quad<64><<<NC, 64, 0, st>>>(p.C, p.Ct, p.c_off, p.k, p.H, p.kused, p.nu, p.s_out,
+                                          p.minabs, p.flags);
 }
 
 }  // namespace ecnt

@@ -291,12 +291,13 @@ class Workload:
     seed: int               # potential seed
     xi: float
     eta: float
-    prec: str               # 'none' | 'jacobi' | 'cheb'
+    prec: str               # 'none' | 'jacobi' | 'cheb' (M = c4 of x^-1/2) | 'cheb_inv' (T = c8 of 1/x)
     m: int
     k: int
     probe_seed: int = 12345
     vec: str = "f64"        # storage type of A values and Lanczos vectors
     smooth_w: float = 0.0   # width of the erf-smoothed step (0: the paper's step)
+    method: str = "lanczos" # 'lanczos' (Algorithm 2 on M(A - tau I)M) | 'arnoldi' (Algorithm 4 on T(A - tau I))
 
     @property
     def n(self) -> int:
@@ -312,6 +313,9 @@ WORKLOADS = {
     "c3": Workload("c3", (128, 128, 128), "wells", 1, -8.0, -2.0, "cheb", 512, 30, vec="f32"),
     # the 64^3 problem in the FP32 storage form (its exact count is known)
     "c2_f32": Workload("c2_f32", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb", 256, 30, vec="f32"),
+    # the 64^3 problem with the unfactored T = c8(L+I) ~ (L+I)^-1 and the Arnoldi estimator
+    "c2_arn": Workload("c2_arn", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb_inv", 256, 30,
+                       method="arnoldi"),
     # 96^3, erf-smoothed count of width 0.05, 128 probes
     "c5": Workload("c5", (96, 96, 96), "wells", 1, -8.0, -2.0, "cheb", 128, 30, smooth_w=0.05),
     # small cases that the oracle finishes in seconds
@@ -343,6 +347,8 @@ def make_potential(wl: Workload) -> np.ndarray:
 def make_prec(kind: str, dims) -> PrecSpec:
     if kind == "cheb":
         return cheb_invsqrt_prec(dims)
+    if kind == "cheb_inv":
+        return cheb_inverse_prec(dims)
     if kind in ("jacobi", "none"):
         return PrecSpec(kind, tuple(dims))
     raise ValueError(kind)
