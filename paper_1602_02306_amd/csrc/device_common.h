@@ -36,6 +36,33 @@ __device__ __forceinline__ int find_seg(const int64_t *__restrict__ off, int nse
     return lo;
 }
 
+// Two-phase column sums, second phase: the sum over the row chunks
+// [ch0, ch1) of part[(ch * rows + row) * C + c] for column c = lane's column,
+// computed by the kFinWaves wavefronts of a block (wavefront w takes chunks
+// ch0 + w, ch0 + w + kFinWaves, ...; the partial sums are added in wavefront
+// order, so the result is reproducible).  Every thread of the block must call
+// it (it synchronizes the block); the sum is returned to all of them.
+constexpr int kFinWaves = 8;
+
+__device__ __forceinline__ double block_chunk_sum(const double *__restrict__ part, int rows,
+                                                  int C, int row, int c, int64_t ch0, int64_t ch1,
+                                                  bool valid)
+{
+    __shared__ double red[kFinWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double s = 0.0;
+    if (valid)
+        for (int64_t ch = ch0 + w; ch < ch1; ch += kFinWaves)
+            s += part[((size_t)ch * rows + row) * C + c];
+    red[w][lane] = s;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kFinWaves; ++q) t += red[q][lane];
+    __syncthreads();
+    return t;
+}
+
 // VW consecutive columns per lane, moved as one vector load/store.
 template <typename T, int VW> struct VecT;
 template <> struct VecT<double, 1> { using type = double; };

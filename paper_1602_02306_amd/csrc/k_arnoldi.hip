@@ -32,13 +32,13 @@ __global__ void k_arn_fin(int C, int nseg, int step, int l0, int nb, int k, int 
                           double *__restrict__ cf, double *__restrict__ H)
 {
     const int NC = nseg * C;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nb * NC) return;
-    const int l = idx / NC, vc = idx - l * NC;
-    const int seg = vc / C, c = vc - seg * C;
-    double s = 0.0;
-    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
-        s += part[((size_t)ch * kPartRows + l) * C + c];
+    const int l = blockIdx.y;
+    const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
+    const bool valid = vc < NC;
+    const int seg = valid ? vc / C : 0, c = valid ? vc - seg * C : 0;
+    const double s = block_chunk_sum(part, kPartRows, C, l, c, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    if (!valid || threadIdx.x >= 64) return;
+    (void)nb;
     const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = active[vc] ? s * sg : 0.0;
     cf[(size_t)(l0 + l) * NC + vc] = g * sg;
@@ -54,14 +54,13 @@ __global__ void k_arn_norm_fin(int C, int nseg, int step, int k, double eps_vec,
                                int32_t *__restrict__ active, int32_t *__restrict__ kused,
                                int ku_ld, int ku_off)
 {
-    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
+    const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
     const int NC = nseg * C;
-    if (vc >= NC) return;
-    const int seg = vc / C, cc = vc - seg * C;
+    const bool valid = vc < NC;
+    const int seg = valid ? vc / C : 0, cc = valid ? vc - seg * C : 0;
     const int j = step;
-    double ss = 0.0;
-    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
-        ss += part[(size_t)ch * kPartRows * C + cc];
+    const double ss = block_chunk_sum(part, kPartRows, C, 0, cc, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    if (!valid || threadIdx.x >= 64) return;
     const double b = sqrt(ss);
     double rm = runmax[vc];
     for (int i = 0; i < j; ++i) rm = fmax(rm, fabs(H[((size_t)(j - 1) * (k + 1) + i) * NC + vc]));
@@ -210,8 +209,8 @@ __global__ __launch_bounds__(64) void k_arn_quad(int C, int ld, int off, int k,
 
 void launch_arn_fin(const Plan &p, int step, int l0, int nb, int pass, hipStream_t st)
 {
-    const int tot = nb * p.nseg * p.C;
-    k_arn_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, pass, p.seg_chunk,
+    const int NC = p.nseg * p.C;
+    k_arn_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, pass, p.seg_chunk,
                                                  p.part, p.sig, p.active, p.cf, p.H);
 }
 
@@ -219,7 +218,7 @@ void launch_arn_norm_fin(const Plan &p, int step, hipStream_t st)
 {
     const double eps = p.vec_f32 ? (double)FLT_EPSILON : DBL_EPSILON;
     const int NC = p.nseg * p.C;
-    k_arn_norm_fin<<<(NC + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, p.k, eps, p.seg_chunk,
+    k_arn_norm_fin<<<(NC + 63) / 64, 64 * kFinWaves, 0, st>>>(p.C, p.nseg, step, p.k, eps, p.seg_chunk,
                                                      p.part, p.H, p.sig, p.runmax, p.active,
                                                      p.kused, p.Ct, p.c_off);
 }

@@ -76,12 +76,12 @@ __global__ void k_setup_fin(int C, int nseg, int k, const int64_t *__restrict__ 
                             int32_t *__restrict__ active, int32_t *__restrict__ kused, int ku_ld,
                             int ku_off)
 {
-    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (vc >= nseg * C) return;
-    const int seg = vc / C, c = vc - seg * C;
-    double s = 0.0;
-    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
-        s += part[(size_t)ch * kPartRows * C + c];
+    // block: kFinWaves wavefronts over the chunks of 64 virtual columns
+    const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
+    const bool valid = vc < nseg * C;
+    const int seg = valid ? vc / C : 0, c = valid ? vc - seg * C : 0;
+    const double s = block_chunk_sum(part, kPartRows, C, 0, c, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    if (!valid || threadIdx.x >= 64) return;
     nu[vc] = s;
     const bool ok = s > 0.0;
     sig[vc] = ok ? 1.0 / sqrt(s) : 0.0;
@@ -147,21 +147,22 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
-// One thread per (l, vc); arrays indexed [row][nseg*C].
+// Arrays indexed [row][nseg*C].
 __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
                            const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
                            const double *__restrict__ sig, const int32_t *__restrict__ active,
                            double *__restrict__ cf, double *__restrict__ alpha,
                            double *__restrict__ gall)
 {
+    // block (x: 64 virtual columns, y: basis vector l), kFinWaves wavefronts over the chunks
     const int NC = nseg * C;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nb * NC) return;
-    const int l = idx / NC, vc = idx - l * NC;
-    const int seg = vc / C, c = vc - seg * C;
-    double s = 0.0;
-    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
-        s += part[((size_t)ch * kPartRows + l) * C + c];
+    const int l = blockIdx.y;
+    const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
+    const bool valid = vc < NC;
+    const int seg = valid ? vc / C : 0, c = valid ? vc - seg * C : 0;
+    const double s = block_chunk_sum(part, kPartRows, C, l, c, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    if (!valid || threadIdx.x >= 64) return;
+    (void)nb;
     const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = s * sg;
     cf[(size_t)(l0 + l) * NC + vc] = g * sg;
@@ -234,14 +235,13 @@ __global__ void k_norm_fin(int C, int nseg, int step, double eps_vec,
                            double *__restrict__ runmax, int32_t *__restrict__ active,
                            int32_t *__restrict__ kused, int ku_ld, int ku_off)
 {
-    const int vc = blockIdx.x * blockDim.x + threadIdx.x;
+    const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
     const int NC = nseg * C;
-    if (vc >= NC) return;
-    const int seg = vc / C, cc = vc - seg * C;
+    const bool valid = vc < NC;
+    const int seg = valid ? vc / C : 0, cc = valid ? vc - seg * C : 0;
     const int i = step;
-    double ss = 0.0;
-    for (int64_t ch = seg_chunk[seg]; ch < seg_chunk[seg + 1]; ++ch)
-        ss += part[(size_t)ch * kPartRows * C + cc];
+    const double ss = block_chunk_sum(part, kPartRows, C, 0, cc, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    if (!valid || threadIdx.x >= 64) return;
     const int c = vc;   // per-virtual-column arrays below
     const size_t C_ = NC;
     const double b = sqrt(ss);
@@ -286,7 +286,7 @@ void launch_setup(const Plan &p, const void *probes, hipStream_t st)
 void launch_setup_fin(const Plan &p, hipStream_t st)
 {
     const int NC = p.nseg * p.C;
-    k_setup_fin<<<(NC + 255) / 256, 256, 0, st>>>(p.C, p.nseg, p.k, p.seg_chunk, p.part, p.nu, p.sig,
+    k_setup_fin<<<(NC + 63) / 64, 64 * kFinWaves, 0, st>>>(p.C, p.nseg, p.k, p.seg_chunk, p.part, p.nu, p.sig,
                                                   p.kappa, p.runmax, p.beta, p.active, p.kused,
                                                   p.Ct, p.c_off);
 }
@@ -362,8 +362,8 @@ void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
 
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
 {
-    const int tot = nb * p.nseg * p.C;
-    k_dots_fin<<<(tot + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part,
+    const int NC = p.nseg * p.C;
+    k_dots_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part,
                                                   p.sig, p.active, p.cf, p.alpha, p.g_gall);
 }
 
@@ -381,7 +381,7 @@ void launch_norm_fin(const Plan &p, int step, hipStream_t st)
 {
     const double eps = p.vec_f32 ? (double)FLT_EPSILON : DBL_EPSILON;
     const int NC = p.nseg * p.C;
-    k_norm_fin<<<(NC + 255) / 256, 256, 0, st>>>(p.C, p.nseg, step, eps, p.seg_chunk, p.part, p.alpha,
+    k_norm_fin<<<(NC + 63) / 64, 64 * kFinWaves, 0, st>>>(p.C, p.nseg, step, eps, p.seg_chunk, p.part, p.alpha,
                                                  p.beta, p.sig, p.kappa, p.runmax, p.active, p.kused,
                                                  p.Ct, p.c_off);
 }
