@@ -89,6 +89,29 @@ __device__ __forceinline__ void vload(const T *__restrict__ p, size_t e, double 
     }
 }
 
+// The same load marked non-temporal: for streams read once per launch (the
+// Lanczos basis in the reorthogonalization sweeps), so that they do not evict
+// what is reused from the caches.
+template <typename T, int VW>
+__device__ __forceinline__ void vload_nt(const T *__restrict__ p, size_t e, double (&o)[VW])
+{
+    if constexpr (sizeof(T) * VW == 8) {
+        const double raw = __builtin_nontemporal_load(reinterpret_cast<const double *>(p + e));
+        if constexpr (VW == 1) {
+            o[0] = raw;
+        } else {
+            T t[VW];
+            __builtin_memcpy(t, &raw, sizeof raw);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) o[v] = static_cast<double>(t[v]);
+        }
+    } else if constexpr (sizeof(T) * VW == 4) {
+        o[0] = static_cast<double>(__builtin_nontemporal_load(reinterpret_cast<const float *>(p + e)));
+    } else {
+        vload<T, VW>(p, e, o);
+    }
+}
+
 template <typename T, int VW>
 __device__ __forceinline__ void vstore(T *__restrict__ p, size_t e, const double (&o)[VW])
 {

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
         vload<T, VW>(Y, e, y);
         vload<T, VW>(Qm, e, qm);
 #pragma unroll
-        for (int l = 0; l < NB; ++l) vload<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
         // keep all NB + 2 loads of the row in flight before the first use
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64) void k_update(int C, int nct, int64_t rpc, int 
         vload<T, VW>(W, e, w);
         vload<T, VW>(Qm, e, qm);
 #pragma unroll
-        for (int l = 0; l < NB; ++l) vload<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
