@@ -156,8 +156,6 @@ size_t plan_layout(Plan &p, char *base)
         p.g_vpart = (double *)take(sizeof(double) * ((C + 63) / 64) * (size_t)p.n);
         p.g_taubar = (double *)take(sizeof(double) * C);
         p.g_sums = (double *)take(sizeof(double) * 64 * C);
-        p.g_w = (double *)p.tmp[0];
-        p.g_r = (double *)p.tmp[1];
     }
     p.bytes = align_up(off, 256) + 256;   // slack for aligning the caller's pointer
     return p.bytes;
@@ -709,16 +707,13 @@ static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, dou
             launch_bdots_fin(p, i, !last, st);
         }
         {
-            Timed t(F_BUPD, (i + 1 + (last ? 0 : 1) + 3) * blk_b, st);
-            launch_bupdate1(p, i, st);
+            // reads: slots 0..i, qbar_{i+1}, qbar_0..i-1; writes: ybar, qbar_0..i-1
+            Timed t(F_BUPD, ((i + 1) + (last ? 0 : 1) + (last ? 0 : i) + (1 + i)) * blk_b, st);
+            launch_bupdate(p, i, last, st);
         }
         {
             Timed t(F_FIN, 0.0, st);
             launch_bnorm_fin(p, i, st);
-        }
-        {
-            Timed t(F_BUPD, ((last ? i : 2 * i) + 3) * blk_b, st);
-            launch_bupdate2(p, i, last, st);
         }
         // qbar_i += C ybar:  tbar = M ybar ; u = (A - tau I) tbar ; qbar_i += M u
         apply_M(p, p.g_ybar, nullptr, p.tmp[0], p.tmp[1], p.g_tbar, p.g_tbar, false, st);

@@ -96,8 +96,6 @@ struct Plan {
     double *g_qbar = nullptr;  // k blocks: adjoints of q_1..q_k (slot-indexed)
     double *g_ybar = nullptr;  // block: adjoint of C q_i
     double *g_tbar = nullptr;  // block: M ybar
-    double *g_w = nullptr;     // block views of scratch used by the backward
-    double *g_r = nullptr;
     double *g_gall = nullptr;  // k*k*C: Gram-Schmidt coefficients g_i[l] of every step
     double *g_Z = nullptr;     // k*k*C: eigenvectors of J
     double *g_theta = nullptr; // k*C
@@ -155,9 +153,8 @@ void launch_arn_quad(const Plan &p, hipStream_t st);
 void launch_tridiag_bwd(const Plan &p, double g_out, hipStream_t st);
 void launch_bdots(const Plan &p, int i, hipStream_t st);
 void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st);
-void launch_bupdate1(const Plan &p, int i, hipStream_t st);
+void launch_bupdate(const Plan &p, int i, bool first, hipStream_t st);
 void launch_bnorm_fin(const Plan &p, int i, hipStream_t st);
-void launch_bupdate2(const Plan &p, int i, bool first, hipStream_t st);
 void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st);
 void launch_grad_out(const Plan &p, double *dV, hipStream_t st);
 

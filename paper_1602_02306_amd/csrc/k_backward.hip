@@ -241,31 +241,39 @@ __global__ void k_bdots_fin(int C, int k, int nchunk, int i, int have_dots,
     scal[(size_t)C + c] = b * sgi;
 }
 
-// Pass 1: rbar, wbar (= ybar), w per row; partial wbar . slot_{i-2}.
-template <int NB, bool HASQ>
-__global__ __launch_bounds__(64) void k_bupdate1(int64_t n, int C, int nct, int64_t rpc,
-                                                 const double *__restrict__ basis,
-                                                 const double *__restrict__ qbar, size_t ss, int i,
-                                                 const double *__restrict__ cA,
-                                                 const double *__restrict__ cW,
+// One sweep per row: rbar, wbar (= ybar) and w of step i, the partial
+// wbar . slot_{i-2}, then qbar_s += cG_s w - cR_s rbar (s < i) and
+// qbar_{i-1} -= beta_i wbar.  rbar and w never leave registers.  A workgroup
+// is four wavefronts on four row chunks of one column tile; they share the
+// 4*NB coefficients of their columns through LDS.
+template <int NB, bool HASQ, bool FIRST>
+__global__ __launch_bounds__(256) void k_bupdate(int64_t n, int C, int nct, int64_t rpc,
+                                                 int64_t nchunk, const double *__restrict__ basis,
+                                                 double *__restrict__ qbar, size_t ss, int i,
+                                                 const double *__restrict__ coef,
                                                  const double *__restrict__ scal,
-                                                 double *__restrict__ ybar, double *__restrict__ W,
-                                                 double *__restrict__ R, double *__restrict__ part)
+                                                 const double *__restrict__ beta,
+                                                 double *__restrict__ ybar,
+                                                 double *__restrict__ part)
 {
-    // NB = i (slots 0..i-1), plus slot i
+    // NB = i (slots 0..i-1), plus slot i.  coef: cA, cW, cG, cR, each [32][C]
+    __shared__ double cf[4][NB][64];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = (int)(L % nct);
-    const int64_t chunk = L / nct;
-    const int c = ct * 64 + (int)threadIdx.x;
-    if (c >= C) return;
-    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
-    double ca[NB], cw[NB];
-#pragma unroll
-    for (int s = 0; s < NB; ++s) {
-        ca[s] = cA[(size_t)s * C + c];
-        cw[s] = cW[(size_t)s * C + c];
+    const int64_t grp = L / nct;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = ct * 64 + lane;
+    const bool colok = c < C;
+    for (int idx = wv; idx < 4 * NB; idx += 4) {
+        const int kind = idx / NB, s = idx - kind * NB;
+        cf[kind][s][lane] = colok ? coef[((size_t)kind * 32 + s) * C + c] : 0.0;
     }
+    __syncthreads();
+    const int64_t chunk = grp * 4 + wv;
+    if (!colok || chunk >= nchunk) return;
+    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
     const double a = scal[c], bq = scal[(size_t)C + c];
+    const double bi = i >= 2 ? beta[(size_t)(i - 1) * C + c] : 0.0;   // beta_i
     const double *QB = qbar + (size_t)i * ss;
     const double *SI = basis + (size_t)i * ss;
     const int sm = i >= 2 ? i - 2 : 0;
@@ -276,19 +284,30 @@ __global__ __launch_bounds__(64) void k_bupdate1(int64_t n, int C, int nct, int6
         const double si = SI[e];
         const double qb = HASQ ? QB[e] : 0.0;
 #pragma unroll
-        for (int s = 0; s < NB; ++s) q[s] = basis[(size_t)s * ss + e];
+        for (int s = 0; s < NB; ++s) q[s] = __builtin_nontemporal_load(basis + (size_t)s * ss + e);
         __builtin_amdgcn_sched_barrier(0);
         const double rb = a * qb + bq * si;
         double wb = rb, w = si;
 #pragma unroll
         for (int s = 0; s < NB; ++s) {
-            wb += ca[s] * q[s];
-            w += cw[s] * q[s];
+            wb += cf[0][s][lane] * q[s];
+            w += cf[1][s][lane] * q[s];
         }
         ybar[e] = wb;
-        W[e] = w;
-        R[e] = rb;
-        dotm += wb * q[sm];
+        double qsm = 0.0;   // q[sm] by selects: a runtime index would move q to scratch
+#pragma unroll
+        for (int s = 0; s < NB; ++s) qsm = s == sm ? q[s] : qsm;
+        dotm += wb * qsm;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) q[s] = FIRST ? 0.0 : qbar[(size_t)s * ss + e];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+            double v = q[s] + cf[2][s][lane] * w - cf[3][s][lane] * rb;
+            if (s == i - 2) v -= bi * wb;
+            qbar[(size_t)s * ss + e] = v;
+        }
     }
     part[(size_t)chunk * 64 * C + c] = dotm;
 }
@@ -302,46 +321,6 @@ __global__ void k_bnorm_fin(int C, int nchunk, int i, const double *__restrict__
     double t = 0.0;
     for (int ch = 0; ch < nchunk; ++ch) t += part[(size_t)ch * 64 * C + c];
     bbar[(size_t)(i - 1) * C + c] -= sig[(size_t)(i - 2) * C + c] * t;
-}
-
-// Pass 2: qbar_s += cG_s w - cR_s rbar (s < i); qbar_{i-1} -= beta_i wbar.
-template <int NB, bool FIRST>
-__global__ __launch_bounds__(64) void k_bupdate2(int64_t n, int C, int nct, int64_t rpc,
-                                                 double *__restrict__ qbar, size_t ss, int i,
-                                                 const double *__restrict__ cG,
-                                                 const double *__restrict__ cR,
-                                                 const double *__restrict__ beta,
-                                                 const double *__restrict__ ybar,
-                                                 const double *__restrict__ W,
-                                                 const double *__restrict__ R)
-{
-    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const int ct = (int)(L % nct);
-    const int64_t chunk = L / nct;
-    const int c = ct * 64 + (int)threadIdx.x;
-    if (c >= C) return;
-    const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
-    double cg[NB], cr[NB];
-#pragma unroll
-    for (int s = 0; s < NB; ++s) {
-        cg[s] = cG[(size_t)s * C + c];
-        cr[s] = cR[(size_t)s * C + c];
-    }
-    const double bi = i >= 2 ? beta[(size_t)(i - 1) * C + c] : 0.0;   // beta_i
-    for (int64_t r = r0; r < r1; ++r) {
-        const size_t e = (size_t)r * C + c;
-        const double w = W[e], rb = R[e], yb = ybar[e];
-        double qb[NB];
-#pragma unroll
-        for (int s = 0; s < NB; ++s) qb[s] = FIRST ? 0.0 : qbar[(size_t)s * ss + e];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int s = 0; s < NB; ++s) {
-            double v = qb[s] + cg[s] * w - cr[s] * rb;
-            if (s == i - 2) v -= bi * yb;
-            qbar[(size_t)s * ss + e] = v;
-        }
-    }
 }
 
 // Vbar and taubar contributions of step i: tb = M ybar_i, tq = M q_i.
@@ -465,26 +444,32 @@ void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st)
                                                    p.g_coef + 64 * C, p.g_coef + 96 * C, p.g_scal);
 }
 
-void launch_bupdate1(const Plan &p, int i, hipStream_t st)
+void launch_bupdate(const Plan &p, int i, bool first, hipStream_t st)
 {
     const int nct = (p.C + 63) / 64;
     const size_t ss = (size_t)p.n * p.C;
     const size_t C = p.C;
     const bool hasq = i < p.k;
+    (void)C;
+    const dim3 grid((unsigned)(((int64_t)p.nchunk + 3) / 4 * nct));
     switch (i) {
+#define ECNT_LAUNCH(N, HQ, FI)                                                                    \
+    k_bupdate<N, HQ, FI><<<grid, 256, 0, st>>>(p.n, p.C, nct, p.rpc, (int64_t)p.nchunk,           \
+                                               (const double *)p.basis, p.g_qbar, ss, i, p.g_coef, \
+                                               p.g_scal, p.beta, p.g_ybar, p.part)
 #define ECNT_CASE(N)                                                                              \
     case N:                                                                                       \
-        if (hasq)                                                                                 \
-            k_bupdate1<N, true><<<red_blocks(p), 64, 0, st>>>(                                    \
-                p.n, p.C, nct, p.rpc, (const double *)p.basis, p.g_qbar, ss, i, p.g_coef,         \
-                p.g_coef + 32 * C, p.g_scal, p.g_ybar, p.g_w, p.g_r, p.part);                     \
-        else                                                                                      \
-            k_bupdate1<N, false><<<red_blocks(p), 64, 0, st>>>(                                   \
-                p.n, p.C, nct, p.rpc, (const double *)p.basis, p.g_qbar, ss, i, p.g_coef,         \
-                p.g_coef + 32 * C, p.g_scal, p.g_ybar, p.g_w, p.g_r, p.part);                     \
+        if (hasq) {                                                                               \
+            if (first) ECNT_LAUNCH(N, true, true);                                                \
+            else ECNT_LAUNCH(N, true, false);                                                     \
+        } else {                                                                                  \
+            if (first) ECNT_LAUNCH(N, false, true);                                               \
+            else ECNT_LAUNCH(N, false, false);                                                    \
+        }                                                                                         \
         break;
         ECNT_NS_CASES(ECNT_CASE)
 #undef ECNT_CASE
+#undef ECNT_LAUNCH
     default:
         break;
     }
@@ -493,30 +478,6 @@ void launch_bupdate1(const Plan &p, int i, hipStream_t st)
 void launch_bnorm_fin(const Plan &p, int i, hipStream_t st)
 {
     k_bnorm_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, i, p.part, p.sig, p.g_bbar);
-}
-
-void launch_bupdate2(const Plan &p, int i, bool first, hipStream_t st)
-{
-    const int nct = (p.C + 63) / 64;
-    const size_t ss = (size_t)p.n * p.C;
-    const size_t C = p.C;
-    switch (i) {
-#define ECNT_CASE(N)                                                                              \
-    case N:                                                                                       \
-        if (first)                                                                                \
-            k_bupdate2<N, true><<<red_blocks(p), 64, 0, st>>>(                                    \
-                p.n, p.C, nct, p.rpc, p.g_qbar, ss, i, p.g_coef + 64 * C, p.g_coef + 96 * C,      \
-                p.beta, p.g_ybar, p.g_w, p.g_r);                                                  \
-        else                                                                                      \
-            k_bupdate2<N, false><<<red_blocks(p), 64, 0, st>>>(                                   \
-                p.n, p.C, nct, p.rpc, p.g_qbar, ss, i, p.g_coef + 64 * C, p.g_coef + 96 * C,      \
-                p.beta, p.g_ybar, p.g_w, p.g_r);                                                  \
-        break;
-        ECNT_NS_CASES(ECNT_CASE)
-#undef ECNT_CASE
-    default:
-        break;
-    }
 }
 
 void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st)

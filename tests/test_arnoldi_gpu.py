@@ -107,3 +107,27 @@ def test_arnoldi_rejects_unsupported(ec):
     with pytest.raises(ec.EcntError) as e:
         run(ec, P.A, W.PrecSpec("jacobi", ()), wl.xi, wl.eta, V, wl.k)
     assert e.value.status == ec.ECNT_EUNSUPPORTED
+
+
+def test_arnoldi_one_step_one_probe(ec):
+    """k = 1 (H_1 is a scalar: sign of the Rayleigh quotient) and m = 1
+    (variance NaN) against the oracle."""
+    wl = W.WORKLOADS["c2_small"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)[:, :1]
+    T = t_spec("cheb", wl.dims)
+    for k in (1, 2):
+        r = run(ec, P.A, T, wl.xi, wl.eta, V, k)
+        ref = oracle.count_arnoldi(P.A, T, wl.xi, wl.eta, V, k)
+        check(r, ref, P.A.n)
+        assert np.isnan(r.variance)
+
+
+def test_arnoldi_deterministic(ec):
+    wl = W.WORKLOADS["c2_ragged"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    T = t_spec("cheb", wl.dims)
+    a = run(ec, P.A, T, wl.xi, wl.eta, V, wl.k)
+    b = run(ec, P.A, T, wl.xi, wl.eta, V, wl.k)
+    assert a.estimate == b.estimate and torch.equal(a.per_probe, b.per_probe)

@@ -191,3 +191,12 @@ def test_batch_bench_family_sampled(ec):
     V = W.rademacher(P.Abd.n, 3, 12345)
     r, _ = run_batch(ec, P, V, 25)
     check_against_oracle(P, r, V, 25)
+
+
+def test_batch_single_probe_and_many_shifts(ec):
+    """m = 1 (variances NaN) and 16 shifts per problem."""
+    P = Problems([(5, 5, 5), (4, 6, 5)], nshift=16, seed=10, lo=-9.0, hi=0.0)
+    V = W.rademacher(P.Abd.n, 1, 3)
+    r, _ = run_batch(ec, P, V, 6)
+    check_against_oracle(P, r, V, 6)
+    assert np.all(np.isnan(r.variances))
