@@ -254,7 +254,9 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
-FAMILY_OF = [("k_quad_sweep", "op_cheb_quad"), ("k_bdots_fin", "lz_finalize"),
+FAMILY_OF = [("k_quad_sweep", "op_cheb_quad"), ("k_arn_quad", "quadrature"),
+             ("k_arn_fin", "lz_finalize"), ("k_arn_norm_fin", "lz_finalize"),
+             ("k_bdots_fin", "lz_finalize"),
              ("k_bnorm_fin", "lz_finalize"), ("k_rowsum", "lz_finalize"), ("k_vgrad", "bw_vgrad"),
              ("k_bdots", "bw_dots"), ("k_bupdate", "bw_update"), ("k_grad_", "lz_finalize"),
              ("k_stencil", "op_cheb_sweep"), ("k_csr_op", "op_csr"), ("k_dots_fin", "lz_finalize"),
