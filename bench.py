@@ -104,29 +104,38 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
     return out
 
 
-def cpu_baseline_batch(items, V, off, k: int, target_s: float, m_total: int):
+def cpu_baseline_batch(items, V, off, k: int, target_s: float, m_total: int, gpu_per_probe=None):
     """The oracle on a bounded sample of the batch: problems in order, all
-    shifts, the first few probes of each, until about target_s seconds."""
+    shifts, the first few probes of each, until about target_s seconds; with
+    the GPU's per-probe values (nprob x nshift*m) also their largest distance
+    from the oracle's on the sample (relative to |v|^2 = n of the problem)."""
     import oracle
     threads = oracle.host_threads()
     m = V.shape[1]
     mp = min(m, threads)
     steps, t_tot, nprob = 0, 0.0, 0
+    worst = 0.0
     for b, it in enumerate(items):
         Vb = np.ascontiguousarray(V[off[b]:off[b + 1], :mp])
         t0 = time.perf_counter()
-        for tau in it.shifts:
-            oracle.negcount(it.A, it.prec, float(tau), Vb, k, nthreads=threads)
+        for si, tau in enumerate(it.shifts):
+            _, s_ref, _, _ = oracle.negcount(it.A, it.prec, float(tau), Vb, k, nthreads=threads)
+            if gpu_per_probe is not None:
+                g = gpu_per_probe[b, si * m_total:si * m_total + mp]
+                worst = max(worst, float(np.max(np.abs(g - s_ref))) / it.A.n)
         t_tot += time.perf_counter() - t0
         steps += len(it.shifts) * mp * k
         nprob += 1
         log("cpu oracle: problem %d (n=%d) done, total %.1f s" % (b, it.A.n, t_tot))
         if t_tot >= target_s:
             break
-    return {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "problems 0..%d of %d, all %d shifts, first %d of %d probes, k=%d "
-                      "(%d probe-steps, %.1f s)" % (nprob - 1, len(items), len(items[0].shifts), mp,
-                                                   m_total, k, steps, t_tot)}
+    out = {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
+           "sample": "problems 0..%d of %d, all %d shifts, first %d of %d probes, k=%d "
+                     "(%d probe-steps, %.1f s)" % (nprob - 1, len(items), len(items[0].shifts), mp,
+                                                  m_total, k, steps, t_tot)}
+    if gpu_per_probe is not None:
+        out["gpu_vs_oracle_max_abs_per_probe_over_n"] = worst
+    return out
 
 
 def bench_batched(args, name: str):
@@ -232,7 +241,11 @@ def bench_batched(args, name: str):
     }
     if not args.no_cpu_baseline:
         V = Vd[:, :16].cpu().double().numpy()
-        out["cpu_baseline"] = cpu_baseline_batch(items, V, off, k, args.cpu_seconds, m)
+        # per-probe values of the same batch (one more eager run with details)
+        btd = ec.Batch(A, prec, sizes, taus, Vd, k, dims=dims, vec=vec, max_cols=max_cols,
+                       tune=tune, workspace=bt.ws, details=True)
+        pp = btd.run().per_probe.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline_batch(items, V, off, k, args.cpu_seconds, m, pp)
     print(json.dumps(out), flush=True)
 
 
