@@ -690,15 +690,24 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
                 continue;
             }
             const int i = LI[q], j = LJ[q];
-            const V vym = su[((i + 2) * UW + (j + 1)) * 64 + lane];
-            const V vyp = su[((i + 2) * UW + (j + 3)) * 64 + lane];
-            const V vxm = su[((i + 1) * UW + (j + 2)) * 64 + lane];
-            const V vxp = su[((i + 3) * UW + (j + 2)) * 64 + lane];
+            // lateral neighbours: inside the wavefront's own quadrant from
+            // registers (the same values it wrote to the plane), else from LDS
+            const bool qd = q < 4;
+            const bool in_ym = qd && (q & 1), in_yp = qd && !(q & 1);
+            const bool in_xm = qd && (q >> 1), in_xp = qd && !(q >> 1);
+            V vym, vyp, vxm, vxp;
+            if (!in_ym) vym = su[((i + 2) * UW + (j + 1)) * 64 + lane];
+            if (!in_yp) vyp = su[((i + 2) * UW + (j + 3)) * 64 + lane];
+            if (!in_xm) vxm = su[((i + 1) * UW + (j + 2)) * 64 + lane];
+            if (!in_xp) vxp = su[((i + 3) * UW + (j + 2)) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
                 const double cu = u0[q][v];
-                const double nb = (double)um[q][v] + zn * (double)un[q][v] + fromV(vym, v) +
-                                  fromV(vyp, v) + fromV(vxm, v) + fromV(vxp, v);
+                const double uym = in_ym ? (double)u0[q - 1][v] : fromV(vym, v);
+                const double uyp = in_yp ? (double)u0[q + 1][v] : fromV(vyp, v);
+                const double uxm = in_xm ? (double)u0[q - 2][v] : fromV(vxm, v);
+                const double uxp = in_xp ? (double)u0[q + 2][v] : fromV(vxp, v);
+                const double nb = (double)um[q][v] + zn * (double)un[q][v] + uym + uyp + uxm + uxp;
                 double t = c1 * xsc[v] * cu;
                 t += xsc[v] * (bd1 * cu - bo1 * nb);
                 tn[q][v] = w[q] != 0.0 ? static_cast<T>(t) : zero;
@@ -710,15 +719,21 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = LI[q], j = LJ[q];
-                const V tym = stp[((i + 1) * TW + j) * 64 + lane];
-                const V typ = stp[((i + 1) * TW + (j + 2)) * 64 + lane];
-                const V txm = stp[(i * TW + (j + 1)) * 64 + lane];
-                const V txp = stp[((i + 2) * TW + (j + 1)) * 64 + lane];
+                const bool in_ym = q & 1, in_xm = q >> 1;   // the other two are in the quadrant too
+                V tym, typ, txm, txp;
+                if (!in_ym) tym = stp[((i + 1) * TW + j) * 64 + lane];
+                if (in_ym) typ = stp[((i + 1) * TW + (j + 2)) * 64 + lane];
+                if (!in_xm) txm = stp[(i * TW + (j + 1)) * 64 + lane];
+                if (in_xm) txp = stp[((i + 2) * TW + (j + 1)) * 64 + lane];
                 double o[VW];
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
-                    const double nb = (double)tm2[q][v] + znt * (double)tn[q][v] + fromV(tym, v) +
-                                      fromV(typ, v) + fromV(txm, v) + fromV(txp, v);
+                    const double tyn = in_ym ? (double)tm1[q - 1][v] : fromV(tym, v);
+                    const double typn = in_ym ? fromV(typ, v) : (double)tm1[q + 1][v];
+                    const double txn = in_xm ? (double)tm1[q - 2][v] : fromV(txm, v);
+                    const double txpn = in_xm ? fromV(txp, v) : (double)tm1[q + 2][v];
+                    const double nb = (double)tm2[q][v] + znt * (double)tn[q][v] + tyn + typn + txn +
+                                      txpn;
                     double val = c2 * xsc[v] * (double)um[q][v];
                     val += 1.0 * (bd2 * (double)tm1[q][v] - bo2 * nb);
                     if (HASZ) val -= cz * (double)zv[q][v];
