@@ -501,15 +501,20 @@ __global__ __launch_bounds__(256) void k_quad_sweep(int C, int ncg, int nseg,
 
 // ---- the same quadratic factor, workgroup-cooperative ----
 // Sixteen wavefronts share one 8 x 8 block of z-lines for 64*VW columns: each
-// owns a 2 x 2 quadrant of output lines, and the quadrants on the block's
-// edge also own the adjacent lines of the distance-1 ring (where t is
-// needed).  Per z value the block's u on every line within distance 2
-// (132 lines) and its t on the block and ring (96 lines) pass through LDS,
-// so every u line is loaded from memory once per workgroup instead of once
-// per neighbouring quadrant.  Two barriers per z value; every wavefront runs
-// the same number of iterations and reaches every barrier.
+// owns a 2 x 2 quadrant of output lines and two of the 32 lines of the
+// distance-1 ring around the block (where t is needed too).  Per z value the
+// block's u on every line within distance 2 (132 lines) and its t on the block
+// and ring (96 lines) pass through LDS, so every u line is loaded from memory
+// once per workgroup instead of once per neighbouring quadrant.  The u values
+// of a wavefront's own lines are loaded two z values ahead.  Two barriers per
+// z value; every wavefront runs the same number of iterations and reaches
+// every barrier.
 namespace quadwg {
-// the 36 lines at distance 2 from the 8 x 8 block, shared out round-robin
+// the 32 lines at distance 1 and the 36 at distance 2 from the 8 x 8 block
+constexpr int R1I[32] = {-1, -1, -1, -1, -1, -1, -1, -1, 8, 8, 8, 8, 8, 8, 8, 8,
+                         0,  1,  2,  3,  4,  5,  6,  7, 0, 1, 2, 3, 4, 5, 6, 7};
+constexpr int R1J[32] = {0,  1,  2,  3,  4,  5,  6,  7,  0, 1, 2, 3, 4, 5, 6, 7,
+                         -1, -1, -1, -1, -1, -1, -1, -1, 8, 8, 8, 8, 8, 8, 8, 8};
 constexpr int R2I[36] = {-2, -2, -2, -2, -2, -2, -2, -2, 9, 9, 9, 9, 9, 9, 9, 9, 0, 1,
                          2,  3,  4,  5,  6,  7,  0,  1, 2, 3, 4, 5, 6, 7, -1, -1, 8, 8};
 constexpr int R2J[36] = {0, 1, 2, 3, 4,  5,  6,  7,  0,  1,  2,  3,  4, 5, 6, 7, -2, -2,
@@ -532,6 +537,7 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
 {
     using namespace quadwg;
     using V = typename VecT<T, VW>::type;
+    constexpr int NT = 6;   // lines of a wavefront: 4 of its quadrant, 2 of the ring
     __shared__ V su[UW * UW * 64];
     __shared__ V stp[TW * TW * 64];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -583,30 +589,24 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         }
     };
     const T zero = T(0);
-    // this wavefront's lines: 0..3 its quadrant, 4..5 the ring beside it in x,
-    // 6..7 the ring beside it in y (present on the block's edges only)
     const int qx = wv >> 2, qy = wv & 3;
-    const bool hasX = qx == 0 || qx == 3, hasY = qy == 0 || qy == 3;
-    int LI[8], LJ[8];
+    int LI[NT], LJ[NT];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         LI[q] = 2 * qx + (q >> 1);
         LJ[q] = 2 * qy + (q & 1);
     }
-    LI[4] = LI[5] = qx == 0 ? -1 : 8;
-    LJ[4] = 2 * qy;
-    LJ[5] = 2 * qy + 1;
-    LI[6] = 2 * qx;
-    LI[7] = 2 * qx + 1;
-    LJ[6] = LJ[7] = qy == 0 ? -1 : 8;
-    bool own[8];
-    int64_t off[8];
-    double w[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        own[q] = q < 4 || (q < 6 ? hasX : hasY);
-        off[q] = own[q] ? offset(LI[q], LJ[q]) : 0;
-        w[q] = own[q] && inside(LI[q], LJ[q]) ? 1.0 : 0.0;
+    for (int q = 4; q < NT; ++q) {
+        LI[q] = R1I[2 * wv + q - 4];
+        LJ[q] = R1J[2 * wv + q - 4];
+    }
+    int64_t off[NT];
+    double w[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        off[q] = offset(LI[q], LJ[q]);
+        w[q] = inside(LI[q], LJ[q]) ? 1.0 : 0.0;
     }
     // ring-2 share
     int64_t off2[3];
@@ -625,15 +625,19 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
     double xsc[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) xsc[v] = xs ? xs[c0 + v] : 1.0;
-    T um[8][VW], u0[8][VW], r2[3][VW], tm2[4][VW], tm1[4][VW];
+    // u of the own lines at z-1, z, z+1 (um, u0, un); ring-2 u at z (r2)
+    T um[NT][VW], u0[NT][VW], un[NT][VW], r2[3][VW], tm2[4][VW], tm1[4][VW];
+    const int64_t e1 = d2 > 1 ? zs : 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        T a[VW];
+    for (int q = 0; q < NT; ++q) {
+        T a[VW], b[VW];
         ldT(base + off[q], a);
+        ldT(base + e1 + off[q], b);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
             um[q][v] = zero;
             u0[q][v] = w[q] != 0.0 ? a[v] : zero;
+            un[q][v] = (w[q] != 0.0 && d2 > 1) ? b[v] : zero;
         }
     }
 #pragma unroll
@@ -648,13 +652,14 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
 #pragma unroll
         for (int v = 0; v < VW; ++v) tm2[q][v] = tm1[q][v] = zero;
     for (int z = 0; z <= d2; ++z) {
-        const bool has_t = z < d2, has_n = z + 1 < d2;
+        const bool has_t = z < d2, has_n = z + 1 < d2, has_nn = z + 2 < d2;
+        const int64_t enn = has_nn ? (int64_t)(z + 2) * zs : 0;
         const int64_t en = has_n ? (int64_t)(z + 1) * zs : 0;
         const int64_t ep = z >= 1 ? (int64_t)(z - 1) * zs : 0;
-        // loads for the next z value (in flight during this one)
-        T un[8][VW], r2n[3][VW], zv[4][VW];
+        // loads in flight during this z value: own lines at z+2, ring 2 at z+1, Z at z-1
+        T unn[NT][VW], r2n[3][VW], zv[4][VW];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ldT(base + en + off[q], un[q]);
+        for (int q = 0; q < NT; ++q) ldT(base + enn + off[q], unn[q]);
 #pragma unroll
         for (int s = 0; s < 3; ++s) ldT(base + en + off2[s], r2n[s]);
         if (HASZ) {
@@ -672,8 +677,8 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         // u at z into the shared plane
         if (has_t) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (own[q]) su[((LI[q] + 2) * UW + (LJ[q] + 2)) * 64 + lane] = toV(u0[q]);
+            for (int q = 0; q < NT; ++q)
+                su[((LI[q] + 2) * UW + (LJ[q] + 2)) * 64 + lane] = toV(u0[q]);
 #pragma unroll
             for (int s = 0; s < 3; ++s)
                 if (has2[s]) su[slot2[s] * 64 + lane] = toV(r2[s]);
@@ -681,10 +686,10 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         __syncthreads();
         // t at z on this wavefront's lines
         const double zn = has_n ? 1.0 : 0.0;
-        T tn[8][VW];
+        T tn[NT][VW];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (!own[q] || !has_t) {
+        for (int q = 0; q < NT; ++q) {
+            if (!has_t) {
 #pragma unroll
                 for (int v = 0; v < VW; ++v) tn[q][v] = zero;
                 continue;
@@ -713,7 +718,7 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
                 tn[q][v] = w[q] != 0.0 ? static_cast<T>(t) : zero;
             }
         }
-        // out at z-1 on the quadrant (t at z-1 of the neighbours from the shared plane)
+        // out at z-1 on the quadrant (t at z-1 of the neighbours outside it from LDS)
         if (z >= 1) {
             const double znt = has_t ? 1.0 : 0.0;
 #pragma unroll
@@ -746,8 +751,8 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         // t at z into the shared plane
         if (has_t) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (own[q]) stp[((LI[q] + 1) * TW + (LJ[q] + 1)) * 64 + lane] = toV(tn[q]);
+            for (int q = 0; q < NT; ++q)
+                stp[((LI[q] + 1) * TW + (LJ[q] + 1)) * 64 + lane] = toV(tn[q]);
         }
         // advance one z value
 #pragma unroll
@@ -758,9 +763,10 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
                 tm1[q][v] = tn[q][v];
             }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < NT; ++q) {
                 um[q][v] = u0[q][v];
-                u0[q][v] = (w[q] != 0.0 && has_n) ? un[q][v] : zero;
+                u0[q][v] = un[q][v];
+                un[q][v] = (w[q] != 0.0 && has_nn) ? unn[q][v] : zero;
             }
 #pragma unroll
             for (int s = 0; s < 3; ++s) r2[s][v] = (w2[s] != 0.0 && has_n) ? r2n[s][v] : zero;
