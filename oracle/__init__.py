@@ -3,14 +3,16 @@
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the GPU library or its binding.
 """
-from .oracle import (ArnoldiResult, CountResult, LanczosResult, arnoldi, arnoldi_quadrature,
-                     build, count, count_arnoldi, count_tangent, dense_operator,
+from .oracle import (ArnoldiResult, CountResult, ILDLFactor, LanczosResult, abs_invsqrt_blocks,
+                     arnoldi, arnoldi_quadrature, build, count, count_arnoldi, count_tangent,
+                     dense_operator, dense_operator_ldl, ildl, lanczos_ldl,
                      divided_difference, host_threads, jacobi_matrix, lanczos, lanczos_tangent,
                      negcount, probe_quadrature, probe_quadrature_tangent, quadrature, step,
                      step_deriv)
 
-__all__ = ["ArnoldiResult", "CountResult", "LanczosResult", "arnoldi", "arnoldi_quadrature",
-           "build", "count", "count_arnoldi", "count_tangent", "dense_operator",
+__all__ = ["ArnoldiResult", "CountResult", "ILDLFactor", "LanczosResult", "abs_invsqrt_blocks",
+           "arnoldi", "arnoldi_quadrature", "build", "count", "count_arnoldi", "count_tangent",
+           "dense_operator", "dense_operator_ldl", "ildl", "lanczos_ldl",
            "divided_difference", "host_threads", "jacobi_matrix", "lanczos", "lanczos_tangent",
            "negcount", "probe_quadrature", "probe_quadrature_tangent", "quadrature", "step",
            "step_deriv"]

@@ -35,6 +35,10 @@
  *   kind 2: M = sum_{j=0}^{d} c_j T_j(B), B = (2 (L + sI) - (lo + hi) I)/(hi - lo),
  *           L the Dirichlet Laplacian of the grid `dims` (diagonal 2*ndim,
  *           neighbours -1), evaluated by Clenshaw's recurrence.
+ *   kind 3: factored ILDL preconditioner of one shift (Section 6):
+ *           P (A - tau I) P^T ~ L D L^T, T = P^T L^{-T} |D|^{-1} L^{-1} P,
+ *           M = |D|^{-1/2} L^{-1} P, M^* = P^T L^{-T} |D|^{-1/2}; this M is
+ *           not symmetric, so C = M (A - tau I) M^* applies M^* first.
  */
 #include <float.h>
 #include <math.h>
@@ -58,6 +62,11 @@ typedef struct {
     const double *coef;
     double tau;
     const double *jac; /* |a_rr - tau|^(-1/2), kind 1 only */
+    /* kind 3: P, strictly lower L (CSR, rows), |D|^(-1/2) by blocks */
+    const int32_t *perm;
+    const int32_t *l_rp, *l_ci;
+    const double *l_val;
+    const double *e_diag, *e_off; /* e_off[i] = E_{i+1,i} at the first row of a 2x2 block, else 0 */
 } op_t;
 
 /* y = (A - tau I) x */
@@ -136,10 +145,58 @@ static void apply_M(const op_t *P, const double *x, double *y, double *work)
     for (int64_t r = 0; r < n; ++r) y[r] = P->coef[0] * x[r] + Bb[r] - b2[r];
 }
 
-/* y = M (A - tau I) M x.  work: 5 vectors of n. */
+/* z = |D|^(-1/2) y, block by block (kind 3) */
+static void apply_E(const op_t *P, const double *y, double *z)
+{
+    int64_t n = P->n;
+    for (int64_t i = 0; i < n; ++i) {
+        if (i + 1 < n && P->e_off[i] != 0.0) {
+            z[i] = P->e_diag[i] * y[i] + P->e_off[i] * y[i + 1];
+            z[i + 1] = P->e_off[i] * y[i] + P->e_diag[i + 1] * y[i + 1];
+            ++i;
+        } else {
+            z[i] = P->e_diag[i] * y[i];
+        }
+    }
+}
+
+/* y = M x = |D|^(-1/2) L^{-1} P x (kind 3): forward substitution by rows */
+static void apply_M_ldl(const op_t *P, const double *x, double *y, double *work)
+{
+    int64_t n = P->n;
+    double *f = work;
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = x[P->perm[i]];
+        for (int32_t p = P->l_rp[i]; p < P->l_rp[i + 1]; ++p) acc -= P->l_val[p] * f[P->l_ci[p]];
+        f[i] = acc;
+    }
+    apply_E(P, f, y);
+}
+
+/* y = M^* x = P^T L^{-T} |D|^(-1/2) x (kind 3): back substitution with L^T,
+ * taking the rows of L as columns of L^T */
+static void apply_Mstar_ldl(const op_t *P, const double *x, double *y, double *work)
+{
+    int64_t n = P->n;
+    double *z = work;
+    apply_E(P, x, z);
+    for (int64_t i = n - 1; i >= 0; --i) {
+        const double zi = z[i]; /* final: every l_ji z_i term with j > i is already removed */
+        for (int32_t p = P->l_rp[i]; p < P->l_rp[i + 1]; ++p) z[P->l_ci[p]] -= P->l_val[p] * zi;
+        y[P->perm[i]] = zi;
+    }
+}
+
+/* y = M (A - tau I) M^* x.  work: 5 vectors of n. */
 static void apply_C(const op_t *P, const double *x, double *y, double *work)
 {
     double *t = work, *u = work + P->n, *mw = work + 2 * P->n;
+    if (P->prec_kind == 3) {
+        apply_Mstar_ldl(P, x, t, mw);
+        shifted_matvec(P, t, u);
+        apply_M_ldl(P, u, y, mw);
+        return;
+    }
     apply_M(P, x, t, mw);
     shifted_matvec(P, t, u);
     apply_M(P, u, y, mw);
@@ -190,6 +247,48 @@ static int lanczos_one(const op_t *P, const double *v, int k, double *alpha, dou
     return k;
 }
 
+/* Algorithm 1 for every column of V, OpenMP over probes. */
+static int run_probes(const op_t *P, const double *V, int64_t m, int k, int nthreads,
+                      double *alpha, double *beta, int32_t *k_used, double *nu)
+{
+    int64_t n = P->n;
+    memset(alpha, 0, (size_t)m * k * sizeof(double));
+    memset(beta, 0, (size_t)m * (k + 1) * sizeof(double));
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *Q = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
+        double *w = (double *)malloc((size_t)n * sizeof(double));
+        double *v = (double *)malloc((size_t)n * sizeof(double));
+        double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+        double *h = (double *)malloc((size_t)(k + 1) * sizeof(double));
+        if (!Q || !w || !v || !work || !h) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t j = 0; j < m; ++j) {
+                for (int64_t r = 0; r < n; ++r) v[r] = V[r * m + j];
+                k_used[j] = lanczos_one(P, v, k, alpha + j * k, beta + j * (k + 1), nu + j, Q, w,
+                                        h, work);
+            }
+        }
+        free(Q);
+        free(w);
+        free(v);
+        free(work);
+        free(h);
+    }
+    return failed ? -1 : 0;
+}
+
 /*
  * Run Algorithm 1 for every probe j = 0..m-1 at shift tau.
  *   V      n x m row-major probe block (v_j is column j)
@@ -238,42 +337,9 @@ int oracle_lanczos(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, co
         }
         P.jac = jac;
     }
-    memset(alpha, 0, (size_t)m * k * sizeof(double));
-    memset(beta, 0, (size_t)m * (k + 1) * sizeof(double));
-    int failed = 0;
-#ifdef _OPENMP
-    if (nthreads < 1) nthreads = 1;
-#pragma omp parallel num_threads(nthreads)
-#endif
-    {
-        double *Q = (double *)malloc((size_t)n * (k + 1) * sizeof(double));
-        double *w = (double *)malloc((size_t)n * sizeof(double));
-        double *v = (double *)malloc((size_t)n * sizeof(double));
-        double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
-        double *h = (double *)malloc((size_t)(k + 1) * sizeof(double));
-        if (!Q || !w || !v || !work || !h) {
-#ifdef _OPENMP
-#pragma omp atomic write
-#endif
-            failed = 1;
-        } else {
-#ifdef _OPENMP
-#pragma omp for schedule(dynamic, 1)
-#endif
-            for (int64_t j = 0; j < m; ++j) {
-                for (int64_t r = 0; r < n; ++r) v[r] = V[r * m + j];
-                k_used[j] = lanczos_one(&P, v, k, alpha + j * k, beta + j * (k + 1), nu + j, Q, w,
-                                        h, work);
-            }
-        }
-        free(Q);
-        free(w);
-        free(v);
-        free(work);
-        free(h);
-    }
+    int rc = run_probes(&P, V, m, k, nthreads, alpha, beta, k_used, nu);
     free(jac);
-    return failed ? -1 : 0;
+    return rc;
 }
 
 /*
@@ -612,6 +678,127 @@ int oracle_arnoldi(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, co
     }
     free(jac);
     return failed ? -1 : 0;
+}
+
+/*
+ * |D|^(-1/2) block by block: 1 / sqrt|d| for a 1x1 block; for a 2x2 block
+ * [[a, b], [b, c]] (b != 0) the spectral form sum_i |mu_i|^(-1/2) v_i v_i^T.
+ */
+static void abs_invsqrt_blocks(int64_t n, const double *d_diag, const double *d_off,
+                               double *e_diag, double *e_off)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        e_off[i] = 0.0;
+        if (i + 1 < n && d_off[i] != 0.0) {
+            const double a = d_diag[i], b = d_off[i], c = d_diag[i + 1];
+            const double mid = 0.5 * (a + c), rad = hypot(0.5 * (a - c), b);
+            const double mu1 = mid + rad, mu2 = mid - rad;
+            /* eigenvector of mu1: (b, mu1 - a) or (mu1 - c, b), whichever is longer */
+            double vx = b, vy = mu1 - a;
+            const double ux = mu1 - c, uy = b;
+            if (hypot(ux, uy) > hypot(vx, vy)) {
+                vx = ux;
+                vy = uy;
+            }
+            const double len = hypot(vx, vy);
+            vx /= len;
+            vy /= len;
+            const double f1 = 1.0 / sqrt(fabs(mu1)), f2 = 1.0 / sqrt(fabs(mu2));
+            e_diag[i] = f1 * vx * vx + f2 * vy * vy;
+            e_diag[i + 1] = f1 * vy * vy + f2 * vx * vx;
+            e_off[i] = (f1 - f2) * vx * vy;
+            e_off[i + 1] = 0.0;
+            ++i;
+        } else {
+            e_diag[i] = 1.0 / sqrt(fabs(d_diag[i]));
+        }
+    }
+}
+
+static void fill_ldl(op_t *P, int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *val, double tau, const int32_t *perm, const int32_t *l_rp,
+                     const int32_t *l_ci, const double *l_val, const double *e_diag,
+                     const double *e_off)
+{
+    memset(P, 0, sizeof *P);
+    P->n = n;
+    P->row_ptr = row_ptr;
+    P->col_idx = col_idx;
+    P->val = val;
+    P->prec_kind = 3;
+    P->tau = tau;
+    P->perm = perm;
+    P->l_rp = l_rp;
+    P->l_ci = l_ci;
+    P->l_val = l_val;
+    P->e_diag = e_diag;
+    P->e_off = e_off;
+}
+
+/*
+ * Algorithm 1 with the factored ILDL preconditioner of shift tau (kind 3):
+ * perm, L (strictly lower, CSR), D (d_diag, d_off as oracle_ildl writes
+ * them).  Outputs as oracle_lanczos.  Returns 0, -1 (bad arguments), -2 (a
+ * zero pivot in D).
+ */
+int oracle_lanczos_ldl(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *val, double tau, const int32_t *perm, const int32_t *l_rp,
+                       const int32_t *l_ci, const double *l_val, const double *d_diag,
+                       const double *d_off, const double *V, int64_t m, int k, int nthreads,
+                       double *alpha, double *beta, int32_t *k_used, double *nu)
+{
+    if (n < 1 || m < 1 || k < 1 || k > n) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (d_diag[i] == 0.0 && !(i > 0 && d_off[i - 1] != 0.0) && d_off[i] == 0.0) return -2;
+    double *e = (double *)malloc((size_t)n * 2 * sizeof(double));
+    if (!e) return -1;
+    abs_invsqrt_blocks(n, d_diag, d_off, e, e + n);
+    op_t P;
+    fill_ldl(&P, n, row_ptr, col_idx, val, tau, perm, l_rp, l_ci, l_val, e, e + n);
+    int rc = run_probes(&P, V, m, k, nthreads, alpha, beta, k_used, nu);
+    free(e);
+    return rc;
+}
+
+/* Dense C = M (A - tau I) M^* with the ILDL preconditioner (small n only). */
+int oracle_dense_operator_ldl(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                              const double *val, double tau, const int32_t *perm,
+                              const int32_t *l_rp, const int32_t *l_ci, const double *l_val,
+                              const double *d_diag, const double *d_off, double *Cout)
+{
+    double *e = (double *)malloc((size_t)n * 2 * sizeof(double));
+    double *x = (double *)calloc((size_t)n, sizeof(double));
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+    if (!e || !x || !y || !work) {
+        free(e);
+        free(x);
+        free(y);
+        free(work);
+        return -1;
+    }
+    abs_invsqrt_blocks(n, d_diag, d_off, e, e + n);
+    op_t P;
+    fill_ldl(&P, n, row_ptr, col_idx, val, tau, perm, l_rp, l_ci, l_val, e, e + n);
+    for (int64_t c = 0; c < n; ++c) {
+        x[c] = 1.0;
+        apply_C(&P, x, y, work);
+        x[c] = 0.0;
+        for (int64_t r = 0; r < n; ++r) Cout[r * n + c] = y[r];
+    }
+    free(e);
+    free(x);
+    free(y);
+    free(work);
+    return 0;
+}
+
+/* |D|^(-1/2) as the oracle forms it (for the pins of the block formula). */
+int oracle_abs_invsqrt_blocks(int64_t n, const double *d_diag, const double *d_off,
+                              double *e_diag, double *e_off)
+{
+    abs_invsqrt_blocks(n, d_diag, d_off, e_diag, e_off);
+    return 0;
 }
 
 int oracle_max_threads(void)

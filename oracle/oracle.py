@@ -42,10 +42,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lanczos_oracle.c")
+_SRC_ILDL = os.path.join(_HERE, "ildl_oracle.c")
 _LIB = os.path.join(_HERE, "liblanczos_oracle.so")
 _lib = None
 
-PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2}
+PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2, "ildl": 3}
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +54,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-o", tmp, _SRC, _SRC_ILDL, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -86,6 +87,21 @@ def _load():
                                        ctypes.c_int, P, ctypes.c_double, P, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_int, P, P, P]
         lib.oracle_max_threads.restype = ctypes.c_int
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        lib.oracle_ildl.restype = ctypes.c_int
+        lib.oracle_ildl.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
+                                    P, P, P, ctypes.POINTER(ctypes.c_int64), PP, PP, PP]
+        lib.oracle_free.restype = None
+        lib.oracle_free.argtypes = [ctypes.c_void_p]
+        lib.oracle_lanczos_ldl.restype = ctypes.c_int
+        lib.oracle_lanczos_ldl.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, P, P, P, P,
+                                           P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                           P, P, P, P]
+        lib.oracle_dense_operator_ldl.restype = ctypes.c_int
+        lib.oracle_dense_operator_ldl.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, P, P,
+                                                  P, P, P, P, P]
+        lib.oracle_abs_invsqrt_blocks.restype = ctypes.c_int
+        lib.oracle_abs_invsqrt_blocks.argtypes = [ctypes.c_int64, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -112,6 +128,99 @@ def _prec_args(prec, n):
     return kind, nd, dims, coef
 
 
+# ---------------------------------------------------------------------------
+# ILDL(t) preconditioner of one shift (Section 6)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class ILDLFactor:
+    """P (A - tau I) P^T ~ L D L^T.  perm[i]: the row of A - tau I placed at
+    row i; L strictly lower (unit diagonal implied) in CSR (l_rp, l_ci, l_val);
+    D block diagonal: d_diag, and d_off[i] = D_{i+1,i} at the first row of a
+    2 x 2 block (0 elsewhere)."""
+    perm: np.ndarray
+    l_rp: np.ndarray
+    l_ci: np.ndarray
+    l_val: np.ndarray
+    d_diag: np.ndarray
+    d_off: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return len(self.perm)
+
+    def dense_L(self) -> np.ndarray:
+        n = self.n
+        L = np.eye(n)
+        for i in range(n):
+            for p in range(self.l_rp[i], self.l_rp[i + 1]):
+                L[i, self.l_ci[p]] = self.l_val[p]
+        return L
+
+    def dense_D(self) -> np.ndarray:
+        D = np.diag(self.d_diag)
+        for i in np.nonzero(self.d_off)[0]:
+            D[i + 1, i] = D[i, i + 1] = self.d_off[i]
+        return D
+
+    def bandwidth(self) -> int:
+        rows = np.repeat(np.arange(self.n), np.diff(self.l_rp))
+        return int(np.max(rows - self.l_ci)) if len(self.l_ci) else 0
+
+
+def _csr_args(A):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    return rp, ci, va
+
+
+def ildl(A, tau: float, droptol: float) -> ILDLFactor:
+    """ILDL(t) of A - tau I with Bunch-Kaufman pivoting (oracle_ildl in
+    ildl_oracle.c: natural order, dense right-looking)."""
+    lib = _load()
+    n = A.n
+    rp, ci, va = _csr_args(A)
+    perm = np.zeros(n, dtype=np.int32)
+    dd = np.zeros(n)
+    do = np.zeros(n)
+    nnz = ctypes.c_int64(0)
+    prp, pci, pval = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    rc = lib.oracle_ildl(n, _ptr(rp), _ptr(ci), _ptr(va), float(tau), float(droptol), _ptr(perm),
+                         _ptr(dd), _ptr(do), ctypes.byref(nnz), ctypes.byref(prp),
+                         ctypes.byref(pci), ctypes.byref(pval))
+    if rc == -3:
+        raise ZeroDivisionError("ILDL: zero pivot (A - tau I singular in the factorization)")
+    if rc != 0:
+        raise ValueError("oracle_ildl failed (%d)" % rc)
+    try:
+        nz = int(nnz.value)
+        l_rp = np.ctypeslib.as_array(ctypes.cast(prp, ctypes.POINTER(ctypes.c_int32)), (n + 1,)).copy()
+        l_ci = np.ctypeslib.as_array(ctypes.cast(pci, ctypes.POINTER(ctypes.c_int32)), (max(nz, 1),))[:nz].copy()
+        l_val = np.ctypeslib.as_array(ctypes.cast(pval, ctypes.POINTER(ctypes.c_double)), (max(nz, 1),))[:nz].copy()
+    finally:
+        for p in (prp, pci, pval):
+            lib.oracle_free(p)
+    return ILDLFactor(perm, l_rp, l_ci, l_val, dd, do)
+
+
+def abs_invsqrt_blocks(F: ILDLFactor):
+    """|D|^(-1/2) by blocks as the oracle forms it: (e_diag, e_off)."""
+    lib = _load()
+    n = F.n
+    ed = np.zeros(n)
+    eo = np.zeros(n)
+    dd = np.ascontiguousarray(F.d_diag)
+    do = np.ascontiguousarray(F.d_off)
+    lib.oracle_abs_invsqrt_blocks(n, _ptr(dd), _ptr(do), _ptr(ed), _ptr(eo))
+    return ed, eo
+
+
+def _ldl_args(F: ILDLFactor):
+    return [np.ascontiguousarray(a) for a in (F.perm, F.l_rp, F.l_ci, F.l_val, F.d_diag, F.d_off)]
+
+
 @dataclass
 class LanczosResult:
     alpha: np.ndarray   # m x k
@@ -121,12 +230,15 @@ class LanczosResult:
 
 
 def lanczos(A, prec, tau: float, V: np.ndarray, k: int, nthreads: int | None = None) -> LanczosResult:
-    """Algorithm 1 on C = M (A - tau I) M for every column of V (n x m)."""
+    """Algorithm 1 on C = M (A - tau I) M^* for every column of V (n x m).
+    For prec.kind == 'ildl' the factor of this shift is built first (ildl)."""
     lib = _load()
     V = np.ascontiguousarray(V, dtype=np.float64)
     n, m = V.shape
     if A.n != n:
         raise ValueError("probe block does not match A")
+    if prec.kind == "ildl":
+        return lanczos_ldl(A, ildl(A, tau, prec.droptol), tau, V, k, nthreads)
     kind, nd, dims, coef = _prec_args(prec, n)
     alpha = np.zeros((m, k))
     beta = np.zeros((m, k + 1))
@@ -147,8 +259,46 @@ def lanczos(A, prec, tau: float, V: np.ndarray, k: int, nthreads: int | None = N
     return LanczosResult(alpha, beta, k_used, nu)
 
 
+def lanczos_ldl(A, F: ILDLFactor, tau: float, V: np.ndarray, k: int,
+                nthreads: int | None = None) -> LanczosResult:
+    """Algorithm 1 on C = M (A - tau I) M^*, M = |D|^(-1/2) L^{-1} P from the
+    factor F of this shift."""
+    lib = _load()
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    n, m = V.shape
+    rp, ci, va = _csr_args(A)
+    perm, lrp, lci, lval, dd, do = _ldl_args(F)
+    alpha = np.zeros((m, k))
+    beta = np.zeros((m, k + 1))
+    k_used = np.zeros(m, dtype=np.int32)
+    nu = np.zeros(m)
+    rc = lib.oracle_lanczos_ldl(n, _ptr(rp), _ptr(ci), _ptr(va), float(tau), _ptr(perm),
+                                _ptr(lrp), _ptr(lci), _ptr(lval), _ptr(dd), _ptr(do), _ptr(V), m,
+                                int(k), int(nthreads or host_threads()), _ptr(alpha), _ptr(beta),
+                                _ptr(k_used), _ptr(nu))
+    if rc == -2:
+        raise ZeroDivisionError("ILDL factor has a zero pivot")
+    if rc != 0:
+        raise ValueError("oracle_lanczos_ldl failed (%d)" % rc)
+    return LanczosResult(alpha, beta, k_used, nu)
+
+
+def dense_operator_ldl(A, F: ILDLFactor, tau: float) -> np.ndarray:
+    """C = M (A - tau I) M^* with the ILDL preconditioner (small n only)."""
+    lib = _load()
+    n = A.n
+    rp, ci, va = _csr_args(A)
+    perm, lrp, lci, lval, dd, do = _ldl_args(F)
+    C = np.zeros((n, n))
+    lib.oracle_dense_operator_ldl(n, _ptr(rp), _ptr(ci), _ptr(va), float(tau), _ptr(perm),
+                                  _ptr(lrp), _ptr(lci), _ptr(lval), _ptr(dd), _ptr(do), _ptr(C))
+    return C
+
+
 def dense_operator(A, prec, tau: float) -> np.ndarray:
-    """C = M (A - tau I) M as a dense matrix (small n only)."""
+    """C = M (A - tau I) M^* as a dense matrix (small n only)."""
+    if prec.kind == "ildl":
+        return dense_operator_ldl(A, ildl(A, tau, prec.droptol), tau)
     lib = _load()
     n = A.n
     kind, nd, dims, coef = _prec_args(prec, n)

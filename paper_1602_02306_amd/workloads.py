@@ -244,14 +244,17 @@ def cheb_interp_coeffs(f, lo: float, hi: float, degree: int) -> np.ndarray:
 @dataclasses.dataclass
 class PrecSpec:
     """kind: 'none' (M = I), 'jacobi' (M_tau = |diag(A) - tau|^(-1/2), per shift),
-    or 'cheb' (M = sum_j coef[j] T_j((2(L + s I) - (lo + hi) I)/(hi - lo)) with
-    L the Dirichlet Laplacian of `dims`, shared by all shifts)."""
+    'cheb' (M = sum_j coef[j] T_j((2(L + s I) - (lo + hi) I)/(hi - lo)) with
+    L the Dirichlet Laplacian of `dims`, shared by all shifts), or 'ildl'
+    (M_tau = |D|^(-1/2) L^{-1} P from an ILDL(droptol) factorization of
+    A - tau I, one per shift)."""
     kind: str
     dims: tuple = ()
     s: float = 0.0
     lo: float = 0.0
     hi: float = 0.0
     coef: np.ndarray | None = None
+    droptol: float = 0.0
 
     @property
     def degree(self) -> int:
