@@ -80,12 +80,48 @@ typedef struct {
  *                             2*ndim, neighbours -1; a grid point (x, y, z) is row
  *                             (x*dims[1] + y)*dims[2] + z), shared by all shifts.
  *                             M is symmetric; T = M^2 must be HPD (the caller's
- *                             responsibility: M nonsingular on the spectrum of L). */
+ *                             responsibility: M nonsingular on the spectrum of L).
+ *   ECNT_PREC_LDL             the factored absolute-value preconditioner of Section 6,
+ *                             one factor per shift: P (A - tau I) P^T ~ L D L^T,
+ *                             T = P^T L^{-T} |D|^{-1} L^{-1} P (HPD for any L, D),
+ *                             M = |D|^{-1/2} L^{-1} P, M^* = P^T L^{-T} |D|^{-1/2};
+ *                             |D|^{-1/2} is formed block by block from D.  Factors
+ *                             come from ecnt_ildl_factor (or any other source in the
+ *                             same layout).  The triangular solves keep the last 256
+ *                             solved rows of every column on chip: a factor whose
+ *                             bandwidth (max i - j over the entries of L) exceeds
+ *                             256 is EUNSUPPORTED. */
 typedef enum {
     ECNT_PREC_NONE = 0,
     ECNT_PREC_JACOBI = 1,
-    ECNT_PREC_CHEB_LAPLACIAN = 2
+    ECNT_PREC_CHEB_LAPLACIAN = 2,
+    ECNT_PREC_LDL = 3
 } ecnt_prec_kind;
+
+/* One shift's L D L^T factor on the device (ECNT_PREC_LDL).  All arrays are
+ * device memory owned by the caller and must stay valid for the call.
+ *   perm        n: row i of P (A - tau I) P^T is row perm[i] of A - tau I
+ *   l_row_ptr   n+1, l_col_idx / l_val nnz: the strictly lower part of L
+ *               (unit diagonal implied) by rows, columns ascending in a row
+ *   lt_row_ptr  n+1, lt_col_idx / lt_val nnz: the same entries by columns
+ *               (rows of L^T), rows ascending
+ *   d_diag      n: D_ii;  d_off n: D_{i+1,i} at the first row i of a 2 x 2
+ *               block (non-zero there), 0 elsewhere
+ *   nnz, bandwidth  entry count and max (i - j) over the entries */
+typedef struct {
+    const int32_t *perm;
+    const int32_t *l_row_ptr;
+    const int32_t *l_col_idx;
+    const double *l_val;
+    const int32_t *lt_row_ptr;
+    const int32_t *lt_col_idx;
+    const double *lt_val;
+    const double *d_diag;
+    const double *d_off;
+    int64_t nnz;
+    int32_t bandwidth;
+    int32_t reserved;
+} ecnt_ldl_factor;
 
 /* How M is evaluated (CHEB only).  Both compute the same polynomial in B. */
 typedef enum {
@@ -102,6 +138,8 @@ typedef struct {
     int32_t eval;        /* ecnt_eval (CHEB only) */
     double s, lo, hi;    /* shift of L and the interval mapped to [-1, 1] (CHEB only) */
     const double *coef;  /* host, degree+1 entries, copied at call time (CHEB only) */
+    const ecnt_ldl_factor *ldl; /* host, one factor per shift in shift order, read at call
+                                   time (LDL only; NULL otherwise) */
 } ecnt_prec;
 
 /* Quadrature rule applied to the Lanczos coefficients. */
@@ -324,6 +362,43 @@ ECNT_API ecnt_status ecnt_count_batched(const ecnt_csr *A, const ecnt_prec *T,
                                         const ecnt_opts *opts, void *ws, size_t ws_bytes,
                                         void *stream, double *negcounts, double *counts,
                                         double *variances, ecnt_info *info);
+
+/* ---- ILDL(t) factorization on the host (Section 6) ----
+ *
+ * Incomplete L D L^T of A - tau I with 1 x 1 / 2 x 2 pivots and a drop
+ * tolerance, from which ECNT_PREC_LDL builds T = P^T L^{-T} |D|^{-1} L^{-1} P
+ * (HPD whatever is dropped).  The paper takes the factorization from an
+ * external package; this one is right-looking in the matrix's own order with
+ * Bunch-Kaufman partial pivoting (alpha = (1 + sqrt 17) / 8), and after each
+ * pivot drops the multipliers l_i with |l_i| < droptol * sum_i |l_i| of their
+ * column before the Schur update.  droptol = 0 gives the exact factorization
+ * (Sylvester: the inertia of D is that of A - tau I).
+ *   A          host CSR (row_ptr n+1, col_idx, val), symmetric, both triangles
+ *   out        receives an opaque host object; release it with ecnt_ildl_free
+ * Errors: EINVAL (bad arguments), ENOTHPD (a zero 1 x 1 or singular 2 x 2
+ * pivot), EUNSUPPORTED (the factor exceeds int32 indexing).  Runs on the
+ * host only: no device work. */
+typedef struct ecnt_ildl_s *ecnt_ildl;
+
+ECNT_API ecnt_status ecnt_ildl_factor(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                      const double *val, double tau, double droptol,
+                                      ecnt_ildl *out);
+
+/* nnz of L (strict lower part), its bandwidth, the number of 2 x 2 blocks
+ * and of negative eigenvalues of D.  Null outputs are skipped. */
+ECNT_API ecnt_status ecnt_ildl_sizes(const ecnt_ildl f, int64_t *nnz, int32_t *bandwidth,
+                                     int32_t *n2x2, int32_t *nneg);
+
+/* Copies the factor into caller-allocated host arrays laid out as
+ * ecnt_ldl_factor describes (perm n, l_row_ptr n+1, l_col_idx / l_val nnz,
+ * lt_row_ptr n+1, lt_col_idx / lt_val nnz, d_diag n, d_off n).  Null outputs
+ * are skipped. */
+ECNT_API ecnt_status ecnt_ildl_export(const ecnt_ildl f, int32_t *perm, int32_t *l_row_ptr,
+                                      int32_t *l_col_idx, double *l_val, int32_t *lt_row_ptr,
+                                      int32_t *lt_col_idx, double *lt_val, double *d_diag,
+                                      double *d_off);
+
+ECNT_API void ecnt_ildl_free(ecnt_ildl f);
 
 /* Per-kernel-family timing, for measurement.  While enabled, every launch
  * made by ecnt_count / ecnt_negcounts is bracketed by two hipEvents recorded

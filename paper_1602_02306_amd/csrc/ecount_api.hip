@@ -18,10 +18,11 @@ namespace ecnt {
 
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
-              F_VGRAD, F_CHEB2, F_COUNT };
+              F_VGRAD, F_CHEB2, F_LDL, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
-                                           "bw_update", "bw_vgrad", "op_cheb_quad"};
+                                           "bw_update", "bw_vgrad", "op_cheb_quad",
+                                           "op_ldl_solve"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -95,6 +96,12 @@ static ecnt_status fail(ecnt_status st, const char *fmt, ...)
     return st;
 }
 
+int32_t set_error(int32_t st, const char *msg)
+{
+    g_err = msg;
+    return st;
+}
+
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 static void col_geometry(Plan &p);
@@ -113,7 +120,7 @@ size_t plan_layout(Plan &p, char *base)
     const size_t NC = (size_t)p.nseg * p.wave_cols;   // virtual columns of one wave
     const size_t NCt = (size_t)p.nseg * p.Ct;         // of the whole run
     p.basis = take(blk * (p.k + 1));
-    const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : 0;
+    const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : (p.prec_kind == ECNT_PREC_LDL ? 2 : 0);
     for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;
     p.part = (double *)take(sizeof(double) * (size_t)p.nchunk * kPartRows * p.wave_cols);
     p.sig = (double *)take(sizeof(double) * (p.k + 1) * NC);
@@ -126,6 +133,7 @@ size_t plan_layout(Plan &p, char *base)
     p.s_out = (double *)take(sizeof(double) * NCt);
     p.minabs = (double *)take(sizeof(double) * NCt);
     p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
+    p.e_blk = (double *)take(p.prec_kind == ECNT_PREC_LDL ? sizeof(double) * 2 * p.S * p.n : 0);
     p.result = (double *)take(sizeof(double) * kResStride * p.nseg);
     p.active = (int32_t *)take(sizeof(int32_t) * NC);
     p.kused = (int32_t *)take(sizeof(int32_t) * NCt);
@@ -371,6 +379,36 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         p.hi = T->hi;
         break;
     }
+    case ECNT_PREC_LDL: {
+        if (!T->ldl) return fail(ECNT_EINVAL, "prec.ldl is null (one factor per shift)");
+        for (int s = 0; s < S; ++s) {
+            const ecnt_ldl_factor &f = T->ldl[s];
+            if (!f.perm || !f.l_row_ptr || !f.lt_row_ptr || !f.d_diag || !f.d_off)
+                return fail(ECNT_EINVAL, "factor %d: null array", s);
+            if (f.nnz < 0 || f.nnz >= INT32_MAX) return fail(ECNT_EINVAL, "factor %d: bad nnz", s);
+            if (f.nnz > 0 && (!f.l_col_idx || !f.l_val || !f.lt_col_idx || !f.lt_val))
+                return fail(ECNT_EINVAL, "factor %d: null entry arrays", s);
+            if (f.reserved != 0) return fail(ECNT_EINVAL, "factor %d: reserved must be 0", s);
+            if (f.bandwidth < 0 || f.bandwidth >= n)
+                return fail(ECNT_EINVAL, "factor %d: bandwidth out of range", s);
+            if (f.bandwidth > ldl_ring_rows())
+                return fail(ECNT_EUNSUPPORTED, "factor %d: bandwidth %d above %d", s, f.bandwidth,
+                            ldl_ring_rows());
+            LdlDev &d = p.ldl[s];
+            d.perm = f.perm;
+            d.lrp = f.l_row_ptr;
+            d.lci = f.l_col_idx;
+            d.lval = f.l_val;
+            d.ltrp = f.lt_row_ptr;
+            d.ltci = f.lt_col_idx;
+            d.ltval = f.lt_val;
+            d.dd = f.d_diag;
+            d.doff = f.d_off;
+            d.nnz = f.nnz;
+            d.bw = f.bandwidth;
+        }
+        break;
+    }
     default:
         return fail(ECNT_EINVAL, "unknown preconditioner kind %d", T->kind);
     }
@@ -546,6 +584,10 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
         Timed t(F_SETUP, csr_b + 8.0 * p.S * p.n, st);
         launch_jacobi_diag(p, A->row_ptr, A->col_idx, A->val, st);
     }
+    if (p.prec_kind == ECNT_PREC_LDL) {
+        Timed t(F_SETUP, 32.0 * p.S * p.n, st);
+        launch_ldl_eblocks(p, st);
+    }
     for (int c_off = 0; c_off < p.Ct; c_off += p.wave_cols) {
         Plan w = p;
         w.c_off = c_off;
@@ -642,6 +684,10 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     const size_t blk = (size_t)p.n * p.C * bv;
     char *basis = (char *)p.basis;
     const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
+    // factor bytes one application streams: perm, row pointers, entries, D and |D|^{-1/2}
+    double ldl_b = 0.0;
+    if (p.prec_kind == ECNT_PREC_LDL)
+        for (int s = 0; s < p.S; ++s) ldl_b += 4.0 * (2 * p.n + 1) + 12.0 * p.ldl[s].nnz + 24.0 * p.n;
     for (int i = 1; i <= p.k; ++i) {
         void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
@@ -655,6 +701,21 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
                 launch_csr_op(p, A->row_ptr, A->col_idx, A->val, t, nullptr, nullptr, p.tmp[0], st);
             }
             apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
+        } else if (p.prec_kind == ECNT_PREC_LDL) {
+            // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
+            // y = M u = |D|^{-1/2} (L^{-1} P u)
+            {
+                Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+                launch_ldl(p, 0, x, xs, p.tmp[0], st);
+                launch_ldl(p, 2, p.tmp[0], nullptr, p.tmp[1], st);
+            }
+            {
+                Timed tm(F_CSR, 2 * blk_b + csr_b, st);
+                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[1], nullptr, nullptr, p.tmp[0], st);
+            }
+            Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+            launch_ldl(p, 1, p.tmp[0], nullptr, p.tmp[1], st);
+            launch_ldl(p, 0, p.tmp[1], nullptr, y, st);
         } else {
             Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
             launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,
@@ -819,7 +880,7 @@ static ecnt_status arnoldi_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, cons
 {
     ecnt_status rc = make_plan(p, n, m, 2, T, o);
     if (rc) return rc;
-    if (T->kind == ECNT_PREC_JACOBI)
+    if (T->kind == ECNT_PREC_JACOBI || T->kind == ECNT_PREC_LDL)
         return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator takes T = I or a Laplacian polynomial");
     if (o->rule != ECNT_RULE_GAUSS) return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator has no GA rule");
     if (o->smooth_w != 0.0) return fail(ECNT_EUNSUPPORTED, "the Arnoldi estimator uses the step h");
@@ -895,6 +956,8 @@ static ecnt_status batch_plan(Plan &p, SegHost &sh, const ecnt_batch_item *items
         for (int t = 0; t < nshift; ++t) taus[(size_t)b * nshift + t] = items[b].taus[t];
     }
     if (!T) return fail(ECNT_EINVAL, "null preconditioner");
+    if (T->kind == ECNT_PREC_LDL)
+        return fail(ECNT_EUNSUPPORTED, "batches do not take the LDL preconditioner");
     if (T->kind == ECNT_PREC_CHEB_LAPLACIAN && T->ndim != 3)
         return fail(ECNT_EINVAL, "batches with the Laplacian preconditioner need prec.ndim = 3");
     ecnt_prec Tb = *T;

@@ -29,6 +29,17 @@ constexpr int kBasisChunk = 32;    // basis vectors per reorthogonalization laun
 constexpr int kMaxShifts = 64;
 constexpr int kMaxK = 512;
 
+// One shift's factor of the LDL preconditioner (device pointers).
+struct LdlDev {
+    const int32_t *perm = nullptr, *lrp = nullptr, *lci = nullptr;
+    const double *lval = nullptr;
+    const int32_t *ltrp = nullptr, *ltci = nullptr;
+    const double *ltval = nullptr;
+    const double *dd = nullptr, *doff = nullptr;
+    int64_t nnz = 0;
+    int bw = 0;
+};
+
 struct Plan {
     int64_t n = 0;
     int m = 0, S = 0, k = 0;
@@ -87,6 +98,9 @@ struct Plan {
     int32_t *active = nullptr; // C
     int32_t *kused = nullptr;  // Ct
     int32_t *flags = nullptr;  // 4 status flags
+    // ---- LDL preconditioner: one factor per shift, |D|^{-1/2} blocks ----
+    LdlDev ldl[kMaxShifts];
+    double *e_blk = nullptr;   // S * 2n: e_diag then e_off of every shift
     // ---- Arnoldi estimator for an unfactored T (one problem) ----
     int arnoldi = 0;
     double *H = nullptr;       // k x (k+1) x NC: H[(l*(k+1) + i)*NC + vc] = h_{i+1,l+1}
@@ -157,5 +171,15 @@ void launch_bupdate(const Plan &p, int i, bool first, hipStream_t st);
 void launch_bnorm_fin(const Plan &p, int i, hipStream_t st);
 void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st);
 void launch_grad_out(const Plan &p, double *dV, hipStream_t st);
+
+// LDL preconditioner: |D|^{-1/2} blocks of every shift; on the columns of the
+// current wave, what = 0: Y = |D|^{-1/2}(xs.*X), 1: Y = L^{-1} P (xs.*X),
+// 2: Y = P^T L^{-T} X (X and Y distinct)
+void launch_ldl_eblocks(const Plan &p, hipStream_t st);
+void launch_ldl(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st);
+int ldl_ring_rows();
+
+// the message ecnt_last_error() returns; gives back st
+int32_t set_error(int32_t st, const char *msg);
 
 }  // namespace ecnt

@@ -22,7 +22,7 @@ ECNT_OK, ECNT_EINVAL, ECNT_ENOTHPD, ECNT_EWORKSPACE, ECNT_EDEVICE, ECNT_EUNSUPPO
 STATUS_NAMES = {0: "ECNT_OK", -1: "ECNT_EINVAL", -2: "ECNT_ENOTHPD", -3: "ECNT_EWORKSPACE",
                 -4: "ECNT_EDEVICE", -5: "ECNT_EUNSUPPORTED"}
 DTYPES = {"f64": 0, "f32": 1}
-PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2}
+PREC_KINDS = {"none": 0, "jacobi": 1, "cheb": 2, "ldl": 3}
 RULES = {"gauss": 0, "ga": 1}
 
 
@@ -41,7 +41,16 @@ class CsrT(ctypes.Structure):
 class PrecT(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("ndim", ctypes.c_int32), ("dims", ctypes.c_int32 * 3),
                 ("degree", ctypes.c_int32), ("eval", ctypes.c_int32), ("s", ctypes.c_double),
-                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("coef", ctypes.c_void_p)]
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("coef", ctypes.c_void_p),
+                ("ldl", ctypes.c_void_p)]
+
+
+class LdlFactorT(ctypes.Structure):
+    _fields_ = [("perm", ctypes.c_void_p), ("l_row_ptr", ctypes.c_void_p),
+                ("l_col_idx", ctypes.c_void_p), ("l_val", ctypes.c_void_p),
+                ("lt_row_ptr", ctypes.c_void_p), ("lt_col_idx", ctypes.c_void_p),
+                ("lt_val", ctypes.c_void_p), ("d_diag", ctypes.c_void_p), ("d_off", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64), ("bandwidth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class OptsT(ctypes.Structure):
@@ -129,6 +138,17 @@ def load():
         lib.ecnt_count_arnoldi.restype = ctypes.c_int32
         lib.ecnt_count_arnoldi.argtypes = lib.ecnt_count.argtypes
         lib.ecnt_profile_enable.restype = ctypes.c_int32
+        lib.ecnt_ildl_factor.restype = ctypes.c_int32
+        lib.ecnt_ildl_factor.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        lib.ecnt_ildl_sizes.restype = ctypes.c_int32
+        lib.ecnt_ildl_sizes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int32)]
+        lib.ecnt_ildl_export.restype = ctypes.c_int32
+        lib.ecnt_ildl_export.argtypes = [ctypes.c_void_p] + [P] * 9
+        lib.ecnt_ildl_free.restype = None
+        lib.ecnt_ildl_free.argtypes = [ctypes.c_void_p]
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
         lib.ecnt_profile_read.restype = ctypes.c_int32
         lib.ecnt_profile_read.argtypes = [ctypes.POINTER(KernelStatT), ctypes.c_int32]
@@ -175,12 +195,104 @@ def upload_csr(A, val_dtype: str = "f64", device: str = "cuda") -> DeviceCSR:
                      torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device, tdt))
 
 
+# ---------------------------------------------------------------------------
+# ILDL(t) preconditioner (factored on the host by the library, applied on the GPU)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class HostLDL:
+    """P (A - tau I) P^T ~ L D L^T as ecnt_ildl_export lays it out (host arrays)."""
+    n: int
+    perm: np.ndarray
+    l_rp: np.ndarray
+    l_ci: np.ndarray
+    l_val: np.ndarray
+    lt_rp: np.ndarray
+    lt_ci: np.ndarray
+    lt_val: np.ndarray
+    d_diag: np.ndarray
+    d_off: np.ndarray
+    bandwidth: int
+    n2x2: int
+    nneg: int
+
+
+def ildl_factor(A, tau: float, droptol: float) -> HostLDL:
+    """ILDL(droptol) of A - tau I (ecnt_ildl_factor; host CSR `A`, host work)."""
+    lib = load()
+    n = int(A.n)
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _check(lib.ecnt_ildl_factor(n, rp.ctypes.data, ci.ctypes.data, va.ctypes.data, float(tau),
+                                float(droptol), ctypes.byref(h)))
+    try:
+        nnz, bw, n2, nneg = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.ecnt_ildl_sizes(h, ctypes.byref(nnz), ctypes.byref(bw), ctypes.byref(n2),
+                                   ctypes.byref(nneg)))
+        z = int(nnz.value)
+        a = dict(perm=np.zeros(n, np.int32), l_rp=np.zeros(n + 1, np.int32),
+                 l_ci=np.zeros(z, np.int32), l_val=np.zeros(z), lt_rp=np.zeros(n + 1, np.int32),
+                 lt_ci=np.zeros(z, np.int32), lt_val=np.zeros(z), d_diag=np.zeros(n),
+                 d_off=np.zeros(n))
+        _check(lib.ecnt_ildl_export(h, *[a[k].ctypes.data for k in (
+            "perm", "l_rp", "l_ci", "l_val", "lt_rp", "lt_ci", "lt_val", "d_diag", "d_off")]))
+    finally:
+        lib.ecnt_ildl_free(h)
+    return HostLDL(n, bandwidth=int(bw.value), n2x2=int(n2.value), nneg=int(nneg.value), **a)
+
+
+@dataclass
+class DeviceLDL:
+    n: int
+    nnz: int
+    bandwidth: int
+    t: dict   # torch device tensors
+
+    def struct(self) -> LdlFactorT:
+        t = self.t
+        return LdlFactorT(*[t[k].data_ptr() for k in ("perm", "l_rp", "l_ci", "l_val", "lt_rp",
+                                                      "lt_ci", "lt_val", "d_diag", "d_off")],
+                          self.nnz, self.bandwidth, 0)
+
+
+def upload_ldl(F: HostLDL, device: str = "cuda") -> DeviceLDL:
+    import torch
+    t = {}
+    for k in ("perm", "l_rp", "l_ci", "l_val", "lt_rp", "lt_ci", "lt_val", "d_diag", "d_off"):
+        a = getattr(F, k)
+        if a.size == 0:   # keep a valid pointer for empty entry arrays
+            a = np.zeros(1, dtype=a.dtype)
+        t[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return DeviceLDL(F.n, int(F.l_val.size), F.bandwidth, t)
+
+
+@dataclass
+class LDLPrecond:
+    """ECNT_PREC_LDL: one device factor per shift, in shift order."""
+    factors: list
+    kind: str = "ldl"
+
+
+def ildl_precond(A, taus, droptol: float, device: str = "cuda") -> LDLPrecond:
+    """Factor A - tau I for every shift on the host and upload the factors."""
+    return LDLPrecond([upload_ldl(ildl_factor(A, float(t), droptol), device) for t in taus])
+
+
 EVALS = {"auto": 0, "clenshaw": 1}
 
 
 def prec_struct(prec, eval: str = "auto"):
-    """ecnt_prec from a workloads.PrecSpec; returns (struct, keep-alive coef array)."""
+    """ecnt_prec from a workloads.PrecSpec or an LDLPrecond; returns (struct,
+    keep-alive array)."""
     kind = PREC_KINDS[prec.kind]
+    if kind == 3:
+        arr = (LdlFactorT * len(prec.factors))(*[f.struct() for f in prec.factors])
+        st = PrecT(3, 0, (ctypes.c_int32 * 3)(0, 0, 0), 0, EVALS[eval], 0.0, 0.0, 0.0, None,
+                   ctypes.addressof(arr))
+        return st, arr
     dims = (ctypes.c_int32 * 3)(0, 0, 0)
     coef = np.zeros(1)
     ndim = 0
@@ -192,6 +304,13 @@ def prec_struct(prec, eval: str = "auto"):
     st = PrecT(kind, ndim, dims, max(len(coef) - 1, 0) if kind == 2 else 0, EVALS[eval],
                float(prec.s), float(prec.lo), float(prec.hi), coef.ctypes.data if kind == 2 else None)
     return st, coef
+
+
+def _check_factors(prec, nshift: int):
+    # the library reads one factor per shift from the host array
+    if prec.kind == "ldl" and len(prec.factors) != nshift:
+        raise ValueError("the LDL preconditioner needs one factor per shift (%d, got %d)"
+                         % (nshift, len(prec.factors)))
 
 
 def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
@@ -206,6 +325,7 @@ def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float =
 def workspace_bytes(n: int, m: int, nshift: int, prec, k: int, vec: str = "f64",
                     rule: str = "gauss", smooth_w: float = 0.0, max_cols: int = 0,
                     tune: dict | None = None) -> int:
+    _check_factors(prec, nshift)
     ps, _coef = prec_struct(prec)
     o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     return int(load().ecnt_workspace_bytes(int(n), int(m), int(nshift), ctypes.byref(ps),
@@ -270,6 +390,7 @@ def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = 
     n x m (float64 for vec='f64', float32 for vec='f32')."""
     lib = load()
     n, m = probes.shape
+    _check_factors(prec, 2)
     ps, _coef = prec_struct(prec, eval)
     o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     need = lib.ecnt_workspace_bytes(n, m, 2, ctypes.byref(ps), ctypes.byref(o))
@@ -343,6 +464,7 @@ def negcounts(A: DeviceCSR, prec, taus, probes, k: int, vec: str = "f64", rule: 
     n, m = probes.shape
     taus = np.ascontiguousarray(taus, dtype=np.float64)
     S = len(taus)
+    _check_factors(prec, S)
     ps, _coef = prec_struct(prec, eval)
     o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
     need = lib.ecnt_workspace_bytes(n, m, S, ctypes.byref(ps), ctypes.byref(o))

@@ -301,6 +301,9 @@ class Workload:
     vec: str = "f64"        # storage type of A values and Lanczos vectors
     smooth_w: float = 0.0   # width of the erf-smoothed step (0: the paper's step)
     method: str = "lanczos" # 'lanczos' (Algorithm 2 on M(A - tau I)M) | 'arnoldi' (Algorithm 4 on T(A - tau I))
+    scale: float = 1.0      # A = scale * L + diag(potential)
+    droptol: float = 0.0    # ILDL drop tolerance (prec 'ildl')
+    taus: tuple = ()        # non-empty: the workload is n_(A - tau I) at these shifts
 
     @property
     def n(self) -> int:
@@ -324,6 +327,13 @@ WORKLOADS = {
     # small cases that the oracle finishes in seconds
     "c2_small": Workload("c2_small", (16, 16, 16), "wells", 1, -8.0, -2.0, "cheb", 24, 12),
     "c2_ragged": Workload("c2_ragged", (13, 11, 9), "wells", 7, -60.0, -30.0, "cheb", 37, 9),
+    # Table 1 "Laplace": (1/h^2) x 5-point Laplacian, h = 2^-7, n_(A - 3000 I) = 226, m = 50,
+    # ILDL(t) preconditioner; k = 6 Lanczos steps
+    "t1": Workload("t1", (127, 127), "zero", 0, 0.0, 3000.0, "ildl", 50, 6, scale=16384.0,
+                   droptol=1e-6, taus=(3000.0,)),
+    # its small counterpart (h = 2^-5) for parity tests
+    "t1_small": Workload("t1_small", (31, 31), "zero", 0, 0.0, 300.0, "ildl", 37, 8, scale=1024.0,
+                         droptol=1e-3, taus=(300.0,)),
 }
 
 
@@ -347,7 +357,9 @@ def make_potential(wl: Workload) -> np.ndarray:
     raise ValueError(wl.potential)
 
 
-def make_prec(kind: str, dims) -> PrecSpec:
+def make_prec(kind: str, dims, droptol: float = 0.0) -> PrecSpec:
+    if kind == "ildl":
+        return PrecSpec("ildl", tuple(dims), droptol=float(droptol))
     if kind == "cheb":
         return cheb_invsqrt_prec(dims)
     if kind == "cheb_inv":
@@ -359,8 +371,14 @@ def make_prec(kind: str, dims) -> PrecSpec:
 
 def make_problem(wl: Workload) -> Problem:
     V = make_potential(wl)
-    A = laplacian_csr(wl.dims, V)
-    return Problem(A, V, make_prec(wl.prec, wl.dims), wl.xi, wl.eta, tuple(wl.dims))
+    if wl.scale == 1.0:
+        A = laplacian_csr(wl.dims, V)
+    else:
+        A = laplacian_csr(wl.dims)
+        A.val = A.val * wl.scale
+        if np.any(V != 0.0):
+            raise ValueError("a scaled Laplacian takes no potential")
+    return Problem(A, V, make_prec(wl.prec, wl.dims, wl.droptol), wl.xi, wl.eta, tuple(wl.dims))
 
 
 def make_probes(wl: Workload, dtype=np.float64) -> np.ndarray:

@@ -1,0 +1,152 @@
+"""GPU parity of the factored ILDL preconditioner (Section 6) against the
+oracle: the library factors A - tau I on the host (its own code, checked
+bitwise against the oracle's factorization on the CPU), applies
+M = |D|^{-1/2} L^{-1} P and M^* on the GPU, and the counts must agree with the
+oracle's (which factors and applies with its own code) to the FP64 bar:
+estimate within 1e-10 * max(|ref|, 1), every s_j within 1e-10 |v_j|^2."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02306_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ec():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_02306_amd import ecount
+    ecount.load()
+    return ecount
+
+
+def run_pair(ec, A, taus, droptol, V, k, vec="f64", max_cols=0):
+    print("LDL case n=%d m=%d k=%d taus=%s t=%g vec=%s" % (A.n, V.shape[1], k, list(taus), droptol,
+                                                         vec), flush=True)
+    prec = ec.ildl_precond(A, taus, droptol)
+    Vd = torch.from_numpy(V).to("cuda", torch.float32 if vec == "f32" else torch.float64)
+    r = ec.negcounts(ec.upload_csr(A), prec, taus, Vd, k, vec=vec, max_cols=max_cols)
+    refs = [oracle.negcount(A, W.PrecSpec("ildl", (), droptol=droptol), t, V, k) for t in taus]
+    return r, refs
+
+
+def assert_negcount_parity(r, refs, V, tol=TOL):
+    m = V.shape[1]
+    nu = np.sum(V.astype(np.float64) ** 2, axis=0)
+    s = r.per_probe.cpu().numpy()
+    ku = r.k_used.cpu().numpy()
+    for i, (mean, s_ref, res, _) in enumerate(refs):
+        ds = np.abs(s[i * m:(i + 1) * m] - s_ref)
+        print("shift %d: gpu %.15f oracle %.15f max |ds|/nu %.2e" % (
+            i, r.negcounts[i], mean, np.max(ds / nu)), flush=True)
+        assert abs(r.negcounts[i] - mean) <= tol * max(1.0, abs(mean))
+        assert np.all(ds <= tol * nu)
+        assert np.array_equal(ku[i * m:(i + 1) * m], res.k_used)
+
+
+@pytest.mark.parametrize("droptol", [0.0, 1e-3, 1e-6])
+def test_ldl_negcount_parity_small(ec, droptol):
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    r, refs = run_pair(ec, P.A, wl.taus, droptol, V, wl.k)
+    assert_negcount_parity(r, refs, V)
+
+
+def test_ldl_two_shifts_interval_count(ec):
+    """count(xi, eta) with one factor per shift; 2 x 2 pivots in both."""
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    xi, eta = 150.0, 420.0
+    prec = ec.ildl_precond(P.A, [xi, eta], 1e-4)
+    Vd = torch.from_numpy(V).to("cuda")
+    r = ec.count(ec.upload_csr(P.A), prec, xi, eta, Vd, 10)
+    ref = oracle.count(P.A, W.PrecSpec("ildl", (), droptol=1e-4), xi, eta, V, 10)
+    print("gpu %.15f oracle %.15f" % (r.estimate, ref.estimate), flush=True)
+    assert abs(r.estimate - ref.estimate) <= TOL * max(1.0, abs(ref.estimate))
+    s = r.per_probe.cpu().numpy()
+    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    assert np.all(np.abs(s - np.concatenate([ref.s_xi, ref.s_eta])) <= TOL * nu)
+
+
+def test_ldl_random_indefinite_with_2x2_pivots(ec):
+    """A random sparse symmetric matrix (many 2 x 2 pivots and interchanges)."""
+    rng = np.random.default_rng(11)
+    n = 300
+    K = np.zeros((n, n))
+    for i in range(n):
+        for j in range(max(0, i - 12), i):
+            if rng.random() < 0.3:
+                K[i, j] = K[j, i] = rng.standard_normal()
+        K[i, i] = 0.2 * rng.standard_normal()
+    rp, ci, va = [0], [], []
+    for i in range(n):
+        nz = np.nonzero(K[i])[0]
+        ci += list(nz)
+        va += list(K[i, nz])
+        rp.append(len(ci))
+    A = W.CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va))
+    H = ec.ildl_factor(A, 0.05, 0.0)
+    assert H.n2x2 > 10
+    V = W.rademacher(n, 45, 3)
+    r, refs = run_pair(ec, A, (0.05,), 0.0, V, 12)
+    assert_negcount_parity(r, refs, V)
+    # exact factor: C = sign(D), so the estimate's mean is trace P_- and equals
+    # n_(A - tau I) in expectation; per probe s_j = v^T P_- v (checked by parity)
+    assert H.nneg == int(np.sum(np.linalg.eigvalsh(K - 0.05 * np.eye(n)) < 0))
+
+
+def test_ldl_column_waves_and_ragged_groups(ec):
+    """m = 100 probes (two column groups, the second partial) in waves of 70."""
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 100, 5)
+    r, refs = run_pair(ec, P.A, (250.0, 300.0), 1e-3, V, 7, max_cols=70)
+    assert_negcount_parity(r, refs, V)
+
+
+def test_ldl_fp32_storage_within_bound(ec):
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    r, refs = run_pair(ec, P.A, wl.taus, 1e-6, V, wl.k, vec="f32")
+    mean = refs[0][0]
+    print("fp32 %.10f oracle %.10f" % (r.negcounts[0], mean), flush=True)
+    assert abs(r.negcounts[0] - mean) <= 1e-4 * max(1.0, abs(mean))
+
+
+def test_ldl_table1_full_size(ec):
+    """Table 1, Laplace (127 x 127, tau = 3000, m = 50) at the bench's
+    configuration: parity with the oracle, and the estimate within the 5% of
+    the exact 226 that the paper reports."""
+    wl = W.WORKLOADS["t1"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    r, refs = run_pair(ec, P.A, wl.taus, wl.droptol, V, wl.k)
+    assert_negcount_parity(r, refs, V)
+    g = json.load(open(os.path.join(GOLDEN, "paper_table1.json")))["laplace"]
+    assert abs(r.negcounts[0] - g["exact_negcount"]) <= 0.05 * g["exact_negcount"]
+
+
+def test_ldl_unsupported_forms(ec):
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = torch.from_numpy(W.make_probes(wl)).to("cuda")
+    Ad = ec.upload_csr(P.A)
+    prec = ec.ildl_precond(P.A, [wl.xi, wl.eta], 1e-3)
+    with pytest.raises(ec.EcntError) as e:
+        ec.count_arnoldi(Ad, prec, wl.xi, wl.eta, V, 5)
+    assert e.value.status == ec.ECNT_EUNSUPPORTED
+    with pytest.raises(ec.EcntError) as e:
+        ec.smooth_forward(Ad, prec, wl.xi, wl.eta, V, 5, 0.05)
+    assert e.value.status == ec.ECNT_EUNSUPPORTED
