@@ -102,20 +102,18 @@ typedef enum {
  * device memory owned by the caller and must stay valid for the call.
  *   perm        n: row i of P (A - tau I) P^T is row perm[i] of A - tau I
  *   l_row_ptr   n+1, l_col_idx / l_val nnz: the strictly lower part of L
- *               (unit diagonal implied) by rows, columns ascending in a row
- *   lt_row_ptr  n+1, lt_col_idx / lt_val nnz: the same entries by columns
- *               (rows of L^T), rows ascending
+ *               (unit diagonal implied) by rows; entries with i - j above
+ *               `bandwidth` are ignored
  *   d_diag      n: D_ii;  d_off n: D_{i+1,i} at the first row i of a 2 x 2
  *               block (non-zero there), 0 elsewhere
- *   nnz, bandwidth  entry count and max (i - j) over the entries */
+ *   nnz, bandwidth  entry count and max (i - j) over the entries
+ * Each call first writes L and L^T into its workspace as bands of 256 values
+ * per row (2 * 256 * 8 bytes per row and shift). */
 typedef struct {
     const int32_t *perm;
     const int32_t *l_row_ptr;
     const int32_t *l_col_idx;
     const double *l_val;
-    const int32_t *lt_row_ptr;
-    const int32_t *lt_col_idx;
-    const double *lt_val;
     const double *d_diag;
     const double *d_off;
     int64_t nnz;
@@ -391,11 +389,10 @@ ECNT_API ecnt_status ecnt_ildl_sizes(const ecnt_ildl f, int64_t *nnz, int32_t *b
 
 /* Copies the factor into caller-allocated host arrays laid out as
  * ecnt_ldl_factor describes (perm n, l_row_ptr n+1, l_col_idx / l_val nnz,
- * lt_row_ptr n+1, lt_col_idx / lt_val nnz, d_diag n, d_off n).  Null outputs
- * are skipped. */
+ * columns ascending within a row, d_diag n, d_off n).  Null outputs are
+ * skipped. */
 ECNT_API ecnt_status ecnt_ildl_export(const ecnt_ildl f, int32_t *perm, int32_t *l_row_ptr,
-                                      int32_t *l_col_idx, double *l_val, int32_t *lt_row_ptr,
-                                      int32_t *lt_col_idx, double *lt_val, double *d_diag,
+                                      int32_t *l_col_idx, double *l_val, double *d_diag,
                                       double *d_off);
 
 ECNT_API void ecnt_ildl_free(ecnt_ildl f);

@@ -134,6 +134,8 @@ size_t plan_layout(Plan &p, char *base)
     p.minabs = (double *)take(sizeof(double) * NCt);
     p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
     p.e_blk = (double *)take(p.prec_kind == ECNT_PREC_LDL ? sizeof(double) * 2 * p.S * p.n : 0);
+    p.band = (double *)take(p.prec_kind == ECNT_PREC_LDL
+                                ? sizeof(double) * 2 * p.S * p.n * (size_t)ldl_ring_rows() : 0);
     p.result = (double *)take(sizeof(double) * kResStride * p.nseg);
     p.active = (int32_t *)take(sizeof(int32_t) * NC);
     p.kused = (int32_t *)take(sizeof(int32_t) * NCt);
@@ -383,10 +385,10 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         if (!T->ldl) return fail(ECNT_EINVAL, "prec.ldl is null (one factor per shift)");
         for (int s = 0; s < S; ++s) {
             const ecnt_ldl_factor &f = T->ldl[s];
-            if (!f.perm || !f.l_row_ptr || !f.lt_row_ptr || !f.d_diag || !f.d_off)
+            if (!f.perm || !f.l_row_ptr || !f.d_diag || !f.d_off)
                 return fail(ECNT_EINVAL, "factor %d: null array", s);
             if (f.nnz < 0 || f.nnz >= INT32_MAX) return fail(ECNT_EINVAL, "factor %d: bad nnz", s);
-            if (f.nnz > 0 && (!f.l_col_idx || !f.l_val || !f.lt_col_idx || !f.lt_val))
+            if (f.nnz > 0 && (!f.l_col_idx || !f.l_val))
                 return fail(ECNT_EINVAL, "factor %d: null entry arrays", s);
             if (f.reserved != 0) return fail(ECNT_EINVAL, "factor %d: reserved must be 0", s);
             if (f.bandwidth < 0 || f.bandwidth >= n)
@@ -399,9 +401,6 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
             d.lrp = f.l_row_ptr;
             d.lci = f.l_col_idx;
             d.lval = f.l_val;
-            d.ltrp = f.lt_row_ptr;
-            d.ltci = f.lt_col_idx;
-            d.ltval = f.lt_val;
             d.dd = f.d_diag;
             d.doff = f.d_off;
             d.nnz = f.nnz;
@@ -585,7 +584,7 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
         launch_jacobi_diag(p, A->row_ptr, A->col_idx, A->val, st);
     }
     if (p.prec_kind == ECNT_PREC_LDL) {
-        Timed t(F_SETUP, 32.0 * p.S * p.n, st);
+        Timed t(F_SETUP, (32.0 + 2 * 8.0 * ldl_ring_rows()) * p.S * p.n, st);
         launch_ldl_eblocks(p, st);
     }
     for (int c_off = 0; c_off < p.Ct; c_off += p.wave_cols) {
@@ -684,10 +683,10 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     const size_t blk = (size_t)p.n * p.C * bv;
     char *basis = (char *)p.basis;
     const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
-    // factor bytes one application streams: perm, row pointers, entries, D and |D|^{-1/2}
-    double ldl_b = 0.0;
-    if (p.prec_kind == ECNT_PREC_LDL)
-        for (int s = 0; s < p.S; ++s) ldl_b += 4.0 * (2 * p.n + 1) + 12.0 * p.ldl[s].nnz + 24.0 * p.n;
+    // factor bytes one application streams: the band rows of one triangle,
+    // the permutation, D and |D|^{-1/2}
+    const double ldl_b = p.prec_kind == ECNT_PREC_LDL
+                             ? (8.0 * ldl_ring_rows() + 4.0 + 24.0) * p.S * p.n : 0.0;
     for (int i = 1; i <= p.k; ++i) {
         void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
@@ -703,17 +702,19 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
             apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
         } else if (p.prec_kind == ECNT_PREC_LDL) {
             // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
-            // y = M u = |D|^{-1/2} (L^{-1} P u)
+            // y = M u = |D|^{-1/2} (L^{-1} (P u))
             {
-                Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+                Timed tm(F_LDL, 4 * blk_b + ldl_b, st);
                 launch_ldl(p, 0, x, xs, p.tmp[0], st);
                 launch_ldl(p, 2, p.tmp[0], nullptr, p.tmp[1], st);
+                launch_ldl(p, 4, p.tmp[1], nullptr, p.tmp[0], st);
             }
             {
                 Timed tm(F_CSR, 2 * blk_b + csr_b, st);
-                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[1], nullptr, nullptr, p.tmp[0], st);
+                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[0], nullptr, nullptr, p.tmp[1], st);
             }
-            Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+            Timed tm(F_LDL, 4 * blk_b + ldl_b, st);
+            launch_ldl(p, 3, p.tmp[1], nullptr, p.tmp[0], st);
             launch_ldl(p, 1, p.tmp[0], nullptr, p.tmp[1], st);
             launch_ldl(p, 0, p.tmp[1], nullptr, y, st);
         } else {

@@ -33,8 +33,6 @@ constexpr int kMaxK = 512;
 struct LdlDev {
     const int32_t *perm = nullptr, *lrp = nullptr, *lci = nullptr;
     const double *lval = nullptr;
-    const int32_t *ltrp = nullptr, *ltci = nullptr;
-    const double *ltval = nullptr;
     const double *dd = nullptr, *doff = nullptr;
     int64_t nnz = 0;
     int bw = 0;
@@ -101,6 +99,7 @@ struct Plan {
     // ---- LDL preconditioner: one factor per shift, |D|^{-1/2} blocks ----
     LdlDev ldl[kMaxShifts];
     double *e_blk = nullptr;   // S * 2n: e_diag then e_off of every shift
+    double *band = nullptr;    // S * 2 * n * 256: rows of L and of L^T by distance
     // ---- Arnoldi estimator for an unfactored T (one problem) ----
     int arnoldi = 0;
     double *H = nullptr;       // k x (k+1) x NC: H[(l*(k+1) + i)*NC + vc] = h_{i+1,l+1}
@@ -172,9 +171,10 @@ void launch_bnorm_fin(const Plan &p, int i, hipStream_t st);
 void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st);
 void launch_grad_out(const Plan &p, double *dV, hipStream_t st);
 
-// LDL preconditioner: |D|^{-1/2} blocks of every shift; on the columns of the
-// current wave, what = 0: Y = |D|^{-1/2}(xs.*X), 1: Y = L^{-1} P (xs.*X),
-// 2: Y = P^T L^{-T} X (X and Y distinct)
+// LDL preconditioner: |D|^{-1/2} blocks and band form of every shift's
+// factor; on the columns of the current wave (X and Y distinct):
+// what = 0: Y = |D|^{-1/2}(xs.*X), 1: Y = L^{-1} X, 2: Y = L^{-T} X,
+// 3: Y = P X, 4: Y = P^T X
 void launch_ldl_eblocks(const Plan &p, hipStream_t st);
 void launch_ldl(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st);
 int ldl_ring_rows();

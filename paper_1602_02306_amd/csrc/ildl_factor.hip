@@ -389,8 +389,7 @@ ECNT_API ecnt_status ecnt_ildl_sizes(const ecnt_ildl f, int64_t *nnz, int32_t *b
 }
 
 ECNT_API ecnt_status ecnt_ildl_export(const ecnt_ildl f, int32_t *perm, int32_t *l_row_ptr,
-                                      int32_t *l_col_idx, double *l_val, int32_t *lt_row_ptr,
-                                      int32_t *lt_col_idx, double *lt_val, double *d_diag,
+                                      int32_t *l_col_idx, double *l_val, double *d_diag,
                                       double *d_off)
 {
     if (!f) return ecnt::set_error(ECNT_EINVAL, "ecnt_ildl_export: NULL factor");
@@ -402,20 +401,6 @@ ECNT_API ecnt_status ecnt_ildl_export(const ecnt_ildl f, int32_t *perm, int32_t 
     if (l_val && nnz) std::memcpy(l_val, f->lval.data(), sizeof(double) * nnz);
     if (d_diag) std::memcpy(d_diag, f->dd.data(), sizeof(double) * n);
     if (d_off) std::memcpy(d_off, f->doff.data(), sizeof(double) * n);
-    if (lt_row_ptr || lt_col_idx || lt_val) {
-        // L^T by rows = L by columns (counting sort, rows ascending within a column)
-        std::vector<int32_t> cnt(n + 1, 0);
-        for (size_t e = 0; e < nnz; ++e) ++cnt[f->lci[e] + 1];
-        for (int64_t j = 0; j < n; ++j) cnt[j + 1] += cnt[j];
-        if (lt_row_ptr) std::memcpy(lt_row_ptr, cnt.data(), sizeof(int32_t) * (n + 1));
-        std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
-        for (int64_t i = 0; i < n; ++i)
-            for (int32_t p = f->lrp[i]; p < f->lrp[i + 1]; ++p) {
-                const int32_t q = pos[f->lci[p]]++;
-                if (lt_col_idx) lt_col_idx[q] = (int32_t)i;
-                if (lt_val) lt_val[q] = f->lval[p];
-            }
-    }
     return ECNT_OK;
 }
 

@@ -1,22 +1,25 @@
 // Factored absolute-value preconditioner of Section 6 on a block of columns:
-//   M x   = |D|^{-1/2} L^{-1} P x      (k_ldl_solve<FWD> with the gather, then k_ldl_eapply)
-//   M^* x = P^T L^{-T} |D|^{-1/2} x    (k_ldl_eapply, then k_ldl_solve<BWD> with the scatter)
+//   M x   = |D|^{-1/2} L^{-1} P x      (gather, k_ldl_solve<FWD>, k_ldl_eapply)
+//   M^* x = P^T L^{-T} |D|^{-1/2} x    (k_ldl_eapply, k_ldl_solve<BWD>, scatter)
 // with P (A - tau I) P^T ~ L D L^T the factor of the columns' shift.
 //
 // The substitutions are sequential in the rows; the columns (probes) are the
-// parallel dimension: one wavefront owns 64 columns and walks all n rows,
+// parallel dimension: one wavefront owns 4 or 8 columns and walks all n rows,
 // keeping the last kRing solved rows of its columns in LDS (a ring indexed by
 // row mod kRing), so every x_j a row needs comes from LDS when the factor's
-// bandwidth is at most kRing.  The row's entries (index, value) are the same
-// for every lane: they are staged in LDS two rows ahead and read back as
-// broadcasts.  Four partial sums break the dependence chain of a long row.
+// bandwidth is at most kRing.  The factor is used in band form (each row as
+// 256 values by distance from the diagonal, built once per call), so a row
+// needs no column indices; 16 or 8 lanes share a column and split its row.
+#include <type_traits>
+#include <utility>
+
 #include "device_common.h"
 #include "ecount_internal.h"
 
 namespace ecnt {
 
 namespace {
-constexpr int kRing = 256;   // rows kept per column: 256 x 64 x 8 B = 128 KiB of LDS
+constexpr int kRing = 256;   // rows kept per column (the largest bandwidth served)
 }
 
 // |D|^{-1/2} block by block, for one shift.  A 2 x 2 block [[a, b], [b, c]]
@@ -76,144 +79,168 @@ __global__ __launch_bounds__(256) void k_ldl_eapply(int64_t n, int C, int c_lo, 
     Y[(size_t)r * C + c] = static_cast<T>(y);
 }
 
-// Substitution with the unit triangular factor on columns [c_lo, c_hi):
-//   FWD: y_r = (xs .* X)[perm[r]] - sum_{j<r} l_rj y_j, rows r = 0..n-1, Y[r] = y_r
-//   BWD: w_r = X[r] - sum_{j>r} l_jr w_j (rows of L^T), r = n-1..0, Y[perm[r]] = w_r
-// One wavefront, one column per lane.  Row t of the walk (t = 0..n-1) uses:
-//   - its entries, staged in LDS (value, ring offset) at the end of row t-1,
-//     loaded from HBM at the end of row t-2 (two register sets by row parity);
-//   - its input value, loaded at the end of row t-2;
-//   - its entry range and permutation index, loaded 64 rows ahead (lane l of a
-//     chunk register holds row 64k + l) and read with readlane.
-// Entries past the row's count are staged as (0, offset 0); the ring starts at 0.
-template <typename T, bool FWD>
-__global__ __launch_bounds__(64) void k_ldl_solve(int64_t n, int C, int c_lo, int c_hi,
-                                                  int64_t nnz, const int32_t *__restrict__ perm,
-                                                  const int32_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ lv,
-                                                  const T *__restrict__ X,
-                                                  const double *__restrict__ xs,
-                                                  T *__restrict__ Y)
+// Band form of one factor, built once per call: row i of L as 256 values
+// bf[i][256 - d] = l_{i, i-d}, and row i of L^T as bb[i][256 - d] = l_{i+d, i}
+// (d = 1..256; zeros where L has no entry).
+__global__ void k_ldl_band_zero(int64_t n, double *__restrict__ bf, double *__restrict__ bb)
 {
-    constexpr int kQ = kRing / 64;   // staging chunks of 64 entries
-    __shared__ double ring[kRing * 64];
-    __shared__ double sv[2][kRing];
-    __shared__ int32_t so[2][kRing];
+    const int64_t total = n * kRing;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        bf[g] = 0.0;
+        bb[g] = 0.0;
+    }
+}
+
+__global__ void k_ldl_band_fill(int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                const int32_t *__restrict__ ci, const double *__restrict__ lv,
+                                double *__restrict__ bf, double *__restrict__ bb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t p0 = rp[i], p1 = rp[i + 1];
+    p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
+    p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
+    for (int64_t p = p0; p < p1; ++p) {
+        const int64_t j = ci[p], d = i - j;
+        if (j < 0 || j >= n || d < 1 || d > kRing) continue;   // outside the declared bandwidth
+        bf[(size_t)i * kRing + kRing - d] = lv[p];
+        bb[(size_t)j * kRing + kRing - d] = lv[p];
+    }
+}
+
+// Sum over NS (8 or 16) consecutive lanes (the entry slices of one column),
+// by DPP: swap neighbours, swap pairs, mirror the two quads of each 8 lanes,
+// then (16) mirror the two halves of each 16 lanes.
+template <int NS>
+__device__ __forceinline__ double sum_slices(double x)
+{
+    auto dpp = [](double v, auto ctrl_tag) -> double {
+        constexpr int ctrl = decltype(ctrl_tag)::value;
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    };
+    x += dpp(x, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
+    x += dpp(x, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
+    x += dpp(x, std::integral_constant<int, 0x141>{});  // row_half_mirror
+    if constexpr (NS == 16) x += dpp(x, std::integral_constant<int, 0x140>{});   // row_mirror
+    return x;
+}
+
+// Y[r] = X[perm[r]] (gather) or Y[perm[r]] = X[r] (scatter) on columns [c_lo, c_hi).
+template <typename T, bool GATHER>
+__global__ __launch_bounds__(256) void k_ldl_permute(int64_t n, int C, int c_lo, int c_hi,
+                                                     const int32_t *__restrict__ perm,
+                                                     const T *__restrict__ X, T *__restrict__ Y)
+{
+    const int w = c_hi - c_lo;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n * w) return;
+    const int64_t r = g / w;
+    const int c = c_lo + (int)(g - r * w);
+    int64_t pr = perm[r];
+    pr = pr < 0 ? 0 : (pr >= n ? n - 1 : pr);
+    if (GATHER) Y[(size_t)r * C + c] = X[(size_t)pr * C + c];
+    else Y[(size_t)pr * C + c] = X[(size_t)r * C + c];
+}
+
+// Substitution with the unit triangular factor on columns [c_lo, c_hi):
+//   FWD: y_r = X[r] - sum_{j<r} l_rj y_j, rows r = 0..n-1
+//   BWD: w_r = X[r] - sum_{j>r} l_jr w_j, rows r = n-1..0
+// (Y[r] = y_r / w_r).  NS lanes share a column (a wavefront owns 64 / NS
+// columns); lane = NS * column + slice, and slice q takes the band entries
+// k = q + NS rr (rr = 0 .. 256/NS - 1) of every row, so the slices of a
+// column read NS consecutive ring rows.  The ring keeps each solved row twice
+// (rows j mod 256 and j mod 256 + 256), so all reads of one row use immediate
+// offsets from a single base.  Rows are fetched in batches of kBatch (band
+// rows and inputs into registers) one batch ahead and staged into LDS at the
+// batch boundary: one wait on HBM per batch.
+template <typename T, bool FWD, int NS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ldl_solve(
+    int64_t n, int C, int c_lo, int c_hi, const double *__restrict__ band,
+    const T *__restrict__ X, T *__restrict__ Y)
+{
+    constexpr int kBatch = 16;
+    constexpr int NC = 64 / NS;        // columns per wavefront
+    constexpr int NR = kRing / NS;     // rounds per row
+    __shared__ double ring[2 * kRing * NC];
+    __shared__ double stg[kBatch][kRing];
     const int lane = threadIdx.x;
-    const int craw = c_lo + blockIdx.x * 64 + lane;
+    const int cl = lane / NS, q = lane % NS;
+    const int craw = c_lo + blockIdx.x * NC + cl;
     const bool ok = craw < c_hi;
     const int c = ok ? craw : c_lo;
-    const double sc = (FWD && xs) ? xs[c] : 1.0;
-    for (int q = 0; q < kRing; ++q) ring[q * 64 + lane] = 0.0;
+    for (int e = lane; e < 2 * kRing * NC; e += 64) ring[e] = 0.0;
 
-    auto row_of = [&](int64_t t) -> int64_t { return FWD ? t : n - 1 - t; };
-    // chunk registers: entry start, entry count, permutation of rows 64k + lane
-    int32_t mA0 = 0, mAc = 0, mAp = 0, mB0 = 0, mBc = 0, mBp = 0;
-    auto load_chunk = [&](int64_t k, int32_t &m0, int32_t &mc, int32_t &mp) {
-        const int64_t t = k * 64 + lane;
-        if (t < n) {
-            const int64_t r = row_of(t);
-            int32_t a = rp[r], b = rp[r + 1];
-            a = a < 0 ? 0 : (a > nnz ? (int32_t)nnz : a);
-            b = b < a ? a : (b > nnz ? (int32_t)nnz : b);
-            int32_t pr = perm[r];
-            pr = pr < 0 ? 0 : (pr >= n ? (int32_t)(n - 1) : pr);
-            m0 = a;
-            mc = (b - a) > kRing ? kRing : (b - a);
-            mp = pr;
-        } else {
-            m0 = 0;
-            mc = 0;
-            mp = 0;
-        }
+    auto row_of = [&](int64_t t) -> int64_t {
+        const int64_t tt = t < n ? t : n - 1;   // past the end: repeat the last row (unused)
+        return FWD ? tt : n - 1 - tt;
     };
-    int64_t chunkA = 0;   // chunk held in mA*; mB* holds chunkA + 1
-    load_chunk(0, mA0, mAc, mAp);
-    load_chunk(1, mB0, mBc, mBp);
-    struct Meta {
-        int32_t p0, cnt, pr;
-    };
-    auto meta = [&](int64_t t) -> Meta {
-        const int l = (int)(t & 63);
-        if ((t >> 6) == chunkA)
-            return {__builtin_amdgcn_readlane(mA0, l), __builtin_amdgcn_readlane(mAc, l),
-                    __builtin_amdgcn_readlane(mAp, l)};
-        return {__builtin_amdgcn_readlane(mB0, l), __builtin_amdgcn_readlane(mBc, l),
-                __builtin_amdgcn_readlane(mBp, l)};
-    };
-    struct Set {
-        double v[kQ];
-        int32_t o[kQ];
-        double b;
-        int32_t cnt;
-    };
-    auto fetch = [&](int64_t t, Set &S) {
-        const Meta m = meta(t);
-        S.cnt = m.cnt;
+    double nv[kBatch][4];   // next batch: band values 2 lane, 2 lane + 1, 128 + 2 lane, 129 + 2 lane
+    T nx[kBatch];           // next batch: inputs
+    T cx[kBatch];           // current batch: inputs
+    auto load_batch = [&](int64_t t0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            const int e = q * 64 + lane;
-            const bool in = e < m.cnt;
-            S.v[q] = in ? lv[m.p0 + e] : 0.0;
-            S.o[q] = in ? (ci[m.p0 + e] & (kRing - 1)) * 64 : 0;
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t r = row_of(t0 + u);
+            const double2 *row = reinterpret_cast<const double2 *>(band + (size_t)r * kRing);
+            const double2 a = row[lane], b = row[64 + lane];
+            nv[u][0] = a.x;
+            nv[u][1] = a.y;
+            nv[u][2] = b.x;
+            nv[u][3] = b.y;
+            nx[u] = X[(size_t)r * C + c];
         }
-        const int64_t src = FWD ? (int64_t)m.pr : row_of(t);
-        S.b = static_cast<double>(X[(size_t)src * C + c]) * sc;
     };
-    auto commit = [&](const Set &S, int buf) {
+    auto stage_batch = [&]() __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-            sv[buf][q * 64 + lane] = S.v[q];
-            so[buf][q * 64 + lane] = S.o[q];
+        for (int u = 0; u < kBatch; ++u) {
+            double2 a, b;
+            a.x = nv[u][0];
+            a.y = nv[u][1];
+            b.x = nv[u][2];
+            b.y = nv[u][3];
+            reinterpret_cast<double2 *>(stg[u])[lane] = a;
+            reinterpret_cast<double2 *>(stg[u])[64 + lane] = b;
+            cx[u] = nx[u];
         }
     };
-    // row t: entries in staging buffer t & 1, input b
-    auto solve_row = [&](int64_t t, int buf, int32_t cnt, double b) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        const double *v = sv[buf];
-        const int32_t *o = so[buf];
-        for (int e = 0; e < cnt; e += 4) {
-            a0 += v[e] * ring[o[e] + lane];
-            a1 += v[e + 1] * ring[o[e + 1] + lane];
-            a2 += v[e + 2] * ring[o[e + 2] + lane];
-            a3 += v[e + 3] * ring[o[e + 3] + lane];
-        }
-        const double y = b - ((a0 + a1) + (a2 + a3));
+    auto solve_row = [&](int64_t t, int u, double b) __attribute__((always_inline)) {
         const int64_t r = row_of(t);
-        ring[(int)(r & (kRing - 1)) * 64 + lane] = y;
-        const int64_t dst = FWD ? r : (int64_t)meta(t).pr;
-        if (ok) Y[(size_t)dst * C + c] = static_cast<T>(y);
+        // ring row of round rr: FWD (r + q + NS rr) mod 256, BWD (r - q - NS rr) mod 256;
+        // every round is read (entries outside the row's span are zeros)
+        const int x = (int)((FWD ? r + q : r - q) & (kRing - 1));
+        const double *rb = FWD ? ring + (x * NC + cl) : ring + ((x + NS) * NC + cl);
+        const double *vb = stg[u] + q;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < NR; rr += 4) {
+            a0 += vb[NS * rr] * rb[NS * NC * (FWD ? rr : NR - 1 - rr)];
+            a1 += vb[NS * (rr + 1)] * rb[NS * NC * (FWD ? rr + 1 : NR - 2 - rr)];
+            a2 += vb[NS * (rr + 2)] * rb[NS * NC * (FWD ? rr + 2 : NR - 3 - rr)];
+            a3 += vb[NS * (rr + 3)] * rb[NS * NC * (FWD ? rr + 3 : NR - 4 - rr)];
+        }
+        const double y = b - sum_slices<NS>((a0 + a1) + (a2 + a3));
+        const int w = (int)(r & (kRing - 1));
+        if (q == 0) {
+            ring[w * NC + cl] = y;
+            ring[(w + kRing) * NC + cl] = y;
+            if (ok) Y[(size_t)r * C + c] = static_cast<T>(y);
+        }
     };
 
-    Set S0, S1;   // rows of even / odd walk index
-    fetch(0, S0);
-    commit(S0, 0);
-    int32_t cnt_cur = S0.cnt;
-    double b_cur = S0.b;
-    if (n > 1) fetch(1, S1);
-    if (n > 2) fetch(2, S0);
-    for (int64_t t = 0; t < n; t += 2) {
-        // even row t (staging 0), then odd row t+1 (staging 1)
-        if ((t >> 6) != chunkA) {   // entering a new chunk: shift and load the next one
-            chunkA = t >> 6;
-            mA0 = mB0;
-            mAc = mBc;
-            mAp = mBp;
-            load_chunk(chunkA + 1, mB0, mBc, mBp);
+    load_batch(0);
+    stage_batch();
+    load_batch(kBatch);
+    for (int64_t t0 = 0; t0 < n; t0 += kBatch) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (t0 + u < n) solve_row(t0 + u, u, static_cast<double>(cx[u]));
+        if (t0 + kBatch < n) {
+            stage_batch();                  // the batch loaded one batch ago
+            load_batch(t0 + 2 * kBatch);
         }
-        solve_row(t, 0, cnt_cur, b_cur);
-        if (t + 1 >= n) break;
-        commit(S1, 1);
-        cnt_cur = S1.cnt;
-        b_cur = S1.b;
-        if (t + 3 < n) fetch(t + 3, S1);
-        solve_row(t + 1, 1, cnt_cur, b_cur);
-        if (t + 2 >= n) break;
-        commit(S0, 0);
-        cnt_cur = S0.cnt;
-        b_cur = S0.b;
-        if (t + 4 < n) fetch(t + 4, S0);
     }
 }
 
@@ -225,6 +252,10 @@ void launch_ldl_eblocks(const Plan &p, hipStream_t st)
         double *ed = p.e_blk + (size_t)s * 2 * p.n, *eo = ed + p.n;
         k_ldl_eblocks<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(p.n, p.ldl[s].dd, p.ldl[s].doff,
                                                                      ed, eo);
+        double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
+        k_ldl_band_zero<<<1024, 256, 0, st>>>(p.n, bf, bb);
+        k_ldl_band_fill<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(
+            p.n, p.ldl[s].nnz, p.ldl[s].lrp, p.ldl[s].lci, p.ldl[s].lval, bf, bb);
     }
 }
 
@@ -245,24 +276,46 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
         if (!shift_cols(p, s, lo, hi)) continue;
         const LdlDev &f = p.ldl[s];
         const double *ed = p.e_blk + (size_t)s * 2 * p.n, *eo = ed + p.n;
-        if (what == 0) {
-            const int64_t total = p.n * (hi - lo);
-            k_ldl_eapply<T><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
-                p.n, p.C, lo, hi, f.doff, ed, eo, (const T *)X, xs, (T *)Y);
-            continue;
+        const int64_t total = p.n * (hi - lo);
+        const unsigned egrid = (unsigned)((total + 255) / 256);
+        switch (what) {
+        case 0:
+            k_ldl_eapply<T><<<egrid, 256, 0, st>>>(p.n, p.C, lo, hi, f.doff, ed, eo, (const T *)X,
+                                                   xs, (T *)Y);
+            break;
+        case 3:
+            k_ldl_permute<T, true><<<egrid, 256, 0, st>>>(p.n, p.C, lo, hi, f.perm, (const T *)X,
+                                                          (T *)Y);
+            break;
+        case 4:
+            k_ldl_permute<T, false><<<egrid, 256, 0, st>>>(p.n, p.C, lo, hi, f.perm, (const T *)X,
+                                                           (T *)Y);
+            break;
+        default: {
+            const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
+            // 16 lanes per column while the columns fill at most 256 wavefronts
+            // (fewer rounds per row), else 8 (less LDS traffic per column)
+            if (hi - lo <= 4 * 256) {
+                const unsigned grid = (unsigned)((hi - lo + 3) / 4);
+                if (what == 1)
+                    k_ldl_solve<T, true, 16><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
+                else
+                    k_ldl_solve<T, false, 16><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
+            } else {
+                const unsigned grid = (unsigned)((hi - lo + 7) / 8);
+                if (what == 1)
+                    k_ldl_solve<T, true, 8><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
+                else
+                    k_ldl_solve<T, false, 8><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
+            }
         }
-        const unsigned grid = (unsigned)((hi - lo + 63) / 64);
-        if (what == 1)
-            k_ldl_solve<T, true><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, f.nnz, f.perm, f.lrp, f.lci,
-                                                      f.lval, (const T *)X, xs, (T *)Y);
-        else
-            k_ldl_solve<T, false><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, f.nnz, f.perm, f.ltrp,
-                                                       f.ltci, f.ltval, (const T *)X, xs, (T *)Y);
+        }
     }
 }
 
-// what: 0 = |D|^{-1/2} blocks, 1 = forward substitution with the gather by P,
-// 2 = back substitution with L^T and the scatter by P^T
+// what: 0 = |D|^{-1/2} blocks (with the column scales xs), 1 = forward
+// substitution with L, 2 = back substitution with L^T, 3 = gather by P,
+// 4 = scatter by P^T
 void launch_ldl(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st)
 {
     if (p.vec_f32) ldl_t<float>(p, what, X, xs, Y, st);

@@ -48,8 +48,7 @@ class PrecT(ctypes.Structure):
 class LdlFactorT(ctypes.Structure):
     _fields_ = [("perm", ctypes.c_void_p), ("l_row_ptr", ctypes.c_void_p),
                 ("l_col_idx", ctypes.c_void_p), ("l_val", ctypes.c_void_p),
-                ("lt_row_ptr", ctypes.c_void_p), ("lt_col_idx", ctypes.c_void_p),
-                ("lt_val", ctypes.c_void_p), ("d_diag", ctypes.c_void_p), ("d_off", ctypes.c_void_p),
+                ("d_diag", ctypes.c_void_p), ("d_off", ctypes.c_void_p),
                 ("nnz", ctypes.c_int64), ("bandwidth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -146,7 +145,7 @@ def load():
                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int32)]
         lib.ecnt_ildl_export.restype = ctypes.c_int32
-        lib.ecnt_ildl_export.argtypes = [ctypes.c_void_p] + [P] * 9
+        lib.ecnt_ildl_export.argtypes = [ctypes.c_void_p] + [P] * 6
         lib.ecnt_ildl_free.restype = None
         lib.ecnt_ildl_free.argtypes = [ctypes.c_void_p]
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
@@ -208,9 +207,6 @@ class HostLDL:
     l_rp: np.ndarray
     l_ci: np.ndarray
     l_val: np.ndarray
-    lt_rp: np.ndarray
-    lt_ci: np.ndarray
-    lt_val: np.ndarray
     d_diag: np.ndarray
     d_off: np.ndarray
     bandwidth: int
@@ -234,11 +230,10 @@ def ildl_factor(A, tau: float, droptol: float) -> HostLDL:
                                    ctypes.byref(nneg)))
         z = int(nnz.value)
         a = dict(perm=np.zeros(n, np.int32), l_rp=np.zeros(n + 1, np.int32),
-                 l_ci=np.zeros(z, np.int32), l_val=np.zeros(z), lt_rp=np.zeros(n + 1, np.int32),
-                 lt_ci=np.zeros(z, np.int32), lt_val=np.zeros(z), d_diag=np.zeros(n),
+                 l_ci=np.zeros(z, np.int32), l_val=np.zeros(z), d_diag=np.zeros(n),
                  d_off=np.zeros(n))
         _check(lib.ecnt_ildl_export(h, *[a[k].ctypes.data for k in (
-            "perm", "l_rp", "l_ci", "l_val", "lt_rp", "lt_ci", "lt_val", "d_diag", "d_off")]))
+            "perm", "l_rp", "l_ci", "l_val", "d_diag", "d_off")]))
     finally:
         lib.ecnt_ildl_free(h)
     return HostLDL(n, bandwidth=int(bw.value), n2x2=int(n2.value), nneg=int(nneg.value), **a)
@@ -253,15 +248,15 @@ class DeviceLDL:
 
     def struct(self) -> LdlFactorT:
         t = self.t
-        return LdlFactorT(*[t[k].data_ptr() for k in ("perm", "l_rp", "l_ci", "l_val", "lt_rp",
-                                                      "lt_ci", "lt_val", "d_diag", "d_off")],
+        return LdlFactorT(*[t[k].data_ptr() for k in ("perm", "l_rp", "l_ci", "l_val", "d_diag",
+                                                      "d_off")],
                           self.nnz, self.bandwidth, 0)
 
 
 def upload_ldl(F: HostLDL, device: str = "cuda") -> DeviceLDL:
     import torch
     t = {}
-    for k in ("perm", "l_rp", "l_ci", "l_val", "lt_rp", "lt_ci", "lt_val", "d_diag", "d_off"):
+    for k in ("perm", "l_rp", "l_ci", "l_val", "d_diag", "d_off"):
         a = getattr(F, k)
         if a.size == 0:   # keep a valid pointer for empty entry arrays
             a = np.zeros(1, dtype=a.dtype)

@@ -58,12 +58,6 @@ def test_library_factor_equals_oracle_bitwise(name, make, tau, t):
     rows = np.repeat(np.arange(A.n), np.diff(H.l_rp))
     assert H.bandwidth == (int(np.max(rows - H.l_ci)) if len(H.l_ci) else 0)
     assert H.n2x2 == int(np.count_nonzero(H.d_off))
-    # L^T by rows is the same entries by columns
-    Lt = np.zeros((A.n, A.n))
-    for i in range(A.n):
-        for p in range(H.lt_rp[i], H.lt_rp[i + 1]):
-            Lt[i, H.lt_ci[p]] = H.lt_val[p]
-    assert np.array_equal(Lt, (F.dense_L() - np.eye(A.n)).T)
 
 
 def test_library_inertia_count():
@@ -121,7 +115,7 @@ def test_ildl_rejects_bad_arguments():
 
 
 def _fake_factor(bandwidth, nnz=10):
-    return ec.LdlFactorT(*([0x1000] * 9), nnz, bandwidth, 0)
+    return ec.LdlFactorT(*([0x1000] * 6), nnz, bandwidth, 0)
 
 
 class _FakePrec:

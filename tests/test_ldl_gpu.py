@@ -150,3 +150,12 @@ def test_ldl_unsupported_forms(ec):
     with pytest.raises(ec.EcntError) as e:
         ec.smooth_forward(Ad, prec, wl.xi, wl.eta, V, 5, 0.05)
     assert e.value.status == ec.ECNT_EUNSUPPORTED
+
+
+def test_ldl_many_columns_eight_lane_slices(ec):
+    """More than 1024 columns of one shift take the 8-lanes-per-column solve."""
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 1100, 9)
+    r, refs = run_pair(ec, P.A, (300.0,), 1e-3, V, 5)
+    assert_negcount_parity(r, refs, V)
