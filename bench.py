@@ -379,8 +379,9 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
-FAMILY_OF = [("k_ldl_solve", "op_ldl_solve"), ("k_ldl_eapply", "op_ldl_solve"),
-             ("k_ldl_permute", "op_ldl_solve"), ("k_ldl_band", "lz_setup"), ("k_ldl_eblocks", "lz_setup"),
+FAMILY_OF = [("k_ldl_solve", "op_ldl_solve"), ("k_ldl_eapply", "op_ldl_elementwise"),
+             ("k_ldl_permute", "op_ldl_elementwise"), ("k_ldl_band", "lz_setup"),
+             ("k_ldl_eblocks", "lz_setup"),
              ("k_quad_sweep", "op_cheb_quad"), ("k_arn_quad", "quadrature"),
              ("k_arn_fin", "lz_finalize"), ("k_arn_norm_fin", "lz_finalize"),
              ("k_bdots_fin", "lz_finalize"),

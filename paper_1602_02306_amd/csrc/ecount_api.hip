@@ -18,11 +18,11 @@ namespace ecnt {
 
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
-              F_VGRAD, F_CHEB2, F_LDL, F_COUNT };
+              F_VGRAD, F_CHEB2, F_LDL, F_LDLE, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
                                            "bw_update", "bw_vgrad", "op_cheb_quad",
-                                           "op_ldl_solve"};
+                                           "op_ldl_solve", "op_ldl_elementwise"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -683,10 +683,10 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     const size_t blk = (size_t)p.n * p.C * bv;
     char *basis = (char *)p.basis;
     const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
-    // factor bytes one application streams: the band rows of one triangle,
-    // the permutation, D and |D|^{-1/2}
-    const double ldl_b = p.prec_kind == ECNT_PREC_LDL
-                             ? (8.0 * ldl_ring_rows() + 4.0 + 24.0) * p.S * p.n : 0.0;
+    // factor bytes a triangular solve streams (the band rows of one triangle)
+    // and an elementwise pass (|D|^{-1/2} blocks and D's structure, or P)
+    const double ldl_b = p.prec_kind == ECNT_PREC_LDL ? 8.0 * ldl_ring_rows() * p.S * p.n : 0.0;
+    const double ldle_b = p.prec_kind == ECNT_PREC_LDL ? 24.0 * p.S * p.n : 0.0;
     for (int i = 1; i <= p.k; ++i) {
         void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
@@ -703,20 +703,24 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         } else if (p.prec_kind == ECNT_PREC_LDL) {
             // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
             // y = M u = |D|^{-1/2} (L^{-1} (P u))
-            {
-                Timed tm(F_LDL, 4 * blk_b + ldl_b, st);
-                launch_ldl(p, 0, x, xs, p.tmp[0], st);
-                launch_ldl(p, 2, p.tmp[0], nullptr, p.tmp[1], st);
-                launch_ldl(p, 4, p.tmp[1], nullptr, p.tmp[0], st);
-            }
+            auto elem = [&](int what, const void *in, const double *sc, void *out) {
+                Timed tm(F_LDLE, 2 * blk_b + ldle_b, st);
+                launch_ldl(p, what, in, sc, out, st);
+            };
+            auto solve = [&](int what, const void *in, void *out) {
+                Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+                launch_ldl(p, what, in, nullptr, out, st);
+            };
+            elem(0, x, xs, p.tmp[0]);
+            solve(2, p.tmp[0], p.tmp[1]);
+            elem(4, p.tmp[1], nullptr, p.tmp[0]);
             {
                 Timed tm(F_CSR, 2 * blk_b + csr_b, st);
                 launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[0], nullptr, nullptr, p.tmp[1], st);
             }
-            Timed tm(F_LDL, 4 * blk_b + ldl_b, st);
-            launch_ldl(p, 3, p.tmp[1], nullptr, p.tmp[0], st);
-            launch_ldl(p, 1, p.tmp[0], nullptr, p.tmp[1], st);
-            launch_ldl(p, 0, p.tmp[1], nullptr, y, st);
+            elem(3, p.tmp[1], nullptr, p.tmp[0]);
+            solve(1, p.tmp[0], p.tmp[1]);
+            elem(0, p.tmp[1], nullptr, y);
         } else {
             Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
             launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,

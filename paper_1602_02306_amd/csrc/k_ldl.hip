@@ -4,12 +4,12 @@
 // with P (A - tau I) P^T ~ L D L^T the factor of the columns' shift.
 //
 // The substitutions are sequential in the rows; the columns (probes) are the
-// parallel dimension: one wavefront owns 4 or 8 columns and walks all n rows,
+// parallel dimension: one wavefront owns 2, 4 or 8 columns and walks all n rows,
 // keeping the last kRing solved rows of its columns in LDS (a ring indexed by
 // row mod kRing), so every x_j a row needs comes from LDS when the factor's
 // bandwidth is at most kRing.  The factor is used in band form (each row as
 // 256 values by distance from the diagonal, built once per call), so a row
-// needs no column indices; 16 or 8 lanes share a column and split its row.
+// needs no column indices; 32, 16 or 8 lanes share a column and split its row.
 #include <type_traits>
 #include <utility>
 
@@ -109,9 +109,10 @@ __global__ void k_ldl_band_fill(int64_t n, int64_t nnz, const int32_t *__restric
     }
 }
 
-// Sum over NS (8 or 16) consecutive lanes (the entry slices of one column),
-// by DPP: swap neighbours, swap pairs, mirror the two quads of each 8 lanes,
-// then (16) mirror the two halves of each 16 lanes.
+// Sum over NS (8, 16 or 32) consecutive lanes (the entry slices of one
+// column), by DPP: swap neighbours, swap pairs, mirror the two quads of each
+// 8 lanes, (16) mirror the two halves of each 16 lanes, (32) swap the two
+// halves of each 32 lanes.
 template <int NS>
 __device__ __forceinline__ double sum_slices(double x)
 {
@@ -124,7 +125,12 @@ __device__ __forceinline__ double sum_slices(double x)
     x += dpp(x, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
     x += dpp(x, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
     x += dpp(x, std::integral_constant<int, 0x141>{});  // row_half_mirror
-    if constexpr (NS == 16) x += dpp(x, std::integral_constant<int, 0x140>{});   // row_mirror
+    if constexpr (NS >= 16) x += dpp(x, std::integral_constant<int, 0x140>{});   // row_mirror
+    if constexpr (NS == 32) {   // lane ^ 16 within 32 lanes (ds_swizzle bit mode)
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+        x += __hiloint2double(hi, lo);
+    }
     return x;
 }
 
@@ -293,9 +299,16 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
             break;
         default: {
             const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
-            // 16 lanes per column while the columns fill at most 256 wavefronts
-            // (fewer rounds per row), else 8 (less LDS traffic per column)
-            if (hi - lo <= 4 * 256) {
+            // more lanes per column (fewer rounds per row) while the columns
+            // fill at most 256 wavefronts; 8 lanes (least LDS traffic per
+            // column) beyond that
+            if (hi - lo <= 2 * 256) {
+                const unsigned grid = (unsigned)((hi - lo + 1) / 2);
+                if (what == 1)
+                    k_ldl_solve<T, true, 32><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
+                else
+                    k_ldl_solve<T, false, 32><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
+            } else if (hi - lo <= 4 * 256) {
                 const unsigned grid = (unsigned)((hi - lo + 3) / 4);
                 if (what == 1)
                     k_ldl_solve<T, true, 16><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);

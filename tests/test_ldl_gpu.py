@@ -152,10 +152,12 @@ def test_ldl_unsupported_forms(ec):
     assert e.value.status == ec.ECNT_EUNSUPPORTED
 
 
-def test_ldl_many_columns_eight_lane_slices(ec):
-    """More than 1024 columns of one shift take the 8-lanes-per-column solve."""
+@pytest.mark.parametrize("m", [600, 1100])
+def test_ldl_many_columns_fewer_lane_slices(ec, m):
+    """513..1024 columns of one shift take the 16-lanes-per-column solve,
+    more than 1024 the 8-lanes one (up to 512: 32 lanes, the other tests)."""
     wl = W.WORKLOADS["t1_small"]
     P = W.make_problem(wl)
-    V = W.rademacher(P.A.n, 1100, 9)
+    V = W.rademacher(P.A.n, m, 9)
     r, refs = run_pair(ec, P.A, (300.0,), 1e-3, V, 5)
     assert_negcount_parity(r, refs, V)
