@@ -4,12 +4,11 @@
 // with P (A - tau I) P^T ~ L D L^T the factor of the columns' shift.
 //
 // The substitutions are sequential in the rows; the columns (probes) are the
-// parallel dimension: one wavefront owns 2, 4 or 8 columns and walks all n rows,
-// keeping the last kRing solved rows of its columns in LDS (a ring indexed by
-// row mod kRing), so every x_j a row needs comes from LDS when the factor's
-// bandwidth is at most kRing.  The factor is used in band form (each row as
-// 256 values by distance from the diagonal, built once per call), so a row
-// needs no column indices; 32, 16 or 8 lanes share a column and split its row.
+// parallel dimension: one wavefront owns 2 columns and walks all n rows in
+// column form, keeping the pending sums of the next kRing rows in registers,
+// which serves any factor of bandwidth at most kRing.  The factor is used in
+// band form (each row as 256 values by distance from the diagonal, built once
+// per call), so no column indices are read.
 #include <type_traits>
 #include <utility>
 
@@ -19,7 +18,7 @@
 namespace ecnt {
 
 namespace {
-constexpr int kRing = 256;   // rows kept per column (the largest bandwidth served)
+constexpr int kRing = 256;   // band width (the largest bandwidth served)
 }
 
 // |D|^{-1/2} block by block, for one shift.  A 2 x 2 block [[a, b], [b, c]]
@@ -109,31 +108,6 @@ __global__ void k_ldl_band_fill(int64_t n, int64_t nnz, const int32_t *__restric
     }
 }
 
-// Sum over NS (8, 16 or 32) consecutive lanes (the entry slices of one
-// column), by DPP: swap neighbours, swap pairs, mirror the two quads of each
-// 8 lanes, (16) mirror the two halves of each 16 lanes, (32) swap the two
-// halves of each 32 lanes.
-template <int NS>
-__device__ __forceinline__ double sum_slices(double x)
-{
-    auto dpp = [](double v, auto ctrl_tag) -> double {
-        constexpr int ctrl = decltype(ctrl_tag)::value;
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xf, 0xf, false);
-        return __hiloint2double(hi, lo);
-    };
-    x += dpp(x, std::integral_constant<int, 0xB1>{});   // quad_perm [1,0,3,2]
-    x += dpp(x, std::integral_constant<int, 0x4E>{});   // quad_perm [2,3,0,1]
-    x += dpp(x, std::integral_constant<int, 0x141>{});  // row_half_mirror
-    if constexpr (NS >= 16) x += dpp(x, std::integral_constant<int, 0x140>{});   // row_mirror
-    if constexpr (NS == 32) {   // lane ^ 16 within 32 lanes (ds_swizzle bit mode)
-        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
-        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
-        x += __hiloint2double(hi, lo);
-    }
-    return x;
-}
-
 // Y[r] = X[perm[r]] (gather) or Y[perm[r]] = X[r] (scatter) on columns [c_lo, c_hi).
 template <typename T, bool GATHER>
 __global__ __launch_bounds__(256) void k_ldl_permute(int64_t n, int C, int c_lo, int c_hi,
@@ -151,52 +125,59 @@ __global__ __launch_bounds__(256) void k_ldl_permute(int64_t n, int C, int c_lo,
     else Y[(size_t)pr * C + c] = X[(size_t)r * C + c];
 }
 
-// Substitution with the unit triangular factor on columns [c_lo, c_hi):
+// Substitution with the unit triangular factor on columns [c_lo, c_hi), in
+// column (right-looking) form:
 //   FWD: y_r = X[r] - sum_{j<r} l_rj y_j, rows r = 0..n-1
 //   BWD: w_r = X[r] - sum_{j>r} l_jr w_j, rows r = n-1..0
-// (Y[r] = y_r / w_r).  NS lanes share a column (a wavefront owns 64 / NS
-// columns); lane = NS * column + slice, and slice q takes the band entries
-// k = q + NS rr (rr = 0 .. 256/NS - 1) of every row, so the slices of a
-// column read NS consecutive ring rows.  The ring keeps each solved row twice
-// (rows j mod 256 and j mod 256 + 256), so all reads of one row use immediate
-// offsets from a single base.  Rows are fetched in batches of kBatch (band
-// rows and inputs into registers) one batch ahead and staged into LDS at the
-// batch boundary: one wait on HBM per batch.
-template <typename T, bool FWD, int NS>
+// (Y[r] = y_r / w_r).  In walk order t (FWD r = t, BWD r = n-1-t) the value of
+// step t enters steps t+1 .. t+256 with the coefficients of one band row:
+// band[r][256 - d] links step t to step t + d (FWD: column r of L, i.e. the
+// band of L^T; BWD: row r of L).  A wavefront owns 2 columns, 32 lanes each;
+// lane q keeps the pending sums of steps T0 + q + 32 s (s = 0..7) of the
+// current group of 32 steps in registers (9 slots: from step T0 + 31 the
+// values reach T0 + 287).  Step t = T0 + q0: lane q0 forms
+// y = X - pending, one swizzle broadcasts it to the 32 lanes of its column,
+// and every lane adds coefficient * y to its 8 pending sums; at the end of a
+// group the sums shift by one slot.  The dependence from one step to the next
+// is one FMA, a subtraction and the broadcast; no reduction across lanes.
+// Band rows are loaded 16 steps ahead into registers and staged into LDS per
+// 16 steps between 32 zeros on each side (read for distances outside 1..256).
+template <typename T, bool FWD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ldl_solve(
     int64_t n, int C, int c_lo, int c_hi, const double *__restrict__ band,
     const T *__restrict__ X, T *__restrict__ Y)
 {
-    constexpr int kBatch = 16;
-    constexpr int NC = 64 / NS;        // columns per wavefront
-    constexpr int NR = kRing / NS;     // rounds per row
-    __shared__ double ring[2 * kRing * NC];
-    __shared__ double stg[kBatch][kRing];
+    constexpr int NS = 32;             // lanes per column, steps per group
+    constexpr int NR = kRing / NS;     // the pending sums per lane are NR + 1
+    constexpr int kBatch = 16;         // band rows staged at a time
+    constexpr int kRow = NS + kRing + NS;   // staged row: zeros, band, zeros
+    __shared__ double stg[kBatch][kRow];
     const int lane = threadIdx.x;
-    const int cl = lane / NS, q = lane % NS;
-    const int craw = c_lo + blockIdx.x * NC + cl;
+    const int hcol = lane >> 5, q = lane & 31;
+    const int craw = c_lo + blockIdx.x * 2 + hcol;
     const bool ok = craw < c_hi;
     const int c = ok ? craw : c_lo;
-    for (int e = lane; e < 2 * kRing * NC; e += 64) ring[e] = 0.0;
+    if (lane < NS)
+        for (int u = 0; u < kBatch; ++u) {
+            stg[u][lane] = 0.0;
+            stg[u][NS + kRing + lane] = 0.0;
+        }
 
     auto row_of = [&](int64_t t) -> int64_t {
         const int64_t tt = t < n ? t : n - 1;   // past the end: repeat the last row (unused)
         return FWD ? tt : n - 1 - tt;
     };
     double nv[kBatch][4];   // next batch: band values 2 lane, 2 lane + 1, 128 + 2 lane, 129 + 2 lane
-    T nx[kBatch];           // next batch: inputs
-    T cx[kBatch];           // current batch: inputs
     auto load_batch = [&](int64_t t0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int64_t r = row_of(t0 + u);
-            const double2 *row = reinterpret_cast<const double2 *>(band + (size_t)r * kRing);
+            const double2 *row =
+                reinterpret_cast<const double2 *>(band + (size_t)row_of(t0 + u) * kRing);
             const double2 a = row[lane], b = row[64 + lane];
             nv[u][0] = a.x;
             nv[u][1] = a.y;
             nv[u][2] = b.x;
             nv[u][3] = b.y;
-            nx[u] = X[(size_t)r * C + c];
         }
     };
     auto stage_batch = [&]() __attribute__((always_inline)) {
@@ -207,45 +188,58 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
             a.y = nv[u][1];
             b.x = nv[u][2];
             b.y = nv[u][3];
-            reinterpret_cast<double2 *>(stg[u])[lane] = a;
-            reinterpret_cast<double2 *>(stg[u])[64 + lane] = b;
-            cx[u] = nx[u];
+            reinterpret_cast<double2 *>(stg[u] + NS)[lane] = a;
+            reinterpret_cast<double2 *>(stg[u] + NS)[64 + lane] = b;
         }
     };
-    auto solve_row = [&](int64_t t, int u, double b) __attribute__((always_inline)) {
-        const int64_t r = row_of(t);
-        // ring row of round rr: FWD (r + q + NS rr) mod 256, BWD (r - q - NS rr) mod 256;
-        // every round is read (entries outside the row's span are zeros)
-        const int x = (int)((FWD ? r + q : r - q) & (kRing - 1));
-        const double *rb = FWD ? ring + (x * NC + cl) : ring + ((x + NS) * NC + cl);
-        const double *vb = stg[u] + q;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    auto load_b = [&](int64_t T0) -> T { return X[(size_t)row_of(T0 + q) * C + c]; };
+
+    double slot[NR + 1];
 #pragma unroll
-        for (int rr = 0; rr < NR; rr += 4) {
-            a0 += vb[NS * rr] * rb[NS * NC * (FWD ? rr : NR - 1 - rr)];
-            a1 += vb[NS * (rr + 1)] * rb[NS * NC * (FWD ? rr + 1 : NR - 2 - rr)];
-            a2 += vb[NS * (rr + 2)] * rb[NS * NC * (FWD ? rr + 2 : NR - 3 - rr)];
-            a3 += vb[NS * (rr + 3)] * rb[NS * NC * (FWD ? rr + 3 : NR - 4 - rr)];
-        }
-        const double y = b - sum_slices<NS>((a0 + a1) + (a2 + a3));
-        const int w = (int)(r & (kRing - 1));
-        if (q == 0) {
-            ring[w * NC + cl] = y;
-            ring[(w + kRing) * NC + cl] = y;
-            if (ok) Y[(size_t)r * C + c] = static_cast<T>(y);
-        }
+    for (int s2 = 0; s2 <= NR; ++s2) slot[s2] = 0.0;
+    double yown = 0.0;
+    T b_own = load_b(0), b_next = load_b(NS);
+
+    // one step: Q0 = position in the group (compile-time), U = staging row
+    auto step = [&]<int Q0>(std::integral_constant<int, Q0>, int u) __attribute__((always_inline)) {
+        const double y = static_cast<double>(b_own) - slot[0];   // meaningful in lane Q0
+        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(y), Q0 << 5);
+        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(y), Q0 << 5);
+        const double yb = __hiloint2double(hi, lo);
+        yown = q == Q0 ? yb : yown;
+        // coefficient for slot s (distance d = q - Q0 + 32 s): staged index
+        // 32 + 256 - d, zero unless 1 <= d <= 256
+        const double *sr = stg[u] + (NS - q + Q0);
+#pragma unroll
+        for (int s2 = 0; s2 <= NR; ++s2) slot[s2] += sr[NS * (NR - s2)] * yb;
+    };
+    auto half = [&]<int H>(int64_t T0, std::integral_constant<int, H>) __attribute__((always_inline)) {
+        [&]<int... U>(std::integer_sequence<int, U...>) __attribute__((always_inline)) {
+            ((T0 + H * kBatch + U < n ? step(std::integral_constant<int, H * kBatch + U>{}, U)
+                                      : void()),
+             ...);
+        }(std::make_integer_sequence<int, kBatch>{});
     };
 
     load_batch(0);
     stage_batch();
     load_batch(kBatch);
-    for (int64_t t0 = 0; t0 < n; t0 += kBatch) {
+    for (int64_t T0 = 0; T0 < n; T0 += NS) {
+        half(T0, std::integral_constant<int, 0>{});
+        if (T0 + kBatch < n) {
+            stage_batch();                 // steps T0+16 .. T0+31, loaded 16 steps ago
+            load_batch(T0 + 2 * kBatch);
+        }
+        half(T0, std::integral_constant<int, 1>{});
+        if (ok && T0 + q < n) Y[(size_t)row_of(T0 + q) * C + c] = static_cast<T>(yown);
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-            if (t0 + u < n) solve_row(t0 + u, u, static_cast<double>(cx[u]));
-        if (t0 + kBatch < n) {
-            stage_batch();                  // the batch loaded one batch ago
-            load_batch(t0 + 2 * kBatch);
+        for (int s2 = 0; s2 < NR; ++s2) slot[s2] = slot[s2 + 1];
+        slot[NR] = 0.0;
+        b_own = b_next;
+        b_next = load_b(T0 + 2 * NS);
+        if (T0 + NS < n) {
+            stage_batch();                 // steps T0+32 .. T0+47
+            load_batch(T0 + 3 * kBatch);
         }
     }
 }
@@ -298,29 +292,14 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
                                                            (T *)Y);
             break;
         default: {
+            // forward substitution walks the columns of L (the band of L^T),
+            // back substitution the rows of L
             const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
-            // more lanes per column (fewer rounds per row) while the columns
-            // fill at most 256 wavefronts; 8 lanes (least LDS traffic per
-            // column) beyond that
-            if (hi - lo <= 2 * 256) {
-                const unsigned grid = (unsigned)((hi - lo + 1) / 2);
-                if (what == 1)
-                    k_ldl_solve<T, true, 32><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
-                else
-                    k_ldl_solve<T, false, 32><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
-            } else if (hi - lo <= 4 * 256) {
-                const unsigned grid = (unsigned)((hi - lo + 3) / 4);
-                if (what == 1)
-                    k_ldl_solve<T, true, 16><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
-                else
-                    k_ldl_solve<T, false, 16><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
-            } else {
-                const unsigned grid = (unsigned)((hi - lo + 7) / 8);
-                if (what == 1)
-                    k_ldl_solve<T, true, 8><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
-                else
-                    k_ldl_solve<T, false, 8><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
-            }
+            const unsigned grid = (unsigned)((hi - lo + 1) / 2);
+            if (what == 1)
+                k_ldl_solve<T, true><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
+            else
+                k_ldl_solve<T, false><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
         }
         }
     }

@@ -153,11 +153,24 @@ def test_ldl_unsupported_forms(ec):
 
 
 @pytest.mark.parametrize("m", [600, 1100])
-def test_ldl_many_columns_fewer_lane_slices(ec, m):
-    """513..1024 columns of one shift take the 16-lanes-per-column solve,
-    more than 1024 the 8-lanes one (up to 512: 32 lanes, the other tests)."""
+def test_ldl_many_columns(ec, m):
+    """Hundreds of columns of one shift (hundreds of wavefronts walking the
+    rows side by side)."""
     wl = W.WORKLOADS["t1_small"]
     P = W.make_problem(wl)
     V = W.rademacher(P.A.n, m, 9)
     r, refs = run_pair(ec, P.A, (300.0,), 1e-3, V, 5)
+    assert_negcount_parity(r, refs, V)
+
+
+def test_ldl_bandwidth_near_the_limit(ec):
+    """A factor whose bandwidth (246) is close to the 256 the solves serve:
+    the entries at distances above 224 reach rows beyond a 256-row window of
+    the step that produces them (24 x 127 grid, interchanges widen the band)."""
+    A = W.laplacian_csr((24, 127))
+    A.val = A.val * 16384.0
+    H = ec.ildl_factor(A, 8000.0, 1e-6)
+    assert 224 < H.bandwidth <= 256
+    V = W.rademacher(A.n, 40, 13)
+    r, refs = run_pair(ec, A, (8000.0,), 1e-6, V, 6)
     assert_negcount_parity(r, refs, V)
