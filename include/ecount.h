@@ -87,10 +87,10 @@ typedef struct {
  *                             M = |D|^{-1/2} L^{-1} P, M^* = P^T L^{-T} |D|^{-1/2};
  *                             |D|^{-1/2} is formed block by block from D.  Factors
  *                             come from ecnt_ildl_factor (or any other source in the
- *                             same layout).  The triangular solves keep the last 256
- *                             solved rows of every column on chip: a factor whose
- *                             bandwidth (max i - j over the entries of L) exceeds
- *                             256 is EUNSUPPORTED. */
+ *                             same layout; perm must be a permutation).  The
+ *                             triangular solves take L as a band of 256 diagonals: a
+ *                             factor whose bandwidth (max i - j over the entries of L)
+ *                             exceeds 256 is EUNSUPPORTED. */
 typedef enum {
     ECNT_PREC_NONE = 0,
     ECNT_PREC_JACOBI = 1,

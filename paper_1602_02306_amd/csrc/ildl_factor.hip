@@ -366,6 +366,9 @@ ECNT_API ecnt_status ecnt_ildl_factor(int64_t n, const int32_t *row_ptr, const i
     } catch (const std::bad_alloc &) {
         delete F;
         return ecnt::set_error(ECNT_EINVAL, "ecnt_ildl_factor: out of host memory");
+    } catch (...) {   // no C++ exception crosses the ABI
+        delete F;
+        return ecnt::set_error(ECNT_EINVAL, "ecnt_ildl_factor: internal error");
     }
     if (st != ECNT_OK) {
         delete F;
