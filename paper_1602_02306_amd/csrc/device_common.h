@@ -131,6 +131,22 @@ __device__ __forceinline__ void vstore(T *__restrict__ p, size_t e, const double
     *reinterpret_cast<V *>(p + e) = v;
 }
 
+// vstore with the non-temporal hint: the line is not kept in the caches for
+// reuse (outputs that no later access of the same launch reads).
+template <typename T, int VW>
+__device__ __forceinline__ void vstore_nt(T *__restrict__ p, size_t e, const double (&o)[VW])
+{
+    if constexpr (VW == 1) {
+        __builtin_nontemporal_store(static_cast<T>(o[0]), p + e);
+    } else {
+        typedef T TV __attribute__((ext_vector_type(VW)));
+        TV v;
+#pragma unroll
+        for (int i = 0; i < VW; ++i) v[i] = static_cast<T>(o[i]);
+        __builtin_nontemporal_store(v, reinterpret_cast<TV *>(p + e));
+    }
+}
+
 // Value after rounding to the storage type T (what a later load returns).
 template <typename T>
 __device__ __forceinline__ double rounded(double x)

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
             const double xsc = xs ? xs[(size_t)seg * C + c0 + v] : 1.0;
             out[v] = o * xsc;
         }
-        if (r0 + i < n) vstore<T, VW>(y, (size_t)r * C + c0, out);
+        if (r0 + i < n) vstore_nt<T, VW>(y, (size_t)r * C + c0, out);
     }
 }
 
@@ -744,7 +744,7 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
                     if (HASZ) val -= cz * (double)zv[q][v];
                     o[v] = val;
                 }
-                if (w[q] != 0.0 && colok) vstore<T, VW>(out, base + ep + off[q], o);
+                if (w[q] != 0.0 && colok) vstore_nt<T, VW>(out, base + ep + off[q], o);
             }
         }
         __syncthreads();
