@@ -809,3 +809,80 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * Y = C X for an n x m block (both row-major, column j = one vector), column
+ * by column with apply_C; C = M (A - tau I) M^* with preconditioner kinds
+ * 0..2.  Used by the block-Lanczos oracle, which does its own recurrence in
+ * numpy.  Returns 0, -1 on bad arguments or allocation failure, -2 if the
+ * Jacobi preconditioner is singular.
+ */
+int oracle_apply_operator(int64_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                          const double *val, int prec_kind, int ndim, const int32_t *dims,
+                          double s, double lo, double hi, int degree, const double *coef,
+                          double tau, const double *X, int64_t m, int nthreads, double *Y)
+{
+    if (n < 1 || m < 1 || prec_kind < 0 || prec_kind > 2) return -1;
+    op_t P;
+    memset(&P, 0, sizeof P);
+    P.n = n;
+    P.row_ptr = row_ptr;
+    P.col_idx = col_idx;
+    P.val = val;
+    P.prec_kind = prec_kind;
+    P.ndim = ndim;
+    for (int a = 0; a < ndim && a < 3; ++a) P.dims[a] = dims[a];
+    P.s = s;
+    P.lo = lo;
+    P.hi = hi;
+    P.degree = degree;
+    P.coef = coef;
+    P.tau = tau;
+    double *jac = NULL;
+    if (prec_kind == 1) {
+        jac = (double *)malloc((size_t)n * sizeof(double));
+        if (!jac) return -1;
+        for (int64_t r = 0; r < n; ++r) {
+            double arr = 0.0;
+            for (int32_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p)
+                if (col_idx[p] == r) arr = val[p];
+            double d = fabs(arr - tau);
+            if (d == 0.0) {
+                free(jac);
+                return -2;
+            }
+            jac[r] = 1.0 / sqrt(d);
+        }
+        P.jac = jac;
+    }
+    int failed = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        double *x = (double *)malloc((size_t)n * sizeof(double));
+        double *y = (double *)malloc((size_t)n * sizeof(double));
+        double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+        if (!x || !y || !work) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            failed = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+            for (int64_t j = 0; j < m; ++j) {
+                for (int64_t r = 0; r < n; ++r) x[r] = X[r * m + j];
+                apply_C(&P, x, y, work);
+                for (int64_t r = 0; r < n; ++r) Y[r * m + j] = y[r];
+            }
+        }
+        free(x);
+        free(y);
+        free(work);
+    }
+    free(jac);
+    return failed ? -1 : 0;
+}

@@ -87,6 +87,11 @@ def _load():
                                        ctypes.c_int, P, ctypes.c_double, P, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_int, P, P, P]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_apply_operator.restype = ctypes.c_int
+        lib.oracle_apply_operator.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int, ctypes.c_int,
+                                              P, ctypes.c_double, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_int, P, ctypes.c_double,
+                                              P, ctypes.c_int64, ctypes.c_int, P]
         PP = ctypes.POINTER(ctypes.c_void_p)
         lib.oracle_ildl.restype = ctypes.c_int
         lib.oracle_ildl.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
@@ -310,6 +315,30 @@ def dense_operator(A, prec, tau: float) -> np.ndarray:
                               float(prec.s), float(prec.lo), float(prec.hi), len(coef) - 1,
                               _ptr(coef), float(tau), _ptr(C))
     return C
+
+
+def apply_operator(A, prec, tau: float, X: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """Y = C X, C = M (A - tau I) M^*, for an n x m block X (preconditioner
+    kinds none, jacobi, cheb), column by column with the oracle's operator."""
+    if prec.kind == "ildl":
+        raise ValueError("apply_operator takes the preconditioners none, jacobi and cheb")
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, m = X.shape
+    if A.n != n:
+        raise ValueError("block does not match A")
+    kind, nd, dims, coef = _prec_args(prec, n)
+    Y = np.zeros((n, m))
+    rp, ci, va = _csr_args(A)
+    rc = lib.oracle_apply_operator(n, _ptr(rp), _ptr(ci), _ptr(va), kind, nd, _ptr(dims),
+                                   float(prec.s), float(prec.lo), float(prec.hi), len(coef) - 1,
+                                   _ptr(coef), float(tau), _ptr(X), m,
+                                   int(nthreads or host_threads()), _ptr(Y))
+    if rc == -2:
+        raise ZeroDivisionError("Jacobi preconditioner is singular: a_rr == tau")
+    if rc != 0:
+        raise ValueError("oracle_apply_operator failed (%d)" % rc)
+    return Y
 
 
 # ---------------------------------------------------------------------------
