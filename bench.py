@@ -34,6 +34,9 @@ WORKLOAD_TEXT = {
     "c2_f32": "the 64^3 problem of c2 with A values and all Lanczos vectors in FP32 (FP64 alpha/beta, dots, eigensolve)",
     "c2_arn": "the 64^3 problem of c2 with the unfactored T = degree-8 Chebyshev approximation of (L+I)^-1 "
               "and the Arnoldi estimator (Algorithm 4), m=256, k=30, FP64",
+    "c2_blk": "the 64^3 problem of c2 in the block-Lanczos form: blocks of 16 probes, one block "
+              "Lanczos process per block (MFMA f64 dots and updates, Cholesky QR twice), block Gauss "
+              "rule, m=256, k=30, FP64",
     "c5": "3D 7-pt 96^3 CSR + 32 Gaussian wells (seed 1), Chebyshev M, erf-smoothed count w=0.05, [-8,-2], m=128, k=30",
     "t1": "Table 1 Laplace: (1/h^2) 2D 5-pt Laplacian, h=2^-7 (127x127, n=16129), n_(A-3000I), "
           "ILDL(1e-6) preconditioner with |D| (library factorization, 2x2 pivots), m=50, k=6, FP64",
@@ -76,6 +79,8 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
     threads = oracle.host_threads()
     m = V.shape[1]
     done, t_tot, batch = 0, 0.0, max(1, min(threads, m))
+    if wl.method == "block":
+        batch = 16
     worst = 0.0
     while done < m:
         s = min(batch, m - done)
@@ -83,6 +88,9 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
         if wl.method == "arnoldi":
             ref = oracle.count_arnoldi(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
                                        nthreads=threads)
+        elif wl.method == "block":
+            ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
+                                     nthreads=threads)
         else:
             ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
                                nthreads=threads, smooth_w=wl.smooth_w)
@@ -97,6 +105,8 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
             break
         per = t_tot / done
         batch = max(1, min(m - done, int((target_s - t_tot) / per) + 1, 4 * threads))
+        if wl.method == "block":   # whole blocks of 16 probes
+            batch = min(m - done, max(16, (batch + 15) // 16 * 16))
     steps = 2 * done * wl.k
     out = {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
            "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
@@ -379,7 +389,10 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
-FAMILY_OF = [("k_ldl_solve", "op_ldl_solve"), ("k_ldl_eapply", "op_ldl_elementwise"),
+FAMILY_OF = [("k_blk_update<1, true>", "blk_normalize"), ("k_blk_update", "blk_update"),
+             ("k_blk_dots_fin", "lz_finalize"), ("k_blk_norm_fin", "lz_finalize"),
+             ("k_blk_dots", "blk_dots"), ("k_blk_quad", "blk_quadrature"),
+             ("k_ldl_solve", "op_ldl_solve"), ("k_ldl_eapply", "op_ldl_elementwise"),
              ("k_ldl_permute", "op_ldl_elementwise"), ("k_ldl_band", "lz_setup"),
              ("k_ldl_eblocks", "lz_setup"),
              ("k_quad_sweep", "op_cheb_quad"), ("k_arn_quad", "quadrature"),
@@ -528,7 +541,8 @@ def main():
     max_cols = wl.m if wl.name == "c3" else 0
     tune, tuned = None, None
     arn = wl.method == "arnoldi"
-    if not grad and not arn and args.tune != "off":
+    blk = wl.method == "block"
+    if not grad and not arn and not blk and args.tune != "off":
         from paper_1602_02306_amd import autotune
         free, _total = torch.cuda.mem_get_info()
         cfg = autotune.tune_count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec,
@@ -542,6 +556,8 @@ def main():
         need = ec.smooth_workspace_bytes(wl.n, wl.m, P.prec, wl.k, wl.smooth_w)
     elif arn:
         need = ec.arnoldi_workspace_bytes(wl.n, wl.m, P.prec, wl.k, vec=vec, max_cols=max_cols)
+    elif blk:
+        need = ec.block_workspace_bytes(wl.n, wl.m, P.prec, wl.k, max_cols=max_cols)
     else:
         need = ec.workspace_bytes(wl.n, wl.m, S, P.prec, wl.k, vec=vec, smooth_w=wl.smooth_w,
                                   max_cols=max_cols)
@@ -553,6 +569,9 @@ def main():
         if arn:
             return ec.count_arnoldi(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws,
                                     details=False, max_cols=max_cols)
+        if blk:
+            return ec.count_block(A, P.prec, wl.xi, wl.eta, Vd, wl.k, workspace=ws, details=False,
+                                  max_cols=max_cols)
         if not grad:
             return ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, smooth_w=wl.smooth_w,
                             workspace=ws, details=False, max_cols=max_cols, tune=tune)
@@ -615,7 +634,7 @@ def main():
     if os.path.exists(gpath):
         golden = json.load(open(gpath))
         # the FP32 storage form of a problem has the problem's exact count
-        base = wl.name.replace("_f32", "").replace("_arn", "")
+        base = wl.name.replace("_f32", "").replace("_arn", "").replace("_blk", "")
         exact = golden.get(wl.name, golden.get(base, {})).get("count")
     accuracy = {"estimate": r.estimate, "std_error": math.sqrt(r.variance) if r.variance == r.variance else None,
                 "exact_count": exact, "method_exact": "LDL^T Sylvester inertia" if exact is not None else None,
@@ -679,6 +698,9 @@ def main():
         if arn:
             rd = ec.count_arnoldi(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws,
                                   details=True, max_cols=max_cols)
+        elif blk:
+            rd = ec.count_block(A, P.prec, wl.xi, wl.eta, Vd, wl.k, workspace=ws, details=True,
+                                max_cols=max_cols)
         else:
             rd = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws, details=True,
                           max_cols=max_cols, tune=tune)

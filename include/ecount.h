@@ -290,6 +290,35 @@ ECNT_API ecnt_status ecnt_count_arnoldi(const ecnt_csr *A, const ecnt_prec *T, d
                                         void *stream, double *estimate, double *variance,
                                         ecnt_info *info);
 
+/* ---- Block-Lanczos form of the estimator (blocks of 16 probes) ----
+ *
+ * Not in the paper: the probe block is taken 16 columns at a time and each
+ * block V_b runs one block Lanczos process on C = M (A - tau I) M^* (the
+ * recurrence of Algorithm 1 with 16 x 16 blocks, one classical Gram-Schmidt
+ * pass against the whole basis per step).  The block Gauss rule gives
+ *   V_b^T h(C) V_b ~ R_0^T E_1^T h(T_k) E_1 R_0,   V_b = Q_1 R_0,
+ * T_k the block-tridiagonal matrix of order 16 k; its diagonal entries are the
+ * per-probe values s_j of eq. rand_prec_quad (Section 3.2), which with one
+ * column per block is eq. gauss_quad itself.  A block stops early (k_used)
+ * when a new block of the basis is numerically rank deficient: the smallest
+ * diagonal entry of B_{i+1} is <= 1e3 eps times the largest entry of the
+ * earlier A_i, B_i.  Same arguments and outputs as ecnt_count with: FP64
+ * probes (opts.vec_type = ECNT_F64), m and opts.max_cols (if set) multiples
+ * of 16, opts.rule = ECNT_RULE_GAUSS and k <= 32 (else ECNT_EINVAL or
+ * ECNT_EUNSUPPORTED); any preconditioner kind.  With 16 k > n the block
+ * Krylov space is exhausted and every block stops by then (k_used).  info->alpha /
+ * info->beta are not written; info->per_probe and info->k_used (the block's
+ * k_used for each of its columns, 0 if the probe block itself is rank
+ * deficient) are. */
+ECNT_API size_t ecnt_block_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T,
+                                           const ecnt_opts *opts);
+
+ECNT_API ecnt_status ecnt_count_block(const ecnt_csr *A, const ecnt_prec *T, double xi,
+                                      double eta, const void *probes, int64_t m,
+                                      const ecnt_opts *opts, void *ws, size_t ws_bytes,
+                                      void *stream, double *estimate, double *variance,
+                                      ecnt_info *info);
+
 /* ---- Batches of independent problems ----
  *
  * Many small problems (each its own A_b, shifts and probe block) run as one

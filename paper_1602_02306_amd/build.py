@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libecount.so")
 SOURCES = ["ecount_api.hip", "k_operator.hip", "k_lanczos.hip", "k_quad.hip", "k_backward.hip", "k_arnoldi.hip",
-           "ildl_factor.hip", "k_ldl.hip"]
+           "ildl_factor.hip", "k_ldl.hip", "k_block.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

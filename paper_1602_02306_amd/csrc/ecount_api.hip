@@ -18,11 +18,13 @@ namespace ecnt {
 
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
-              F_VGRAD, F_CHEB2, F_LDL, F_LDLE, F_COUNT };
+              F_VGRAD, F_CHEB2, F_LDL, F_LDLE, F_BKDOTS, F_BKUPD, F_BKNORM, F_BKQUAD,
+              F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
                                            "bw_update", "bw_vgrad", "op_cheb_quad",
-                                           "op_ldl_solve", "op_ldl_elementwise"};
+                                           "op_ldl_solve", "op_ldl_elementwise", "blk_dots",
+                                           "blk_update", "blk_normalize", "blk_quadrature"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -148,6 +150,27 @@ size_t plan_layout(Plan &p, char *base)
     if (p.arnoldi) {
         const size_t k = p.k;
         p.H = (double *)take(sizeof(double) * k * (k + 1) * NC);
+    }
+    if (p.block) {
+        // row chunks of the block reductions: about 8192 wavefronts, 16-row tiles
+        p.nblk = p.wave_cols / kBlk;
+        const int64_t tiles = (p.n + 15) / 16;
+        int64_t nch = (8192 + p.nblk - 1) / p.nblk;
+        if (nch > tiles) nch = tiles;
+        if (nch < 1) nch = 1;
+        p.bk_rpc = ((p.n + nch - 1) / nch + 15) / 16 * 16;
+        p.bk_nchunk = (int)((p.n + p.bk_rpc - 1) / p.bk_rpc);
+        const size_t mat = sizeof(double) * 256 * (size_t)p.nblk;
+        p.bk_part = (double *)take(mat * (size_t)p.bk_nchunk * kBlkChunk);
+        p.bk_S = (double *)take(mat * (p.k + 1));
+        p.bk_K = (double *)take(mat * p.k);
+        p.bk_A = (double *)take(mat * p.k);
+        p.bk_B = (double *)take(mat * (p.k + 1));
+        p.bk_R0 = (double *)take(mat);
+        p.bk_R1 = (double *)take(mat);
+        p.bk_T = (double *)take(mat);
+        p.bk_rm = (double *)take(sizeof(double) * p.nblk);
+        p.bk_act = (int32_t *)take(sizeof(int32_t) * p.nblk);
     }
     if (p.grad) {
         const size_t k = p.k, C = p.wave_cols;
@@ -591,14 +614,15 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
         Plan w = p;
         w.c_off = c_off;
         w.C = (p.Ct - c_off) < p.wave_cols ? (p.Ct - c_off) : p.wave_cols;
+        if (w.block) w.nblk = w.C / kBlk;   // whole blocks: m and wave_cols are multiples of kBlk
         col_geometry(w);
         enqueue_wave(w, A, probes, st);
         // diagnostics of a single problem: alpha/beta of this wave into the caller's arrays
-        if (p.nseg == 1 && !p.arnoldi && info && info->alpha)
+        if (p.nseg == 1 && !p.arnoldi && !p.block && info && info->alpha)
             (void)hipMemcpy2DAsync(info->alpha + c_off, sizeof(double) * p.Ct, w.alpha,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k,
                                    hipMemcpyDeviceToDevice, st);
-        if (p.nseg == 1 && !p.arnoldi && info && info->beta)
+        if (p.nseg == 1 && !p.arnoldi && !p.block && info && info->beta)
             (void)hipMemcpy2DAsync(info->beta + c_off, sizeof(double) * p.Ct, w.beta,
                                    sizeof(double) * w.C, sizeof(double) * w.C, p.k + 1,
                                    hipMemcpyDeviceToDevice, st);
@@ -662,6 +686,106 @@ static void enqueue_wave_arnoldi(const Plan &p, const ecnt_csr *A, const void *p
     launch_arn_quad(p, st);
 }
 
+// y = C x = M (A - tau I) M^* x on the columns of the wave, x = xs .* X (xs may
+// be null).  Step i only matters to the differentiated form, which keeps M q_i.
+static void apply_op(const Plan &p, const ecnt_csr *A, void *x, const double *xs, void *y, int i,
+                     hipStream_t st)
+{
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
+    const size_t blk = (size_t)p.n * p.C * (p.vec_f32 ? 4 : 8);
+    const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
+    // factor bytes a triangular solve streams (the band rows of one triangle)
+    // and an elementwise pass (|D|^{-1/2} blocks and D's structure, or P)
+    const double ldl_b = p.prec_kind == ECNT_PREC_LDL ? 8.0 * ldl_ring_rows() * p.S * p.n : 0.0;
+    const double ldle_b = p.prec_kind == ECNT_PREC_LDL ? 24.0 * p.S * p.n : 0.0;
+    if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
+        // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
+        void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * blk : p.tmp[2];
+        apply_M(p, x, xs, p.tmp[0], p.tmp[1], t, t, false, st);
+        {
+            Timed tm(F_CSR, 2 * blk_b + csr_b, st);
+            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, t, nullptr, nullptr, p.tmp[0], st);
+        }
+        apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
+    } else if (p.prec_kind == ECNT_PREC_LDL) {
+        // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
+        // y = M u = |D|^{-1/2} (L^{-1} (P u))
+        auto elem = [&](int what, const void *in, const double *sc, void *out) {
+            Timed tm(F_LDLE, 2 * blk_b + ldle_b, st);
+            launch_ldl(p, what, in, sc, out, st);
+        };
+        auto solve = [&](int what, const void *in, void *out) {
+            Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
+            launch_ldl(p, what, in, nullptr, out, st);
+        };
+        elem(0, x, xs, p.tmp[0]);
+        solve(2, p.tmp[0], p.tmp[1]);
+        elem(4, p.tmp[1], nullptr, p.tmp[0]);
+        {
+            Timed tm(F_CSR, 2 * blk_b + csr_b, st);
+            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[0], nullptr, nullptr, p.tmp[1], st);
+        }
+        elem(3, p.tmp[1], nullptr, p.tmp[0]);
+        solve(1, p.tmp[0], p.tmp[1]);
+        elem(0, p.tmp[1], nullptr, y);
+    } else {
+        Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
+        launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,
+                      p.prec_kind == ECNT_PREC_JACOBI ? p.jac : nullptr, y, st);
+    }
+}
+
+// One wave of columns in the block-Lanczos form (blocks of kBlk columns):
+// orthonormalize every probe block (two Cholesky QR passes), then k block
+// steps, each one Gram-Schmidt pass against the whole basis followed by two
+// Cholesky QR passes; then the block Gauss rule of every block.
+static void enqueue_wave_block(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st)
+{
+    const double blk_b = block_bytes(p);
+    {
+        Timed t(F_SETUP, blk_b + (double)p.n * p.C * 8 / p.S, st);
+        launch_setup(p, probes, st);
+    }
+    auto dots = [&](int l0, int nb, int ys) {
+        Timed t(F_BKDOTS, (nb + 1) * blk_b, st);
+        launch_blk_dots(p, l0, nb, ys, st);
+    };
+    auto normalize = [&](int ws) {
+        Timed t(F_BKNORM, 2 * blk_b, st);
+        launch_blk_normalize(p, ws, st);
+    };
+    auto fin = [&](int mode, int step) {
+        Timed t(F_FIN, 0.0, st);
+        launch_blk_norm_fin(p, mode, step, st);
+    };
+    dots(0, 1, 0);
+    fin(2, 0);
+    normalize(0);
+    fin(3, 0);
+    const size_t blk = (size_t)p.n * p.C * 8;
+    char *basis = (char *)p.basis;
+    for (int i = 1; i <= p.k; ++i) {
+        apply_op(p, A, basis + (size_t)(i - 1) * blk, nullptr, basis + (size_t)i * blk, i, st);
+        for (int l0 = 0; l0 < i; l0 += kBlkChunk) {
+            const int nb = (i - l0) < kBlkChunk ? (i - l0) : kBlkChunk;
+            dots(l0, nb, i);
+            Timed t(F_FIN, 0.0, st);
+            launch_blk_dots_fin(p, l0, nb, i - 1, st);
+        }
+        for (int l0 = 0; l0 < i; l0 += kBlkChunk) {
+            const int nb = (i - l0) < kBlkChunk ? (i - l0) : kBlkChunk;
+            Timed t(F_BKUPD, (nb + 2) * blk_b, st);
+            launch_blk_update(p, l0, nb, i, l0 + kBlkChunk >= i, st);
+        }
+        fin(0, i);
+        normalize(i);
+        fin(1, i);
+    }
+    Timed t(F_BKQUAD, 0.0, st);
+    launch_blk_quad(p, st);
+}
+
 // One wave of columns: Algorithm 1 on every column, then the quadrature.
 static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, hipStream_t st)
 {
@@ -669,8 +793,11 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         enqueue_wave_arnoldi(p, A, probes, st);
         return;
     }
+    if (p.block) {
+        enqueue_wave_block(p, A, probes, st);
+        return;
+    }
     const double blk_b = block_bytes(p);
-    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
     {
         Timed t(F_SETUP, blk_b + (double)p.n * p.C * (p.vec_f32 ? 4 : 8) / p.S, st);
         launch_setup(p, probes, st);
@@ -682,50 +809,11 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
     const size_t bv = p.vec_f32 ? 4 : 8;
     const size_t blk = (size_t)p.n * p.C * bv;
     char *basis = (char *)p.basis;
-    const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
-    // factor bytes a triangular solve streams (the band rows of one triangle)
-    // and an elementwise pass (|D|^{-1/2} blocks and D's structure, or P)
-    const double ldl_b = p.prec_kind == ECNT_PREC_LDL ? 8.0 * ldl_ring_rows() * p.S * p.n : 0.0;
-    const double ldle_b = p.prec_kind == ECNT_PREC_LDL ? 24.0 * p.S * p.n : 0.0;
     for (int i = 1; i <= p.k; ++i) {
         void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
         void *y = basis + (size_t)i * blk;         // slot i receives C q_i
         const double *xs = p.sig + (size_t)(i - 1) * p.nseg * p.C;
-        if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
-            // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
-            void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * blk : p.tmp[2];
-            apply_M(p, x, xs, p.tmp[0], p.tmp[1], t, t, false, st);
-            {
-                Timed tm(F_CSR, 2 * blk_b + csr_b, st);
-                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, t, nullptr, nullptr, p.tmp[0], st);
-            }
-            apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
-        } else if (p.prec_kind == ECNT_PREC_LDL) {
-            // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
-            // y = M u = |D|^{-1/2} (L^{-1} (P u))
-            auto elem = [&](int what, const void *in, const double *sc, void *out) {
-                Timed tm(F_LDLE, 2 * blk_b + ldle_b, st);
-                launch_ldl(p, what, in, sc, out, st);
-            };
-            auto solve = [&](int what, const void *in, void *out) {
-                Timed tm(F_LDL, 2 * blk_b + ldl_b, st);
-                launch_ldl(p, what, in, nullptr, out, st);
-            };
-            elem(0, x, xs, p.tmp[0]);
-            solve(2, p.tmp[0], p.tmp[1]);
-            elem(4, p.tmp[1], nullptr, p.tmp[0]);
-            {
-                Timed tm(F_CSR, 2 * blk_b + csr_b, st);
-                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.tmp[0], nullptr, nullptr, p.tmp[1], st);
-            }
-            elem(3, p.tmp[1], nullptr, p.tmp[0]);
-            solve(1, p.tmp[0], p.tmp[1]);
-            elem(0, p.tmp[1], nullptr, y);
-        } else {
-            Timed t(F_CSR, 2 * blk_b + csr_b + jac_b, st);
-            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs,
-                          p.prec_kind == ECNT_PREC_JACOBI ? p.jac : nullptr, y, st);
-        }
+        apply_op(p, A, x, xs, y, i, st);
         const int sm = i >= 2 ? i - 2 : -1;
         for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
             const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;
@@ -894,6 +982,23 @@ static ecnt_status arnoldi_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, cons
     return single_segment(p, sh, taus);
 }
 
+// The block-Lanczos form: FP64, one problem, probes in blocks of kBlk
+// (m and the wave width multiples of kBlk), Gauss rule, k <= kBlkMaxK.
+static ecnt_status block_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, const ecnt_prec *T,
+                              const ecnt_opts *o, const double *taus)
+{
+    ecnt_status rc = make_plan(p, n, m, 2, T, o);
+    if (rc) return rc;
+    if (o->vec_type != ECNT_F64) return fail(ECNT_EUNSUPPORTED, "the block form needs FP64 vectors");
+    if (o->rule != ECNT_RULE_GAUSS) return fail(ECNT_EUNSUPPORTED, "the block form has no GA rule");
+    if (m % kBlk != 0) return fail(ECNT_EINVAL, "the block form needs m a multiple of %d (got %lld)", kBlk, (long long)m);
+    if (p.wave_cols % kBlk != 0)
+        return fail(ECNT_EINVAL, "the block form needs opts.max_cols a multiple of %d", kBlk);
+    if (o->k > kBlkMaxK) return fail(ECNT_EUNSUPPORTED, "the block form needs k <= %d", kBlkMaxK);
+    p.block = 1;
+    return single_segment(p, sh, taus);
+}
+
 static void begin_launches()
 {
     (void)hipGetLastError();
@@ -915,6 +1020,8 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
         if (!rc) rc = single_segment(p, sh, taus);
     } else if (mode == 4) {
         rc = arnoldi_plan(p, sh, A ? A->n : 0, m, T, o, taus);
+    } else if (mode == 5) {
+        rc = block_plan(p, sh, A ? A->n : 0, m, T, o, taus);
     } else {
         rc = grad_plan(p, sh, A ? A->n : 0, m, T, o, taus);
     }
@@ -1074,6 +1181,39 @@ ecnt_status ecnt_count_arnoldi(const ecnt_csr *A, const ecnt_prec *T, double xi,
         info->neg_xi = res[0];
         info->neg_eta = res[1];
         info->min_abs_ritz = INFINITY;
+    }
+    return ECNT_OK;
+}
+
+size_t ecnt_block_workspace_bytes(int64_t n, int64_t m, const ecnt_prec *T, const ecnt_opts *opts)
+{
+    Plan p;
+    SegHost sh;
+    const double taus[2] = {0.0, 1.0};
+    if (block_plan(p, sh, n, m, T, opts, taus) != ECNT_OK) return 0;
+    return p.bytes;
+}
+
+ecnt_status ecnt_count_block(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                             const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
+                             size_t ws_bytes, void *stream, double *estimate, double *variance,
+                             ecnt_info *info)
+{
+    g_err.clear();
+    if (!estimate || !variance) return fail(ECNT_EINVAL, "estimate/variance output is null");
+    if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
+    if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
+    const double taus[2] = {xi, eta};
+    double res[kResStride];
+    Plan p;
+    ecnt_status rc = run(A, T, taus, 2, probes, m, opts, ws, ws_bytes, stream, res, info, p, 5);
+    if (rc) return rc;
+    *estimate = res[2];
+    *variance = res[3];
+    if (info) {
+        info->neg_xi = res[0];
+        info->neg_eta = res[1];
+        info->min_abs_ritz = res[4];
     }
     return ECNT_OK;
 }

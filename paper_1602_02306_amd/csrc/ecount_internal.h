@@ -28,6 +28,9 @@ constexpr int kColTile = 64;       // columns per wavefront (one lane per column
 constexpr int kBasisChunk = 32;    // basis vectors per reorthogonalization launch
 constexpr int kMaxShifts = 64;
 constexpr int kMaxK = 512;
+constexpr int kBlk = 16;           // probe columns per block of the block-Lanczos form
+constexpr int kBlkMaxK = 32;       // block-Lanczos steps (T_k of order <= 512)
+constexpr int kBlkChunk = 8;       // basis blocks per block reorthogonalization launch
 
 // One shift's factor of the LDL preconditioner (device pointers).
 struct LdlDev {
@@ -103,6 +106,21 @@ struct Plan {
     // ---- Arnoldi estimator for an unfactored T (one problem) ----
     int arnoldi = 0;
     double *H = nullptr;       // k x (k+1) x NC: H[(l*(k+1) + i)*NC + vc] = h_{i+1,l+1}
+    // ---- block-Lanczos form: blocks of kBlk columns, FP64, one problem ----
+    int block = 0;
+    int nblk = 0;              // column blocks of a wave (wave_cols / kBlk)
+    int bk_nchunk = 0;         // row chunks of the block reductions
+    int64_t bk_rpc = 0;        // rows per chunk, a multiple of 16
+    double *bk_part = nullptr; // bk_nchunk * kBlkChunk * nblk * 256 partial 16 x 16 sums
+    double *bk_S = nullptr;    // (k+1) * nblk * 256: S_l (Q_l = X_l S_l)
+    double *bk_K = nullptr;    // k * nblk * 256: -K_l in MFMA operand order
+    double *bk_A = nullptr;    // k * nblk * 256: A_1..A_k
+    double *bk_B = nullptr;    // (k+1) * nblk * 256: B[i] = B_{i+1}
+    double *bk_R0 = nullptr;   // nblk * 256
+    double *bk_R1 = nullptr;   // nblk * 256: first Cholesky factor of the current step
+    double *bk_T = nullptr;    // nblk * 256: normalizing transform, operand order
+    double *bk_rm = nullptr;   // nblk: largest |entry| of the A_i, B_i so far
+    int32_t *bk_act = nullptr; // nblk
     // ---- differentiated form (smoothed count), single wave, FP64 ----
     int grad = 0;
     void *g_tslots = nullptr;  // k blocks: M q_i of every forward step
@@ -170,6 +188,14 @@ void launch_bupdate(const Plan &p, int i, bool first, hipStream_t st);
 void launch_bnorm_fin(const Plan &p, int i, hipStream_t st);
 void launch_vgrad(const Plan &p, const double *tq, bool first, hipStream_t st);
 void launch_grad_out(const Plan &p, double *dV, hipStream_t st);
+
+// block-Lanczos form (k_block.hip); slots are basis slot indices
+void launch_blk_dots(const Plan &p, int l0, int nb, int ys, hipStream_t st);
+void launch_blk_dots_fin(const Plan &p, int l0, int nb, int icur, hipStream_t st);
+void launch_blk_update(const Plan &p, int l0, int nb, int ws, bool last, hipStream_t st);
+void launch_blk_normalize(const Plan &p, int ws, hipStream_t st);
+void launch_blk_norm_fin(const Plan &p, int mode, int step, hipStream_t st);
+void launch_blk_quad(const Plan &p, hipStream_t st);
 
 // LDL preconditioner: |D|^{-1/2} blocks and band form of every shift's
 // factor; on the columns of the current wave (X and Y distinct):

@@ -136,6 +136,10 @@ def load():
         lib.ecnt_arnoldi_workspace_bytes.argtypes = lib.ecnt_smooth_workspace_bytes.argtypes
         lib.ecnt_count_arnoldi.restype = ctypes.c_int32
         lib.ecnt_count_arnoldi.argtypes = lib.ecnt_count.argtypes
+        lib.ecnt_block_workspace_bytes.restype = ctypes.c_size_t
+        lib.ecnt_block_workspace_bytes.argtypes = lib.ecnt_smooth_workspace_bytes.argtypes
+        lib.ecnt_count_block.restype = ctypes.c_int32
+        lib.ecnt_count_block.argtypes = lib.ecnt_count.argtypes
         lib.ecnt_profile_enable.restype = ctypes.c_int32
         lib.ecnt_ildl_factor.restype = ctypes.c_int32
         lib.ecnt_ildl_factor.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_double, ctypes.c_double,
@@ -433,6 +437,40 @@ def count_arnoldi(A: DeviceCSR, T, xi: float, eta: float, probes, k: int, vec: s
                                 probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
                                 _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
                                 ctypes.byref(info))
+    _check(rc)
+    return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
+                       keep.get("per_probe"), keep.get("k_used"))
+
+
+def block_workspace_bytes(n: int, m: int, prec, k: int, smooth_w: float = 0.0, max_cols: int = 0,
+                          eval: str = "auto") -> int:
+    ps, _coef = prec_struct(prec, eval)
+    o = opts_struct(k, "f64", "gauss", smooth_w, max_cols, None)
+    return int(load().ecnt_block_workspace_bytes(int(n), int(m), ctypes.byref(ps), ctypes.byref(o)))
+
+
+def count_block(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, smooth_w: float = 0.0,
+                workspace: Workspace | None = None, stream=None, details: bool = True,
+                eval: str = "auto", max_cols: int = 0) -> CountResult:
+    """Interval count with the block-Lanczos form (ecnt_count_block): probes
+    in blocks of 16 columns (m a multiple of 16), FP64, k <= 32."""
+    lib = load()
+    n, m = probes.shape
+    _check_factors(prec, 2)
+    ps, _coef = prec_struct(prec, eval)
+    o = opts_struct(k, "f64", "gauss", smooth_w, max_cols, None)
+    need = lib.ecnt_block_workspace_bytes(n, m, ctypes.byref(ps), ctypes.byref(o))
+    ws = (workspace or Workspace(max(need, 1), probes.device)).ensure(need)
+    info, keep = _info(2 * m, k, details, probes.device)
+    if details:
+        info.alpha = None
+        info.beta = None
+    est, var = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    rc = lib.ecnt_count_block(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                              probes.data_ptr(), m, ctypes.byref(o), ws.buf.data_ptr(), ws.nbytes,
+                              _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
+                              ctypes.byref(info))
     _check(rc)
     return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
                        keep.get("per_probe"), keep.get("k_used"))

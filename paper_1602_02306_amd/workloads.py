@@ -301,6 +301,7 @@ class Workload:
     vec: str = "f64"        # storage type of A values and Lanczos vectors
     smooth_w: float = 0.0   # width of the erf-smoothed step (0: the paper's step)
     method: str = "lanczos" # 'lanczos' (Algorithm 2 on M(A - tau I)M) | 'arnoldi' (Algorithm 4 on T(A - tau I))
+                            # | 'block' (block Lanczos on blocks of 16 probes, block Gauss rule)
     scale: float = 1.0      # A = scale * L + diag(potential)
     droptol: float = 0.0    # ILDL drop tolerance (prec 'ildl')
     taus: tuple = ()        # non-empty: the workload is n_(A - tau I) at these shifts
@@ -322,6 +323,9 @@ WORKLOADS = {
     # the 64^3 problem with the unfactored T = c8(L+I) ~ (L+I)^-1 and the Arnoldi estimator
     "c2_arn": Workload("c2_arn", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb_inv", 256, 30,
                        method="arnoldi"),
+    # the 64^3 problem of c2 in the block-Lanczos form (blocks of 16 probes)
+    "c2_blk": Workload("c2_blk", (64, 64, 64), "wells", 1, -8.0, -2.0, "cheb", 256, 30,
+                       method="block"),
     # 96^3, erf-smoothed count of width 0.05, 128 probes
     "c5": Workload("c5", (96, 96, 96), "wells", 1, -8.0, -2.0, "cheb", 128, 30, smooth_w=0.05),
     # small cases that the oracle finishes in seconds

@@ -1,0 +1,124 @@
+"""GPU parity of the block-Lanczos form (blocks of 16 probes, block Gauss
+rule) against the block oracle on the same seeded probes.
+
+The GPU orthonormalizes each block by Cholesky QR applied twice and keeps the
+basis as X_l with Q_l = X_l S_l; the oracle uses Householder QR with a
+positive diagonal.  Both give the same basis up to rounding (the positive-
+diagonal QR is unique), so the tolerances are those of the Lanczos parity
+tests: the estimate within 1e-10 * max(|ref|, 1) and every per-probe value
+within 1e-10 * n (= |v_j|^2 for sign probes).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1602_02306_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ec():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1602_02306_amd import ecount
+    ecount.load()
+    return ecount
+
+
+def prec_of(kind, dims):
+    if kind == "cheb":
+        return W.cheb_invsqrt_prec(dims)
+    return W.PrecSpec(kind, ())
+
+
+def run(ec, A, prec, xi, eta, V, k, **kw):
+    Ad = ec.upload_csr(A)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).to("cuda", torch.float64)
+    return ec.count_block(Ad, prec, xi, eta, Vd, k, **kw)
+
+
+def check(r, ref, n, tol=TOL):
+    s = r.per_probe.cpu().numpy()
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    d = np.max(np.abs(s - s_ref)) / n
+    print("gpu %.15f oracle %.15f | max |ds|/n %.2e" % (r.estimate, ref.estimate, d), flush=True)
+    assert abs(r.estimate - ref.estimate) <= tol * max(1.0, abs(ref.estimate))
+    assert d <= tol
+    assert abs(r.neg_xi - ref.neg_xi) <= tol * n and abs(r.neg_eta - ref.neg_eta) <= tol * n
+
+
+def kused_ref(ref, m):
+    ku = [np.repeat(x.k_used, 16) for x in (ref.lan_xi, ref.lan_eta)]
+    return np.concatenate(ku)
+
+
+@pytest.mark.parametrize("kind", ["cheb", "none", "jacobi"])
+@pytest.mark.parametrize("name", ["c2_small", "c2_ragged"])
+def test_block_parity(ec, name, kind):
+    wl = W.WORKLOADS[name]
+    P = W.make_problem(wl)
+    prec = prec_of(kind, wl.dims) if kind != "cheb" else P.prec
+    V = W.rademacher(P.A.n, 32, 5)
+    print("block parity", name, kind, P.A.n, flush=True)
+    r = run(ec, P.A, prec, wl.xi, wl.eta, V, wl.k)
+    ref = oracle.block_count(P.A, prec, wl.xi, wl.eta, V, wl.k)
+    check(r, ref, P.A.n)
+    assert np.array_equal(r.k_used.cpu().numpy(), kused_ref(ref, 32))
+
+
+def test_block_column_waves_and_basis_chunks(ec):
+    """k = 20 (three launches of at most 8 basis blocks per Gram-Schmidt pass)
+    and column waves of one block each."""
+    wl = W.WORKLOADS["c2_ragged"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 32, 8)
+    ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V, 20)
+    print("block waves/chunks", flush=True)
+    r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, 20)
+    check(r, ref, P.A.n, tol=1e-9)
+    r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, 20, max_cols=16)
+    check(r, ref, P.A.n, tol=1e-9)
+
+
+def test_block_smoothed_step(ec):
+    wl = W.WORKLOADS["c2_small"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 16, 3)
+    ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V, wl.k, smooth_w=0.3)
+    print("block smoothed", flush=True)
+    r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, smooth_w=0.3)
+    check(r, ref, P.A.n)
+
+
+def test_block_exhausted_space_is_exact(ec):
+    """n = 48, identity probes (3 blocks): the fourth residual vanishes,
+    k_used = 3 and the counts are the exact inertias."""
+    wl = W.Workload("t", (4, 4, 3), "wells", 7, -5.0, 1.0, "cheb", 4, 4)
+    P = W.make_problem(wl)
+    n = P.A.n
+    lam = np.sort(np.linalg.eigvalsh(P.A.to_dense()))
+    xi, eta = 0.5 * (lam[5] + lam[6]), 0.5 * (lam[30] + lam[31])
+    V = W.identity_probes(n)
+    print("block exhausted", flush=True)
+    r = run(ec, P.A, P.prec, xi, eta, V, 5)
+    ref = oracle.block_count(P.A, P.prec, xi, eta, V, 5)
+    assert np.all(r.k_used.cpu().numpy() == 3)
+    check(r, ref, n, tol=1e-9)
+    assert abs(r.neg_xi - 6.0) < 1e-8 and abs(r.neg_eta - 31.0) < 1e-8
+    assert abs(r.estimate - 25.0) < 1e-8
+
+
+def test_block_several_tiles_ragged_tail(ec):
+    """30,690 rows (a ragged last tile of 2 rows in each row chunk's grid),
+    4 blocks per shift, k = 10."""
+    wl = W.Workload("b", (33, 31, 30), "wells", 1, -8.0, -2.0, "cheb", 64, 10)
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 64, 21)
+    print("block tiles", P.A.n, flush=True)
+    r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    check(r, ref, P.A.n)
