@@ -23,7 +23,8 @@ Steps for one block (every line a plain numpy operation):
     for i = 1..k:
         W   = C Q_i
         H_l = Q_l^T W,  l = 1..i      (one classical Gram-Schmidt pass
-        W   = W - sum_l Q_l H_l        against the whole basis)
+        W   = W - sum_l Q_l H_l        against the whole basis: two matrix
+                                       products with [Q_1 .. Q_i])
         A_i = (H_i + H_i^T) / 2       (the diagonal block, symmetric part)
         W   = Q_{i+1} B_{i+1}         (QR, diagonal of B_{i+1} positive)
         stop with k_used = i when min diag(B_{i+1}) <= 1e3 eps rm, rm the
@@ -54,8 +55,9 @@ class BlockLanczosResult:
 
 
 def qr_pos(W: np.ndarray):
-    """Thin QR with a non-negative diagonal of R (Householder QR, then signs)."""
-    Q, R = np.linalg.qr(W)
+    """Thin QR with a non-negative diagonal of R (Householder QR, then signs;
+    LAPACK takes the column-major copy without transposing it)."""
+    Q, R = np.linalg.qr(np.asfortranarray(W))
     d = np.sign(np.diag(R))
     d[d == 0] = 1.0
     return Q * d, R * d[:, None]
@@ -78,15 +80,17 @@ def block_lanczos(A, prec, tau: float, V: np.ndarray, k: int, P: int = 16,
     for b in range(nblk):
         Q1, R0 = qr_pos(V[:, b * P:(b + 1) * P])
         R0s[b] = R0
-        Qs = [Q1]
+        Q = np.zeros((n, (k + 1) * P))      # [Q_1 Q_2 ...], block l in columns (l-1)P..lP-1
+        Q[:, :P] = Q1
         rm = 0.0
         kused[b] = k
         for i in range(1, k + 1):
-            W = apply_operator(A, prec, tau, Qs[i - 1], nthreads)
-            H = [Ql.T @ W for Ql in Qs]
-            for Ql, Hl in zip(Qs, H):
-                W = W - Ql @ Hl
-            Ai = 0.5 * (H[i - 1] + H[i - 1].T)
+            Qi = Q[:, :i * P]
+            W = apply_operator(A, prec, tau, Q[:, (i - 1) * P:i * P], nthreads)
+            H = Qi.T @ W                     # stacked H_1..H_i
+            W = W - Qi @ H
+            Hi = H[(i - 1) * P:i * P]
+            Ai = 0.5 * (Hi + Hi.T)
             Qn, Bn = qr_pos(W)
             Ab[b, i - 1] = Ai
             Bb[b, i] = Bn
@@ -96,7 +100,7 @@ def block_lanczos(A, prec, tau: float, V: np.ndarray, k: int, P: int = 16,
             if float(np.min(np.diag(Bn))) <= 1e3 * eps * rm:
                 kused[b] = i
                 break
-            Qs.append(Qn)
+            Q[:, i * P:(i + 1) * P] = Qn
     return BlockLanczosResult(Ab, Bb, R0s, kused)
 
 
