@@ -330,7 +330,10 @@ __global__ __launch_bounds__(256) void k_blk_norm_fin(int mode, int step, int k,
 }
 
 // ---- quadrature: one workgroup (one wavefront) per block ----
-constexpr int kQN = kBlk * kBlkMaxK;   // largest order of T_k
+constexpr int kQMax = kBlk * kBlkMaxK;   // largest order of T_k
+// LDS row stride: one double more than the order, so that lanes walking a row
+// of the band (one diagonal to the next) or the 16 rows of Z hit distinct banks
+constexpr int kQN = kQMax + 1;
 constexpr int kBand = kBlk + 2;         // diagonals kept: 0..16 and the bulge
 
 __device__ __forceinline__ int bidx(int r, int c)
@@ -384,9 +387,12 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
     auto rotate = [&](int p, int t) {
         const int q = p + 1;
         const double x = Lb[bidx(p, t)], y = Lb[bidx(q, t)];
-        const double rr = hypot(x, y);
-        if (rr == 0.0) return;
-        const double c = x / rr, s = y / rr;
+        // |x|, |y| far from the under/overflow range: T_k holds O(|C|) entries
+        const double q2 = x * x + y * y;
+        if (q2 == 0.0) return;
+        const double ir = rsqrt(q2);
+        const double rr = q2 * ir;
+        const double c = x * ir, s = y * ir;
         const int hi = min(N - 1, q + kBlk);
         // reads
         const int xx = t + lane;
@@ -403,7 +409,7 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
             zp = Z[zr * kQN + p];
             zq = Z[zr * kQN + q];
         }
-        __syncthreads();
+        // one wavefront: every lane's reads above are issued before any write below
         if (el) {
             Lb[bidx(p, xx)] = c * u + s * w;
             Lb[bidx(q, xx)] = -s * u + c * w;
@@ -465,43 +471,52 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
         const double den = dh + copysign(hypot(dh, bb0), dh);
         const double mu = A_[hi] - (den != 0.0 ? bb0 * bb0 / den : 0.0);
         double x = A_[lo] - mu, y = B_[lo];
-        if (lo > 0) {
-            __syncthreads();
-            if (lane == 0) B_[lo - 1] = 0.0;
-        }
+        if (lo > 0 && lane == 0) B_[lo - 1] = 0.0;   // the split found above (not read by the sweep)
+        // the values a rotation changes and the next one reads (A[kk], B[kk],
+        // row `lane` of Z at kk) are carried in registers; what it reads ahead
+        // (A[kk+1], B[kk+1], Z at kk+1) is not yet written in this sweep
+        double ak = A_[lo], bk = B_[lo];
+        double zk = lane < kBlk ? Z[lane * kQN + lo] : 0.0;
+        double nbk = bk;
+        double ak1 = A_[lo + 1];
+        double bk1 = lo + 1 < hi ? B_[lo + 1] : 0.0;
+        double z1 = lane < kBlk ? Z[lane * kQN + lo + 1] : 0.0;
         for (int kk = lo; kk < hi; ++kk) {
-            const double r = hypot(x, y);
-            double cs = 1.0, sn = 0.0;
-            if (r > 0.0) {
-                cs = x / r;
-                sn = y / r;
+            // next iteration's operands, loaded before this iteration's writes
+            const double ak2 = kk + 2 <= hi ? A_[kk + 2] : 0.0;
+            const double bk2 = kk + 2 < hi ? B_[kk + 2] : 0.0;
+            const double z2 = (lane < kBlk && kk + 2 <= hi) ? Z[lane * kQN + kk + 2] : 0.0;
+            const double q2 = x * x + y * y;
+            double cs = 1.0, sn = 0.0, r = 0.0;
+            if (q2 > 0.0) {
+                const double ir = rsqrt(q2);
+                r = q2 * ir;
+                cs = x * ir;
+                sn = y * ir;
             }
-            const double ak = A_[kk], ak1 = A_[kk + 1], bk = B_[kk];
-            const double bk1 = kk + 1 < hi ? B_[kk + 1] : 0.0;
-            const double nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-            double z0 = 0.0, z1 = 0.0;
-            if (lane < kBlk) {
-                z0 = Z[lane * kQN + kk];
-                z1 = Z[lane * kQN + kk + 1];
-            }
-            __syncthreads();
+            const double na = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
+            nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
             if (lane == 0) {
                 if (kk > lo) B_[kk - 1] = r;
-                A_[kk] = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
-                A_[kk + 1] = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
-                B_[kk] = nbk;
-                if (kk + 1 < hi) B_[kk + 1] = cs * bk1;
+                A_[kk] = na;
             }
-            if (lane < kBlk) {
-                Z[lane * kQN + kk] = cs * z0 + sn * z1;
-                Z[lane * kQN + kk + 1] = -sn * z0 + cs * z1;
-            }
-            __syncthreads();
-            if (kk + 1 < hi) {
-                y = sn * bk1;
-                x = nbk;
-            }
+            if (lane < kBlk) Z[lane * kQN + kk] = cs * zk + sn * z1;
+            zk = -sn * zk + cs * z1;
+            ak = na1;
+            bk = cs * bk1;
+            x = nbk;
+            y = sn * bk1;
+            ak1 = ak2;
+            bk1 = bk2;
+            z1 = z2;
         }
+        if (lane == 0) {
+            A_[hi] = ak;
+            B_[hi - 1] = nbk;
+        }
+        if (lane < kBlk) Z[lane * kQN + hi] = zk;
+        __syncthreads();
     }
     __syncthreads();
     // F = Z h(Theta) Z^T, then S = R0^T F R0 (diagonal only)

@@ -528,8 +528,8 @@ def profile_enable(on: bool = True):
 
 def profile_read() -> dict:
     """{family: {launches, ms, bytes}} accumulated since profile_enable(True)."""
-    arr = (KernelStatT * 16)()
-    n = load().ecnt_profile_read(arr, 16)
+    arr = (KernelStatT * 64)()
+    n = load().ecnt_profile_read(arr, 64)
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].total_ms),
                                    "bytes": float(arr[i].bytes)} for i in range(n)}
 

@@ -122,3 +122,24 @@ def test_block_several_tiles_ragged_tail(ec):
     r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k)
     ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
     check(r, ref, P.A.n)
+
+
+def test_block_bench_configuration_sampled(ec):
+    """The c2_blk bench configuration (64^3, m = 256, k = 30, both shifts in one
+    wave, default launch shapes): the first probe block against the oracle,
+    per probe and k_used; the estimate is the mean of the per-probe values."""
+    wl = W.WORKLOADS["c2_blk"]
+    P = W.make_problem(wl)
+    Vd = W.rademacher_torch(wl.n, wl.m, wl.probe_seed, device="cuda", dtype=torch.float64)
+    print("block bench configuration", wl.n, wl.m, wl.k, flush=True)
+    r = ec.count_block(ec.upload_csr(P.A), P.prec, wl.xi, wl.eta, Vd, wl.k)
+    s = r.per_probe.cpu().numpy()
+    V0 = Vd[:, :16].cpu().numpy()
+    ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V0, wl.k)
+    d = max(np.max(np.abs(s[:16] - ref.s_xi)), np.max(np.abs(s[wl.m:wl.m + 16] - ref.s_eta))) / wl.n
+    print("sampled block: max |ds|/n %.2e" % d, flush=True)
+    assert d <= TOL
+    ku = r.k_used.cpu().numpy()
+    assert np.all(ku[:16] == ref.lan_xi.k_used[0]) and np.all(ku[wl.m:wl.m + 16] == ref.lan_eta.k_used[0])
+    mean = np.mean(s[wl.m:]) - np.mean(s[:wl.m])
+    assert abs(r.estimate - mean) <= 1e-12 * max(1.0, abs(mean))
