@@ -152,10 +152,11 @@ size_t plan_layout(Plan &p, char *base)
         p.H = (double *)take(sizeof(double) * k * (k + 1) * NC);
     }
     if (p.block) {
-        // row chunks of the block reductions: about 8192 wavefronts, 16-row tiles
+        // row chunks of the block reductions: about 2048 workgroups of 4
+        // wavefronts, 16-row tiles
         p.nblk = p.wave_cols / kBlk;
         const int64_t tiles = (p.n + 15) / 16;
-        int64_t nch = (8192 + p.nblk - 1) / p.nblk;
+        int64_t nch = (2048 + p.nblk - 1) / p.nblk;
         if (nch > tiles) nch = tiles;
         if (nch < 1) nch = 1;
         p.bk_rpc = ((p.n + nch - 1) / nch + 15) / 16 * 16;

@@ -30,7 +30,7 @@ constexpr int kMaxShifts = 64;
 constexpr int kMaxK = 512;
 constexpr int kBlk = 16;           // probe columns per block of the block-Lanczos form
 constexpr int kBlkMaxK = 32;       // block-Lanczos steps (T_k of order <= 512)
-constexpr int kBlkChunk = 8;       // basis blocks per block reorthogonalization launch
+constexpr int kBlkChunk = 32;      // basis blocks per block reorthogonalization launch
 
 // One shift's factor of the LDL preconditioner (device pointers).
 struct LdlDev {

@@ -46,27 +46,36 @@ __device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// ---- G_l = X_l^T Y for slots l0..l0+NB-1 against slot ys, per row chunk ----
-// One wavefront per (row chunk, column block).  MFMA v of a 16-row tile takes
-// rows t0 + 4(l/16) + v: A = X_l (row, column l%16), B = Y (row, column l%16).
-template <int NB>
-__global__ __launch_bounds__(64) void k_blk_dots(int64_t n, int C, int nblk, int64_t rpc,
-                                                 const double *__restrict__ basis, size_t ss,
-                                                 int l0, int ys, double *__restrict__ part)
+// ---- G_l = X_l^T Y for slots l0..l0+nb-1 (nb <= kBlkChunk) against slot ys ----
+// One workgroup of kBlkWaves wavefronts per (row chunk, column block).
+// Wavefront w accumulates the basis blocks l0 + w, l0 + w + 4, ... (at most 8);
+// all four stream the same rows of Y, whose repeated reads hit the caches.
+// MFMA v of a 16-row tile takes rows t0 + 4(lane/16) + v: A = X_l (row,
+// column lane%16), B = Y (row, column lane%16).
+constexpr int kBlkWaves = 4;
+constexpr int kBlkPerWave = kBlkChunk / kBlkWaves;
+
+__global__ __launch_bounds__(64 * kBlkWaves) void k_blk_dots(int64_t n, int C, int nblk, int64_t rpc,
+                                                             const double *__restrict__ basis,
+                                                             size_t ss, int l0, int nb, int ys,
+                                                             double *__restrict__ part)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int blk = (int)(L % nblk);
     const int64_t chunk = L / nblk;
-    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int nw = (nb - wv + kBlkWaves - 1) / kBlkWaves;   // basis blocks of this wavefront
+    if (nw <= 0) return;                                    // (no barrier in this kernel)
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
     const int col = blk * kBlk + li;
     const double *Y = basis + (size_t)ys * ss;
-    const double *X0 = basis + (size_t)l0 * ss;
-    d4_t acc[NB];
+    const double *X0 = basis + (size_t)(l0 + wv) * ss;
+    const size_t xs = (size_t)kBlkWaves * ss;
+    d4_t acc[kBlkPerWave];
 #pragma unroll
-    for (int l = 0; l < NB; ++l) acc[l] = d4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < kBlkPerWave; ++j) acc[j] = d4_t{0.0, 0.0, 0.0, 0.0};
     for (int64_t t0 = r0; t0 < r1; t0 += 16) {
-        double y[4], x[NB][4];
+        double y[4], x[kBlkPerWave][4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = t0 + 4 * lk + v;
@@ -74,50 +83,56 @@ __global__ __launch_bounds__(64) void k_blk_dots(int64_t n, int C, int nblk, int
             const size_t e = (size_t)(ok ? row : r0) * C + col;
             y[v] = ok ? Y[e] : 0.0;
 #pragma unroll
-            for (int l = 0; l < NB; ++l)
-                x[l][v] = ok ? __builtin_nontemporal_load(X0 + (size_t)l * ss + e) : 0.0;
+            for (int j = 0; j < kBlkPerWave; ++j)
+                x[j][v] = (ok && j < nw) ? __builtin_nontemporal_load(X0 + j * xs + e) : 0.0;
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) acc[l] = mfma16(x[l][v], y[v], acc[l]);
+            for (int j = 0; j < kBlkPerWave; ++j)
+                if (j < nw) acc[j] = mfma16(x[j][v], y[v], acc[j]);
     }
 #pragma unroll
-    for (int l = 0; l < NB; ++l)
+    for (int j = 0; j < kBlkPerWave; ++j) {
+        if (j >= nw) break;
+        const int l = wv + kBlkWaves * j;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            part[(((size_t)chunk * NB + l) * nblk + blk) * 256 + (4 * v + lk) * 16 + li] = acc[l][v];
+            part[(((size_t)chunk * nb + l) * nblk + blk) * 256 + (4 * v + lk) * 16 + li] = acc[j][v];
+    }
 }
 
-// ---- Y <- Y - sum_l X_l K_l in place (ZI: Y <- X T with X the slot itself),
-// Gram Y^T Y of the result per row chunk when `last` ----
-// Kop holds -K_l (or T) in B-operand order: for MFMA q, lane l holds
-// K[4(l/16)+q][l%16] at Kop[lane*4 + q]; the A operand of MFMA q is
+// ---- Y <- Y - sum_l X_l K_l in place for l = l0..l0+nb-1 (ZI: Y <- X T with
+// X the slot itself), and the Gram matrix of the result per row chunk when
+// `last` ----
+// One workgroup of kBlkWaves wavefronts per (row chunk, column block); the
+// coefficients (-K_l or T, in B-operand order: for MFMA q, lane l holds
+// K[4(l/16)+q][l%16] at [l*4 + q]) are staged in LDS and the wavefronts take
+// the row chunk's 16-row tiles in turn.  The A operand of MFMA q is
 // X_l[t0 + l%16][4(l/16) + q], so each lane loads 4 consecutive columns.
-template <int NB, bool ZI>
-__global__ __launch_bounds__(64) void k_blk_update(int64_t n, int C, int nblk, int64_t rpc,
-                                                   double *__restrict__ basis, size_t ss, int l0,
-                                                   int ws, const double *__restrict__ Kop,
-                                                   int last, double *__restrict__ part)
+template <bool ZI>
+__global__ __launch_bounds__(64 * kBlkWaves) void k_blk_update(int64_t n, int C, int nblk, int64_t rpc,
+                                                               double *__restrict__ basis, size_t ss,
+                                                               int l0, int nb, int ws,
+                                                               const double *__restrict__ Kop, int last,
+                                                               double *__restrict__ part)
 {
+    extern __shared__ double kl[];   // nb * 256 coefficients
+    __shared__ double gred[kBlkWaves - 1][256];
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int blk = (int)(L % nblk);
     const int64_t chunk = L / nblk;
-    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    for (int e = threadIdx.x; e < nb * 256; e += 64 * kBlkWaves)
+        kl[e] = Kop[((size_t)(l0 + (e >> 8)) * nblk + blk) * 256 + (e & 255)];
+    __syncthreads();
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
     const int col = blk * kBlk + li;
-    double kq[NB][4];
-#pragma unroll
-    for (int l = 0; l < NB; ++l) {
-        const d4_t kv = *reinterpret_cast<const d4_t *>(Kop + ((size_t)(l0 + l) * nblk + blk) * 256 + lane * 4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) kq[l][q] = kv[q];
-    }
     double *W = basis + (size_t)ws * ss;
     const double *X0 = ZI ? W : basis + (size_t)l0 * ss;
     d4_t gram = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t t0 = r0; t0 < r1; t0 += 16) {
+    for (int64_t t0 = r0 + 16 * wv; t0 < r1; t0 += 16 * kBlkWaves) {
         d4_t d = {0.0, 0.0, 0.0, 0.0};
         if (!ZI) {
 #pragma unroll
@@ -129,22 +144,46 @@ __global__ __launch_bounds__(64) void k_blk_update(int64_t n, int C, int nblk, i
         const int64_t ra = t0 + li;
         const bool oka = ra < r1;
         const size_t ea = (size_t)(oka ? ra : r0) * C + blk * kBlk + 4 * lk;
-        double xa[NB][4];
+        // groups of 8 basis blocks; the next group's loads are issued before
+        // the current group's MFMAs
+        double xa[2][8][4];
+        auto load_group = [&](int lg, double (&dst)[8][4]) {
 #pragma unroll
-        for (int l = 0; l < NB; ++l) {
-            const d2_t *src = reinterpret_cast<const d2_t *>(X0 + (size_t)l * ss + ea);
-            d2_t u = ZI ? src[0] : __builtin_nontemporal_load(src);
-            d2_t w = ZI ? src[1] : __builtin_nontemporal_load(src + 1);
-            xa[l][0] = oka ? u[0] : 0.0;
-            xa[l][1] = oka ? u[1] : 0.0;
-            xa[l][2] = oka ? w[0] : 0.0;
-            xa[l][3] = oka ? w[1] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+                d2_t a = {0.0, 0.0}, b = {0.0, 0.0};
+                if (lg + u < nb) {
+                    const d2_t *src = reinterpret_cast<const d2_t *>(X0 + (size_t)(lg + u) * ss + ea);
+                    a = ZI ? src[0] : __builtin_nontemporal_load(src);
+                    b = ZI ? src[1] : __builtin_nontemporal_load(src + 1);
+                }
+                dst[u][0] = oka ? a[0] : 0.0;
+                dst[u][1] = oka ? a[1] : 0.0;
+                dst[u][2] = oka ? b[0] : 0.0;
+                dst[u][3] = oka ? b[1] : 0.0;
+            }
+        };
+        load_group(0, xa[0]);
+        for (int lg = 0; lg < nb; lg += 16) {
+            if (lg + 8 < nb) load_group(lg + 8, xa[1]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (lg + u >= nb) break;
+                const d4_t kv = *reinterpret_cast<const d4_t *>(kl + (lg + u) * 256 + lane * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d = mfma16(xa[0][u][q], kv[q], d);
+            }
+            if (lg + 8 >= nb) break;
+            if (lg + 16 < nb) load_group(lg + 16, xa[0]);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (lg + 8 + u >= nb) break;
+                const d4_t kv = *reinterpret_cast<const d4_t *>(kl + (lg + 8 + u) * 256 + lane * 4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d = mfma16(xa[1][u][q], kv[q], d);
+            }
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int l = 0; l < NB; ++l)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) d = mfma16(xa[l][q], kq[l][q], d);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t row = t0 + 4 * v + lk;
@@ -156,22 +195,41 @@ __global__ __launch_bounds__(64) void k_blk_update(int64_t n, int C, int nblk, i
         }
     }
     if (last) {
+        // the wavefronts' Gram matrices added in wavefront order
+        if (wv > 0)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            part[((size_t)chunk * nblk + blk) * 256 + (4 * v + lk) * 16 + li] = gram[v];
+            for (int v = 0; v < 4; ++v) gred[wv - 1][(4 * v + lk) * 16 + li] = gram[v];
+        __syncthreads();
+        if (wv == 0)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int idx = (4 * v + lk) * 16 + li;
+                double g = gram[v];
+#pragma unroll
+                for (int w = 0; w < kBlkWaves - 1; ++w) g += gred[w][idx];
+                part[((size_t)chunk * nblk + blk) * 256 + idx] = g;
+            }
     }
 }
 
 // ---- small 16 x 16 algebra of one block, one workgroup of 256 threads ----
 // (thread t = element (t/16, t%16)).  Matrices row-major in LDS.
 
-// Sum over the row chunks of a 16 x 16 partial, fixed chunk order.
+// Sum over the row chunks of a 16 x 16 partial: eight running sums over the
+// chunks ch = 8q + u (u = 0..7), added in u order, so the result does not
+// depend on the launch and the loads are not one dependent chain.
 __device__ __forceinline__ double chunk_sum16(const double *__restrict__ part, int nchunk, int NB,
                                               int l, int nblk, int blk, int t)
 {
-    double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[(((size_t)ch * NB + l) * nblk + blk) * 256 + t];
-    return s;
+    const size_t stride = (size_t)NB * nblk * 256;
+    const double *p = part + ((size_t)l * nblk + blk) * 256 + t;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int ch = 0;
+    for (; ch + 8 <= nchunk; ch += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += p[(size_t)(ch + u) * stride];
+    for (int u = 0; ch + u < nchunk; ++u) s[u] += p[(size_t)(ch + u) * stride];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // out = op(a) * b with op(a) = a or a^T; every thread computes its element.
@@ -544,34 +602,11 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
 
 static inline unsigned blk_grid(const Plan &p) { return (unsigned)((int64_t)p.bk_nchunk * p.nblk); }
 
-template <int NB>
-static void blk_dots_t(const Plan &p, int l0, int ys, hipStream_t st)
-{
-    k_blk_dots<NB><<<blk_grid(p), 64, 0, st>>>(p.n, p.C, p.nblk, p.bk_rpc, (const double *)p.basis,
-                                               (size_t)p.n * p.C, l0, ys, p.bk_part);
-}
-
-template <int NB>
-static void blk_update_t(const Plan &p, int l0, int ws, bool last, hipStream_t st)
-{
-    k_blk_update<NB, false><<<blk_grid(p), 64, 0, st>>>(p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis,
-                                                        (size_t)p.n * p.C, l0, ws, p.bk_K,
-                                                        last ? 1 : 0, p.bk_part);
-}
-
 void launch_blk_dots(const Plan &p, int l0, int nb, int ys, hipStream_t st)
 {
-    switch (nb) {
-    case 1: blk_dots_t<1>(p, l0, ys, st); break;
-    case 2: blk_dots_t<2>(p, l0, ys, st); break;
-    case 3: blk_dots_t<3>(p, l0, ys, st); break;
-    case 4: blk_dots_t<4>(p, l0, ys, st); break;
-    case 5: blk_dots_t<5>(p, l0, ys, st); break;
-    case 6: blk_dots_t<6>(p, l0, ys, st); break;
-    case 7: blk_dots_t<7>(p, l0, ys, st); break;
-    case 8: blk_dots_t<8>(p, l0, ys, st); break;
-    default: break;
-    }
+    k_blk_dots<<<blk_grid(p), 64 * kBlkWaves, 0, st>>>(p.n, p.C, p.nblk, p.bk_rpc,
+                                                       (const double *)p.basis, (size_t)p.n * p.C,
+                                                       l0, nb, ys, p.bk_part);
 }
 
 void launch_blk_dots_fin(const Plan &p, int l0, int nb, int icur, hipStream_t st)
@@ -583,23 +618,16 @@ void launch_blk_dots_fin(const Plan &p, int l0, int nb, int icur, hipStream_t st
 
 void launch_blk_update(const Plan &p, int l0, int nb, int ws, bool last, hipStream_t st)
 {
-    switch (nb) {
-    case 1: blk_update_t<1>(p, l0, ws, last, st); break;
-    case 2: blk_update_t<2>(p, l0, ws, last, st); break;
-    case 3: blk_update_t<3>(p, l0, ws, last, st); break;
-    case 4: blk_update_t<4>(p, l0, ws, last, st); break;
-    case 5: blk_update_t<5>(p, l0, ws, last, st); break;
-    case 6: blk_update_t<6>(p, l0, ws, last, st); break;
-    case 7: blk_update_t<7>(p, l0, ws, last, st); break;
-    case 8: blk_update_t<8>(p, l0, ws, last, st); break;
-    default: break;
-    }
+    k_blk_update<false><<<blk_grid(p), 64 * kBlkWaves, sizeof(double) * 256 * nb, st>>>(
+        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, (size_t)p.n * p.C, l0, nb, ws, p.bk_K,
+        last ? 1 : 0, p.bk_part);
 }
 
 void launch_blk_normalize(const Plan &p, int ws, hipStream_t st)
 {
-    k_blk_update<1, true><<<blk_grid(p), 64, 0, st>>>(p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis,
-                                                      (size_t)p.n * p.C, 0, ws, p.bk_T, 1, p.bk_part);
+    k_blk_update<true><<<blk_grid(p), 64 * kBlkWaves, sizeof(double) * 256, st>>>(
+        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, (size_t)p.n * p.C, 0, 1, ws, p.bk_T, 1,
+        p.bk_part);
 }
 
 void launch_blk_norm_fin(const Plan &p, int mode, int step, hipStream_t st)
