@@ -305,7 +305,8 @@ ECNT_API ecnt_status ecnt_count_arnoldi(const ecnt_csr *A, const ecnt_prec *T, d
  * earlier A_i, B_i.  Same arguments and outputs as ecnt_count with: FP64
  * probes (opts.vec_type = ECNT_F64), m and opts.max_cols (if set) multiples
  * of 16, opts.rule = ECNT_RULE_GAUSS and k <= 32 (else ECNT_EINVAL or
- * ECNT_EUNSUPPORTED); any preconditioner kind.  With 16 k > n the block
+ * ECNT_EUNSUPPORTED); M = I, Jacobi or the Laplacian polynomial
+ * (ECNT_PREC_LDL is ECNT_EUNSUPPORTED).  With 16 k > n the block
  * Krylov space is exhausted and every block stops by then (k_used).  info->alpha /
  * info->beta are not written; info->per_probe and info->k_used (the block's
  * k_used for each of its columns, 0 if the probe block itself is rank

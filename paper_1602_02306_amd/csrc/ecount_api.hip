@@ -996,6 +996,8 @@ static ecnt_status block_plan(Plan &p, SegHost &sh, int64_t n, int64_t m, const 
     if (p.wave_cols % kBlk != 0)
         return fail(ECNT_EINVAL, "the block form needs opts.max_cols a multiple of %d", kBlk);
     if (o->k > kBlkMaxK) return fail(ECNT_EUNSUPPORTED, "the block form needs k <= %d", kBlkMaxK);
+    if (T->kind == ECNT_PREC_LDL)
+        return fail(ECNT_EUNSUPPORTED, "the block form takes no LDL preconditioner");
     p.block = 1;
     return single_segment(p, sh, taus);
 }

@@ -28,10 +28,17 @@ def test_block_workspace_rejects(n, m, k, kw):
     assert ec.block_workspace_bytes(n, m, W.PrecSpec("none", ()), k, **kw) == 0
 
 
-def _call(m=32, k=4, vec=0, rule=0, n=4096):
+def _call(m=32, k=4, vec=0, rule=0, n=4096, ldl=False):
     lib = ec.load()
     cs = ec.CsrT(n, 5 * n, 0x3000, 0x4000, 0x5000, 0, 0)
     ps, keep = ec.prec_struct(W.PrecSpec("none", ()))
+    if ldl:
+        f = (ec.LdlFactorT * 2)()
+        for s in range(2):
+            f[s] = ec.LdlFactorT(0x100, 0x200, 0x300, 0x400, 0x500, 0x600, 0, 0, 0)
+        ps.kind = ec.PREC_KINDS["ldl"]
+        ps.ldl = ctypes.cast(f, ctypes.c_void_p)
+        keep = (keep, f)
     o = ec.OptsT(k, vec, rule, 0, 0.0)
     e, v = ctypes.c_double(), ctypes.c_double()
     rc = lib.ecnt_count_block(ctypes.byref(cs), ctypes.byref(ps), 0.0, 1.0, 0x1000, m,
@@ -46,6 +53,7 @@ def _call(m=32, k=4, vec=0, rule=0, n=4096):
     (dict(vec=1), ec.ECNT_EUNSUPPORTED),
     (dict(rule=1), ec.ECNT_EUNSUPPORTED),
     (dict(n=20, k=21), ec.ECNT_EINVAL),
+    (dict(ldl=True), ec.ECNT_EUNSUPPORTED),
 ])
 def test_block_rejected_on_host(kw, code):
     rc, msg = _call(**kw)
