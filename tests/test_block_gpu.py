@@ -143,3 +143,15 @@ def test_block_bench_configuration_sampled(ec):
     assert np.all(ku[:16] == ref.lan_xi.k_used[0]) and np.all(ku[wl.m:wl.m + 16] == ref.lan_eta.k_used[0])
     mean = np.mean(s[wl.m:]) - np.mean(s[:wl.m])
     assert abs(r.estimate - mean) <= 1e-12 * max(1.0, abs(mean))
+
+
+def test_block_ragged_last_column_wave(ec):
+    """m = 48 probes (96 columns) in waves of 64: the last wave holds 2 blocks."""
+    wl = W.WORKLOADS["c2_ragged"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 48, 13)
+    ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    print("block ragged wave", flush=True)
+    r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, max_cols=64)
+    check(r, ref, P.A.n)
+    assert np.array_equal(r.k_used.cpu().numpy(), kused_ref(ref, 48))
