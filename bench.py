@@ -389,7 +389,7 @@ def traffic_from_profiles(family: str, per_launch_algo: float):
     return ent.get("hbm_bytes_per_launch")
 
 
-FAMILY_OF = [("k_blk_update<1, true>", "blk_normalize"), ("k_blk_update", "blk_update"),
+FAMILY_OF = [("k_blk_update<true>", "blk_normalize"), ("k_blk_update", "blk_update"),
              ("k_blk_dots_fin", "lz_finalize"), ("k_blk_norm_fin", "lz_finalize"),
              ("k_blk_dots", "blk_dots"), ("k_blk_quad", "blk_quadrature"),
              ("k_ldl_solve", "op_ldl_solve"), ("k_ldl_eapply", "op_ldl_elementwise"),
