@@ -121,7 +121,8 @@ size_t plan_layout(Plan &p, char *base)
     const size_t blk = (size_t)p.n * p.wave_cols * bv;
     const size_t NC = (size_t)p.nseg * p.wave_cols;   // virtual columns of one wave
     const size_t NCt = (size_t)p.nseg * p.Ct;         // of the whole run
-    p.basis = take(blk * (p.k + 1));
+    const size_t slot = blk + kSlotPadBytes;   // slot stride of the widest wave
+    p.basis = take(slot * (p.k + 1));
     const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : (p.prec_kind == ECNT_PREC_LDL ? 2 : 0);
     for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;
     p.part = (double *)take(sizeof(double) * (size_t)p.nchunk * kPartRows * p.wave_cols);
@@ -175,8 +176,8 @@ size_t plan_layout(Plan &p, char *base)
     }
     if (p.grad) {
         const size_t k = p.k, C = p.wave_cols;
-        p.g_tslots = take(blk * k);
-        p.g_qbar = (double *)take(blk * k);
+        p.g_tslots = take(slot * k);
+        p.g_qbar = (double *)take(slot * k);
         p.g_ybar = (double *)take(blk);
         p.g_tbar = (double *)take(blk);
         p.g_gall = (double *)take(sizeof(double) * k * k * C);
@@ -648,11 +649,11 @@ static void enqueue_wave_arnoldi(const Plan &p, const ecnt_csr *A, const void *p
         Timed t(F_FIN, 0.0, st);
         launch_setup_fin(p, st);
     }
-    const size_t blk = (size_t)p.n * p.C * (p.vec_f32 ? 4 : 8);
+    const size_t slot = slot_bytes(p);
     char *basis = (char *)p.basis;
     for (int j = 1; j <= p.k; ++j) {
-        void *x = basis + (size_t)(j - 1) * blk;   // slot j-1 holds q_j (unnormalized)
-        void *y = basis + (size_t)j * blk;         // slot j receives C q_j
+        void *x = basis + (size_t)(j - 1) * slot;   // slot j-1 holds q_j (unnormalized)
+        void *y = basis + (size_t)j * slot;         // slot j receives C q_j
         const double *xs = p.sig + (size_t)(j - 1) * p.nseg * p.C;
         if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
             {
@@ -694,7 +695,7 @@ static void apply_op(const Plan &p, const ecnt_csr *A, void *x, const double *xs
 {
     const double blk_b = block_bytes(p);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
-    const size_t blk = (size_t)p.n * p.C * (p.vec_f32 ? 4 : 8);
+    const size_t slot = slot_bytes(p);
     const double jac_b = p.prec_kind == ECNT_PREC_JACOBI ? 8.0 * p.S * p.n : 0.0;
     // factor bytes a triangular solve streams (the band rows of one triangle)
     // and an elementwise pass (|D|^{-1/2} blocks and D's structure, or P)
@@ -702,7 +703,7 @@ static void apply_op(const Plan &p, const ecnt_csr *A, void *x, const double *xs
     const double ldle_b = p.prec_kind == ECNT_PREC_LDL ? 24.0 * p.S * p.n : 0.0;
     if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
         // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
-        void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * blk : p.tmp[2];
+        void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * slot : p.tmp[2];
         apply_M(p, x, xs, p.tmp[0], p.tmp[1], t, t, false, st);
         {
             Timed tm(F_CSR, 2 * blk_b + csr_b, st);
@@ -764,10 +765,10 @@ static void enqueue_wave_block(const Plan &p, const ecnt_csr *A, const void *pro
     fin(2, 0);
     normalize(0);
     fin(3, 0);
-    const size_t blk = (size_t)p.n * p.C * 8;
+    const size_t slot = slot_bytes(p);
     char *basis = (char *)p.basis;
     for (int i = 1; i <= p.k; ++i) {
-        apply_op(p, A, basis + (size_t)(i - 1) * blk, nullptr, basis + (size_t)i * blk, i, st);
+        apply_op(p, A, basis + (size_t)(i - 1) * slot, nullptr, basis + (size_t)i * slot, i, st);
         for (int l0 = 0; l0 < i; l0 += kBlkChunk) {
             const int nb = (i - l0) < kBlkChunk ? (i - l0) : kBlkChunk;
             dots(l0, nb, i);
@@ -807,12 +808,11 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         Timed t(F_FIN, 0.0, st);
         launch_setup_fin(p, st);
     }
-    const size_t bv = p.vec_f32 ? 4 : 8;
-    const size_t blk = (size_t)p.n * p.C * bv;
+    const size_t slot = slot_bytes(p);
     char *basis = (char *)p.basis;
     for (int i = 1; i <= p.k; ++i) {
-        void *x = basis + (size_t)(i - 1) * blk;   // slot i-1 holds q_i (unnormalized)
-        void *y = basis + (size_t)i * blk;         // slot i receives C q_i
+        void *x = basis + (size_t)(i - 1) * slot;   // slot i-1 holds q_i (unnormalized)
+        void *y = basis + (size_t)i * slot;         // slot i receives C q_i
         const double *xs = p.sig + (size_t)(i - 1) * p.nseg * p.C;
         apply_op(p, A, x, xs, y, i, st);
         const int sm = i >= 2 ? i - 2 : -1;
@@ -844,7 +844,7 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
 static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, double *dV,
                              hipStream_t st)
 {
-    const size_t blk = (size_t)p.n * p.C * 8;
+    const size_t slot = slot_bytes(p);
     const double blk_b = block_bytes(p);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * 12;
     {
@@ -876,11 +876,11 @@ static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, dou
             Timed t(F_CSR, 2 * blk_b + csr_b, st);
             launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.g_tbar, nullptr, nullptr, p.tmp[2], st);
         }
-        double *qbi = (double *)((char *)p.g_qbar + (size_t)(i - 1) * blk);
+        double *qbi = (double *)((char *)p.g_qbar + (size_t)(i - 1) * slot);
         apply_M(p, p.tmp[2], nullptr, p.tmp[0], p.tmp[1], p.g_ybar, qbi, true, st);
         {
             Timed t(F_VGRAD, 2 * blk_b, st);
-            launch_vgrad(p, (const double *)((char *)p.g_tslots + (size_t)(i - 1) * blk), last, st);
+            launch_vgrad(p, (const double *)((char *)p.g_tslots + (size_t)(i - 1) * slot), last, st);
         }
     }
     Timed t(F_FIN, 0.0, st);

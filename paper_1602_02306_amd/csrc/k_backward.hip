@@ -417,7 +417,7 @@ void launch_tridiag_bwd(const Plan &p, double g_out, hipStream_t st)
 void launch_bdots(const Plan &p, int i, hipStream_t st)
 {
     const int nct = (p.C + 63) / 64;
-    const size_t ss = (size_t)p.n * p.C;
+    const size_t ss = slot_elems(p);
     switch (i + 1) {
 #define ECNT_CASE(N)                                                                             \
     case N:                                                                                      \
@@ -447,7 +447,7 @@ void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st)
 void launch_bupdate(const Plan &p, int i, bool first, hipStream_t st)
 {
     const int nct = (p.C + 63) / 64;
-    const size_t ss = (size_t)p.n * p.C;
+    const size_t ss = slot_elems(p);
     const size_t C = p.C;
     const bool hasq = i < p.k;
     (void)C;

@@ -605,7 +605,7 @@ static inline unsigned blk_grid(const Plan &p) { return (unsigned)((int64_t)p.bk
 void launch_blk_dots(const Plan &p, int l0, int nb, int ys, hipStream_t st)
 {
     k_blk_dots<<<blk_grid(p), 64 * kBlkWaves, 0, st>>>(p.n, p.C, p.nblk, p.bk_rpc,
-                                                       (const double *)p.basis, (size_t)p.n * p.C,
+                                                       (const double *)p.basis, slot_elems(p),
                                                        l0, nb, ys, p.bk_part);
 }
 
@@ -619,14 +619,14 @@ void launch_blk_dots_fin(const Plan &p, int l0, int nb, int icur, hipStream_t st
 void launch_blk_update(const Plan &p, int l0, int nb, int ws, bool last, hipStream_t st)
 {
     k_blk_update<false><<<blk_grid(p), 64 * kBlkWaves, sizeof(double) * 256 * nb, st>>>(
-        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, (size_t)p.n * p.C, l0, nb, ws, p.bk_K,
+        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, slot_elems(p), l0, nb, ws, p.bk_K,
         last ? 1 : 0, p.bk_part);
 }
 
 void launch_blk_normalize(const Plan &p, int ws, hipStream_t st)
 {
     k_blk_update<true><<<blk_grid(p), 64 * kBlkWaves, sizeof(double) * 256, st>>>(
-        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, (size_t)p.n * p.C, 0, 1, ws, p.bk_T, 1,
+        p.n, p.C, p.nblk, p.bk_rpc, (double *)p.basis, slot_elems(p), 0, 1, ws, p.bk_T, 1,
         p.bk_part);
 }
 

@@ -269,7 +269,6 @@ __global__ void k_norm_fin(int C, int nseg, int step, double eps_vec,
 // ------------------------------------------------------------------ launchers
 
 static inline dim3 red_grid(const Plan &p) { return dim3((unsigned)((int64_t)p.nchunk * p.nct)); }
-static inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C; }
 
 void launch_setup(const Plan &p, const void *probes, hipStream_t st)
 {
