@@ -121,7 +121,9 @@ size_t plan_layout(Plan &p, char *base)
     const size_t blk = (size_t)p.n * p.wave_cols * bv;
     const size_t NC = (size_t)p.nseg * p.wave_cols;   // virtual columns of one wave
     const size_t NCt = (size_t)p.nseg * p.Ct;         // of the whole run
-    const size_t slot = blk + kSlotPadBytes;   // slot stride of the widest wave
+    const bool pow2 = blk != 0 && (blk & (blk - 1)) == 0;
+    p.slot_pad = pow2 ? kSlotPadBytes / bv : 0;
+    const size_t slot = blk + p.slot_pad * bv;   // slot stride of the widest wave
     p.basis = take(slot * (p.k + 1));
     const int ntmp = p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN ? 3 : (p.prec_kind == ECNT_PREC_LDL ? 2 : 0);
     for (int t = 0; t < 3; ++t) p.tmp[t] = t < ntmp ? take(blk) : nullptr;

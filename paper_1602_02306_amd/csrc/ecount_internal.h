@@ -81,7 +81,8 @@ struct Plan {
     int32_t *seg_dims = nullptr;   // device, 3*nseg (d0, d1, d2; d2 contiguous)
     double *seg_taus = nullptr;    // device, nseg*S
     // workspace carve (device pointers)
-    void *basis = nullptr;     // (k+1) * n * C elements
+    void *basis = nullptr;     // (k+1) slots of n * C elements, slot_elems() apart
+    size_t slot_pad = 0;       // elements between consecutive slots beyond n * C
     void *tmp[3] = {nullptr, nullptr, nullptr};
     double *part = nullptr;    // nchunk * kBasisChunk * C
     double *sig = nullptr;     // (k+1) * C
@@ -143,13 +144,15 @@ struct Plan {
 
 constexpr int kPartRows = 64;      // rows per chunk of the partial-sum buffer
 
-// Consecutive basis slots (and the per-step slots of the differentiated form)
-// are this many bytes more than one block vector apart: with slots an exact
-// power of two apart, the ~30 streams of a reorthogonalization sweep hit the
-// same HBM channels and banks row after row (measured: +6% for the dots
-// sweep, +4% for the update sweep at 64^3 x 512 columns).  A multiple of 256.
+// When a block vector is an exact power of two in size, consecutive basis
+// slots (and the per-step slots of the differentiated form) are this many
+// bytes further apart: slots 2^k bytes apart send the ~30 streams of a
+// reorthogonalization sweep to the same HBM channels and banks row after row
+// (measured at 64^3 x 512 columns: +6% for the dots sweep, +4% for the update
+// sweep).  Other sizes keep contiguous slots (at 96^3 x 256 columns the pad
+// cost the backward update sweep 8%).  A multiple of 256.
 constexpr size_t kSlotPadBytes = 4352;
-inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C + kSlotPadBytes / (p.vec_f32 ? 4 : 8); }
+inline size_t slot_elems(const Plan &p) { return (size_t)p.n * p.C + p.slot_pad; }
 inline size_t slot_bytes(const Plan &p) { return slot_elems(p) * (p.vec_f32 ? 4 : 8); }
 constexpr int kResStride = 4 * kMaxShifts + 8;   // result doubles per segment
 
