@@ -687,6 +687,23 @@ def main():
             "fwd_probe_steps_per_s": probe_steps / (sum(f) / len(f) / 1e3),
             "dxi": grad_times["dxi"], "deta": grad_times["deta"], "dV_norm": grad_times["dV_norm"],
             "workspace_gib": need / 2 ** 30}
+    if blk:
+        # the block form's 16 x 16 contractions on the FP64 matrix cores: G_l = X_l^T Y and
+        # Y -= X_l K_l cost 2 * 16 * 16 * n flops per basis block per column block at step i
+        nblk = S * wl.m // 16
+        step_flops = 2.0 * 16 * 16 * wl.n * nblk * (wl.k * (wl.k + 1) // 2)
+        mf = {}
+        for fam in ("blk_dots", "blk_update"):
+            if fam in fams and fams[fam]["ms"] > 0:
+                ms_per_count = fams[fam]["ms"] / args.steps
+                mf[fam] = step_flops / (ms_per_count / 1e3) / 1e12
+        if mf:
+            top = max(mf, key=mf.get)
+            out["mfma"] = {"kernel": top, "achieved": mf[top], "peak": 78.6, "unit": "TFLOP/s",
+                           "frac": mf[top] / 78.6, "dtype": "f64",
+                           "per_kernel_tflops": mf,
+                           "note": "secondary: these kernels are HBM-bound (4 flop per byte of "
+                                   "basis read against a ridge of 78.6/8 = 9.8)"}
     if max_cols:
         out["config"]["column_waves"] = "%d columns per wave" % max_cols
     if tuned:
