@@ -504,9 +504,9 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the estimator on a single "
+        print("bench.py measures one GPU only: the library runs the estimator on a single "
               "MI355X (probe columns would shard across GPUs with one 32-byte all-reduce at the "
-              "end, which is not built); got --gpus %d" % args.gpus, file=sys.stderr)
+              "end, which is not implemented); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -52,7 +52,7 @@ typedef int32_t ecnt_status;
 #define ECNT_ENOTHPD (-2)      /* preconditioner not HPD (Jacobi pivot a_rr == tau)       */
 #define ECNT_EWORKSPACE (-3)   /* workspace missing or smaller than ecnt_workspace_bytes() */
 #define ECNT_EDEVICE (-4)      /* HIP runtime error, or the tridiagonal solver diverged   */
-#define ECNT_EUNSUPPORTED (-5) /* valid request outside what this build supports         */
+#define ECNT_EUNSUPPORTED (-5) /* valid request outside what the library supports        */
 
 typedef enum { ECNT_F64 = 0, ECNT_F32 = 1 } ecnt_dtype;
 
