@@ -251,6 +251,24 @@ def test_parity_column_waves(ec, max_cols):
     assert_parity(r, ref, k)
 
 
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+def test_parity_padded_slots_in_waves(ec, vec):
+    """A block vector of 4096 rows x 32 columns is a power of two in bytes, so
+    the basis slots are padded; two waves of 32 columns (m = 32, both shifts)."""
+    wl = W.WORKLOADS["c2_small"]
+    P = W.make_problem(wl)
+    V = W.rademacher(P.A.n, 32, 17)
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec=vec, max_cols=32)
+    if vec == "f64":
+        assert_parity(r, ref, wl.k)
+    else:
+        s = r.per_probe.cpu().numpy()
+        s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+        assert abs(r.estimate - ref.estimate) <= 1e-4 * max(1.0, abs(ref.estimate))
+        assert np.max(np.abs(s - s_ref)) <= 1e-4 * P.A.n
+
+
 def test_parity_column_waves_jacobi(ec):
     r, ref, k = run_workload(ec, "c1", max_cols=48)
     assert_parity(r, ref, k)
