@@ -371,10 +371,12 @@ def bench_batched(args, name: str):
     print(json.dumps(out), flush=True)
 
 
-def traffic_from_profiles(family: str, per_launch_algo: float):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "counters.json")
+def traffic_from_profiles(family: str, per_launch_algo: float, workload: str = "c2"):
+    """HBM bytes per launch from committed rocprofv3 counter runs of this
+    workload (profiles/counters.json for c2, counters_<workload>.json for the
+    others), if they were taken on the current kernel sources."""
+    name = "counters.json" if workload == "c2" else "counters_%s.json" % workload
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
@@ -622,7 +624,7 @@ def main():
     per_launch_bytes = d["bytes"] / d["launches"]
     per_launch_ms = d["ms"] / d["launches"]
     achieved = per_launch_bytes / (per_launch_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(dom, per_launch_bytes) if wl.name == "c2" else None
+    traffic = traffic_from_profiles(dom, per_launch_bytes, wl.name)
     kernels = {f: {"launches_per_step": v["launches"] / args.steps,
                    "ms_per_step": v["ms"] / args.steps,
                    "share": v["ms"] / total_kernel_ms if total_kernel_ms else None,
