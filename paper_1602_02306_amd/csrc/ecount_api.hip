@@ -132,6 +132,7 @@ size_t plan_layout(Plan &p, char *base)
     p.alpha = (double *)take(sizeof(double) * p.k * NC);
     p.beta = (double *)take(sizeof(double) * (p.k + 1) * NC);
     p.cf = (double *)take(sizeof(double) * (p.k + 1) * NC);
+    p.pq = (double *)take(sizeof(double) * (p.k + 1) * NC);
     p.kappa = (double *)take(sizeof(double) * NC);
     p.runmax = (double *)take(sizeof(double) * NC);
     p.nu = (double *)take(sizeof(double) * NC);
@@ -672,7 +673,7 @@ static void enqueue_wave_arnoldi(const Plan &p, const ecnt_csr *A, const void *p
                 const int nb = (j - l0) < kBasisChunk ? (j - l0) : kBasisChunk;
                 {
                     Timed t(F_DOTS, (nb + 1) * blk_b, st);
-                    launch_dots(p, j, l0, nb, st);
+                    launch_dots(p, j, l0, nb, false, st);
                 }
                 Timed t(F_FIN, 0.0, st);
                 launch_arn_fin(p, j, l0, nb, pass, st);
@@ -818,15 +819,26 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         const double *xs = p.sig + (size_t)(i - 1) * p.nseg * p.C;
         apply_op(p, A, x, xs, y, i, st);
         const int sm = i >= 2 ? i - 2 : -1;
+        // the Gram column of q_i makes the single pass take alpha_i first as
+        // Algorithm 1 does; the differentiated form keeps the plain pass that
+        // its reverse sweep follows (k <= 32)
+        const bool gram = !p.grad;
         for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
             const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;
             const bool m_in = sm >= l0 && sm < l0 + nb;
+            const bool q_in = i - 1 >= l0 && i - 1 < l0 + nb;
             {
-                Timed t(F_DOTS, (nb + 1 + ((sm >= 0 && !m_in) ? 1 : 0)) * blk_b, st);
-                launch_dots(p, i, l0, nb, st);
+                Timed t(F_DOTS,
+                        (nb + 1 + ((sm >= 0 && !m_in) ? 1 : 0) + ((gram && !q_in) ? 1 : 0)) * blk_b,
+                        st);
+                launch_dots(p, i, l0, nb, gram, st);
             }
             Timed t(F_FIN, 0.0, st);
-            launch_dots_fin(p, i, l0, nb, st);
+            launch_dots_fin(p, i, l0, nb, gram, st);
+        }
+        if (gram) {
+            Timed t(F_FIN, 0.0, st);
+            launch_cf_gram(p, i, st);
         }
         for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
             const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;

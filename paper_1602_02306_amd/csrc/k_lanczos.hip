@@ -95,13 +95,16 @@ __global__ void k_setup_fin(int C, int nseg, int k, const int64_t *__restrict__ 
 // ---- reorthogonalization dots: part[chunk][l][c] = sum_rows slot_{l0+l} * w ----
 // One wavefront per (row chunk, column tile); NB is the exact number of basis
 // vectors of the launch, so all NB + 2 row loads are issued back to back.
-template <typename T, int NB, int VW>
+// GRAM: also part[chunk][NB + l][c] = sum_rows slot_{l0+l} * slot_i (the
+// column of the basis' Gram matrix at q_i, from the same row loads; slot_i
+// is read once more per row, from cache when it lies in the launch's range).
+template <typename T, int NB, int VW, bool GRAM>
 __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int nseg,
                                              const int64_t *__restrict__ seg_row,
                                              const int64_t *__restrict__ seg_chunk,
                                              const T *__restrict__ basis, size_t ss, int slot_y,
                                              int l0, int slot_m, const double *__restrict__ kappa_all,
-                                             double *__restrict__ part)
+                                             int slot_i, double *__restrict__ part)
 {
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = (int)(L % nct);
@@ -112,31 +115,41 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
     int64_t r0, r1;
     chunk_rows(seg_row, seg_chunk, nseg, rpc, chunk, seg, r0, r1);
     const double *kappa = kappa_all + (size_t)seg * C;
-    double acc[NB][VW];
+    double acc[NB][VW], gr[GRAM ? NB : 1][VW];
 #pragma unroll
     for (int l = 0; l < NB; ++l)
 #pragma unroll
         for (int v = 0; v < VW; ++v) acc[l][v] = 0.0;
+#pragma unroll
+    for (int l = 0; l < (GRAM ? NB : 1); ++l)
+#pragma unroll
+        for (int v = 0; v < VW; ++v) gr[l][v] = 0.0;
     double kap[VW];
 #pragma unroll
     for (int v = 0; v < VW; ++v) kap[v] = slot_m >= 0 ? kappa[c0 + v] : 0.0;
     const T *Y = basis + (size_t)slot_y * ss;
     const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
+    const T *Qi = basis + (size_t)(GRAM ? slot_i : 0) * ss;
     const T *Q0 = basis + (size_t)l0 * ss;
     for (int64_t r = r0; r < r1; ++r) {
         const size_t e = (size_t)r * C + c0;
-        double y[VW], qm[VW], q[NB][VW];
+        double y[VW], qm[VW], qi[VW], q[NB][VW];
         vload<T, VW>(Y, e, y);
         vload<T, VW>(Qm, e, qm);
+        if (GRAM) vload<T, VW>(Qi, e, qi);
 #pragma unroll
         for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
-        // keep all NB + 2 loads of the row in flight before the first use
+        // keep all the row's loads in flight before the first use
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
             const double w = y[v] - kap[v] * qm[v];
 #pragma unroll
             for (int l = 0; l < NB; ++l) acc[l][v] += q[l][v] * w;
+            if (GRAM) {
+#pragma unroll
+                for (int l = 0; l < NB; ++l) gr[l][v] += q[l][v] * qi[v];
+            }
         }
     }
 #pragma unroll
@@ -144,15 +157,23 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
 #pragma unroll
         for (int v = 0; v < VW; ++v)
             part[((size_t)chunk * kPartRows + l) * C + c0 + v] = acc[l][v];
+    if (GRAM) {
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+                part[((size_t)chunk * kPartRows + NB + l) * C + c0 + v] = gr[l][v];
+    }
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
-// Arrays indexed [row][nseg*C].
+// With the Gram column (pq != null): pq_l = q_l^T q_i = sig_l sig_i * sum_chunks
+// part[.][nb + l].  Arrays indexed [row][nseg*C].
 __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
                            const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
                            const double *__restrict__ sig, const int32_t *__restrict__ active,
                            double *__restrict__ cf, double *__restrict__ alpha,
-                           double *__restrict__ gall)
+                           double *__restrict__ gall, double *__restrict__ pq)
 {
     // block (x: 64 virtual columns, y: basis vector l), kFinWaves wavefronts over the chunks
     const int NC = nseg * C;
@@ -161,13 +182,34 @@ __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
     const bool valid = vc < NC;
     const int seg = valid ? vc / C : 0, c = valid ? vc - seg * C : 0;
     const double s = block_chunk_sum(part, kPartRows, C, l, c, seg_chunk[seg], seg_chunk[seg + 1], valid);
+    const double sp = pq ? block_chunk_sum(part, kPartRows, C, nb + l, c, seg_chunk[seg],
+                                           seg_chunk[seg + 1], valid)
+                         : 0.0;
     if (!valid || threadIdx.x >= 64) return;
-    (void)nb;
     const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = s * sg;
     cf[(size_t)(l0 + l) * NC + vc] = g * sg;
     if (l0 + l == step - 1) alpha[(size_t)(step - 1) * NC + vc] = active[vc] ? g : 0.0;
     if (gall) gall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = g;   // kept for the backward
+    if (pq) pq[(size_t)(l0 + l) * NC + vc] = sp * sg * sig[(size_t)(step - 1) * NC + vc];
+}
+
+// The Gram-schmidt coefficients of w1 = w - alpha_i q_i (alpha first, then
+// the pass over q_1..q_i, as Algorithm 1 orders them) from the dots of w:
+// Q^T w1 = g - alpha_i Q^T q_i, so the update w - alpha_i q_i - Q (Q^T w1)
+// subtracts slot l with cf_l = sig_l (g_l - alpha_i pq_l) + [l = i] alpha_i sig_i.
+// Without the Gram column the alpha_i q_i term would be taken as exact and
+// its orthogonality error would grow by about |alpha_i| / beta_{i+1} per step.
+__global__ void k_cf_gram(int NC, int step, const double *__restrict__ sig,
+                          const double *__restrict__ alpha, const double *__restrict__ pq,
+                          double *__restrict__ cf)
+{
+    const int vc = blockIdx.x * 64 + threadIdx.x;
+    const int l = blockIdx.y;
+    if (vc >= NC) return;
+    const double a = alpha[(size_t)(step - 1) * NC + vc];
+    const double p = pq[(size_t)l * NC + vc] - (l == step - 1 ? 1.0 : 0.0);
+    cf[(size_t)l * NC + vc] -= a * sig[(size_t)l * NC + vc] * p;
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
@@ -291,12 +333,19 @@ void launch_setup_fin(const Plan &p, hipStream_t st)
 }
 
 template <typename T, int NB, int VW>
-static void dots_t(const Plan &p, int step, int l0, hipStream_t st)
+static void dots_t(const Plan &p, int step, int l0, bool gram, hipStream_t st)
 {
     const int nct = (p.C + 64 * VW - 1) / (64 * VW);
-    k_dots<T, NB, VW><<<(unsigned)((int64_t)p.nchunk * nct), 64, 0, st>>>(
-        p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk, (const T *)p.basis, slot_elems(p), step,
-        l0, (step >= 2 && !p.arnoldi) ? step - 2 : -1, p.kappa, p.part);
+    const dim3 grid((unsigned)((int64_t)p.nchunk * nct));
+    const int sm = (step >= 2 && !p.arnoldi) ? step - 2 : -1;
+    if (gram)
+        k_dots<T, NB, VW, true><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
+                                                     (const T *)p.basis, slot_elems(p), step, l0,
+                                                     sm, p.kappa, step - 1, p.part);
+    else
+        k_dots<T, NB, VW, false><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
+                                                      (const T *)p.basis, slot_elems(p), step, l0,
+                                                      sm, p.kappa, -1, p.part);
 }
 
 template <typename T, int NB, int VW>
@@ -315,12 +364,12 @@ static void update_t(const Plan &p, int step, int l0, bool first, bool last, hip
     F(31) F(32)
 
 template <typename T, int VW>
-static void dots_nb(const Plan &p, int step, int l0, int nb, hipStream_t st)
+static void dots_nb(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st)
 {
     switch (nb) {
 #define ECNT_CASE(N) \
     case N:          \
-        dots_t<T, N, VW>(p, step, l0, st); \
+        dots_t<T, N, VW>(p, step, l0, gram, st); \
         break;
         ECNT_NB_CASES(ECNT_CASE)
 #undef ECNT_CASE
@@ -349,21 +398,29 @@ static void update_nb(const Plan &p, int step, int l0, int nb, bool first, bool 
 // already fill the register budget).  Must match the geometry of the plan.
 static inline int red_vw(const Plan &p) { return (p.vec_f32 && p.C % 2 == 0) ? 2 : 1; }
 
-void launch_dots(const Plan &p, int step, int l0, int nb, hipStream_t st)
+void launch_dots(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st)
 {
     if (p.vec_f32) {
-        if (red_vw(p) == 2) dots_nb<float, 2>(p, step, l0, nb, st);
-        else dots_nb<float, 1>(p, step, l0, nb, st);
+        // column pairs with the Gram column would spill beyond 24 basis vectors
+        if (red_vw(p) == 2 && !(gram && nb > 24)) dots_nb<float, 2>(p, step, l0, nb, gram, st);
+        else dots_nb<float, 1>(p, step, l0, nb, gram, st);
     } else {
-        dots_nb<double, 1>(p, step, l0, nb, st);
+        dots_nb<double, 1>(p, step, l0, nb, gram, st);
     }
 }
 
-void launch_dots_fin(const Plan &p, int step, int l0, int nb, hipStream_t st)
+void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st)
 {
     const int NC = p.nseg * p.C;
-    k_dots_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part,
-                                                  p.sig, p.active, p.cf, p.alpha, p.g_gall);
+    k_dots_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(
+        p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part, p.sig, p.active, p.cf, p.alpha,
+        p.g_gall, gram ? p.pq : nullptr);
+}
+
+void launch_cf_gram(const Plan &p, int step, hipStream_t st)
+{
+    const int NC = p.nseg * p.C;
+    k_cf_gram<<<dim3((NC + 63) / 64, step), 64, 0, st>>>(NC, step, p.sig, p.alpha, p.pq, p.cf);
 }
 
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)

@@ -155,3 +155,19 @@ def test_block_ragged_last_column_wave(ec):
     r = run(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, max_cols=64)
     check(r, ref, P.A.n)
     assert np.array_equal(r.k_used.cpu().numpy(), kused_ref(ref, 48))
+
+
+def test_block_maximum_k(ec):
+    """k = 32, the largest block count of steps: T_k of order 512 (the
+    quadrature's largest band matrix) on n = 640."""
+    wl = W.Workload("t", (10, 8, 8), "wells", 3, -5.0, 1.0, "cheb", 16, 32)
+    P = W.make_problem(wl)
+    lam = np.sort(np.linalg.eigvalsh(P.A.to_dense()))
+    xi, eta = 0.5 * (lam[40] + lam[41]), 0.5 * (lam[300] + lam[301])
+    V = W.rademacher(P.A.n, 16, 19)
+    ref = oracle.block_count(P.A, P.prec, xi, eta, V, 32)
+    assert ref.lan_xi.k_used[0] == 32 and ref.lan_eta.k_used[0] == 32
+    print("block maximum k", flush=True)
+    r = run(ec, P.A, P.prec, xi, eta, V, 32)
+    check(r, ref, P.A.n)
+    assert np.all(r.k_used.cpu().numpy() == 32)

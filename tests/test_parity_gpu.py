@@ -168,6 +168,28 @@ def test_single_probe_variance_nan(ec):
     assert rel(r.estimate, ref.estimate) <= TOL
 
 
+def max_k_problem():
+    wl = W.Workload("t", (10, 8, 8), "wells", 3, -5.0, 1.0, "cheb", 4, 512)
+    P = W.make_problem(wl)
+    lam = np.sort(np.linalg.eigvalsh(P.A.to_dense()))
+    return P, 0.5 * (lam[40] + lam[41]), 0.5 * (lam[300] + lam[301])
+
+
+@pytest.mark.parametrize("rule,k", [("gauss", 512), ("ga", 256)])
+def test_parity_maximum_k(ec, rule, k):
+    """The largest k the library takes (512 for the Gauss rule, 256 for the
+    GA rule) on n = 640: a 513-slot basis and the largest tridiagonal
+    eigenproblem.  Two FP64 oracles that differ only in rounding order (the C
+    oracle and the block oracle at P = 1) agree to 1e-14 |v|^2 here."""
+    P, xi, eta = max_k_problem()
+    V = W.rademacher(P.A.n, 4, 17)
+    print("maximum k", rule, k, flush=True)
+    r = gpu_count(ec, P.A, P.prec, xi, eta, V, k, rule=rule)
+    ref = oracle.count(P.A, P.prec, xi, eta, V, k, rule=rule)
+    assert np.all(ref.lan_xi.k_used == k) and np.all(ref.lan_eta.k_used == k)
+    assert_parity(r, ref)
+
+
 def test_one_step(ec):
     r, ref, k = run_workload(ec, "c2_ragged", k=1)
     assert_parity(r, ref, k)
@@ -413,7 +435,10 @@ def test_smooth_keep_and_recompute_agree(ec):
     wl, P, V, Ad, Vd = grad_setup(ec, "c2_small", w)
     res, ws = ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w)
     cnt = ec.count(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, smooth_w=w)
-    assert res.estimate == cnt.estimate
+    # the count takes alpha_i before the Gram-Schmidt pass (through the Gram
+    # column of q_i); the differentiated forward keeps the single plain pass
+    # that its reverse sweep follows: the same values up to rounding at k <= 32
+    assert abs(res.estimate - cnt.estimate) <= 1e-12 * abs(cnt.estimate)
     a = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, workspace=ws)
     b = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, ckpt="recompute")
     assert torch.equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
