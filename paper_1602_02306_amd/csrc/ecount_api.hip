@@ -132,7 +132,6 @@ size_t plan_layout(Plan &p, char *base)
     p.alpha = (double *)take(sizeof(double) * p.k * NC);
     p.beta = (double *)take(sizeof(double) * (p.k + 1) * NC);
     p.cf = (double *)take(sizeof(double) * (p.k + 1) * NC);
-    p.pq = (double *)take(sizeof(double) * (p.k + 1) * NC);
     p.kappa = (double *)take(sizeof(double) * NC);
     p.runmax = (double *)take(sizeof(double) * NC);
     p.nu = (double *)take(sizeof(double) * NC);
@@ -823,7 +822,10 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         // Algorithm 1 does; the differentiated form keeps the plain pass that
         // its reverse sweep follows (k <= 32)
         const bool gram = !p.grad;
-        for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
+        // the launch that holds q_i first: its finalize yields alpha_i for the others
+        const int lq = (i - 1) / kBasisChunk * kBasisChunk;
+        for (int c = 0; c * kBasisChunk < i; ++c) {
+            const int l0 = c == 0 ? lq : (c - 1) * kBasisChunk;
             const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;
             const bool m_in = sm >= l0 && sm < l0 + nb;
             const bool q_in = i - 1 >= l0 && i - 1 < l0 + nb;
@@ -835,10 +837,6 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
             }
             Timed t(F_FIN, 0.0, st);
             launch_dots_fin(p, i, l0, nb, gram, st);
-        }
-        if (gram) {
-            Timed t(F_FIN, 0.0, st);
-            launch_cf_gram(p, i, st);
         }
         for (int l0 = 0; l0 < i; l0 += kBasisChunk) {
             const int nb = (i - l0) < kBasisChunk ? (i - l0) : kBasisChunk;

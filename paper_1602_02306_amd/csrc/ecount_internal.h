@@ -89,7 +89,6 @@ struct Plan {
     double *alpha = nullptr;   // k * C
     double *beta = nullptr;    // (k+1) * C
     double *cf = nullptr;      // (k+1) * NC   (update coefficients of the basis slots)
-    double *pq = nullptr;      // (k+1) * NC   (Gram column q_l^T q_i of the current step)
     double *kappa = nullptr;   // C                 (beta_i * sig_{i-2})
     double *runmax = nullptr;  // C
     double *nu = nullptr;      // C
@@ -185,7 +184,6 @@ void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1
                        double c2, const void *Z, double cz, void *out, hipStream_t st);
 void launch_dots(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st);
 void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st);
-void launch_cf_gram(const Plan &p, int step, hipStream_t st);
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st);
 void launch_norm_fin(const Plan &p, int step, hipStream_t st);
 void launch_tridiag(const Plan &p, hipStream_t st);

@@ -167,13 +167,20 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
 }
 
 // g_l = sig_l * sum_chunks part; cf_l = g_l * sig_l; alpha_i = g_i.
-// With the Gram column (pq != null): pq_l = q_l^T q_i = sig_l sig_i * sum_chunks
-// part[.][nb + l].  Arrays indexed [row][nseg*C].
+// With the Gram column (gram != 0), p_l = q_l^T q_i = sig_l sig_i * sum_chunks
+// part[.][nb + l] and the coefficients are those of Algorithm 1's order (alpha
+// first, then the pass over q_1..q_i): with w1 = w - alpha_i q_i,
+// Q^T w1 = g - alpha_i p, so the update w - alpha_i q_i - Q (Q^T w1) subtracts
+// slot l with cf_l = sig_l (g_l - alpha_i p_l) + [l = i] alpha_i sig_i.  (Taking
+// p = e_i instead lets the orthogonality error of q_i re-enter every step
+// multiplied by about |alpha_i| / beta_{i+1}.)  Every block of the launch that
+// holds q_i sums alpha_i itself; the others read it, that launch running first.
+// Arrays indexed [row][nseg*C].
 __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
                            const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
                            const double *__restrict__ sig, const int32_t *__restrict__ active,
                            double *__restrict__ cf, double *__restrict__ alpha,
-                           double *__restrict__ gall, double *__restrict__ pq)
+                           double *__restrict__ gall, int gram)
 {
     // block (x: 64 virtual columns, y: basis vector l), kFinWaves wavefronts over the chunks
     const int NC = nseg * C;
@@ -181,35 +188,27 @@ __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
     const int vc = blockIdx.x * 64 + (threadIdx.x & 63);
     const bool valid = vc < NC;
     const int seg = valid ? vc / C : 0, c = valid ? vc - seg * C : 0;
-    const double s = block_chunk_sum(part, kPartRows, C, l, c, seg_chunk[seg], seg_chunk[seg + 1], valid);
-    const double sp = pq ? block_chunk_sum(part, kPartRows, C, nb + l, c, seg_chunk[seg],
-                                           seg_chunk[seg + 1], valid)
-                         : 0.0;
+    const int64_t ch0 = seg_chunk[seg], ch1 = seg_chunk[seg + 1];
+    const int arow = step - 1 - l0;   // row of q_i in this launch, if it holds q_i
+    const double s = block_chunk_sum(part, kPartRows, C, l, c, ch0, ch1, valid);
+    double sp = 0.0, sa = 0.0;
+    if (gram) {
+        sp = block_chunk_sum(part, kPartRows, C, nb + l, c, ch0, ch1, valid);
+        if (arow < nb) sa = block_chunk_sum(part, kPartRows, C, arow, c, ch0, ch1, valid);
+    }
     if (!valid || threadIdx.x >= 64) return;
     const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = s * sg;
-    cf[(size_t)(l0 + l) * NC + vc] = g * sg;
+    double co = g * sg;
+    if (gram) {
+        const double si = sig[(size_t)(step - 1) * NC + vc];
+        const double a = arow < nb ? (active[vc] ? sa * si : 0.0) : alpha[(size_t)(step - 1) * NC + vc];
+        const double pl = sp * sg * si - (l0 + l == step - 1 ? 1.0 : 0.0);
+        co -= a * sg * pl;
+    }
+    cf[(size_t)(l0 + l) * NC + vc] = co;
     if (l0 + l == step - 1) alpha[(size_t)(step - 1) * NC + vc] = active[vc] ? g : 0.0;
     if (gall) gall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = g;   // kept for the backward
-    if (pq) pq[(size_t)(l0 + l) * NC + vc] = sp * sg * sig[(size_t)(step - 1) * NC + vc];
-}
-
-// The Gram-schmidt coefficients of w1 = w - alpha_i q_i (alpha first, then
-// the pass over q_1..q_i, as Algorithm 1 orders them) from the dots of w:
-// Q^T w1 = g - alpha_i Q^T q_i, so the update w - alpha_i q_i - Q (Q^T w1)
-// subtracts slot l with cf_l = sig_l (g_l - alpha_i pq_l) + [l = i] alpha_i sig_i.
-// Without the Gram column the alpha_i q_i term would be taken as exact and
-// its orthogonality error would grow by about |alpha_i| / beta_{i+1} per step.
-__global__ void k_cf_gram(int NC, int step, const double *__restrict__ sig,
-                          const double *__restrict__ alpha, const double *__restrict__ pq,
-                          double *__restrict__ cf)
-{
-    const int vc = blockIdx.x * 64 + threadIdx.x;
-    const int l = blockIdx.y;
-    if (vc >= NC) return;
-    const double a = alpha[(size_t)(step - 1) * NC + vc];
-    const double p = pq[(size_t)l * NC + vc] - (l == step - 1 ? 1.0 : 0.0);
-    cf[(size_t)l * NC + vc] -= a * sig[(size_t)l * NC + vc] * p;
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
@@ -414,13 +413,7 @@ void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStre
     const int NC = p.nseg * p.C;
     k_dots_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(
         p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part, p.sig, p.active, p.cf, p.alpha,
-        p.g_gall, gram ? p.pq : nullptr);
-}
-
-void launch_cf_gram(const Plan &p, int step, hipStream_t st)
-{
-    const int NC = p.nseg * p.C;
-    k_cf_gram<<<dim3((NC + 63) / 64, step), 64, 0, st>>>(NC, step, p.sig, p.alpha, p.pq, p.cf);
+        p.g_gall, gram ? 1 : 0);
 }
 
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
