@@ -362,6 +362,30 @@ def test_fp32_form_within_stated_bound(ec, name):
     assert e_probe <= FP32_BOUND
 
 
+@pytest.mark.parametrize("k", [40, 128])
+def test_fp32_form_more_than_one_basis_chunk(ec, k):
+    """FP32 storage past one basis chunk (the Gram column with one column per
+    lane beyond 24 basis vectors, alpha_i from the launch that holds q_i):
+    within the FP32 bound of the FP64 oracle."""
+    if k == 40:
+        wl = W.WORKLOADS["c2_small"]
+        P = W.make_problem(wl)
+        V, xi, eta = W.make_probes(wl), wl.xi, wl.eta
+    else:
+        P, xi, eta = max_k_problem()
+        V = W.rademacher(P.A.n, 4, 17)
+    r = gpu_count(ec, P.A, P.prec, xi, eta, V, k, vec="f32", val="f32")
+    ref = oracle.count(P.A, P.prec, xi, eta, V, k)
+    s = r.per_probe.cpu().numpy()
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    e_est = rel(r.estimate, ref.estimate)
+    e_probe = float(np.max(np.abs(s - s_ref) / nu))
+    print("fp32 k=%d: est %.10f oracle %.10f rel %.2e  max|ds|/nu %.2e" % (k, r.estimate, ref.estimate, e_est, e_probe), flush=True)
+    assert e_est <= FP32_BOUND
+    assert e_probe <= FP32_BOUND
+
+
 # ---------------------------------------------------------------------------
 # Differentiated form: gradient of the erf-smoothed count
 # ---------------------------------------------------------------------------
