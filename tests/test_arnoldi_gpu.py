@@ -131,3 +131,19 @@ def test_arnoldi_deterministic(ec):
     a = run(ec, P.A, T, wl.xi, wl.eta, V, wl.k)
     b = run(ec, P.A, T, wl.xi, wl.eta, V, wl.k)
     assert a.estimate == b.estimate and torch.equal(a.per_probe, b.per_probe)
+
+
+@pytest.mark.parametrize("kind", ["none", "cheb"])
+def test_arnoldi_maximum_k(ec, kind):
+    """k = 64, the largest the Arnoldi estimator takes, on n = 640 with one shift
+    near the bottom of the spectrum and one inside it."""
+    wl = W.Workload("t", (10, 8, 8), "wells", 3, -5.0, 1.0, "cheb", 4, 64)
+    P = W.make_problem(wl)
+    lam = np.sort(np.linalg.eigvalsh(P.A.to_dense()))
+    xi, eta = 0.5 * (lam[40] + lam[41]), 0.5 * (lam[300] + lam[301])
+    V = W.rademacher(P.A.n, 4, 17)
+    T = t_spec(kind, wl.dims)
+    print("arnoldi maximum k", kind, flush=True)
+    r = run(ec, P.A, T, xi, eta, V, 64)
+    ref = oracle.count_arnoldi(P.A, T, xi, eta, V, 64)
+    check(r, ref, P.A.n)

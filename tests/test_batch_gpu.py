@@ -200,3 +200,13 @@ def test_batch_single_probe_and_many_shifts(ec):
     r, _ = run_batch(ec, P, V, 6)
     check_against_oracle(P, r, V, 6)
     assert np.all(np.isnan(r.variances))
+
+
+def test_batch_large_k(ec):
+    """k = 200 (seven basis chunks per Gram-Schmidt pass) on three problems of
+    640..704 rows, every segment against the oracle."""
+    P = Problems([(10, 8, 8), (9, 9, 8), (8, 8, 11)], nshift=2, seed=5, lo=-120.0, hi=-20.0)
+    V = W.rademacher(P.Abd.n, 4, 31)
+    print("batch k = 200", flush=True)
+    r, _ = run_batch(ec, P, V, 200)
+    check_against_oracle(P, r, V, 200)

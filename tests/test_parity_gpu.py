@@ -362,6 +362,42 @@ def test_fp32_form_within_stated_bound(ec, name):
     assert e_probe <= FP32_BOUND
 
 
+@pytest.mark.parametrize("prec_kind", ["none", "jacobi"])
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_problems(ec, n, prec_kind):
+    """n = 1..3 rows (far below one tile or wavefront), k = n: the Krylov
+    space is the whole space, so every s_j is v_j^T h(C) v_j exactly
+    (eq. gauss_quad with k = n)."""
+    rng = np.random.default_rng(40 + n)
+    d = np.sort(rng.uniform(-3.0, 3.0, n)) + np.arange(n)
+    e = rng.uniform(0.2, 0.6, max(n - 1, 0))
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    rows, cols, vals = [], [], []
+    for r in range(n):
+        for c in range(max(0, r - 1), min(n, r + 2)):
+            rows.append(r)
+            cols.append(c)
+            vals.append(T[r, c])
+    rp = np.searchsorted(np.array(rows), np.arange(n + 1)).astype(np.int32)
+    A = W.CSR(n, rp, np.array(cols, dtype=np.int32), np.array(vals))
+    lam = np.linalg.eigvalsh(T)
+    xi = lam[0] - 0.5 if n == 1 else 0.5 * (lam[0] + lam[1])
+    eta = lam[-1] + 0.5
+    prec = W.PrecSpec(prec_kind, ())
+    V = W.rademacher(n, 3, 7 + n)
+    print("tiny n=%d %s" % (n, prec_kind), flush=True)
+    r = gpu_count(ec, A, prec, xi, eta, V, n)
+    ref = oracle.count(A, prec, xi, eta, V, n)
+    assert_parity(r, ref)
+    s = r.per_probe.cpu().numpy()
+    for t, tau in enumerate((xi, eta)):
+        Cd = oracle.dense_operator(A, prec, tau)
+        ev, U = np.linalg.eigh(0.5 * (Cd + Cd.T))
+        Pm = (U * (ev < 0)) @ U.T
+        exact = np.einsum("ij,ik,kj->j", V, Pm, V)
+        assert np.all(np.abs(s[3 * t:3 * t + 3] - exact) <= 1e-10 * n)
+
+
 @pytest.mark.parametrize("k", [40, 128])
 def test_fp32_form_more_than_one_basis_chunk(ec, k):
     """FP32 storage past one basis chunk (the Gram column with one column per
