@@ -79,6 +79,24 @@ def test_ldl_two_shifts_interval_count(ec):
     assert np.all(np.abs(s - np.concatenate([ref.s_xi, ref.s_eta])) <= TOL * nu)
 
 
+def test_ldl_two_basis_chunks(ec):
+    """ILDL preconditioner with k = 40: two basis chunks per Gram-Schmidt pass."""
+    wl = W.WORKLOADS["t1_small"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    xi, eta = 150.0, 420.0
+    prec = ec.ildl_precond(P.A, [xi, eta], 1e-4)
+    Vd = torch.from_numpy(V).to("cuda")
+    r = ec.count(ec.upload_csr(P.A), prec, xi, eta, Vd, 40)
+    ref = oracle.count(P.A, W.PrecSpec("ildl", (), droptol=1e-4), xi, eta, V, 40)
+    s = r.per_probe.cpu().numpy()
+    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    d = np.max(np.abs(s - np.concatenate([ref.s_xi, ref.s_eta])) / nu)
+    print("gpu %.15f oracle %.15f max |ds|/nu %.2e" % (r.estimate, ref.estimate, d), flush=True)
+    assert abs(r.estimate - ref.estimate) <= TOL * max(1.0, abs(ref.estimate))
+    assert d <= TOL
+
+
 def test_ldl_random_indefinite_with_2x2_pivots(ec):
     """A random sparse symmetric matrix (many 2 x 2 pivots and interchanges)."""
     rng = np.random.default_rng(11)

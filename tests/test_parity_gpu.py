@@ -273,6 +273,13 @@ def test_parity_column_waves(ec, max_cols):
     assert_parity(r, ref, k)
 
 
+def test_parity_column_waves_two_basis_chunks(ec):
+    """k = 40 (two basis chunks per pass, alpha_i from the second) in column
+    waves of 30 (a ragged last wave): every wave against the oracle."""
+    r, ref, k = run_workload(ec, "c1", k=40, max_cols=30)
+    assert_parity(r, ref, k, coef_tol=1e-6)
+
+
 @pytest.mark.parametrize("vec", ["f64", "f32"])
 def test_parity_padded_slots_in_waves(ec, vec):
     """A block vector of 4096 rows x 32 columns is a power of two in bytes, so
