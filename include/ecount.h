@@ -236,7 +236,10 @@ ECNT_API ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const
  * function of A's diagonal and of the shifts.  The backward pass is the exact
  * reverse-mode derivative of what the forward kernels compute (Algorithm 1
  * with its one Gram-Schmidt pass, differentiated line by line in reverse; the
- * tridiagonal step by the Daleckii-Krein formula).  Restrictions: FP64, Gauss
+ * tridiagonal step by the Daleckii-Krein formula).  This forward takes every
+ * Gram-Schmidt coefficient, alpha_i included, from the same vector, where
+ * ecnt_count takes alpha_i first as Algorithm 1 orders it; at k <= 32 the two
+ * agree up to rounding.  Restrictions: FP64, Gauss
  * rule, ECNT_PREC_CHEB_LAPLACIAN (M does not depend on A or tau), k <= 32,
  * max_cols = 0; otherwise ECNT_EUNSUPPORTED.
  *
