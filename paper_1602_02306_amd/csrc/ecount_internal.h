@@ -84,7 +84,7 @@ struct Plan {
     void *basis = nullptr;     // (k+1) slots of n * C elements, slot_elems() apart
     size_t slot_pad = 0;       // elements between consecutive slots beyond n * C
     void *tmp[3] = {nullptr, nullptr, nullptr};
-    double *part = nullptr;    // nchunk * kBasisChunk * C
+    double *part = nullptr;    // nchunk * kPartRows * C
     double *sig = nullptr;     // (k+1) * C
     double *alpha = nullptr;   // k * C
     double *beta = nullptr;    // (k+1) * C

@@ -95,10 +95,11 @@ __global__ void k_setup_fin(int C, int nseg, int k, const int64_t *__restrict__ 
 // ---- reorthogonalization dots: part[chunk][l][c] = sum_rows slot_{l0+l} * w ----
 // One wavefront per (row chunk, column tile); NB is the exact number of basis
 // vectors of the launch, so all NB + 2 row loads are issued back to back.
-// GRAM: also part[chunk][NB + l][c] = sum_rows slot_{l0+l} * slot_i (the
-// column of the basis' Gram matrix at q_i, from the same row loads; slot_i
-// is read once more per row, from cache when it lies in the launch's range).
-template <typename T, int NB, int VW, bool GRAM>
+// GRAM > 0: also part[chunk][NB + l][c] = sum_rows slot_{l0+l} * slot_i (the
+// column of the basis' Gram matrix at q_i, from the same row loads).  GRAM = 1:
+// slot_i is the launch's last basis vector (always so in the launch holding
+// q_i); GRAM = 2: slot_i is read as one more row.
+template <typename T, int NB, int VW, int GRAM>
 __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int nseg,
                                              const int64_t *__restrict__ seg_row,
                                              const int64_t *__restrict__ seg_chunk,
@@ -115,13 +116,13 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
     int64_t r0, r1;
     chunk_rows(seg_row, seg_chunk, nseg, rpc, chunk, seg, r0, r1);
     const double *kappa = kappa_all + (size_t)seg * C;
-    double acc[NB][VW], gr[GRAM ? NB : 1][VW];
+    double acc[NB][VW], gr[GRAM > 0 ? NB : 1][VW];
 #pragma unroll
     for (int l = 0; l < NB; ++l)
 #pragma unroll
         for (int v = 0; v < VW; ++v) acc[l][v] = 0.0;
 #pragma unroll
-    for (int l = 0; l < (GRAM ? NB : 1); ++l)
+    for (int l = 0; l < (GRAM > 0 ? NB : 1); ++l)
 #pragma unroll
         for (int v = 0; v < VW; ++v) gr[l][v] = 0.0;
     double kap[VW];
@@ -129,14 +130,14 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
     for (int v = 0; v < VW; ++v) kap[v] = slot_m >= 0 ? kappa[c0 + v] : 0.0;
     const T *Y = basis + (size_t)slot_y * ss;
     const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
-    const T *Qi = basis + (size_t)(GRAM ? slot_i : 0) * ss;
+    const T *Qi = basis + (size_t)(GRAM == 2 ? slot_i : 0) * ss;
     const T *Q0 = basis + (size_t)l0 * ss;
     for (int64_t r = r0; r < r1; ++r) {
         const size_t e = (size_t)r * C + c0;
         double y[VW], qm[VW], qi[VW], q[NB][VW];
         vload<T, VW>(Y, e, y);
         vload<T, VW>(Qm, e, qm);
-        if (GRAM) vload<T, VW>(Qi, e, qi);
+        if (GRAM == 2) vload<T, VW>(Qi, e, qi);
 #pragma unroll
         for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
         // keep all the row's loads in flight before the first use
@@ -146,9 +147,10 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
             const double w = y[v] - kap[v] * qm[v];
 #pragma unroll
             for (int l = 0; l < NB; ++l) acc[l][v] += q[l][v] * w;
-            if (GRAM) {
+            if (GRAM > 0) {
+                const double qv = GRAM == 1 ? (double)q[NB - 1][v] : qi[v];
 #pragma unroll
-                for (int l = 0; l < NB; ++l) gr[l][v] += q[l][v] * qi[v];
+                for (int l = 0; l < NB; ++l) gr[l][v] += q[l][v] * qv;
             }
         }
     }
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
 #pragma unroll
         for (int v = 0; v < VW; ++v)
             part[((size_t)chunk * kPartRows + l) * C + c0 + v] = acc[l][v];
-    if (GRAM) {
+    if (GRAM > 0) {
 #pragma unroll
         for (int l = 0; l < NB; ++l)
 #pragma unroll
@@ -337,14 +339,18 @@ static void dots_t(const Plan &p, int step, int l0, bool gram, hipStream_t st)
     const int nct = (p.C + 64 * VW - 1) / (64 * VW);
     const dim3 grid((unsigned)((int64_t)p.nchunk * nct));
     const int sm = (step >= 2 && !p.arnoldi) ? step - 2 : -1;
-    if (gram)
-        k_dots<T, NB, VW, true><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
-                                                     (const T *)p.basis, slot_elems(p), step, l0,
-                                                     sm, p.kappa, step - 1, p.part);
+    if (gram && step - 1 == l0 + NB - 1)
+        k_dots<T, NB, VW, 1><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
+                                                  (const T *)p.basis, slot_elems(p), step, l0, sm,
+                                                  p.kappa, step - 1, p.part);
+    else if (gram)
+        k_dots<T, NB, VW, 2><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
+                                                  (const T *)p.basis, slot_elems(p), step, l0, sm,
+                                                  p.kappa, step - 1, p.part);
     else
-        k_dots<T, NB, VW, false><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
-                                                      (const T *)p.basis, slot_elems(p), step, l0,
-                                                      sm, p.kappa, -1, p.part);
+        k_dots<T, NB, VW, 0><<<grid, 64, 0, st>>>(p.C, nct, p.rpc, p.nseg, p.seg_row, p.seg_chunk,
+                                                  (const T *)p.basis, slot_elems(p), step, l0, sm,
+                                                  p.kappa, -1, p.part);
 }
 
 template <typename T, int NB, int VW>
