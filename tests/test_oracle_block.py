@@ -114,3 +114,24 @@ def test_block_count_is_difference_of_shifts():
     assert r.estimate == pytest.approx(r.neg_eta - r.neg_xi, abs=1e-12)
     with pytest.raises(ValueError):
         oracle.block_lanczos(P.A, P.prec, xi, V[:, :20], 3, P=16)
+
+
+def test_oracle_at_the_largest_k_against_the_block_transcription():
+    """k = 512 on n = 640 (shift near the bottom of the spectrum and inside it):
+    the C oracle (alpha first, then one Gram-Schmidt pass) and the numpy block
+    oracle at P = 1 (one pass from C q_i) sum in different orders; both keep the
+    basis orthogonal to rounding, so their per-probe values agree to 1e-12 n
+    and both estimates lie within a few units of the exact count."""
+    P = problem((10, 8, 8), seed=3)
+    n = P.A.n
+    lam = np.sort(np.linalg.eigvalsh(P.A.to_dense()))
+    xi, eta = mid_gap(lam, 40), mid_gap(lam, 300)
+    V = W.rademacher(n, 2, 17)
+    ref = oracle.count(P.A, P.prec, xi, eta, V, 512)
+    blk = oracle.block_count(P.A, P.prec, xi, eta, V, 512, P=1)
+    s1 = np.concatenate([ref.s_xi, ref.s_eta])
+    s2 = np.concatenate([blk.s_xi, blk.s_eta])
+    assert np.max(np.abs(s1 - s2)) <= 1e-12 * n
+    exact = int(np.sum((lam >= xi) & (lam < eta)))
+    assert exact == 260
+    assert abs(ref.estimate - exact) < 30 and abs(blk.estimate - exact) < 30
