@@ -142,11 +142,25 @@ __global__ __launch_bounds__(256) void k_ldl_permute(int64_t n, int C, int c_lo,
 // is one FMA, a subtraction and the broadcast; no reduction across lanes.
 // Band rows are loaded 16 steps ahead into registers and staged into LDS per
 // 16 steps between 32 zeros on each side (read for distances outside 1..256).
+// All shifts of the wave in one launch (each solve is a latency-bound chain,
+// so the shifts' chains run side by side): blocks [blk0[s], blk0[s+1]) serve
+// shift s, its columns [lo[s], hi[s]) and its factor's band.
+struct LdlSolveSet {
+    int nsh;
+    int blk0[kMaxShifts + 1];
+    int lo[kMaxShifts], hi[kMaxShifts];
+    const double *band[kMaxShifts];
+};
+
 template <typename T, bool FWD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_ldl_solve(
-    int64_t n, int C, int c_lo, int c_hi, const double *__restrict__ band,
-    const T *__restrict__ X, T *__restrict__ Y)
+    int64_t n, int C, const LdlSolveSet set, const T *__restrict__ X, T *__restrict__ Y)
 {
+    int sh = 0;
+    while (sh + 1 < set.nsh && (int)blockIdx.x >= set.blk0[sh + 1]) ++sh;
+    const int c_lo = set.lo[sh], c_hi = set.hi[sh];
+    const double *__restrict__ band = set.band[sh];
+    const int blk = (int)blockIdx.x - set.blk0[sh];
     constexpr int NS = 32;             // lanes per column, steps per group
     constexpr int NR = kRing / NS;     // the pending sums per lane are NR + 1
     constexpr int kBatch = 16;         // band rows staged at a time
@@ -154,7 +168,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __shared__ double stg[kBatch][kRow];
     const int lane = threadIdx.x;
     const int hcol = lane >> 5, q = lane & 31;
-    const int craw = c_lo + blockIdx.x * 2 + hcol;
+    const int craw = c_lo + blk * 2 + hcol;
     const bool ok = craw < c_hi;
     const int c = ok ? craw : c_lo;
     if (lane < NS)
@@ -271,6 +285,30 @@ static inline bool shift_cols(const Plan &p, int s, int &lo, int &hi)
 template <typename T>
 static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st)
 {
+    if (what == 1 || what == 2) {
+        // forward substitution walks the columns of L (the band of L^T),
+        // back substitution the rows of L
+        LdlSolveSet set;
+        set.nsh = 0;
+        set.blk0[0] = 0;
+        for (int s = 0; s < p.S; ++s) {
+            int lo, hi;
+            if (!shift_cols(p, s, lo, hi)) continue;
+            const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
+            const int k = set.nsh++;
+            set.lo[k] = lo;
+            set.hi[k] = hi;
+            set.band[k] = what == 1 ? bb : bf;
+            set.blk0[k + 1] = set.blk0[k] + (hi - lo + 1) / 2;
+        }
+        if (set.nsh == 0) return;
+        const unsigned grid = (unsigned)set.blk0[set.nsh];
+        if (what == 1)
+            k_ldl_solve<T, true><<<grid, 64, 0, st>>>(p.n, p.C, set, (const T *)X, (T *)Y);
+        else
+            k_ldl_solve<T, false><<<grid, 64, 0, st>>>(p.n, p.C, set, (const T *)X, (T *)Y);
+        return;
+    }
     for (int s = 0; s < p.S; ++s) {
         int lo, hi;
         if (!shift_cols(p, s, lo, hi)) continue;
@@ -291,16 +329,8 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
             k_ldl_permute<T, false><<<egrid, 256, 0, st>>>(p.n, p.C, lo, hi, f.perm, (const T *)X,
                                                            (T *)Y);
             break;
-        default: {
-            // forward substitution walks the columns of L (the band of L^T),
-            // back substitution the rows of L
-            const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
-            const unsigned grid = (unsigned)((hi - lo + 1) / 2);
-            if (what == 1)
-                k_ldl_solve<T, true><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bb, (const T *)X, (T *)Y);
-            else
-                k_ldl_solve<T, false><<<grid, 64, 0, st>>>(p.n, p.C, lo, hi, bf, (const T *)X, (T *)Y);
-        }
+        default:
+            break;
         }
     }
 }
