@@ -158,6 +158,31 @@ def test_ideal_preconditioner_breakdown_gpu(ec):
     assert abs(r.estimate - np.sum((d >= -0.5) & (d < 0.7))) < 1e-9
 
 
+def test_breakdown_mixed_within_a_wave(ec):
+    """Diagonal A without preconditioner: probes that are unit vectors span an
+    invariant space at once (k_used = 1), a probe on two coordinates after two
+    steps, Rademacher probes run to k; all in one wave, each column against the
+    oracle (its k_used and s_j) while the others keep iterating."""
+    rng = np.random.default_rng(8)
+    n = 300
+    d = np.sort(rng.uniform(-3.0, 3.0, n))
+    A = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    V = W.rademacher(n, 6, 21)
+    V[:, 0] = 0.0
+    V[7, 0] = 1.0
+    V[:, 3] = 0.0
+    V[200, 3] = 1.0
+    V[:, 4] = 0.0
+    V[10, 4] = 1.0
+    V[250, 4] = -1.0
+    print("mixed breakdown", flush=True)
+    r = gpu_count(ec, A, W.PrecSpec("none", ()), -0.5, 0.7, V, 12)
+    ref = oracle.count(A, W.PrecSpec("none", ()), -0.5, 0.7, V, 12)
+    ku = np.concatenate([ref.lan_xi.k_used, ref.lan_eta.k_used])
+    assert set(ku.tolist()) >= {1, 2, 12}
+    assert_parity(r, ref)
+
+
 def test_single_probe_variance_nan(ec):
     wl = W.WORKLOADS["c1"]
     P = W.make_problem(wl)
