@@ -39,6 +39,31 @@ def test_inertia_methods_agree(N):
         assert exact.planewise_negcount(P.dims, P.V, tau) == d
 
 
+@pytest.mark.parametrize("dims,leaves", [((6, 6, 6), (4, 10 ** 6)), ((9, 8, 11), (40,)),
+                                         ((13, 11, 9), (64,)), ((2, 17, 3), (4, 10 ** 6))])
+def test_nested_dissection_inertia_matches_dense(dims, leaves):
+    """The multifrontal nested-dissection LDL^T count equals the dense
+    eigenvalue count, with leaf boxes small enough that every kind of front
+    (separator with ancestors on several faces, a ragged split, a leaf) occurs,
+    and with the whole grid as one leaf."""
+    wl = W.Workload("t", dims, "wells", 3, -8.0, -2.0, "cheb", 1, 1)
+    P = W.make_problem(wl)
+    lam = np.linalg.eigvalsh(P.A.to_dense())
+    for tau in (-30.0, -8.0, -2.0, 0.5, 7.0, 20.0):
+        d = int(np.sum(lam < tau))
+        for leaf in leaves:
+            assert exact.nd_negcount(P.dims, P.V, tau, leaf=leaf) == d, (tau, leaf)
+
+
+def test_nested_dissection_closed_form():
+    """V = 0: the count of the Dirichlet Laplacian below tau from its
+    closed-form spectrum."""
+    dims = (14, 12, 13)
+    lam = np.sort(exact.laplacian_eigenvalues(dims))
+    for tau in (0.37, 2.0, 6.05, 11.3):
+        assert exact.nd_negcount(dims, np.zeros(int(np.prod(dims))), tau) == int(np.sum(lam < tau))
+
+
 def test_stored_exact_counts_small():
     data = json.load(open(os.path.join(GOLDEN, "exact_counts.json")))
     for name in ("c1", "c2_small", "c2_ragged"):
