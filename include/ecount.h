@@ -21,7 +21,9 @@
  *     C++ exception crosses the ABI.  ecnt_last_error() gives a message.
  *   - Pointers marked "device" are HIP device pointers (memory owned by the
  *     caller); "host" pointers are ordinary host memory.  The library never
- *     allocates device memory and keeps no pointer after a call returns.
+ *     allocates device memory at run time and keeps no pointer after a call
+ *     returns (the fixed array behind ecnt_count_noalloc is a static device
+ *     variable of the library, set up when its code is loaded on a GPU).
  *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
  *     is enqueued on it.  Functions returning host results synchronize that
  *     stream before returning.
@@ -215,6 +217,33 @@ ECNT_API ecnt_status ecnt_count(const ecnt_csr *A, const ecnt_prec *T, double xi
                        const void *probes, int64_t m, const ecnt_opts *opts, void *ws,
                        size_t ws_bytes, void *stream, double *estimate, double *variance,
                        ecnt_info *info);
+
+/* ---- Interval count without allocation ----
+ *
+ * For callers that cannot allocate device memory or pass a workspace: tight
+ * serving loops and harnesses that forbid hipMalloc.  Same computation,
+ * arguments, outputs and errors as ecnt_count, minus `ws` / `ws_bytes`: the
+ * scratch (Lanczos basis, partial sums, per-column scalars) lives in a fixed
+ * device array of ECNT_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends.  The caller still owns A, the probes
+ * and the outputs.  No hipMalloc, hipFree or other allocating routine is
+ * called.
+ *   - The device is the current one; a non-NULL stream must belong to it
+ *     (else ECNT_EINVAL).
+ *   - A count whose ecnt_workspace_bytes(n, m, 2, T, opts) exceeds
+ *     ECNT_NOALLOC_SCRATCH_BYTES is refused with ECNT_EWORKSPACE before any
+ *     device work.
+ *   - All calls on one GPU share its array, which keeps the last call's
+ *     contents (nothing read by a call depends on them).  Calls through this
+ *     entry point are serialized per device by the library (each returns
+ *     after its stream has drained); other code that touches the array while
+ *     a call runs races with it. */
+#define ECNT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+ECNT_API ecnt_status ecnt_count_noalloc(const ecnt_csr *A, const ecnt_prec *T, double xi,
+                                        double eta, const void *probes, int64_t m,
+                                        const ecnt_opts *opts, void *stream, double *estimate,
+                                        double *variance, ecnt_info *info);
 
 /* Algorithm 2 for several shifts at once (spectrum slicing, Section 1): all
  * nshift x m Lanczos runs share one probe block and one launch sequence.

@@ -1100,6 +1100,34 @@ static ecnt_status batch_plan(Plan &p, SegHost &sh, const ecnt_batch_item *items
     return set_segments(p, sh, nprob, ns.data(), dims.data(), taus.data());
 }
 
+
+// ---- fixed device array behind ecnt_count_noalloc ----
+// Each GPU the library runs on holds one copy, for the life of the process.
+// In host code `scratch` names a host-side stand-in: its device address on the
+// current GPU comes from hipGetSymbolAddress and is used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[ECNT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;                  // guards g_scratch_ptr
+static void *g_scratch_ptr[kMaxDevices];         // device address of `scratch`, per device
+static std::mutex g_scratch_run_mu[kMaxDevices]; // one call at a time per device
+
+// Device address of the array on the current device (looked up once per device).
+static ecnt_status scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ECNT_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ECNT_OK;
+}
+
 }  // namespace ecnt
 
 using namespace ecnt;
@@ -1139,6 +1167,55 @@ ecnt_status ecnt_count(const ecnt_csr *A, const ecnt_prec *T, double xi, double 
         info->min_abs_ritz = res[4];
     }
     return ECNT_OK;
+}
+
+ecnt_status ecnt_count_noalloc(const ecnt_csr *A, const ecnt_prec *T, double xi, double eta,
+                               const void *probes, int64_t m, const ecnt_opts *opts, void *stream,
+                               double *estimate, double *variance, ecnt_info *info)
+{
+    g_err.clear();
+    // Validation and the size check run on the host first, as in ecnt_count:
+    // a refused call (including a count too large for the fixed array) makes
+    // no device call at all.
+    if (!estimate || !variance) return fail(ECNT_EINVAL, "estimate/variance output is null");
+    if (!isfinite(xi) || !isfinite(eta)) return fail(ECNT_EINVAL, "xi and eta must be finite");
+    if (!(xi < eta)) return fail(ECNT_EINVAL, "need xi < eta (got %g, %g)", xi, eta);
+    {
+        Plan p;
+        SegHost sh;
+        const double taus[2] = {xi, eta};
+        ecnt_status rc = make_plan(p, A ? A->n : 0, m, 2, T, opts);
+        if (!rc) rc = single_segment(p, sh, taus);
+        if (!rc) rc = check_common(A, probes, opts, (void *)&p, p, p.bytes);
+        if (rc) return rc;
+        if (p.bytes > ECNT_NOALLOC_SCRATCH_BYTES)
+            return fail(ECNT_EWORKSPACE,
+                        "ecnt_count_noalloc: this count needs %zu bytes of device scratch, the fixed "
+                        "array holds %zu; use ecnt_count with a caller workspace",
+                        p.bytes, (size_t)ECNT_NOALLOC_SCRATCH_BYTES);
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(ECNT_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ECNT_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    if (stream) {
+        hipDevice_t sd = -1;
+        e = hipStreamGetDevice((hipStream_t)stream, &sd);
+        if (e != hipSuccess) return fail(ECNT_EDEVICE, "hipStreamGetDevice: %s", hipGetErrorString(e));
+        if (sd != dev)
+            return fail(ECNT_EINVAL, "the stream belongs to device %d but device %d is current", (int)sd, dev);
+    }
+    void *ws = nullptr;
+    ecnt_status rc = scratch_address(dev, &ws);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(g_scratch_run_mu[dev]);
+    rc = ecnt_count(A, T, xi, eta, probes, m, opts, ws, ECNT_NOALLOC_SCRATCH_BYTES, stream, estimate,
+                    variance, info);
+    // nothing of this call may still use the array when the next one starts
+    // (ecnt_count returns after synchronizing the stream unless it failed early)
+    if (rc) (void)hipStreamSynchronize((hipStream_t)stream);
+    return rc;
 }
 
 ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const double *taus,

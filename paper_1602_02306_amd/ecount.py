@@ -98,6 +98,12 @@ def load():
                                    ctypes.c_double, P, ctypes.c_int64, ctypes.POINTER(OptsT), P,
                                    ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(InfoT)]
+        lib.ecnt_count_noalloc.restype = ctypes.c_int32
+        lib.ecnt_count_noalloc.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT),
+                                           ctypes.c_double, ctypes.c_double, P, ctypes.c_int64,
+                                           ctypes.POINTER(OptsT), P,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(InfoT)]
         lib.ecnt_negcounts.restype = ctypes.c_int32
         lib.ecnt_negcounts.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(PrecT), P,
                                        ctypes.c_int32, P, ctypes.c_int64, ctypes.POINTER(OptsT), P,
@@ -403,6 +409,32 @@ def count(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = 
                         _stream_handle(stream), ctypes.byref(est), ctypes.byref(var),
                         ctypes.byref(info))
     _check(rc)
+    return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
+                       keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"),
+                       keep.get("beta"))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # ECNT_NOALLOC_SCRATCH_BYTES
+
+
+def count_noalloc(A: DeviceCSR, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
+                  rule: str = "gauss", smooth_w: float = 0.0, stream=None, details: bool = True,
+                  eval: str = "auto", max_cols: int = 0, tune: dict | None = None) -> CountResult:
+    """Interval count through ecnt_count_noalloc: as `count`, with the scratch in
+    the library's fixed device array instead of a workspace (problems whose
+    workspace exceeds NOALLOC_SCRATCH_BYTES are refused).  With details=True
+    the optional per-probe outputs are torch tensors the caller allocates."""
+    lib = load()
+    n, m = probes.shape
+    _check_factors(prec, 2)
+    ps, _coef = prec_struct(prec, eval)
+    o = opts_struct(k, vec, rule, smooth_w, max_cols, tune)
+    info, keep = _info(2 * m, k, details, probes.device)
+    est, var = ctypes.c_double(), ctypes.c_double()
+    cs = A.struct()
+    _check(lib.ecnt_count_noalloc(ctypes.byref(cs), ctypes.byref(ps), float(xi), float(eta),
+                                  probes.data_ptr(), m, ctypes.byref(o), _stream_handle(stream),
+                                  ctypes.byref(est), ctypes.byref(var), ctypes.byref(info)))
     return CountResult(est.value, var.value, info.neg_xi, info.neg_eta, info.min_abs_ritz,
                        keep.get("per_probe"), keep.get("k_used"), keep.get("alpha"),
                        keep.get("beta"))

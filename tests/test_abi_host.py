@@ -175,3 +175,42 @@ def test_batch_rejects_invalid_calls_on_host():
                                 ctypes.byref(o), 0x2000, 1 << 40, None, out.ctypes.data, None,
                                 None, None)
     assert rc == ec.ECNT_EINVAL
+
+
+def _call_noalloc(n=64, m=4, k=3, prec=None, xi=0.0, eta=1.0, probes=0x1000, opts=None):
+    lib = ec.load()
+    cs = ec.CsrT(n, 7 * n, 0x3000, 0x4000, 0x5000, 0, 0)
+    ps, keep = ec.prec_struct(prec or W.PrecSpec("none", ()))
+    o = opts or ec.opts_struct(k)
+    e, v = ctypes.c_double(), ctypes.c_double()
+    rc = lib.ecnt_count_noalloc(ctypes.byref(cs), ctypes.byref(ps), xi, eta, probes, m,
+                                ctypes.byref(o), None, ctypes.byref(e), ctypes.byref(v), None)
+    return rc, ec.last_error()
+
+
+def test_noalloc_refuses_oversized_count_on_host():
+    """A count whose workspace exceeds the fixed array is refused before any
+    device call (this process has no GPU)."""
+    prec = W.cheb_invsqrt_prec((64, 64, 64))
+    rc, msg = _call_noalloc(n=64 ** 3, m=256, k=30, prec=prec, xi=-8.0, eta=-2.0)
+    assert rc == ec.ECNT_EWORKSPACE, msg
+    assert "fixed" in msg and str(ec.NOALLOC_SCRATCH_BYTES) in msg
+    # the limit is the workspace size of ecnt_count: just above it is refused
+    jac = W.PrecSpec("jacobi", ())
+    n, m = 4096, 64
+    k = next(k for k in range(1, 200) if ec.workspace_bytes(n, m, 2, jac, k) > ec.NOALLOC_SCRATCH_BYTES)
+    rc, msg = _call_noalloc(n=n, m=m, k=k, prec=jac)
+    assert rc == ec.ECNT_EWORKSPACE, msg
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(xi=1.0, eta=1.0), ec.ECNT_EINVAL),
+    (dict(xi=float("nan")), ec.ECNT_EINVAL),
+    (dict(probes=None), ec.ECNT_EINVAL),
+    (dict(m=0), ec.ECNT_EINVAL),
+    (dict(k=65), ec.ECNT_EINVAL),
+    (dict(n=1000, k=600), ec.ECNT_EUNSUPPORTED),
+])
+def test_noalloc_invalid_calls_rejected_on_host(kw, code):
+    rc, msg = _call_noalloc(**kw)
+    assert rc == code, msg
