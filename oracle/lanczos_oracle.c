@@ -7,20 +7,20 @@
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
  * load it.  It shares no code with the GPU library.
  *
- * What it computes, per probe vector v_j and one shift tau
- * (Section 3.1, Algorithm 1; Section 3.2, Algorithm 2 steps 3-4):
+ * What it computes, per probe vector v_j and one shift tau (Section 3.1,
+ * Algorithm 1; Section 3.2, Algorithm 2 steps 3-4): the k-step Lanczos
+ * decomposition of C = M (A - tau I) M^* (Section 2, eq. negi_T) started at
+ * q_1 = v/|v|,
  *
- *   C = M (A - tau I) M^*                         (Section 2, eq. negi_T)
- *   q_1 = v/|v|, q_0 = 0, beta_1 = 0
- *   for i = 1..k:
- *     w = C q_i - beta_i q_{i-1}
- *     alpha_i = q_i^* w ;  w = w - alpha_i q_i
- *     w = w - Q_i (Q_i^* w)                        (full reorthogonalization,
- *                                                   one classical Gram-Schmidt
- *                                                   pass against q_1..q_i)
- *     beta_{i+1} = |w| ;  q_{i+1} = w / beta_{i+1}
+ *   C Q_k = Q_k J_k + beta_{k+1} q_{k+1} e_k^T      (eq. lan)
  *
- * and returns alpha_1..alpha_k, beta_1..beta_{k+1} (beta_1 = 0) and |v|^2.
+ * built one column at a time: the coefficients of C q_i along q_{i-1} (beta_i,
+ * already known) and q_i (alpha_i, taken first) are removed, the remainder
+ * is projected off the whole basis q_1..q_i (full reorthogonalization: one
+ * classical Gram-Schmidt pass that does not update alpha_i), and its norm
+ * and direction give beta_{i+1} and q_{i+1}.
+ *
+ * It returns alpha_1..alpha_k, beta_1..beta_{k+1} (beta_1 = 0) and |v|^2.
  * The quadrature (eigendecomposition of J_k and the weighted count) is done
  * by the Python half of the oracle.
  *
@@ -209,35 +209,59 @@ static double dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
-/* Algorithm 1 for one probe.  Q: n x (k+1), column i holds q_{i+1}. */
+/* Column i of the Lanczos relation C Q_k = Q_k J_k + beta_{k+1} q_{k+1} e_k^T
+ * (Section 3.1, eq. lan): C q_i = beta_i q_{i-1} + alpha_i q_i + beta_{i+1} q_{i+1}.
+ * Forms the part of C q_i that is not along q_{i-1} and q_i:
+ *   w = C q_i - beta_i q_{i-1},  alpha_i = q_i^T w,  w <- w - alpha_i q_i
+ * and returns alpha_i (the diagonal entry of J_k). */
+static double relation_residual(const op_t *P, const double *Q, int i, double beta_i, double *w,
+                                double *work)
+{
+    const int64_t n = P->n;
+    const double *qi = Q + (size_t)(i - 1) * n;
+    apply_C(P, qi, w, work);
+    if (i > 1) {
+        const double *qm = Q + (size_t)(i - 2) * n;
+        for (int64_t r = 0; r < n; ++r) w[r] -= beta_i * qm[r];
+    }
+    const double a = dot(n, qi, w);
+    for (int64_t r = 0; r < n; ++r) w[r] -= a * qi[r];
+    return a;
+}
+
+/* w <- (I - Q Q^T) w for the nq columns of Q (the full reorthogonalization of
+ * Section 3.1): one classical Gram-Schmidt pass, every coefficient
+ * h_l = q_l^T w taken from the incoming w, then w -= sum_l h_l q_l. */
+static void project_out(int64_t n, const double *Q, int nq, double *w, double *h)
+{
+    for (int l = 0; l < nq; ++l) h[l] = dot(n, Q + (size_t)l * n, w);
+    for (int l = 0; l < nq; ++l) {
+        const double *ql = Q + (size_t)l * n;
+        for (int64_t r = 0; r < n; ++r) w[r] -= h[l] * ql[r];
+    }
+}
+
+/* k steps of Lanczos with full reorthogonalization on C from v (Section 3.1,
+ * Algorithm 1): the columns of the relation above, one at a time, each
+ * residual projected off the whole basis before it is normalized into the
+ * next basis vector.  Q: n x (k+1), column i holds q_{i+1}.  Returns the steps
+ * taken (fewer than k when the Krylov space is invariant). */
 static int lanczos_one(const op_t *P, const double *v, int k, double *alpha, double *beta,
                        double *nu_out, double *Q, double *w, double *h, double *work)
 {
-    int64_t n = P->n;
-    double nu = dot(n, v, v);
+    const int64_t n = P->n;
+    const double nu = dot(n, v, v);
     *nu_out = nu;
-    double inv = 1.0 / sqrt(nu);
-    for (int64_t r = 0; r < n; ++r) Q[r] = v[r] * inv; /* q_1 */
-    beta[0] = 0.0;                                        /* beta_1 */
-    double scale = 0.0;
+    const double inv = 1.0 / sqrt(nu);
+    for (int64_t r = 0; r < n; ++r) Q[r] = v[r] * inv; /* q_1 = v / |v| */
+    beta[0] = 0.0;                                        /* beta_1 = 0, q_0 = 0 */
+    double scale = 0.0;   /* largest |alpha_l|, beta_l so far (breakdown test) */
     for (int i = 1; i <= k; ++i) {
-        const double *qi = Q + (size_t)(i - 1) * n;
-        apply_C(P, qi, w, work);
-        if (i > 1) {
-            const double *qm = Q + (size_t)(i - 2) * n;
-            for (int64_t r = 0; r < n; ++r) w[r] -= beta[i - 1] * qm[r];
-        }
-        double a = dot(n, qi, w);
+        const double a = relation_residual(P, Q, i, beta[i - 1], w, work);
         alpha[i - 1] = a;
-        for (int64_t r = 0; r < n; ++r) w[r] -= a * qi[r];
-        /* one classical Gram-Schmidt pass against q_1..q_i */
-        for (int l = 0; l < i; ++l) h[l] = dot(n, Q + (size_t)l * n, w);
-        for (int l = 0; l < i; ++l) {
-            const double *ql = Q + (size_t)l * n;
-            for (int64_t r = 0; r < n; ++r) w[r] -= h[l] * ql[r];
-        }
-        double b = sqrt(dot(n, w, w));
-        beta[i] = b;
+        project_out(n, Q, i, w, h);
+        const double b = sqrt(dot(n, w, w));
+        beta[i] = b;   /* beta_{i+1} */
         if (fabs(a) > scale) scale = fabs(a);
         if (i > 1 && beta[i - 1] > scale) scale = beta[i - 1];
         if (b <= 1e3 * DBL_EPSILON * scale) return i; /* invariant Krylov space */

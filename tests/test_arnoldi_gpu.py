@@ -6,7 +6,7 @@ e_1^T h(H_k) e_1 through the matrix sign function; the oracle follows
 Algorithm 3 (modified Gram-Schmidt) and Algorithm 4 (eigendecomposition of
 H_k, first column of its inverse).  The two agree in exact arithmetic; the
 tolerances are those of the Lanczos parity tests: the estimate within
-1e-10 * max(|ref|, 1) and every per-probe value within 1e-10 * |v_j|^2.
+1e-10 * max(|ref|, 1) and every per-probe value within 1e-10 * max(|s_j|, 1).
 """
 import numpy as np
 import pytest
@@ -43,11 +43,12 @@ def run(ec, A, T, xi, eta, V, k, **kw):
 def check(r, ref, n, tol=TOL):
     s = r.per_probe.cpu().numpy()
     s_ref = np.concatenate([ref.s_xi, ref.s_eta])
-    d = np.max(np.abs(s - s_ref)) / n
-    print("gpu %.15f oracle %.15f | max |ds|/n %.2e" % (r.estimate, ref.estimate, d))
+    d = np.max(np.abs(s - s_ref) / np.maximum(1.0, np.abs(s_ref)))
+    print("gpu %.15f oracle %.15f | max |ds|/max(|s|,1) %.2e" % (r.estimate, ref.estimate, d), flush=True)
     assert abs(r.estimate - ref.estimate) <= tol * max(1.0, abs(ref.estimate))
     assert d <= tol
-    assert abs(r.neg_xi - ref.neg_xi) <= tol * n and abs(r.neg_eta - ref.neg_eta) <= tol * n
+    assert abs(r.neg_xi - ref.neg_xi) <= tol * max(1.0, abs(ref.neg_xi))
+    assert abs(r.neg_eta - ref.neg_eta) <= tol * max(1.0, abs(ref.neg_eta))
 
 
 @pytest.mark.parametrize("kind", ["cheb", "none"])

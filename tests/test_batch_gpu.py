@@ -3,7 +3,7 @@ block-diagonal launch sequence, against the oracle run on each problem alone
 (same probe rows), and against the single-problem GPU call.
 
 Tolerances as for the single-problem parity tests: per-shift means and every
-per-probe quadrature value within 1e-10 * |v_j|^2 (FP64).  The batched and the
+per-probe quadrature value within 1e-10 * max(|ref|, 1) (FP64).  The batched and the
 single-problem GPU runs differ only in the row chunking of the column sums.
 """
 import numpy as np
@@ -68,18 +68,18 @@ def check_against_oracle(P, r, V, k, prec_kind="cheb", rule="gauss", smooth_w=0.
     worst = 0.0
     for b in range(len(P.sizes)):
         Vb = np.ascontiguousarray(V[P.off[b]:P.off[b + 1]])
-        nu = float(P.sizes[b])   # Rademacher: |v|^2 = n
         for t in range(S):
             mean, s, _, _ = oracle.negcount(P.A[b], P.prec_for(prec_kind, b), P.taus[b, t], Vb, k,
                                             rule=rule, smooth_w=smooth_w)
-            d = np.max(np.abs(s_gpu[b, t] - s)) / nu
-            worst = max(worst, d, abs(r.negcounts[b, t] - mean) / nu)
-            assert abs(r.negcounts[b, t] - mean) <= tol * nu, (b, t, r.negcounts[b, t], mean)
+            d = np.max(np.abs(s_gpu[b, t] - s) / np.maximum(1.0, np.abs(s)))
+            dm = abs(r.negcounts[b, t] - mean) / max(1.0, abs(mean))
+            worst = max(worst, d, dm)
+            assert dm <= tol, (b, t, r.negcounts[b, t], mean)
             assert d <= tol, (b, t, d)
         for t in range(S - 1):
             dd = s_gpu[b, t + 1] - s_gpu[b, t]
             assert abs(r.counts[b, t] - dd.mean()) <= 1e-12 * max(1.0, abs(dd.mean()))
-    print("max deviation / |v|^2: %.2e" % worst)
+    print("max deviation / max(|ref|, 1): %.2e" % worst)
 
 
 def test_batch_matches_oracle_per_problem(ec):
@@ -132,8 +132,8 @@ def test_batch_equals_single_problem_calls(ec):
         Vd = torch.from_numpy(np.ascontiguousarray(V[P.off[b]:P.off[b + 1]])).cuda()
         one = ec.negcounts(Ad, P.prec_for("cheb", b), P.taus[b], Vd, 10)
         s1 = one.per_probe.cpu().numpy().reshape(4, 16)
-        assert np.max(np.abs(s1 - s_b[b])) <= TOL * P.sizes[b]
-        assert np.max(np.abs(one.negcounts - r.negcounts[b])) <= TOL * P.sizes[b]
+        assert np.all(np.abs(s1 - s_b[b]) <= 1e-12 * np.maximum(1.0, np.abs(s1)))
+        assert np.all(np.abs(one.negcounts - r.negcounts[b]) <= 1e-12 * np.maximum(1.0, np.abs(one.negcounts)))
 
 
 def test_batch_fp32_vectors(ec):

@@ -3,7 +3,7 @@ oracle: the library factors A - tau I on the host (its own code, checked
 bitwise against the oracle's factorization on the CPU), applies
 M = |D|^{-1/2} L^{-1} P and M^* on the GPU, and the counts must agree with the
 oracle's (which factors and applies with its own code) to the FP64 bar:
-estimate within 1e-10 * max(|ref|, 1), every s_j within 1e-10 |v_j|^2."""
+estimate within 1e-10 * max(|ref|, 1), every s_j within 1e-10 * max(|s_j|, 1)."""
 import json
 import os
 
@@ -41,15 +41,14 @@ def run_pair(ec, A, taus, droptol, V, k, vec="f64", max_cols=0):
 
 def assert_negcount_parity(r, refs, V, tol=TOL):
     m = V.shape[1]
-    nu = np.sum(V.astype(np.float64) ** 2, axis=0)
     s = r.per_probe.cpu().numpy()
     ku = r.k_used.cpu().numpy()
     for i, (mean, s_ref, res, _) in enumerate(refs):
-        ds = np.abs(s[i * m:(i + 1) * m] - s_ref)
-        print("shift %d: gpu %.15f oracle %.15f max |ds|/nu %.2e" % (
-            i, r.negcounts[i], mean, np.max(ds / nu)), flush=True)
+        ds = np.abs(s[i * m:(i + 1) * m] - s_ref) / np.maximum(1.0, np.abs(s_ref))
+        print("shift %d: gpu %.15f oracle %.15f max |ds|/max(|s|,1) %.2e" % (
+            i, r.negcounts[i], mean, np.max(ds)), flush=True)
         assert abs(r.negcounts[i] - mean) <= tol * max(1.0, abs(mean))
-        assert np.all(ds <= tol * nu)
+        assert np.all(ds <= tol)
         assert np.array_equal(ku[i * m:(i + 1) * m], res.k_used)
 
 
@@ -75,8 +74,8 @@ def test_ldl_two_shifts_interval_count(ec):
     print("gpu %.15f oracle %.15f" % (r.estimate, ref.estimate), flush=True)
     assert abs(r.estimate - ref.estimate) <= TOL * max(1.0, abs(ref.estimate))
     s = r.per_probe.cpu().numpy()
-    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
-    assert np.all(np.abs(s - np.concatenate([ref.s_xi, ref.s_eta])) <= TOL * nu)
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    assert np.all(np.abs(s - s_ref) <= TOL * np.maximum(1.0, np.abs(s_ref)))
 
 
 def test_ldl_two_basis_chunks(ec):
@@ -90,9 +89,9 @@ def test_ldl_two_basis_chunks(ec):
     r = ec.count(ec.upload_csr(P.A), prec, xi, eta, Vd, 40)
     ref = oracle.count(P.A, W.PrecSpec("ildl", (), droptol=1e-4), xi, eta, V, 40)
     s = r.per_probe.cpu().numpy()
-    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
-    d = np.max(np.abs(s - np.concatenate([ref.s_xi, ref.s_eta])) / nu)
-    print("gpu %.15f oracle %.15f max |ds|/nu %.2e" % (r.estimate, ref.estimate, d), flush=True)
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    d = np.max(np.abs(s - s_ref) / np.maximum(1.0, np.abs(s_ref)))
+    print("gpu %.15f oracle %.15f max |ds|/max(|s|,1) %.2e" % (r.estimate, ref.estimate, d), flush=True)
     assert abs(r.estimate - ref.estimate) <= TOL * max(1.0, abs(ref.estimate))
     assert d <= TOL
 

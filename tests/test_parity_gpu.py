@@ -4,16 +4,16 @@ same seeded inputs.
 Tolerances for FP64 (stated):
   * the estimate within 1e-10 * max(|ref|, 1);
   * every per-probe quadrature value s_j, and the per-shift means, within
-    1e-10 * |v_j|^2: s_j lies in [0, |v_j|^2] (a sum of Gauss weights), so
-    |v_j|^2 is its natural scale;
+    1e-10 * max(|ref|, 1) of the oracle's;
   * alpha/beta within 1e-8 * max|alpha| (diagnostics only).
 Two correct implementations of Algorithm 1 that differ only in rounding
 (summation order, the fused Gram-Schmidt pass) agree to about 1e-13 at the
 workloads' k; once Ritz values converge next to 0 the quadrature and the late
 coefficients become ill-conditioned (measured on the CPU for the 30x30
 problem at k = 40: per-probe s_j move by up to 2e-8 = 2e-11 |v|^2 and late
-alpha/beta by 1.6e-7 under 1e-16 perturbations of the operator), which the
-k = 40 test accounts for.
+alpha/beta by 1.6e-7 under 1e-16 perturbations of the operator).  The k = 40
+cases on that problem therefore bound s_j by 1e-10 * |v_j|^2 (s_j lies in
+[0, |v_j|^2], a sum of Gauss weights times |v_j|^2) and alpha/beta by 1e-6.
 """
 import json
 import math
@@ -52,19 +52,26 @@ def rel(a, b):
     return abs(a - b) / max(1.0, abs(b))
 
 
-def assert_parity(r, ref, k=None, coef_tol=1e-8):
+def assert_parity(r, ref, k=None, coef_tol=1e-8, probe_scale="rel"):
+    """probe_scale 'rel': s_j within TOL * max(|s_j|, 1); 'nu': within
+    TOL * |v_j|^2 (the ill-conditioned k = 40 cases only, see the header)."""
     s = r.per_probe.cpu().numpy()
     s_ref = np.concatenate([ref.s_xi, ref.s_eta])
     nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    scale = np.maximum(1.0, np.abs(s_ref)) if probe_scale == "rel" else nu
     print("gpu %.15f oracle %.15f | rel est %.2e | max |ds|/nu %.2e | max |ds|/max(|s|,1) %.2e"
           % (r.estimate, ref.estimate, rel(r.estimate, ref.estimate),
              np.max(np.abs(s - s_ref) / nu), np.max(np.abs(s - s_ref) / np.maximum(1, np.abs(s_ref)))),
           flush=True)
     assert rel(r.estimate, ref.estimate) <= TOL
-    nu_mean = float(np.mean(nu))
-    assert abs(r.neg_xi - ref.neg_xi) <= TOL * nu_mean
-    assert abs(r.neg_eta - ref.neg_eta) <= TOL * nu_mean
-    assert np.all(np.abs(s - s_ref) <= TOL * nu)
+    if probe_scale == "rel":
+        assert abs(r.neg_xi - ref.neg_xi) <= TOL * max(1.0, abs(ref.neg_xi))
+        assert abs(r.neg_eta - ref.neg_eta) <= TOL * max(1.0, abs(ref.neg_eta))
+    else:
+        nu_mean = float(np.mean(nu))
+        assert abs(r.neg_xi - ref.neg_xi) <= TOL * nu_mean
+        assert abs(r.neg_eta - ref.neg_eta) <= TOL * nu_mean
+    assert np.all(np.abs(s - s_ref) <= TOL * scale)
     if not math.isnan(ref.variance):
         assert abs(r.variance - ref.variance) <= 1e-8 * max(ref.variance, 1e-12)
     ku = r.k_used.cpu().numpy()
@@ -123,7 +130,7 @@ def test_parity_smoothed(ec):
 def test_parity_more_than_one_basis_chunk(ec):
     # k = 40 > 32: the reorthogonalization runs over two basis chunks
     r, ref, k = run_workload(ec, "c1", k=40)
-    assert_parity(r, ref, k, coef_tol=1e-6)
+    assert_parity(r, ref, k, coef_tol=1e-6, probe_scale="nu")
 
 
 @pytest.mark.parametrize("prec", ["none", "jacobi", "cheb"])
@@ -302,7 +309,7 @@ def test_parity_column_waves_two_basis_chunks(ec):
     """k = 40 (two basis chunks per pass, alpha_i from the second) in column
     waves of 30 (a ragged last wave): every wave against the oracle."""
     r, ref, k = run_workload(ec, "c1", k=40, max_cols=30)
-    assert_parity(r, ref, k, coef_tol=1e-6)
+    assert_parity(r, ref, k, coef_tol=1e-6, probe_scale="nu")
 
 
 @pytest.mark.parametrize("vec", ["f64", "f32"])
