@@ -81,7 +81,7 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
     done, t_tot, batch = 0, 0.0, max(1, min(threads, m))
     if wl.method == "block":
         batch = 16
-    worst = 0.0
+    worst, worst_rel = 0.0, 0.0
     while done < m:
         s = min(batch, m - done)
         t0 = time.perf_counter()
@@ -98,6 +98,9 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
         if gpu_per_probe is not None:
             gx, ge = gpu_per_probe[done:done + s], gpu_per_probe[m + done:m + done + s]
             worst = max(worst, float(np.max(np.abs(gx - ref.s_xi))), float(np.max(np.abs(ge - ref.s_eta))))
+            worst_rel = max(worst_rel,
+                            float(np.max(np.abs(gx - ref.s_xi) / np.maximum(1.0, np.abs(ref.s_xi)))),
+                            float(np.max(np.abs(ge - ref.s_eta) / np.maximum(1.0, np.abs(ref.s_eta)))))
         t_tot += dt
         done += s
         log("cpu oracle: %d probes in %.1f s (total %.1f s)" % (s, dt, t_tot))
@@ -113,6 +116,39 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
                      % (done, m, wl.k, steps, t_tot)}
     if gpu_per_probe is not None:
         out["gpu_vs_oracle_max_abs_per_probe_over_n"] = worst / wl.n
+        out["gpu_vs_oracle_max_rel_per_probe"] = worst_rel
+    return out
+
+
+def grad_check_sample(ec, A, P, wl, Vd, nprobe: int = 1, seed: int = 5):
+    """Sampled check of the differentiated form at full size: the GPU's smoothed
+    forward + backward on the first `nprobe` probes (the estimator on that
+    probe subset) against the oracle's forward-mode tangents on the same
+    subset: <dV, u> for a random direction u, d/dxi and d/deta."""
+    import oracle
+    import torch
+    Vs = Vd[:, :nprobe].contiguous()
+    res, ws = ec.smooth_forward(A, P.prec, wl.xi, wl.eta, Vs, wl.k, wl.smooth_w)
+    dV, dxi, deta = ec.smooth_backward(A, P.prec, wl.xi, wl.eta, Vs, wl.k, wl.smooth_w, workspace=ws)
+    dV = dV.cpu().numpy()
+    del ws
+    torch.cuda.empty_cache()
+    V = Vs.cpu().double().numpy()
+    u = np.random.default_rng(seed).standard_normal(wl.n)
+    t0 = time.perf_counter()
+    est_ref, d_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, u, 0.0, 0.0, wl.smooth_w)
+    _, dxi_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, np.zeros(wl.n), 1.0, 0.0,
+                                      wl.smooth_w)
+    _, deta_ref = oracle.count_tangent(P.A, P.prec, wl.xi, wl.eta, V, wl.k, np.zeros(wl.n), 0.0, 1.0,
+                                       wl.smooth_w)
+    dt = time.perf_counter() - t0
+    d_gpu = float(np.dot(dV, u))
+    out = {"probes": nprobe, "oracle_s": dt,
+           "estimate_rel": abs(res.estimate - est_ref) / max(1.0, abs(est_ref)),
+           "dV_dot_u_rel": abs(d_gpu - d_ref) / abs(d_ref),
+           "dxi_rel": abs(dxi - dxi_ref) / max(abs(dxi_ref), 1e-300),
+           "deta_rel": abs(deta - deta_ref) / max(abs(deta_ref), 1e-300)}
+    log("sampled gradient check (%d probe): %s" % (nprobe, out))
     return out
 
 
@@ -476,6 +512,52 @@ def summarize(trace_dir: str, pmc_dir: str | None, command: str, workload: str):
     return "\n".join(lines) + "\n", counters
 
 
+def k_sweep(args):
+    """Accuracy against the exact count versus k: for each k (and rule), one
+    warm-up and one event-timed count on the workload's probes; prints one
+    JSON line per run.  Throughput at a stated count error is read off these
+    lines (the smallest k whose error is below the target)."""
+    import torch
+    from paper_1602_02306_amd import ecount as ec
+    from paper_1602_02306_amd import workloads as W
+    wl = W.WORKLOADS[args.workload]
+    P = W.make_problem(wl)
+    A = ec.upload_csr(P.A)
+    Vd = W.rademacher_torch(wl.n, wl.m, wl.probe_seed, device="cuda", dtype=torch.float64)
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "exact_counts.json")))
+    base = wl.name.replace("_arn", "").replace("_blk", "")
+    exact = golden.get(wl.name, golden.get(base, {})).get("count")
+    rules = ["gauss"] if wl.method != "lanczos" else args.rules.split(",")
+    ws = ec.Workspace(1)
+    for k in [int(x) for x in args.k_sweep.split(",")]:
+        for rule in rules:
+            def run():
+                if wl.method == "block":
+                    need = ec.block_workspace_bytes(wl.n, wl.m, P.prec, k)
+                    return ec.count_block(A, P.prec, wl.xi, wl.eta, Vd, k, workspace=ws.ensure(need),
+                                          details=False)
+                if wl.method == "arnoldi":
+                    need = ec.arnoldi_workspace_bytes(wl.n, wl.m, P.prec, k)
+                    return ec.count_arnoldi(A, P.prec, wl.xi, wl.eta, Vd, k, workspace=ws.ensure(need),
+                                            details=False)
+                need = ec.workspace_bytes(wl.n, wl.m, 2, P.prec, k, rule=rule)
+                return ec.count(A, P.prec, wl.xi, wl.eta, Vd, k, rule=rule, workspace=ws.ensure(need),
+                                details=False)
+            run()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            r = run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rec = {"workload": wl.name, "form": wl.method, "rule": rule, "k": k, "estimate": r.estimate,
+                   "std_error": math.sqrt(r.variance), "exact_count": exact,
+                   "rel_error": (r.estimate - exact) / exact if exact else None,
+                   "ms_per_count": ms, "probe_steps_per_s": 2 * wl.m * k / (ms / 1e3)}
+            print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,6 +567,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calib", action="store_true")
+    ap.add_argument("--k-sweep", metavar="K1,K2,...",
+                    help="count error against the exact count and probe-steps/s at each k "
+                    "(rules from --rules; one JSON line per run) and exit")
+    ap.add_argument("--rules", default="gauss,ga", help="with --k-sweep: gauss, ga (single-vector form)")
     ap.add_argument("--summarize", metavar="TRACE_DIR",
                     help="print a markdown summary of a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-dir", help="with --summarize: directory holding the counter runs")
@@ -518,6 +604,9 @@ def main():
         copy_calib()
         return
 
+    if args.k_sweep:
+        k_sweep(args)
+        return
     if args.workload in BATCH:
         bench_batched(args, args.workload)
         return
@@ -711,6 +800,15 @@ def main():
     if tuned:
         out["config"]["launch_shape"] = tuned
     gpu_pp = None
+    if grad:
+        # untimed: per-probe smoothed values for the sampled oracle comparison
+        rd, _ = ec.smooth_forward(A, P.prec, wl.xi, wl.eta, Vd, wl.k, wl.smooth_w, workspace=ws,
+                                  details=True)
+        gpu_pp = rd.per_probe.cpu().numpy()
+        if not args.no_cpu_baseline:
+            del ws
+            torch.cuda.empty_cache()
+            out["differentiated"]["sampled_check_vs_oracle"] = grad_check_sample(ec, A, P, wl, Vd)
     if not grad:
         # one more run with per-probe outputs (untimed): sampled parity against
         # the oracle below, and the FP32 form against the FP64 path
@@ -724,6 +822,16 @@ def main():
             rd = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, workspace=ws, details=True,
                           max_cols=max_cols, tune=tune)
         gpu_pp = rd.per_probe.cpu().numpy()
+        if not arn and not blk:
+            # the generalized averaged Gauss rule on the same Lanczos coefficients
+            # (an untimed run on the same probes: the Lanczos data are bitwise the same,
+            # only the quadrature kernel differs)
+            rga = ec.count(A, P.prec, wl.xi, wl.eta, Vd, wl.k, vec=vec, rule="ga", workspace=ws,
+                           details=False, max_cols=max_cols, tune=tune)
+            accuracy["ga_rule"] = {"estimate": rga.estimate,
+                                   "std_error": math.sqrt(rga.variance) if rga.variance == rga.variance else None,
+                                   "rel_error": abs(rga.estimate - exact) / exact if exact else None}
+            log("GA rule on the same probes: %.4f" % rga.estimate)
         if vec == "f32":
             del ws
             torch.cuda.empty_cache()
@@ -742,6 +850,7 @@ def main():
             accuracy["fp32_minus_fp64_max_abs_per_probe_over_n"] = float(np.max(np.abs(gpu_pp - pp64))) / wl.n
             if exact is not None:
                 accuracy["fp64_path_abs_error"] = abs(r64.estimate - exact)
+                accuracy["fp64_path_rel_error"] = abs(r64.estimate - exact) / exact
             log("FP64 path on the same probes: %.6f (FP32 %.6f)" % (r64.estimate, r.estimate))
             del A64, V64
     if not args.no_cpu_baseline:

@@ -262,13 +262,13 @@ ECNT_API ecnt_status ecnt_negcounts(const ecnt_csr *A, const ecnt_prec *T, const
  * With smooth_w = w > 0 the step h(theta) of eq. gauss_quad is replaced at the
  * Ritz values by S_w(theta) = erfc(theta / w) / 2 (the rule only sees h at the
  * Ritz values, Section 3.3), which makes the computed estimate a smooth
- * function of A's diagonal and of the shifts.  The backward pass is the exact
- * reverse-mode derivative of what the forward kernels compute (Algorithm 1
- * with its one Gram-Schmidt pass, differentiated line by line in reverse; the
- * tridiagonal step by the Daleckii-Krein formula).  This forward takes every
- * Gram-Schmidt coefficient, alpha_i included, from the same vector, where
- * ecnt_count takes alpha_i first as Algorithm 1 orders it; at k <= 32 the two
- * agree up to rounding.  Restrictions: FP64, Gauss
+ * function of A's diagonal and of the shifts.  The forward is ecnt_count's
+ * (Algorithm 1: alpha_i first, then one classical Gram-Schmidt pass, fused
+ * into one update), so ecnt_smooth_fwd and ecnt_count with the same smooth_w
+ * return the same estimate.  The backward pass is the exact reverse-mode
+ * derivative of what those kernels compute (each step of Algorithm 1
+ * differentiated in reverse, the Gram-Schmidt coefficients as used; the
+ * tridiagonal step by the Daleckii-Krein formula).  Restrictions: FP64, Gauss
  * rule, ECNT_PREC_CHEB_LAPLACIAN (M does not depend on A or tau), k <= 32,
  * max_cols = 0; otherwise ECNT_EUNSUPPORTED.
  *

@@ -183,13 +183,14 @@ size_t plan_layout(Plan &p, char *base)
         p.g_ybar = (double *)take(blk);
         p.g_tbar = (double *)take(blk);
         p.g_gall = (double *)take(sizeof(double) * k * k * C);
+        p.g_pall = (double *)take(sizeof(double) * k * k * C);
         p.g_Z = (double *)take(sizeof(double) * k * k * C);
         p.g_theta = (double *)take(sizeof(double) * k * C);
         p.g_sval = (double *)take(sizeof(double) * k * C);
         p.g_abar = (double *)take(sizeof(double) * k * C);
         p.g_bbar = (double *)take(sizeof(double) * (k + 1) * C);
         p.g_coef = (double *)take(sizeof(double) * 4 * 32 * C);
-        p.g_scal = (double *)take(sizeof(double) * 2 * C);
+        p.g_scal = (double *)take(sizeof(double) * 5 * C);
         p.g_vpart = (double *)take(sizeof(double) * ((C + 63) / 64) * (size_t)p.n);
         p.g_taubar = (double *)take(sizeof(double) * C);
         p.g_sums = (double *)take(sizeof(double) * 64 * C);
@@ -819,9 +820,9 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         apply_op(p, A, x, xs, y, i, st);
         const int sm = i >= 2 ? i - 2 : -1;
         // the Gram column of q_i makes the single pass take alpha_i first as
-        // Algorithm 1 does; the differentiated form keeps the plain pass that
-        // its reverse sweep follows (k <= 32)
-        const bool gram = !p.grad;
+        // Algorithm 1 does (the reverse sweep of the differentiated form
+        // follows the same coefficients)
+        const bool gram = true;
         // the launch that holds q_i first: its finalize yields alpha_i for the others
         const int lq = (i - 1) / kBasisChunk * kBasisChunk;
         for (int c = 0; c * kBasisChunk < i; ++c) {

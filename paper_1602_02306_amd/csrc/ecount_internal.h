@@ -128,7 +128,8 @@ struct Plan {
     double *g_qbar = nullptr;  // k blocks: adjoints of q_1..q_k (slot-indexed)
     double *g_ybar = nullptr;  // block: adjoint of C q_i
     double *g_tbar = nullptr;  // block: M ybar
-    double *g_gall = nullptr;  // k*k*C: Gram-Schmidt coefficients g_i[l] of every step
+    double *g_gall = nullptr;  // k*k*C: update coefficients c_i[l] of every step
+    double *g_pall = nullptr;  // k*k*C: Gram column q_l^T q_i - [l = i] of every step
     double *g_Z = nullptr;     // k*k*C: eigenvectors of J
     double *g_theta = nullptr; // k*C
     double *g_sval = nullptr;  // k*C

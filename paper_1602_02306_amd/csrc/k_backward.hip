@@ -1,23 +1,27 @@
 // Reverse-mode derivative of the erf-smoothed estimator.
 //
 // Forward, per column (probe j at shift tau), as computed by the forward
-// kernels (q_l = sig_{l-1} * slot_{l-1}; Algorithm 1 with one fused
-// Gram-Schmidt pass):
-//   y_i = C q_i,  w_i = y_i - beta_i q_{i-1},  g_i = Q_i^T w_i (alpha_i = g_i[i]),
-//   r_i = w_i - Q_i g_i,  beta_{i+1} = |r_i|,  q_{i+1} = r_i / beta_{i+1},
+// kernels (q_l = sig_{l-1} * slot_{l-1}; Algorithm 1 with alpha_i taken first
+// and one classical Gram-Schmidt pass, fused into one update):
+//   y_i = C q_i,  w_i = y_i - beta_i q_{i-1},  g = Q_i^T w_i,  alpha_i = g[i],
+//   p = Q_i^T q_i,  c = g - alpha_i (p - e_i),  r_i = w_i - Q_i c,
+//   beta_{i+1} = |r_i|,  q_{i+1} = r_i / beta_{i+1},
 //   s = nu * e_1^T S_w(J_k) e_1,  S_w(x) = erfc(x / w) / 2,
 //   C = M (A - tau I) M,  A = L + diag(V),  M independent of V and tau.
 // Reverse, for i = k..1 (bars are adjoints; all sums over l run to i):
-//   rbar   = qbar_{i+1} / beta_{i+1} + betabar_{i+1} q_{i+1}
-//            (betabar_{i+1} first decreased by qbar_{i+1}^T q_{i+1} / beta_{i+1})
-//   gbar_l = -q_l^T rbar (+ alphabar_i for l = i)
-//   wbar   = rbar + sum_l gbar_l q_l
-//   qbar_l += gbar_l w_i - g_i[l] rbar,   qbar_{i-1} -= beta_i wbar,
-//   betabar_i -= wbar^T q_{i-1},  ybar = wbar,
+//   rbar    = qbar_{i+1} / beta_{i+1} + betabar_{i+1} q_{i+1}
+//             (betabar_{i+1} first decreased by qbar_{i+1}^T q_{i+1} / beta_{i+1})
+//   cbar_l  = -q_l^T rbar,   alphabar = alphabar_J - (p - e_i)^T cbar
+//   gbar    = cbar + alphabar e_i,   u = Q_i cbar
+//   wbar    = rbar + Q_i gbar
+//   qbar_l += gbar_l w_i - c_l rbar - alpha_i cbar_l q_i
+//   qbar_i += alphabar w_i - alpha_i u          (through p = Q^T Q e_i and alpha_i = q_i^T w_i)
+//   qbar_{i-1} -= beta_i wbar,  betabar_i -= wbar^T q_{i-1},  ybar = wbar,
 //   qbar_i += C ybar,  Vbar += (M ybar) .* (M q_i),  taubar -= (M ybar)^T (M q_i)
-// with alphabar, betabar of the tridiagonal step from Daleckii-Krein:
+// with alphabar_J, betabar of the tridiagonal step from Daleckii-Krein:
 //   Jbar = sbar * nu * Z (S[1] o z z^T) Z^T,  z = first row of Z.
-// M q_i is kept from the forward (one block vector per step).
+// M q_i is kept from the forward (one block vector per step); c and p - e_i
+// of every step too (k x k per column each).
 #include <float.h>
 
 #include "device_common.h"
@@ -200,11 +204,15 @@ __global__ void k_rowsum(int C, int nchunk, int nrows, const double *__restrict_
 }
 
 // Per column: finish betabar_{i+1}, form the coefficients of rbar and gbar.
-// coef layout (each [32][C]): cA = gbar*sig (wbar), cW = g*sig (w), cG = gbar, cR = g;
-// scal[0][c] = a (qbar_{i+1} weight in rbar), scal[1][c] = b*sig_i (slot_i weight).
+// coef layout (each [32][C]): cA = gbar*sig (wbar), cW = c*sig (w), cG = gbar, cR = c;
+// scal[0][c] = a (qbar_{i+1} weight in rbar), scal[1][c] = b*sig_i (slot_i weight),
+// scal[2][c] = -alpha_i sig_{i-1} (lambda: slot_{i-1} weight folded into w),
+// scal[3][c] = alphabar sig_{i-1} (mu: slot_{i-1} weight of the alphabar term of wbar),
+// scal[4][c] = -alpha_i.
 __global__ void k_bdots_fin(int C, int k, int nchunk, int i, int have_dots,
                             const double *__restrict__ part, const double *__restrict__ sig,
-                            const double *__restrict__ beta, const double *__restrict__ gall,
+                            const double *__restrict__ beta, const double *__restrict__ alpha,
+                            const double *__restrict__ gall, const double *__restrict__ pall,
                             const double *__restrict__ abar, double *__restrict__ bbar,
                             const int32_t *__restrict__ kused, double *__restrict__ cA,
                             double *__restrict__ cW, double *__restrict__ cG,
@@ -226,23 +234,35 @@ __global__ void k_bdots_fin(int C, int k, int nchunk, int i, int have_dots,
         a = 1.0 / bi1;
         b = bb;
     }
+    auto cbar = [&](int s) {   // -q_s^T rbar
+        if (a == 0.0 && b == 0.0) return 0.0;
+        const double sg = sig[(size_t)s * C + c];
+        return -(a * sg * raw(s) + b * sg * sgi * raw(i + 1 + s));
+    };
+    double ab = i <= ku ? abar[(size_t)(i - 1) * C + c] : 0.0;
+    for (int s = 0; s < i; ++s) ab -= pall[((size_t)(i - 1) * k + s) * C + c] * cbar(s);
     for (int s = 0; s < i; ++s) {
         const double sg = sig[(size_t)s * C + c];
-        double gb = 0.0;
-        if (a != 0.0 || b != 0.0) gb = -(a * sg * raw(s) + b * sg * sgi * raw(i + 1 + s));
-        if (s == i - 1 && i <= ku) gb += abar[(size_t)(i - 1) * C + c];
-        const double g = gall[((size_t)(i - 1) * k + s) * C + c];
+        double gb = cbar(s);
+        if (s == i - 1) gb += ab;
+        const double cl = gall[((size_t)(i - 1) * k + s) * C + c];
         cA[(size_t)s * C + c] = gb * sg;
-        cW[(size_t)s * C + c] = g * sg;
+        cW[(size_t)s * C + c] = cl * sg;
         cG[(size_t)s * C + c] = gb;
-        cR[(size_t)s * C + c] = g;
+        cR[(size_t)s * C + c] = cl;
     }
+    const double al = alpha[(size_t)(i - 1) * C + c];
+    const double sgq = sig[(size_t)(i - 1) * C + c];
     scal[c] = a;
     scal[(size_t)C + c] = b * sgi;
+    scal[(size_t)2 * C + c] = -al * sgq;
+    scal[(size_t)3 * C + c] = ab * sgq;
+    scal[(size_t)4 * C + c] = -al;
 }
 
 // One sweep per row: rbar, wbar (= ybar) and w of step i, the partial
-// wbar . slot_{i-2}, then qbar_s += cG_s w - cR_s rbar (s < i) and
+// wbar . slot_{i-2}, then qbar_s += cG_s (w - alpha_i q_i) - cR_s rbar (s < i),
+// qbar_i += -alpha_i (u - alphabar q_i) (u = wbar - rbar - alphabar q_i) and
 // qbar_{i-1} -= beta_i wbar.  rbar and w never leave registers.  A workgroup
 // is four wavefronts on four row chunks of one column tile; they share the
 // 4*NB coefficients of their columns through LDS.
@@ -273,6 +293,8 @@ __global__ __launch_bounds__(256) void k_bupdate(int64_t n, int C, int nct, int6
     if (!colok || chunk >= nchunk) return;
     const int64_t r0 = chunk * rpc, r1 = min(n, r0 + rpc);
     const double a = scal[c], bq = scal[(size_t)C + c];
+    const double lam = scal[(size_t)2 * C + c], mu = scal[(size_t)3 * C + c];
+    const double nal = scal[(size_t)4 * C + c];
     const double bi = i >= 2 ? beta[(size_t)(i - 1) * C + c] : 0.0;   // beta_i
     const double *QB = qbar + (size_t)i * ss;
     const double *SI = basis + (size_t)i * ss;
@@ -298,14 +320,18 @@ __global__ __launch_bounds__(256) void k_bupdate(int64_t n, int C, int nct, int6
 #pragma unroll
         for (int s = 0; s < NB; ++s) qsm = s == sm ? q[s] : qsm;
         dotm += wb * qsm;
+        const double qi = q[NB - 1];                          // slot i-1 (q_i unnormalized)
+        const double wq = w + lam * qi;                       // w - alpha_i q_i
+        const double xq = nal * (wb - rb - 2.0 * mu * qi);    // -alpha_i (u - alphabar q_i)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < NB; ++s) q[s] = FIRST ? 0.0 : qbar[(size_t)s * ss + e];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < NB; ++s) {
-            double v = q[s] + cf[2][s][lane] * w - cf[3][s][lane] * rb;
+            double v = q[s] + cf[2][s][lane] * wq - cf[3][s][lane] * rb;
             if (s == i - 2) v -= bi * wb;
+            if (s == NB - 1) v += xq;
             qbar[(size_t)s * ss + e] = v;
         }
     }
@@ -439,7 +465,8 @@ void launch_bdots_fin(const Plan &p, int i, bool have_dots, hipStream_t st)
         k_rowsum<<<(rows * p.C + 255) / 256, 256, 0, st>>>(p.C, p.nchunk, rows, p.part, p.g_sums);
     }
     k_bdots_fin<<<(p.C + 255) / 256, 256, 0, st>>>(p.C, p.k, p.nchunk, i, have_dots ? 1 : 0,
-                                                   p.g_sums, p.sig, p.beta, p.g_gall, p.g_abar,
+                                                   p.g_sums, p.sig, p.beta, p.alpha, p.g_gall,
+                                                   p.g_pall, p.g_abar,
                                                    p.g_bbar, p.kused, p.g_coef, p.g_coef + 32 * C,
                                                    p.g_coef + 64 * C, p.g_coef + 96 * C, p.g_scal);
 }

@@ -5,12 +5,15 @@
 // Step i of Algorithm 1, per column c (q_l = sig_{l-1} * slot_{l-1}):
 //   y      = C q_i                                (operator kernels, into slot i)
 //   w      = y - beta_i q_{i-1}
-//   g_l    = q_l^T w,  l = 1..i;  alpha_i = g_i   (k_dots + k_dots_fin)
-//   w     <- w - sum_l g_l q_l                    (k_update, in place in slot i)
+//   g_l    = q_l^T w,  p_l = q_l^T q_i,  l = 1..i (k_dots, one read of the basis)
+//   alpha_i = g_i;  c_l = g_l - alpha_i (p_l - [l = i])          (k_dots_fin)
+//   w     <- w - sum_l c_l q_l                    (k_update, in place in slot i)
 //   beta_{i+1} = |w|; sig_i = 1/beta_{i+1}        (k_norm_fin)
-// The single Gram-Schmidt pass against q_1..q_i (including q_i) also removes
-// the alpha_i q_i component: the result differs from "alpha first, then
-// reorthogonalize" only by rounding, since q_l^T q_i = delta_li + O(eps).
+// Since Q^T (w - alpha_i q_i) = g - alpha_i p, the single update equals
+// Algorithm 1's order (alpha_i first, then one classical Gram-Schmidt pass
+// against q_1..q_i) up to rounding.  Taking p = e_i instead (all coefficients
+// from w) is not such a change: the orthogonality error of q_i would re-enter
+// every step multiplied by about |alpha_i| / beta_{i+1}.
 //
 // Column reductions are two-phase and deterministic: each workgroup writes
 // the partial sums of its row chunk, a finalize kernel adds them in chunk
@@ -182,7 +185,7 @@ __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
                            const int64_t *__restrict__ seg_chunk, const double *__restrict__ part,
                            const double *__restrict__ sig, const int32_t *__restrict__ active,
                            double *__restrict__ cf, double *__restrict__ alpha,
-                           double *__restrict__ gall, int gram)
+                           double *__restrict__ gall, double *__restrict__ pall, int gram)
 {
     // block (x: 64 virtual columns, y: basis vector l), kFinWaves wavefronts over the chunks
     const int NC = nseg * C;
@@ -201,16 +204,19 @@ __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
     if (!valid || threadIdx.x >= 64) return;
     const double sg = sig[(size_t)(l0 + l) * NC + vc];
     const double g = s * sg;
-    double co = g * sg;
+    double c_l = g, pe = 0.0;   // coefficient of q_l in the update; p_l - [l = i]
     if (gram) {
         const double si = sig[(size_t)(step - 1) * NC + vc];
         const double a = arow < nb ? (active[vc] ? sa * si : 0.0) : alpha[(size_t)(step - 1) * NC + vc];
-        const double pl = sp * sg * si - (l0 + l == step - 1 ? 1.0 : 0.0);
-        co -= a * sg * pl;
+        pe = sp * sg * si - (l0 + l == step - 1 ? 1.0 : 0.0);
+        c_l = g - a * pe;
     }
-    cf[(size_t)(l0 + l) * NC + vc] = co;
+    cf[(size_t)(l0 + l) * NC + vc] = c_l * sg;
     if (l0 + l == step - 1) alpha[(size_t)(step - 1) * NC + vc] = active[vc] ? g : 0.0;
-    if (gall) gall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = g;   // kept for the backward
+    if (gall) {   // kept for the backward
+        gall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = c_l;
+        pall[((size_t)(step - 1) * k + l0 + l) * NC + vc] = pe;
+    }
 }
 
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
@@ -419,7 +425,7 @@ void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStre
     const int NC = p.nseg * p.C;
     k_dots_fin<<<dim3((NC + 63) / 64, nb), 64 * kFinWaves, 0, st>>>(
         p.C, p.nseg, step, l0, nb, p.k, p.seg_chunk, p.part, p.sig, p.active, p.cf, p.alpha,
-        p.g_gall, gram ? 1 : 0);
+        p.g_gall, p.g_pall, gram ? 1 : 0);
 }
 
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)

@@ -357,7 +357,11 @@ class Workspace:
     def ensure(self, nbytes: int):
         if self.nbytes < nbytes:
             import torch
-            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.buf.device)
+            dev = self.buf.device
+            # release the old buffer first: old and new together may not fit
+            self.buf = None
+            torch.cuda.empty_cache()
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
         return self
 
 

@@ -507,6 +507,56 @@ def test_smooth_gradient_matches_oracle_tangents(ec, name):
     assert abs(deta - deta_ref) <= 1e-8 * max(abs(deta_ref), 1e-10)
 
 
+def _grad_vs_oracle(ec, P, xi, eta, V, k, w, seed):
+    """Forward per probe at 1e-10 * max(|s_j|, 1) and <dV, u>, dxi, deta
+    against the oracle's forward-mode tangents at 1e-8 relative."""
+    Ad = ec.upload_csr(P.A)
+    Vd = torch.from_numpy(V).cuda()
+    res, ws = ec.smooth_forward(Ad, P.prec, xi, eta, Vd, k, w, details=True)
+    ref = oracle.count(P.A, P.prec, xi, eta, V, k, smooth_w=w)
+    s = res.per_probe.cpu().numpy()
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    ds = np.max(np.abs(s - s_ref) / np.maximum(1.0, np.abs(s_ref)))
+    print("  estimate gpu %.15f oracle %.15f rel %.2e | max |ds|/max(|s|,1) %.2e"
+          % (res.estimate, ref.estimate, rel(res.estimate, ref.estimate), ds), flush=True)
+    assert rel(res.estimate, ref.estimate) <= TOL
+    assert ds <= TOL
+    dV, dxi, deta = ec.smooth_backward(Ad, P.prec, xi, eta, Vd, k, w, workspace=ws)
+    dV = dV.cpu().numpy()
+    u = np.random.default_rng(seed).standard_normal(P.A.n)
+    _, d_ref = oracle.count_tangent(P.A, P.prec, xi, eta, V, k, u, 0.0, 0.0, w)
+    _, dxi_ref = oracle.count_tangent(P.A, P.prec, xi, eta, V, k, np.zeros(P.A.n), 1.0, 0.0, w)
+    _, deta_ref = oracle.count_tangent(P.A, P.prec, xi, eta, V, k, np.zeros(P.A.n), 0.0, 1.0, w)
+    d_gpu = float(np.dot(dV, u))
+    print("  <dV,u> gpu %.12e oracle %.12e | dxi %.12e / %.12e | deta %.12e / %.12e"
+          % (d_gpu, d_ref, dxi, dxi_ref, deta, deta_ref), flush=True)
+    assert abs(d_gpu - d_ref) <= 1e-8 * abs(d_ref)
+    assert abs(dxi - dxi_ref) <= 1e-8 * max(abs(dxi_ref), 1e-10)
+    assert abs(deta - deta_ref) <= 1e-8 * max(abs(deta_ref), 1e-10)
+
+
+@pytest.mark.parametrize("k", [30, 32])
+def test_smooth_gradient_at_largest_k_several_tiles(ec, k):
+    """The differentiated form at the workload's k = 30 and at its limit
+    k = 32, with 64 probes (128 columns: two 64-column tiles) on the 16^3
+    wells problem."""
+    wl = W.Workload("g16", (16, 16, 16), "wells", 1, -8.0, -2.0, "cheb", 64, k, smooth_w=0.05)
+    P = W.make_problem(wl)
+    print("case grad 16^3 m=64 k=%d" % k, flush=True)
+    _grad_vs_oracle(ec, P, wl.xi, wl.eta, W.make_probes(wl), k, 0.05, 21)
+
+
+def test_smooth_gradient_hard_shift_k32(ec):
+    """k = 32, 128 columns, on the n = 640 problem with xi just above the 41st
+    eigenvalue (near the bottom of the spectrum, where a Gram-Schmidt pass
+    that took alpha_i from the same vector as the other coefficients loses
+    orthogonality fastest)."""
+    P, xi, eta = max_k_problem()
+    V = W.rademacher(P.A.n, 64, 23)
+    print("case grad n=640 hard shift k=32", flush=True)
+    _grad_vs_oracle(ec, P, xi, eta, V, 32, 0.05, 22)
+
+
 def test_smooth_gradient_finite_differences_gpu(ec):
     """Central differences of the GPU's own smoothed estimate."""
     w = 0.05
@@ -534,10 +584,9 @@ def test_smooth_keep_and_recompute_agree(ec):
     wl, P, V, Ad, Vd = grad_setup(ec, "c2_small", w)
     res, ws = ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w)
     cnt = ec.count(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, smooth_w=w)
-    # the count takes alpha_i before the Gram-Schmidt pass (through the Gram
-    # column of q_i); the differentiated forward keeps the single plain pass
-    # that its reverse sweep follows: the same values up to rounding at k <= 32
-    assert abs(res.estimate - cnt.estimate) <= 1e-12 * abs(cnt.estimate)
+    # the differentiated forward is the count's forward (alpha_i first, then
+    # the Gram-Schmidt pass): the same kernels, the same estimate
+    assert abs(res.estimate - cnt.estimate) <= 1e-15 * abs(cnt.estimate)
     a = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, workspace=ws)
     b = ec.smooth_backward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, w, g_est=2.0, ckpt="recompute")
     assert torch.equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2]
