@@ -102,6 +102,38 @@ __global__ void k_setup_fin(int C, int nseg, int k, const int64_t *__restrict__ 
 // column of the basis' Gram matrix at q_i, from the same row loads).  GRAM = 1:
 // slot_i is the launch's last basis vector (always so in the launch holding
 // q_i); GRAM = 2: slot_i is read as one more row.
+// Rows r0..r1 of the dots sweep; HASM: w = y - kappa q_{i-1} (otherwise w = y,
+// and q_{i-1} is not read).
+template <typename T, int NB, int VW, int GRAM, bool HASM>
+__device__ __forceinline__ void dots_rows(int C, int c0, int64_t r0, int64_t r1, const T *__restrict__ Y,
+                                          const T *__restrict__ Qm, const T *__restrict__ Qi,
+                                          const T *__restrict__ Q0, size_t ss, const double (&kap)[VW],
+                                          double (&acc)[NB][VW], double (&gr)[GRAM > 0 ? NB : 1][VW])
+{
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c0;
+        double y[VW], qm[VW], qi[VW], q[NB][VW];
+        vload<T, VW>(Y, e, y);
+        if (HASM) vload<T, VW>(Qm, e, qm);
+        if (GRAM == 2) vload<T, VW>(Qi, e, qi);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        // keep all the row's loads in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            const double w = HASM ? y[v] - kap[v] * qm[v] : y[v];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) acc[l][v] += q[l][v] * w;
+            if (GRAM > 0) {
+                const double qv = GRAM == 1 ? (double)q[NB - 1][v] : qi[v];
+#pragma unroll
+                for (int l = 0; l < NB; ++l) gr[l][v] += q[l][v] * qv;
+            }
+        }
+    }
+}
+
 template <typename T, int NB, int VW, int GRAM>
 __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int nseg,
                                              const int64_t *__restrict__ seg_row,
@@ -135,28 +167,10 @@ __global__ __launch_bounds__(64) void k_dots(int C, int nct, int64_t rpc, int ns
     const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
     const T *Qi = basis + (size_t)(GRAM == 2 ? slot_i : 0) * ss;
     const T *Q0 = basis + (size_t)l0 * ss;
-    for (int64_t r = r0; r < r1; ++r) {
-        const size_t e = (size_t)r * C + c0;
-        double y[VW], qm[VW], qi[VW], q[NB][VW];
-        vload<T, VW>(Y, e, y);
-        vload<T, VW>(Qm, e, qm);
-        if (GRAM == 2) vload<T, VW>(Qi, e, qi);
-#pragma unroll
-        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
-        // keep all the row's loads in flight before the first use
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int v = 0; v < VW; ++v) {
-            const double w = y[v] - kap[v] * qm[v];
-#pragma unroll
-            for (int l = 0; l < NB; ++l) acc[l][v] += q[l][v] * w;
-            if (GRAM > 0) {
-                const double qv = GRAM == 1 ? (double)q[NB - 1][v] : qi[v];
-#pragma unroll
-                for (int l = 0; l < NB; ++l) gr[l][v] += q[l][v] * qv;
-            }
-        }
-    }
+    if (slot_m >= 0)
+        dots_rows<T, NB, VW, GRAM, true>(C, c0, r0, r1, Y, Qm, Qi, Q0, ss, kap, acc, gr);
+    else
+        dots_rows<T, NB, VW, GRAM, false>(C, c0, r0, r1, Y, Qm, Qi, Q0, ss, kap, acc, gr);
 #pragma unroll
     for (int l = 0; l < NB; ++l)
 #pragma unroll
@@ -219,6 +233,35 @@ __global__ void k_dots_fin(int C, int nseg, int step, int l0, int nb, int k,
     }
 }
 
+// Rows r0..r1 of the update sweep; HASM: the first chunk's -kappa q_{i-1} term
+// (otherwise q_{i-1} is not read).
+template <typename T, int NB, int VW, bool HASM>
+__device__ __forceinline__ void update_rows(int C, int c0, int64_t r0, int64_t r1, T *__restrict__ W,
+                                            const T *__restrict__ Qm, const T *__restrict__ Q0,
+                                            size_t ss, const double (&kap)[VW],
+                                            const double (&co)[NB][VW], double (&nrm)[VW])
+{
+    for (int64_t r = r0; r < r1; ++r) {
+        const size_t e = (size_t)r * C + c0;
+        double w[VW], qm[VW], q[NB][VW];
+        vload<T, VW>(W, e, w);
+        if (HASM) vload<T, VW>(Qm, e, qm);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            double x = HASM ? w[v] - kap[v] * qm[v] : w[v];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) x -= co[l][v] * q[l][v];
+            w[v] = x;
+            const double xr = rounded<T>(x);
+            nrm[v] += xr * xr;
+        }
+        vstore<T, VW>(W, e, w);
+    }
+}
+
 // w <- w - sum_l cf_l slot_{l0+l} (first chunk: w = y - kappa*slot_m), in place in
 // slot_w; the last chunk also writes partial |w|^2 into part[chunk][0][c]
 // (of the value as stored, i.e. after rounding to T).
@@ -251,25 +294,10 @@ __global__ __launch_bounds__(64) void k_update(int C, int nct, int64_t rpc, int 
     T *W = basis + (size_t)slot_w * ss;
     const T *Qm = basis + (size_t)(slot_m >= 0 ? slot_m : 0) * ss;
     const T *Q0 = basis + (size_t)l0 * ss;
-    for (int64_t r = r0; r < r1; ++r) {
-        const size_t e = (size_t)r * C + c0;
-        double w[VW], qm[VW], q[NB][VW];
-        vload<T, VW>(W, e, w);
-        vload<T, VW>(Qm, e, qm);
-#pragma unroll
-        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int v = 0; v < VW; ++v) {
-            double x = w[v] - kap[v] * qm[v];
-#pragma unroll
-            for (int l = 0; l < NB; ++l) x -= co[l][v] * q[l][v];
-            w[v] = x;
-            const double xr = rounded<T>(x);
-            nrm[v] += xr * xr;
-        }
-        vstore<T, VW>(W, e, w);
-    }
+    if (slot_m >= 0)
+        update_rows<T, NB, VW, true>(C, c0, r0, r1, W, Qm, Q0, ss, kap, co, nrm);
+    else
+        update_rows<T, NB, VW, false>(C, c0, r0, r1, W, Qm, Q0, ss, kap, co, nrm);
     if (last) {
 #pragma unroll
         for (int v = 0; v < VW; ++v) part[(size_t)chunk * kPartRows * C + c0 + v] = nrm[v];
