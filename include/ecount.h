@@ -177,7 +177,13 @@ typedef struct {
                            (sets the rows per chunk of the two-phase sums; 0: 2048) */
     int32_t csr_vw;     /* columns per lane of the CSR sweep: 1, 2 (or 4 with FP32
                            vectors); used when it divides the wave's width (0: widest) */
-    int32_t reserved;   /* must be 0 */
+    int32_t a_form;     /* how A is applied with ECNT_PREC_CHEB_LAPLACIAN (ignored
+                           otherwise).  0: as a stencil sweep on the preconditioner's
+                           grid when A is of that form (checked on the device at the
+                           start of each call: its CSR entries are exactly the grid
+                           neighbours and the diagonal, all off-diagonal values equal),
+                           else row by row from the CSR arrays; 1: always from the CSR
+                           arrays.  Both sum each row in the same order. */
 } ecnt_opts;
 
 /* Optional outputs.  Device arrays may be NULL. */

@@ -19,12 +19,13 @@ namespace ecnt {
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
               F_VGRAD, F_CHEB2, F_LDL, F_LDLE, F_BKDOTS, F_BKUPD, F_BKNORM, F_BKQUAD,
-              F_COUNT };
+              F_STA, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
                                            "bw_update", "bw_vgrad", "op_cheb_quad",
                                            "op_ldl_solve", "op_ldl_elementwise", "blk_dots",
-                                           "blk_update", "blk_normalize", "blk_quadrature"};
+                                           "blk_update", "blk_normalize", "blk_quadrature",
+                                           "op_a_stencil"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -32,6 +33,7 @@ struct PendingEvent {
     int fam;
     hipEvent_t a, b;
     double bytes;
+    int gate;   // 0: always runs; 1: runs only in the stencil form of A; 2: only in the CSR form
 };
 static thread_local std::vector<PendingEvent> t_pending;
 static thread_local std::vector<hipEvent_t> t_event_pool;
@@ -53,8 +55,9 @@ struct Timed {
     int fam;
     double bytes;
     hipStream_t st;
+    int gate;
     hipEvent_t a = nullptr;
-    Timed(int f, double b, hipStream_t s) : fam(f), bytes(b), st(s)
+    Timed(int f, double b, hipStream_t s, int g = 0) : fam(f), bytes(b), st(s), gate(g)
     {
         if (t_prof && (a = get_event())) (void)hipEventRecord(a, st);
     }
@@ -64,20 +67,23 @@ struct Timed {
         hipEvent_t b = get_event();
         if (!b) return;
         (void)hipEventRecord(b, st);
-        t_pending.push_back({fam, a, b, bytes});
+        t_pending.push_back({fam, a, b, bytes, gate});
     }
 };
 
-static void collect_profile()
+// stencil_form: whether the stencil form applied A in the run (flags[2] == 0);
+// a gated launch that returned at once is counted with no bytes
+static void collect_profile(bool stencil_form = false)
 {
     if (t_pending.empty()) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     for (auto &pe : t_pending) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+            const bool idle = (pe.gate == 1 && !stencil_form) || (pe.gate == 2 && stencil_form);
             g_stats[pe.fam].launches += 1;
             g_stats[pe.fam].total_ms += ms;
-            g_stats[pe.fam].bytes += pe.bytes;
+            g_stats[pe.fam].bytes += idle ? 0.0 : pe.bytes;
         }
         t_event_pool.push_back(pe.a);
         t_event_pool.push_back(pe.b);
@@ -138,6 +144,8 @@ size_t plan_layout(Plan &p, char *base)
     p.s_out = (double *)take(sizeof(double) * NCt);
     p.minabs = (double *)take(sizeof(double) * NCt);
     p.jac = (double *)take(p.prec_kind == ECNT_PREC_JACOBI ? sizeof(double) * p.S * p.n : 0);
+    p.st_diag = (double *)take(p.stencil_a ? sizeof(double) * p.n : 0);
+    p.st_coff = (double *)take(p.stencil_a ? sizeof(double) : 0);
     p.e_blk = (double *)take(p.prec_kind == ECNT_PREC_LDL ? sizeof(double) * 2 * p.S * p.n : 0);
     p.band = (double *)take(p.prec_kind == ECNT_PREC_LDL
                                 ? sizeof(double) * 2 * p.S * p.n * (size_t)ldl_ring_rows() : 0);
@@ -358,7 +366,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         return fail(ECNT_EINVAL, "opts.red_waves must be 0 or 64..65536");
     if (o->csr_vw != 0 && o->csr_vw != 1 && o->csr_vw != 2 && o->csr_vw != 4)
         return fail(ECNT_EINVAL, "opts.csr_vw must be 0, 1, 2 or 4");
-    if (o->reserved != 0) return fail(ECNT_EINVAL, "opts.reserved must be 0");
+    if (o->a_form != 0 && o->a_form != 1) return fail(ECNT_EINVAL, "opts.a_form must be 0 or 1");
     const int kmax = o->rule == ECNT_RULE_GA ? kMaxK / 2 : kMaxK;
     if (o->k > kmax) return fail(ECNT_EUNSUPPORTED, "k above %d is not supported", kmax);
     p.n = n;
@@ -441,6 +449,8 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     }
     if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && T->eval == ECNT_EVAL_AUTO)
         p.product = factorize(p) ? 1 : 0;
+    // the grid of the Laplacian preconditioner is where A may be a stencil
+    p.stencil_a = (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && o->a_form == 0) ? 1 : 0;
     return ECNT_OK;
 }
 
@@ -474,6 +484,9 @@ static ecnt_status set_segments(Plan &p, SegHost &sh, int nseg, const int64_t *n
         }
     }
     if (sh.row[nseg] != p.n) return fail(ECNT_EINVAL, "problem sizes do not add up to n");
+    p.st_ref_row = -1;   // the first row of the first problem with an off-diagonal entry
+    for (int b = 0; b < nseg && p.st_ref_row < 0; ++b)
+        if (ns[b] >= 2) p.st_ref_row = sh.row[b];
     col_geometry(p);
     row_geometry(p, sh);
     plan_layout(p, nullptr);
@@ -607,6 +620,10 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
 {
     k_init<<<1, 64, 0, st>>>(p.flags);
     const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
+    if (p.stencil_a && p.a_mode == 0) {
+        Timed t(F_SETUP, csr_b + 8.0 * p.n, st);
+        launch_stencil_check(p, A->row_ptr, A->col_idx, A->val, st);
+    }
     if (p.prec_kind == ECNT_PREC_JACOBI) {
         Timed t(F_SETUP, csr_b + 8.0 * p.S * p.n, st);
         launch_jacobi_diag(p, A->row_ptr, A->col_idx, A->val, st);
@@ -636,6 +653,35 @@ static void enqueue(const Plan &p, const ecnt_csr *A, const void *probes, ecnt_i
     launch_reduce(p, st);
 }
 
+// y = xs .* ((A - tau_c I) x) on the wave's columns.  With the Laplacian
+// preconditioner, A is applied by the stencil sweep when it was found to be a
+// stencil on the grid, else by the CSR sweep.  The single-problem calls learn
+// which before their launches (a_mode 1 or 2); a batch's launch sequence,
+// which takes no host synchronization, launches both, each returning at once
+// when the other one applies (a_mode 0).
+static void apply_A(const Plan &p, const ecnt_csr *A, const void *x, const double *xs, void *y,
+                    hipStream_t st)
+{
+    const double blk_b = block_bytes(p);
+    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * (4 + (p.val_f32 ? 4 : 8));
+    if (p.stencil_a && p.a_mode == 1) {
+        Timed t(F_STA, 2 * blk_b + 8.0 * p.n, st);
+        launch_stencil_a(p, x, xs, y, st);
+        return;
+    }
+    if (p.stencil_a && p.a_mode == 0) {
+        {
+            Timed t(F_STA, 2 * blk_b + 8.0 * p.n, st, 1);
+            launch_stencil_a(p, x, xs, y, st);
+        }
+        Timed t(F_CSR, 2 * blk_b + csr_b, st, 2);
+        launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs, nullptr, y, st, p.flags);
+        return;
+    }
+    Timed t(F_CSR, 2 * blk_b + csr_b, st);
+    launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs, nullptr, y, st);
+}
+
 // One wave of columns for the Arnoldi estimator (Algorithms 3 and 4):
 // w = T (A - tau I) q_j, two classical Gram-Schmidt passes building column j
 // of H, h_{j+1,j} = |w|; then the quadrature of every column.
@@ -659,10 +705,7 @@ static void enqueue_wave_arnoldi(const Plan &p, const ecnt_csr *A, const void *p
         void *y = basis + (size_t)j * slot;         // slot j receives C q_j
         const double *xs = p.sig + (size_t)(j - 1) * p.nseg * p.C;
         if (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN) {
-            {
-                Timed t(F_CSR, 2 * blk_b + csr_b, st);
-                launch_csr_op(p, A->row_ptr, A->col_idx, A->val, x, xs, nullptr, p.tmp[0], st);
-            }
+            apply_A(p, A, x, xs, p.tmp[0], st);
             apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);   // T u
         } else {
             Timed t(F_CSR, 2 * blk_b + csr_b, st);
@@ -708,10 +751,7 @@ static void apply_op(const Plan &p, const ecnt_csr *A, void *x, const double *xs
         // t = M q ; u = (A - tau I) t ; y = M u   (t kept per step for the backward)
         void *t = p.grad ? (char *)p.g_tslots + (size_t)(i - 1) * slot : p.tmp[2];
         apply_M(p, x, xs, p.tmp[0], p.tmp[1], t, t, false, st);
-        {
-            Timed tm(F_CSR, 2 * blk_b + csr_b, st);
-            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, t, nullptr, nullptr, p.tmp[0], st);
-        }
+        apply_A(p, A, t, nullptr, p.tmp[0], st);
         apply_M(p, p.tmp[0], nullptr, p.tmp[1], p.tmp[2], y, y, false, st);
     } else if (p.prec_kind == ECNT_PREC_LDL) {
         // t = M^* q = P^T L^{-T} (|D|^{-1/2} q) ; u = (A - tau I) t ;
@@ -859,7 +899,6 @@ static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, dou
 {
     const size_t slot = slot_bytes(p);
     const double blk_b = block_bytes(p);
-    const double csr_b = (double)(p.n + 1) * 4 + (double)A->nnz * 12;
     {
         Timed t(F_QUAD, 0.0, st);
         launch_tridiag_bwd(p, g_out, st);
@@ -885,10 +924,7 @@ static void enqueue_backward(const Plan &p, const ecnt_csr *A, double g_out, dou
         }
         // qbar_i += C ybar:  tbar = M ybar ; u = (A - tau I) tbar ; qbar_i += M u
         apply_M(p, p.g_ybar, nullptr, p.tmp[0], p.tmp[1], p.g_tbar, p.g_tbar, false, st);
-        {
-            Timed t(F_CSR, 2 * blk_b + csr_b, st);
-            launch_csr_op(p, A->row_ptr, A->col_idx, A->val, p.g_tbar, nullptr, nullptr, p.tmp[2], st);
-        }
+        apply_A(p, A, p.g_tbar, nullptr, p.tmp[2], st);
         double *qbi = (double *)((char *)p.g_qbar + (size_t)(i - 1) * slot);
         apply_M(p, p.tmp[2], nullptr, p.tmp[0], p.tmp[1], p.g_ybar, qbi, true, st);
         {
@@ -955,7 +991,7 @@ static ecnt_status finish(const Plan &p, hipStream_t st, double *res_host, ecnt_
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
-    collect_profile();
+    collect_profile(p.a_mode == 1 || (p.stencil_a && p.a_mode == 0 && flags[2] == 0));
     if (flags[0]) return fail(ECNT_ENOTHPD, "Jacobi preconditioner singular: a_rr == tau for some row");
     if (flags[1]) return fail(ECNT_EDEVICE, "tridiagonal eigensolver did not converge");
     return ECNT_OK;
@@ -1053,6 +1089,15 @@ static ecnt_status run(const ecnt_csr *A, const ecnt_prec *T, const double *taus
     hipStream_t st = (hipStream_t)stream;
     rc = upload_tables(p, sh, st);
     if (rc) return rc;
+    if (p.stencil_a) {   // which form applies A: check once, before the launch sequence
+        int32_t flag = 1;
+        k_init<<<1, 64, 0, st>>>(p.flags);
+        launch_stencil_check(p, A->row_ptr, A->col_idx, A->val, st);
+        hipError_t e = hipMemcpyAsync(&flag, p.flags + 2, sizeof flag, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(ECNT_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+        p.a_mode = flag == 0 ? 1 : 2;
+    }
     begin_launches();
     if (mode != 2) enqueue(p, A, probes, info, st);
     if (mode == 2 || mode == 3) enqueue_backward(p, A, g_out, dV, st);

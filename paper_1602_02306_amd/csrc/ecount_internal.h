@@ -99,7 +99,15 @@ struct Plan {
     double *result = nullptr;  // 4*S + 8 small results
     int32_t *active = nullptr; // C
     int32_t *kused = nullptr;  // Ct
-    int32_t *flags = nullptr;  // 4 status flags
+    int32_t *flags = nullptr;  // 4 status flags: Jacobi singular, tridiagonal diverged,
+                               // A not of the stencil form
+    // ---- A applied as a grid stencil (Laplacian-polynomial preconditioner) ----
+    int stencil_a = 0;         // A may be a stencil on the preconditioner's grid
+    int a_mode = 0;            // 0: decided on the device (both forms launched, each gated
+                               // on flags[2]); 1: the stencil form; 2: the CSR form
+    int64_t st_ref_row = -1;   // row whose first off-diagonal value is a_off
+    double *st_diag = nullptr; // n: diagonal of A
+    double *st_coff = nullptr; // 1: a_off
     // ---- LDL preconditioner: one factor per shift, |D|^{-1/2} blocks ----
     LdlDev ldl[kMaxShifts];
     double *e_blk = nullptr;   // S * 2n: e_diag then e_off of every shift
@@ -172,9 +180,17 @@ void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *co
 void launch_setup(const Plan &p, const void *probes, hipStream_t st);
 void launch_setup_fin(const Plan &p, hipStream_t st);
 // y = M (A - tau_c I) M x  for the Jacobi / no-preconditioner path (one fused sweep)
+// (gate: the status flags; the launch does nothing when flags[2] == 0, i.e.
+// when the stencil form applies A)
 void launch_csr_op(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
                    const void *x, const double *xscale, const double *pre_post, void *y,
-                   hipStream_t st);
+                   hipStream_t st, const int32_t *gate = nullptr);
+// A as a grid stencil: the pattern / value check (sets flags[2] if A is not of
+// that form, fills st_diag, st_coff) and y = xs .* ((A - tau_c I) x) by a
+// stencil sweep that runs only when the check passed
+void launch_stencil_check(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
+                          const void *val, hipStream_t st);
+void launch_stencil_a(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st);
 // out = cx*xs*X + cb*B(ins*IN) - cz*Z  (one stencil sweep on the grid Laplacian)
 void launch_stencil(const Plan &p, const void *X, const double *xs, double cx, const void *IN,
                     bool in_is_x, double cb, const void *Z, double cz, void *out, hipStream_t st);

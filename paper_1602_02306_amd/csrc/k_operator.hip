@@ -53,8 +53,10 @@ __global__ __launch_bounds__(256) void k_csr_op(int64_t n, int C, int m, int c_o
                                                 const double *__restrict__ xs,
                                                 const double *__restrict__ jac,
                                                 const double *__restrict__ seg_taus, T *__restrict__ y,
-                                                int remap)
+                                                int remap, const int32_t *__restrict__ gate)
 {
+    // gate (the status flags): the stencil form applied A already unless flags[2] is set
+    if (gate && gate[2] == 0) return;
     const int64_t L = remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int cg = (int)(L % ncg);
     const int64_t r0 = ((L / ncg) * 4 + uniform(threadIdx.x >> 6)) * RPW;
@@ -774,6 +776,277 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
     }
 }
 
+// ---- A as a grid stencil ----
+// A of the form L_off + diag(d) on each problem's grid (the (2*ndim+1)-point
+// pattern, every off-diagonal entry equal to one value a_off, any diagonal:
+// a kinetic stencil plus a local potential) is applied by a z-march like
+// k_stencil instead of row by row: the x rows of neighbouring grid planes
+// then come from registers and from the L2 copies of neighbouring line
+// blocks rather than from HBM again.
+//
+// k_stencil_check verifies, per row, that its CSR entries are exactly the
+// in-grid neighbours and the diagonal in ascending column order and that the
+// off-diagonal values equal a_off (the first off-diagonal of row ref_row, the
+// first row of the first problem with more than one row); it copies the
+// diagonal to `diag` and a_off to coff[0].  Any mismatch sets flags[2]:
+// the CSR sweep then applies A instead (both kernels read the flag).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_stencil_check(int64_t n, int nseg,
+                                                       const int64_t *__restrict__ seg_row,
+                                                       const int32_t *__restrict__ seg_dims,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const VT *__restrict__ val, int64_t ref_row,
+                                                       double *__restrict__ diag,
+                                                       double *__restrict__ coff,
+                                                       int32_t *__restrict__ flags)
+{
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n) return;
+    // the reference row has its diagonal and at least one neighbour when A is of the form
+    const bool refok = ref_row < 0 || rp[ref_row + 1] - rp[ref_row] >= 2;
+    const double ref = (ref_row >= 0 && refok) ? static_cast<double>(val[rp[ref_row] + 1]) : 0.0;
+    if (r == 0) coff[0] = ref;
+    if (!refok) atomicOr(&flags[2], 1);
+    const int seg = find_seg(seg_row, nseg, r);
+    const int64_t d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int64_t rl = r - seg_row[seg];
+    const int64_t x = rl / (d1 * d2), y = (rl / d2) % d1, z = rl % d2;
+    // expected columns in ascending order; slot 3 is the diagonal
+    int64_t col[7];
+    bool has[7];
+    has[0] = x > 0;      col[0] = r - d1 * d2;
+    has[1] = y > 0;      col[1] = r - d2;
+    has[2] = z > 0;      col[2] = r - 1;
+    has[3] = true;       col[3] = r;
+    has[4] = z < d2 - 1; col[4] = r + 1;
+    has[5] = y < d1 - 1; col[5] = r + d2;
+    has[6] = x < d0 - 1; col[6] = r + d1 * d2;
+    int cnt = 0;
+    for (int k = 0; k < 7; ++k) cnt += has[k] ? 1 : 0;
+    const int32_t p0 = rp[r], len = rp[r + 1] - p0;
+    bool ok = len == cnt;
+    double dg = 0.0;
+    if (ok) {
+        int p = p0;
+        for (int k = 0; k < 7; ++k) {
+            if (!has[k]) continue;
+            const double v = static_cast<double>(val[p]);
+            ok = ok && ci[p] == col[k];
+            if (k == 3) dg = v;
+            else ok = ok && v == ref;
+            ++p;
+        }
+    }
+    diag[r] = dg;
+    if (!ok) atomicOr(&flags[2], 1);
+}
+
+// y = xs_c * ((A - tau_c I) x) with A = a_off * (grid neighbours) + diag(d),
+// summed in the order the CSR sweep sums a row (ascending columns, then the
+// shift), so both forms give the same values.  Line blocks as in k_stencil;
+// a tile of QX*TX by QY*TY lines is split into QX*QY wavefronts.  Runs only
+// when k_stencil_check found the stencil form (flags[2] == 0).
+template <typename T, int VW, int TX, int TY, int QX, int QY>
+__global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int ncg, int S, int nseg,
+                                                   const int64_t *__restrict__ seg_row,
+                                                   const int64_t *__restrict__ seg_tile,
+                                                   const int32_t *__restrict__ seg_dims,
+                                                   int64_t ntiles, const T *__restrict__ IN,
+                                                   const double *__restrict__ xs_all,
+                                                   const double *__restrict__ diag,
+                                                   const double *__restrict__ coff,
+                                                   const double *__restrict__ seg_taus,
+                                                   const int32_t *__restrict__ flags,
+                                                   T *__restrict__ out)
+{
+    if (flags[2] != 0) return;
+    constexpr int Q = QX * QY;
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t gw = L * 4 + uniform(threadIdx.x >> 6);
+    const int64_t per_cg = ntiles * Q;
+    const int cg = (int)(gw / per_cg);
+    if (cg >= ncg) return;
+    const int64_t rem = gw % per_cg;
+    const int64_t tile = rem / Q;
+    const int q = (int)(rem % Q);
+    const int lane = threadIdx.x & 63;
+    const int c0 = (cg * 64 + lane) * VW;
+    if (c0 >= C) return;
+    const int seg = find_seg(seg_tile, nseg, tile);
+    const int d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int nty = (d1 + QY * TY - 1) / (QY * TY);
+    const int lt = (int)(tile - seg_tile[seg]);
+    const int x0 = (lt / nty) * (QX * TX) + (q % QX) * TX;
+    const int y0 = (lt % nty) * (QY * TY) + (q / QX) * TY;
+    if (x0 >= d0 || y0 >= d1) return;
+    const double *xs = xs_all ? xs_all + (size_t)seg * C : nullptr;
+    const double aoff = coff[0];
+    const size_t zs = (size_t)C, ys = (size_t)d2 * C, xs_ = (size_t)d1 * d2 * C;
+    const int64_t row0 = seg_row[seg] + (int64_t)x0 * d1 * d2 + (int64_t)y0 * d2;
+    const size_t base = (size_t)row0 * C + c0;
+    size_t off[TX][TY];
+    int64_t roff[TX][TY];
+    double wt[TX][TY];
+    size_t offym[TX], offyp[TX], offxm[TY], offxp[TY];
+    double wym[TX], wyp[TX], wxm[TY], wxp[TY];
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+            const bool ok = x0 + a < d0 && y0 + b < d1;
+            off[a][b] = ok ? (size_t)a * xs_ + (size_t)b * ys : 0;
+            roff[a][b] = ok ? (int64_t)a * d1 * d2 + (int64_t)b * d2 : 0;
+            wt[a][b] = ok ? 1.0 : 0.0;
+        }
+#pragma unroll
+    for (int a = 0; a < TX; ++a) {
+        const bool okx = x0 + a < d0;
+        const bool okm = okx && y0 > 0, okp = okx && y0 + TY < d1;
+        offym[a] = okm ? (size_t)a * xs_ - ys : 0;
+        offyp[a] = okp ? (size_t)a * xs_ + (size_t)TY * ys : 0;
+        wym[a] = okm ? 1.0 : 0.0;
+        wyp[a] = okp ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < TY; ++b) {
+        const bool oky = y0 + b < d1;
+        const bool okm = oky && x0 > 0, okp = oky && x0 + TX < d0;
+        offxm[b] = okm ? (size_t)b * ys - xs_ : 0;
+        offxp[b] = okp ? (size_t)b * ys + (size_t)TX * xs_ : 0;
+        wxm[b] = okm ? 1.0 : 0.0;
+        wxp[b] = okp ? 1.0 : 0.0;
+    }
+    double xsc[VW], tau[VW];
+#pragma unroll
+    for (int v = 0; v < VW; ++v) {
+        xsc[v] = xs ? xs[c0 + v] : 1.0;
+        tau[v] = seg_taus[(size_t)seg * S + (c_off + c0 + v) / m];
+    }
+    double prev[TX][TY][VW], cur[TX][TY][VW];
+#pragma unroll
+    for (int a = 0; a < TX; ++a)
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+            double t[VW];
+            vload<T, VW>(IN, base + off[a][b], t);
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+                prev[a][b][v] = 0.0;
+                cur[a][b][v] = wt[a][b] * t[v];
+            }
+        }
+    struct StepLoads {
+        double nxt[TX][TY][VW], ym[TX][VW], yp[TX][VW], xm[TY][VW], xp[TY][VW], dg[TX][TY];
+    };
+    auto issue = [&](StepLoads &Ld, int z) {
+        const size_t ez = base + (size_t)z * zs;
+        const size_t en = z + 1 < d2 ? ez + zs : ez;
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TY; ++b) vload<T, VW>(IN, en + off[a][b], Ld.nxt[a][b]);
+#pragma unroll
+        for (int a = 0; a < TX; ++a) {
+            vload<T, VW>(IN, ez + offym[a], Ld.ym[a]);
+            vload<T, VW>(IN, ez + offyp[a], Ld.yp[a]);
+        }
+#pragma unroll
+        for (int b = 0; b < TY; ++b) {
+            vload<T, VW>(IN, ez + offxm[b], Ld.xm[b]);
+            vload<T, VW>(IN, ez + offxp[b], Ld.xp[b]);
+        }
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TY; ++b) Ld.dg[a][b] = diag[row0 + roff[a][b] + z];
+    };
+    auto compute = [&](const StepLoads &Ld, int z) {
+        const size_t ez = base + (size_t)z * zs;
+        const double zn = z + 1 < d2 ? 1.0 : 0.0;
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TY; ++b) {
+                double o[VW];
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    const double nxm = a > 0 ? cur[a - 1][b][v] : wxm[b] * Ld.xm[b][v];
+                    const double nym = b > 0 ? cur[a][b - 1][v] : wym[a] * Ld.ym[a][v];
+                    const double nyp = b + 1 < TY ? cur[a][b + 1][v] : wyp[a] * Ld.yp[a][v];
+                    const double nxp = a + 1 < TX ? cur[a + 1][b][v] : wxp[b] * Ld.xp[b][v];
+                    double acc = 0.0;
+                    acc += aoff * nxm;
+                    acc += aoff * nym;
+                    acc += aoff * prev[a][b][v];
+                    acc += Ld.dg[a][b] * cur[a][b][v];
+                    acc += aoff * (zn * Ld.nxt[a][b][v]);
+                    acc += aoff * nyp;
+                    acc += aoff * nxp;
+                    const double r = acc - tau[v] * cur[a][b][v];
+                    o[v] = r * xsc[v];
+                }
+                if (wt[a][b] != 0.0) vstore_nt<T, VW>(out, ez + off[a][b], o);
+            }
+#pragma unroll
+        for (int a = 0; a < TX; ++a)
+#pragma unroll
+            for (int b = 0; b < TY; ++b)
+#pragma unroll
+                for (int v = 0; v < VW; ++v) {
+                    prev[a][b][v] = cur[a][b][v];
+                    cur[a][b][v] = wt[a][b] * Ld.nxt[a][b][v];
+                }
+    };
+    for (int z = 0; z < d2; ++z) {
+        StepLoads Ld;
+        issue(Ld, z);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(Ld, z);
+    }
+}
+
+void launch_stencil_check(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
+                          const void *val, hipStream_t st)
+{
+    dim3 grid((unsigned)((p.n + 255) / 256));
+    if (p.val_f32)
+        k_stencil_check<float><<<grid, 256, 0, st>>>(p.n, p.nseg, p.seg_row, p.seg_dims, row_ptr,
+                                                     col_idx, (const float *)val, p.st_ref_row,
+                                                     p.st_diag, p.st_coff, p.flags);
+    else
+        k_stencil_check<double><<<grid, 256, 0, st>>>(p.n, p.nseg, p.seg_row, p.seg_dims, row_ptr,
+                                                      col_idx, (const double *)val, p.st_ref_row,
+                                                      p.st_diag, p.st_coff, p.flags);
+}
+
+template <typename T, int VW, int TX, int TY, int QX, int QY>
+static void stencil_a_t(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st)
+{
+    const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
+    const int64_t waves = p.ntiles * QX * QY * ncg;
+    k_stencil_a<T, VW, TX, TY, QX, QY><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(
+        p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles,
+        (const T *)x, xs, p.st_diag, p.st_coff, p.seg_taus, p.flags, (T *)y);
+}
+
+template <typename T, int VW>
+static void stencil_a_shape(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st)
+{
+    if (p.tx == 8) stencil_a_t<T, VW, 4, 4, 2, 2>(p, x, xs, y, st);   // 8 x 8 tiles: four 4 x 4 quadrants
+    else if (p.tx == 4) stencil_a_t<T, VW, 4, 4, 1, 1>(p, x, xs, y, st);
+    else if (p.tx == 2) stencil_a_t<T, VW, 2, 4, 1, 1>(p, x, xs, y, st);
+    else stencil_a_t<T, VW, 1, 8, 1, 1>(p, x, xs, y, st);
+}
+
+void launch_stencil_a(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st)
+{
+    // one column per lane (FP64) / two (FP32, when the width is even), as the plain sweep
+    if (p.vec_f32 && p.C % 2 == 0) stencil_a_shape<float, 2>(p, x, xs, y, st);
+    else if (p.vec_f32) stencil_a_shape<float, 1>(p, x, xs, y, st);
+    else stencil_a_shape<double, 1>(p, x, xs, y, st);
+}
+
 void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
                         const void *val, hipStream_t st)
 {
@@ -792,43 +1065,45 @@ void launch_jacobi_diag(const Plan &p, const int32_t *row_ptr, const int32_t *co
 template <typename T, typename VT, int VW, int RPW = (VW == 4 ? 1 : 2), int NZ = (VW == 4 ? 4 : 8)>
 static void csr_op_t(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
                      const void *x, const double *xs, const double *jac, void *y, hipStream_t st,
-                     int remap = (VW == 4 ? 1 : 0))
+                     const int32_t *gate, int remap = (VW == 4 ? 1 : 0))
 {
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
     dim3 grid((unsigned)(((p.n + 4 * RPW - 1) / (4 * RPW)) * ncg));
     if (jac)
         k_csr_op<T, VT, true, VW, RPW, NZ><<<grid, 256, 0, st>>>(
             p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, rp, ci, (const VT *)val,
-            (const T *)x, xs, jac, p.seg_taus, (T *)y, remap);
+            (const T *)x, xs, jac, p.seg_taus, (T *)y, remap, gate);
     else
         k_csr_op<T, VT, false, VW, RPW, NZ><<<grid, 256, 0, st>>>(
             p.n, p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, rp, ci, (const VT *)val,
-            (const T *)x, xs, nullptr, p.seg_taus, (T *)y, remap);
+            (const T *)x, xs, nullptr, p.seg_taus, (T *)y, remap, gate);
 }
 
 template <typename T, typename VT>
 static void csr_op_vw(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
-                      const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
+                      const void *x, const double *xs, const double *jac, void *y, hipStream_t st,
+                      const int32_t *gate)
 {
     if constexpr (sizeof(T) == 4) {
         if (p.vw == 4) {
-            csr_op_t<T, VT, 4>(p, rp, ci, val, x, xs, jac, y, st);
+            csr_op_t<T, VT, 4>(p, rp, ci, val, x, xs, jac, y, st, gate);
             return;
         }
     }
-    if (p.vw == 2) csr_op_t<T, VT, 2>(p, rp, ci, val, x, xs, jac, y, st);
-    else csr_op_t<T, VT, 1>(p, rp, ci, val, x, xs, jac, y, st);
+    if (p.vw == 2) csr_op_t<T, VT, 2>(p, rp, ci, val, x, xs, jac, y, st, gate);
+    else csr_op_t<T, VT, 1>(p, rp, ci, val, x, xs, jac, y, st, gate);
 }
 
 void launch_csr_op(const Plan &p, const int32_t *rp, const int32_t *ci, const void *val,
-                   const void *x, const double *xs, const double *jac, void *y, hipStream_t st)
+                   const void *x, const double *xs, const double *jac, void *y, hipStream_t st,
+                   const int32_t *gate)
 {
     if (p.vec_f32) {
-        if (p.val_f32) csr_op_vw<float, float>(p, rp, ci, val, x, xs, jac, y, st);
-        else csr_op_vw<float, double>(p, rp, ci, val, x, xs, jac, y, st);
+        if (p.val_f32) csr_op_vw<float, float>(p, rp, ci, val, x, xs, jac, y, st, gate);
+        else csr_op_vw<float, double>(p, rp, ci, val, x, xs, jac, y, st, gate);
     } else {
-        if (p.val_f32) csr_op_vw<double, float>(p, rp, ci, val, x, xs, jac, y, st);
-        else csr_op_vw<double, double>(p, rp, ci, val, x, xs, jac, y, st);
+        if (p.val_f32) csr_op_vw<double, float>(p, rp, ci, val, x, xs, jac, y, st, gate);
+        else csr_op_vw<double, double>(p, rp, ci, val, x, xs, jac, y, st, gate);
     }
 }
 

@@ -622,3 +622,67 @@ def test_smooth_rejects_unsupported(ec):
     with pytest.raises(ec.EcntError) as e:
         ec.smooth_forward(Ad, P.prec, wl.xi, wl.eta, Vd, wl.k, 0.05)   # Jacobi M depends on A
     assert e.value.status == ec.ECNT_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# A as a grid stencil (a_form auto) against the CSR sweep (a_form csr)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,vec", [("c2_small", "f64"), ("c2_ragged", "f64"), ("c2_ragged", "f32")])
+def test_a_stencil_form_equals_csr_form(ec, name, vec):
+    """When A is the grid stencil plus a diagonal, the stencil sweep applies it;
+    it sums each row as the CSR sweep does, so both forms agree bitwise."""
+    wl = W.WORKLOADS[name]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    print("case a-form", name, vec, flush=True)
+    ec.profile_enable(True)
+    a = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec=vec, val=vec)
+    prof = ec.profile_read()
+    ec.profile_enable(False)
+    b = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec=vec, val=vec, tune={"a_form": "csr"})
+    assert prof["op_a_stencil"]["bytes"] > 0 and prof["op_csr"]["bytes"] == 0
+    assert a.estimate == b.estimate
+    assert torch.equal(a.per_probe, b.per_probe)
+    assert torch.equal(a.alpha, b.alpha) and torch.equal(a.beta, b.beta)
+
+
+def _perturbed(A, rng, how):
+    """A copy of A (CSR, both triangles) that is not of the stencil form:
+    'coef' scales every symmetric off-diagonal pair by its own factor in
+    [0.9, 1.1]; 'extra' adds one symmetric pair of long-range entries."""
+    import scipy.sparse as sp
+    S = A.to_scipy().tocoo()
+    r, c, v = S.row.copy(), S.col.copy(), S.data.copy()
+    if how == "coef":
+        lo, hi = np.minimum(r, c), np.maximum(r, c)
+        f = 1.0 + 0.1 * (2.0 * rng.random(A.n * 8) - 1.0)
+        key = (lo * 7919 + hi) % f.size
+        v = np.where(r != c, v * f[key], v)
+    else:
+        i, j = 3, A.n - 5
+        r = np.concatenate([r, [i, j]])
+        c = np.concatenate([c, [j, i]])
+        v = np.concatenate([v, [-0.25, -0.25]])
+    M = sp.csr_matrix((v, (r, c)), shape=(A.n, A.n))
+    M.sort_indices()
+    return W.CSR(A.n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("how", ["coef", "extra"])
+def test_a_not_a_stencil_falls_back_to_csr(ec, how):
+    """Variable off-diagonal coefficients, or a coupling outside the stencil:
+    the device check rejects the stencil form and the CSR sweep applies A
+    (parity with the oracle on the perturbed matrix)."""
+    wl = W.WORKLOADS["c2_ragged"]
+    P = W.make_problem(wl)
+    A2 = _perturbed(P.A, np.random.default_rng(3), how)
+    V = W.make_probes(wl)
+    print("case a-form fallback", how, flush=True)
+    ec.profile_enable(True)
+    r = gpu_count(ec, A2, P.prec, wl.xi, wl.eta, V, wl.k)
+    prof = ec.profile_read()
+    ec.profile_enable(False)
+    assert prof["op_csr"]["bytes"] > 0 and prof["op_a_stencil"]["bytes"] == 0
+    ref = oracle.count(A2, P.prec, wl.xi, wl.eta, V, wl.k)
+    assert_parity(r, ref, wl.k)
