@@ -186,7 +186,7 @@ def cpu_baseline_batch(items, V, off, k: int, target_s: float, m_total: int, gpu
     return out
 
 
-def bench_negcount_ldl(args, wl):
+def bench_negcount_ldl(args, wl, ceilings=None):
     """n_(A - tau I) with the factored ILDL preconditioner (Table 1 Laplace):
     the library factors A - tau I on the host once (outside the timed
     region); one step = one ecnt_negcounts over the m probes."""
@@ -364,7 +364,7 @@ def bench_graph_single(args, name: str):
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(args, name: str):
+def bench_batched(args, name: str, ceilings=None):
     """The batched form: 64 problems of uneven size in one launch sequence,
     captured once into a graph and replayed; one step = one whole batch."""
     import torch
@@ -452,10 +452,10 @@ def bench_batched(args, name: str):
                    "tuned": cfg["source"]},
         "hbm_gbs_algorithmic": algo_bytes / (total_kernel_ms / 1e3) / 1e9 if total_kernel_ms else None,
         "algorithmic_bytes_per_probe_step": algo_bytes / probe_steps,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": per_launch_bytes,
-                     "avg_launch_ms": per_launch_ms},
+        "roofline": add_ceiling({"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                                 "algorithmic_bytes_per_launch": per_launch_bytes,
+                                 "avg_launch_ms": per_launch_ms}, ceilings),
         "kernels": {f: {"launches_per_step": v["launches"], "ms_per_step": v["ms"],
                         "share": v["ms"] / total_kernel_ms,
                         "gbs": (v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["bytes"] > 0 else None}
@@ -473,6 +473,37 @@ def bench_batched(args, name: str):
         pp = btd.run().per_probe.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline_batch(items, V, off, k, args.cpu_seconds, m, pp)
     print(json.dumps(out), flush=True)
+
+
+CEILING_KIND = {"lz_update": "update_mix", "bw_update": "update_mix", "blk_update": "update_mix",
+                "lz_dots": "read", "bw_dots": "read", "blk_dots": "read"}
+
+
+def measure_ceilings(args):
+    """Tuned streams on this device (ecnt_hbm_probe: 1 GiB streams), measured
+    in the same run as the bench: what the sweeps' access mixes can reach."""
+    if args.no_ceiling:
+        return None
+    import torch
+    from paper_1602_02306_amd import ecount as ec
+    free, _ = torch.cuda.mem_get_info()
+    nbytes = 18 << 30 if free > (40 << 30) else 1 << 30
+    out = {k: ec.hbm_probe(k, nbytes if k == "update_mix" else min(nbytes, 2 << 30))
+           for k in ("copy", "read", "update_mix")}
+    torch.cuda.empty_cache()
+    log("HBM ceilings (GB/s): %s" % {k: round(v) for k, v in out.items()})
+    return out
+
+
+def add_ceiling(roof: dict, ceilings):
+    """The dominant kernel's achieved GB/s against the tuned stream of its own
+    access mix (besides the data-sheet peak in `frac`)."""
+    if not ceilings or not roof.get("kernel"):
+        return roof
+    kind = CEILING_KIND.get(roof["kernel"], "copy")
+    roof["ceiling"] = {"kind": kind, "gbs": ceilings[kind], "frac": roof["achieved"] / ceilings[kind],
+                       "measured": {k: v for k, v in ceilings.items()}}
+    return roof
 
 
 def traffic_from_profiles(family: str, per_launch_algo: float, workload: str = "c2"):
@@ -506,11 +537,12 @@ FAMILY_OF = [("k_blk_update<true>", "blk_normalize"), ("k_blk_update", "blk_upda
              ("k_bdots_fin", "lz_finalize"),
              ("k_bnorm_fin", "lz_finalize"), ("k_rowsum", "lz_finalize"), ("k_vgrad", "bw_vgrad"),
              ("k_bdots", "bw_dots"), ("k_bupdate", "bw_update"), ("k_grad_", "lz_finalize"),
+             ("k_stencil_check", "lz_setup"), ("k_stencil_a", "op_a_stencil"),
              ("k_stencil", "op_cheb_sweep"), ("k_csr_op", "op_csr"), ("k_dots_fin", "lz_finalize"),
              ("k_dots", "lz_dots"), ("k_update", "lz_update"), ("k_setup_fin", "lz_finalize"),
              ("k_setup", "lz_setup"), ("k_norm_fin", "lz_finalize"), ("k_jacobi_diag", "lz_setup"),
              ("k_tridiag", "quadrature"), ("k_reduce", "quadrature"), ("k_init", "lz_finalize"),
-             ("copyBuffer", "copy"), ("FillFunc", "fill")]
+             ("k_probe", "hbm_probe"), ("copyBuffer", "copy"), ("FillFunc", "fill")]
 
 
 def family(kernel_name: str) -> str:
@@ -634,6 +666,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the HBM stream probes")
     ap.add_argument("--copy-calib", action="store_true")
     ap.add_argument("--k-sweep", metavar="K1,K2,...",
                     help="count error against the exact count and probe-steps/s at each k "
@@ -675,15 +708,16 @@ def main():
     if args.k_sweep:
         k_sweep(args)
         return
+    ceilings = measure_ceilings(args)
     if args.workload in BATCH:
-        bench_batched(args, args.workload)
+        bench_batched(args, args.workload, ceilings)
         return
     if args.workload == "c1_graph":
         bench_graph_single(args, "c1")
         return
     if args.workload == "t1":
         from paper_1602_02306_amd import workloads as W
-        bench_negcount_ldl(args, W.WORKLOADS["t1"])
+        bench_negcount_ldl(args, W.WORKLOADS["t1"], ceilings)
         return
 
     from paper_1602_02306_amd import ecount as ec
@@ -821,10 +855,10 @@ def main():
                    "probe_steps_per_step": probe_steps},
         "hbm_gbs_algorithmic": algo_bytes / (ms / 1e3) / 1e9,
         "algorithmic_bytes_per_probe_step": algo_bytes / probe_steps,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": per_launch_bytes,
-                     "avg_launch_ms": per_launch_ms},
+        "roofline": add_ceiling({"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                                 "algorithmic_bytes_per_launch": per_launch_bytes,
+                                 "avg_launch_ms": per_launch_ms}, ceilings),
         "kernels": kernels,
         "accuracy": accuracy,
         "kernel_sources_sha": kernel_sources_sha(),

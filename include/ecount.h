@@ -481,6 +481,19 @@ ECNT_API ecnt_status ecnt_profile_enable(int32_t on);
 /* Copies up to `max` families into `out`; returns how many were written. */
 ECNT_API int32_t ecnt_profile_read(ecnt_kernel_stat *out, int32_t max);
 
+/* Bandwidth probe, for measurement: effective GB/s of a simple stream on the
+ * current device, timed with HIP events over `reps` launches on `stream`
+ * (synchronizes it).  kind 0: copy (16-byte loads and non-temporal stores,
+ * four in flight per lane), 1: read only, 2: the read/write mix of one
+ * Gram-Schmidt update sweep (16 vectors read, one read and written back).
+ * `buf` is device scratch of `bytes` (copy/read use two halves, the mix 17
+ * equal streams; at least 64 MiB, 1 GiB streams or more for stable numbers);
+ * its contents are overwritten.  These bound what the estimator's sweeps can
+ * reach; a roofline fraction can be quoted against them besides the peak.
+ * Errors: EINVAL (bad kind, null pointer, buffer too small), EDEVICE. */
+ECNT_API ecnt_status ecnt_hbm_probe(int32_t kind, void *buf, size_t bytes, int32_t reps,
+                                    void *stream, double *gbs);
+
 /* Message for the last failed call on this thread ("" if none). */
 ECNT_API const char *ecnt_last_error(void);
 

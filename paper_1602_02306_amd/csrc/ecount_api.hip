@@ -252,6 +252,8 @@ static void row_geometry(Plan &p, SegHost &sh)
     }
     p.nchunk = (int)sh.chunk[p.nseg];
     p.ntiles = sh.tile[p.nseg];
+    p.max_d2 = 1;
+    for (int b = 0; b < p.nseg; ++b) p.max_d2 = sh.dims[3 * b + 2] > p.max_d2 ? sh.dims[3 * b + 2] : p.max_d2;
 }
 
 // ---- product form of the preconditioner polynomial ----
@@ -1535,6 +1537,19 @@ ecnt_status ecnt_smooth_bwd(const ecnt_csr *A, const ecnt_prec *T, double xi, do
     if (rc) return rc;
     *dxi = res[4 * kMaxShifts + 0];
     *deta = res[4 * kMaxShifts + 1];
+    return ECNT_OK;
+}
+
+ecnt_status ecnt_hbm_probe(int32_t kind, void *buf, size_t bytes, int32_t reps, void *stream,
+                           double *gbs)
+{
+    g_err.clear();
+    if (kind < 0 || kind > 2) return fail(ECNT_EINVAL, "probe kind must be 0, 1 or 2");
+    if (!buf || !gbs) return fail(ECNT_EINVAL, "null buffer or output");
+    if (bytes < ((size_t)64 << 20)) return fail(ECNT_EINVAL, "probe buffer below 64 MiB");
+    if (reps < 1) return fail(ECNT_EINVAL, "reps must be >= 1");
+    if (run_probe(kind, buf, bytes, reps, (hipStream_t)stream, gbs) != 0)
+        return fail(ECNT_EDEVICE, "probe failed: %s", hipGetErrorString(hipGetLastError()));
     return ECNT_OK;
 }
 

@@ -52,6 +52,7 @@ struct Plan {
     int val_f32 = 0;      // A values FP32
     int prec_kind = 0;
     int ndim = 0, dims[3] = {1, 1, 1};
+    int max_d2 = 1;            // largest z extent of the segments' grids
     int degree = 0;
     double coef[17] = {0};
     double s = 0, lo = 0, hi = 0;
@@ -233,6 +234,9 @@ void launch_blk_quad(const Plan &p, hipStream_t st);
 void launch_ldl_eblocks(const Plan &p, hipStream_t st);
 void launch_ldl(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st);
 int ldl_ring_rows();
+
+// bandwidth probes (k_probe.hip): 0 copy, 1 read, 2 update mix; 0 ok, -1 HIP error
+int run_probe(int kind, void *buf, size_t bytes, int reps, hipStream_t st, double *gbs);
 
 // the message ecnt_last_error() returns; gives back st
 int32_t set_error(int32_t st, const char *msg);

@@ -845,10 +845,15 @@ __global__ __launch_bounds__(256) void k_stencil_check(int64_t n, int nseg,
 // y = xs_c * ((A - tau_c I) x) with A = a_off * (grid neighbours) + diag(d),
 // summed in the order the CSR sweep sums a row (ascending columns, then the
 // shift), so both forms give the same values.  Line blocks as in k_stencil;
-// a tile of QX*TX by QY*TY lines is split into QX*QY wavefronts.  Runs only
-// when k_stencil_check found the stencil form (flags[2] == 0).
+// a tile of QX*TX by QY*TY lines is split into QX*QY wavefronts, and the z
+// range into nzc chunks (a wavefront per chunk, starting from its own z-1
+// plane): more wavefronts in flight for the same loads.  Wavefront order:
+// column group, z chunk, tile, quadrant (fastest), so that neighbouring line
+// blocks at the same z run together and share their boundary lines in L2.
+// Runs only when k_stencil_check found the stencil form (flags[2] == 0).
 template <typename T, int VW, int TX, int TY, int QX, int QY>
-__global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int ncg, int S, int nseg,
+__global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int ncg, int nzc, int S,
+                                                   int nseg,
                                                    const int64_t *__restrict__ seg_row,
                                                    const int64_t *__restrict__ seg_tile,
                                                    const int32_t *__restrict__ seg_dims,
@@ -864,10 +869,11 @@ __global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int 
     constexpr int Q = QX * QY;
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t gw = L * 4 + uniform(threadIdx.x >> 6);
-    const int64_t per_cg = ntiles * Q;
-    const int cg = (int)(gw / per_cg);
+    const int64_t per_zc = ntiles * Q;
+    const int64_t czc = gw / per_zc;   // cg * nzc + zc
+    const int cg = (int)(czc / nzc), zc = (int)(czc % nzc);
     if (cg >= ncg) return;
-    const int64_t rem = gw % per_cg;
+    const int64_t rem = gw % per_zc;
     const int64_t tile = rem / Q;
     const int q = (int)(rem % Q);
     const int lane = threadIdx.x & 63;
@@ -875,6 +881,9 @@ __global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int 
     if (c0 >= C) return;
     const int seg = find_seg(seg_tile, nseg, tile);
     const int d0 = seg_dims[3 * seg], d1 = seg_dims[3 * seg + 1], d2 = seg_dims[3 * seg + 2];
+    const int zlen = (d2 + nzc - 1) / nzc;
+    const int za = zc * zlen, zb = min(d2, za + zlen);
+    if (za >= zb) return;
     const int nty = (d1 + QY * TY - 1) / (QY * TY);
     const int lt = (int)(tile - seg_tile[seg]);
     const int x0 = (lt / nty) * (QX * TX) + (q % QX) * TX;
@@ -924,15 +933,18 @@ __global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int 
         tau[v] = seg_taus[(size_t)seg * S + (c_off + c0 + v) / m];
     }
     double prev[TX][TY][VW], cur[TX][TY][VW];
+    const double wpv = za > 0 ? 1.0 : 0.0;
+    const size_t epv = za > 0 ? (size_t)(za - 1) * zs : 0;
 #pragma unroll
     for (int a = 0; a < TX; ++a)
 #pragma unroll
         for (int b = 0; b < TY; ++b) {
-            double t[VW];
-            vload<T, VW>(IN, base + off[a][b], t);
+            double t[VW], tp[VW];
+            vload<T, VW>(IN, base + (size_t)za * zs + off[a][b], t);
+            vload<T, VW>(IN, base + epv + off[a][b], tp);
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
-                prev[a][b][v] = 0.0;
+                prev[a][b][v] = wpv * wt[a][b] * tp[v];
                 cur[a][b][v] = wt[a][b] * t[v];
             }
         }
@@ -998,12 +1010,23 @@ __global__ __launch_bounds__(256) void k_stencil_a(int C, int m, int c_off, int 
                     cur[a][b][v] = wt[a][b] * Ld.nxt[a][b][v];
                 }
     };
-    for (int z = 0; z < d2; ++z) {
+    for (int z = za; z < zb; ++z) {
         StepLoads Ld;
         issue(Ld, z);
         __builtin_amdgcn_sched_barrier(0);
         compute(Ld, z);
     }
+}
+
+// z chunks of the stencil sweeps: enough wavefronts to keep about 32 per CU
+// busy, at least 8 planes per chunk
+static int z_chunks(const Plan &p, int64_t waves)
+{
+    const int64_t want = (8192 + waves - 1) / (waves > 0 ? waves : 1);
+    int nzc = (int)(want < 64 ? want : 64);
+    const int maxc = p.max_d2 / 8 > 0 ? p.max_d2 / 8 : 1;
+    if (nzc > maxc) nzc = maxc;
+    return nzc < 1 ? 1 : nzc;
 }
 
 void launch_stencil_check(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx,
@@ -1024,16 +1047,18 @@ template <typename T, int VW, int TX, int TY, int QX, int QY>
 static void stencil_a_t(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st)
 {
     const int ncg = (p.C + 64 * VW - 1) / (64 * VW);
-    const int64_t waves = p.ntiles * QX * QY * ncg;
+    const int64_t waves1 = p.ntiles * QX * QY * ncg;
+    const int nzc = z_chunks(p, waves1);
+    const int64_t waves = waves1 * nzc;
     k_stencil_a<T, VW, TX, TY, QX, QY><<<(unsigned)((waves + 3) / 4), 256, 0, st>>>(
-        p.C, p.m, p.c_off, ncg, p.S, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles,
+        p.C, p.m, p.c_off, ncg, nzc, p.S, p.nseg, p.seg_row, p.seg_tile, p.seg_dims, p.ntiles,
         (const T *)x, xs, p.st_diag, p.st_coff, p.seg_taus, p.flags, (T *)y);
 }
 
 template <typename T, int VW>
 static void stencil_a_shape(const Plan &p, const void *x, const double *xs, void *y, hipStream_t st)
 {
-    if (p.tx == 8) stencil_a_t<T, VW, 4, 4, 2, 2>(p, x, xs, y, st);   // 8 x 8 tiles: four 4 x 4 quadrants
+    if (p.tx == 8) stencil_a_t<T, VW, 2, 4, 4, 2>(p, x, xs, y, st);   // 8 x 8 tiles: eight 2 x 4 blocks
     else if (p.tx == 4) stencil_a_t<T, VW, 4, 4, 1, 1>(p, x, xs, y, st);
     else if (p.tx == 2) stencil_a_t<T, VW, 2, 4, 1, 1>(p, x, xs, y, st);
     else stencil_a_t<T, VW, 1, 8, 1, 1>(p, x, xs, y, st);

@@ -160,6 +160,9 @@ def load():
         lib.ecnt_ildl_free.restype = None
         lib.ecnt_ildl_free.argtypes = [ctypes.c_void_p]
         lib.ecnt_profile_enable.argtypes = [ctypes.c_int32]
+        lib.ecnt_hbm_probe.restype = ctypes.c_int32
+        lib.ecnt_hbm_probe.argtypes = [ctypes.c_int32, P, ctypes.c_size_t, ctypes.c_int32, P,
+                                       ctypes.POINTER(ctypes.c_double)]
         lib.ecnt_profile_read.restype = ctypes.c_int32
         lib.ecnt_profile_read.argtypes = [ctypes.POINTER(KernelStatT), ctypes.c_int32]
         _lib = lib
@@ -562,6 +565,21 @@ def version() -> str:
 def profile_enable(on: bool = True):
     """Start (and reset) or stop per-kernel-family HIP-event timing."""
     _check(load().ecnt_profile_enable(1 if on else 0))
+
+
+PROBES = {"copy": 0, "read": 1, "update_mix": 2}
+
+
+def hbm_probe(kind: str, nbytes: int = 18 << 30, reps: int = 10, stream=None) -> float:
+    """Effective GB/s of a tuned stream (ecnt_hbm_probe): 'copy', 'read' or
+    'update_mix' (16 vectors read, one read and written in place)."""
+    import torch
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    g = ctypes.c_double()
+    _check(load().ecnt_hbm_probe(PROBES[kind], buf.data_ptr(), buf.numel(), int(reps),
+                                 _stream_handle(stream), ctypes.byref(g)))
+    del buf
+    return g.value
 
 
 def profile_read() -> dict:

@@ -214,3 +214,12 @@ def test_noalloc_refuses_oversized_count_on_host():
 def test_noalloc_invalid_calls_rejected_on_host(kw, code):
     rc, msg = _call_noalloc(**kw)
     assert rc == code, msg
+
+
+def test_hbm_probe_rejects_bad_arguments_on_host():
+    lib = ec.load()
+    g = ctypes.c_double()
+    for kind, buf, nbytes, reps in [(3, 0x1000, 1 << 30, 1), (0, None, 1 << 30, 1),
+                                    (0, 0x1000, 1 << 20, 1), (1, 0x1000, 1 << 30, 0)]:
+        rc = lib.ecnt_hbm_probe(kind, buf, nbytes, reps, None, ctypes.byref(g))
+        assert rc == ec.ECNT_EINVAL, ec.last_error()

@@ -686,3 +686,11 @@ def test_a_not_a_stencil_falls_back_to_csr(ec, how):
     assert prof["op_csr"]["bytes"] > 0 and prof["op_a_stencil"]["bytes"] == 0
     ref = oracle.count(A2, P.prec, wl.xi, wl.eta, V, wl.k)
     assert_parity(r, ref, wl.k)
+
+
+def test_hbm_probes_plausible(ec):
+    """The stream probes report GB/s between a slow and an impossible rate."""
+    for kind in ("copy", "read", "update_mix"):
+        g = ec.hbm_probe(kind, 1 << 30, reps=3)
+        print("probe", kind, g, flush=True)
+        assert 500.0 < g < 9000.0
