@@ -4,7 +4,7 @@
 // with P (A - tau I) P^T ~ L D L^T the factor of the columns' shift.
 //
 // The substitutions are sequential in the rows; the columns (probes) are the
-// parallel dimension: one wavefront owns 2 columns and walks all n rows in
+// parallel dimension: one wavefront owns a column and walks all n rows in
 // column form, keeping the pending sums of the next kRing rows in registers,
 // which serves any factor of bandwidth at most kRing.  The factor is used in
 // band form (each row as 256 values by distance from the diagonal, built once
@@ -132,18 +132,19 @@ __global__ __launch_bounds__(256) void k_ldl_permute(int64_t n, int C, int c_lo,
 // (Y[r] = y_r / w_r).  In walk order t (FWD r = t, BWD r = n-1-t) the value of
 // step t enters steps t+1 .. t+256 with the coefficients of one band row:
 // band[r][256 - d] links step t to step t + d (FWD: column r of L, i.e. the
-// band of L^T; BWD: row r of L).  A wavefront owns 2 columns, 32 lanes each;
-// lane q keeps the pending sums of steps T0 + q + 32 s (s = 0..7) of the
-// current group of 32 steps in registers (9 slots: from step T0 + 31 the
-// values reach T0 + 287).  Step t = T0 + q0: lane q0 forms
-// y = X - pending, one swizzle broadcasts it to the 32 lanes of its column,
-// and every lane adds coefficient * y to its 8 pending sums; at the end of a
-// group the sums shift by one slot.  The dependence from one step to the next
-// is one FMA, a subtraction and the broadcast; no reduction across lanes.
-// Band rows are loaded 16 steps ahead into registers and staged into LDS per
-// 16 steps between 32 zeros on each side (read for distances outside 1..256).
-// All shifts of the wave in one launch (each solve is a latency-bound chain,
-// so the shifts' chains run side by side): blocks [blk0[s], blk0[s+1]) serve
+// band of L^T; BWD: row r of L).  A wavefront owns one column: lane q keeps
+// the pending sums of steps T0 + q + 64 s (s = 0..4) of the current group of
+// 64 steps in registers (5 slots: from step T0 + 63 the values reach
+// T0 + 319).  Step t = T0 + Q0: lane Q0 forms y = X - pending, v_readlane
+// broadcasts it through scalar registers, and every lane adds coefficient * y
+// to its 5 pending sums; at the end of a group the sums shift by one slot.
+// The chain from one row to the next is a subtraction, the broadcast and one
+// FMA; the next step's 5 coefficients are read from LDS before the current
+// step's broadcast (two register sets alternate by step parity).  Band rows
+// are loaded 16 steps ahead into registers and staged into LDS per 16 steps
+// between 64 zeros on each side (read for distances outside 1..256).  All
+// shifts of the wave in one launch (each solve is a latency-bound chain, so
+// the shifts' chains run side by side): blocks [blk0[s], blk0[s+1]) serve
 // shift s, its columns [lo[s], hi[s]) and its factor's band.
 struct LdlSolveSet {
     int nsh;
@@ -161,33 +162,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     const int c_lo = set.lo[sh], c_hi = set.hi[sh];
     const double *__restrict__ band = set.band[sh];
     const int blk = (int)blockIdx.x - set.blk0[sh];
-    constexpr int NS = 32;             // lanes per column, steps per group
+    constexpr int NS = 64;             // lanes per column, steps per group
     constexpr int NR = kRing / NS;     // the pending sums per lane are NR + 1
     constexpr int kBatch = 16;         // band rows staged at a time
     constexpr int kRow = NS + kRing + NS;   // staged row: zeros, band, zeros
     __shared__ double stg[kBatch][kRow];
-    const int lane = threadIdx.x;
-    const int hcol = lane >> 5, q = lane & 31;
-    const int craw = c_lo + blk * 2 + hcol;
+    const int q = threadIdx.x;
+    const int craw = c_lo + blk;
     const bool ok = craw < c_hi;
     const int c = ok ? craw : c_lo;
-    if (lane < NS)
-        for (int u = 0; u < kBatch; ++u) {
-            stg[u][lane] = 0.0;
-            stg[u][NS + kRing + lane] = 0.0;
-        }
+    for (int u = 0; u < kBatch; ++u) {
+        stg[u][q] = 0.0;
+        stg[u][NS + kRing + q] = 0.0;
+    }
 
     auto row_of = [&](int64_t t) -> int64_t {
         const int64_t tt = t < n ? t : n - 1;   // past the end: repeat the last row (unused)
         return FWD ? tt : n - 1 - tt;
     };
-    double nv[kBatch][4];   // next batch: band values 2 lane, 2 lane + 1, 128 + 2 lane, 129 + 2 lane
+    double nv[kBatch][4];   // next batch: band values 2 q, 2 q + 1, 128 + 2 q, 129 + 2 q
     auto load_batch = [&](int64_t t0) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const double2 *row =
                 reinterpret_cast<const double2 *>(band + (size_t)row_of(t0 + u) * kRing);
-            const double2 a = row[lane], b = row[64 + lane];
+            const double2 a = row[q], b = row[64 + q];
             nv[u][0] = a.x;
             nv[u][1] = a.y;
             nv[u][2] = b.x;
@@ -202,8 +201,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
             a.y = nv[u][1];
             b.x = nv[u][2];
             b.y = nv[u][3];
-            reinterpret_cast<double2 *>(stg[u] + NS)[lane] = a;
-            reinterpret_cast<double2 *>(stg[u] + NS)[64 + lane] = b;
+            reinterpret_cast<double2 *>(stg[u] + NS)[q] = a;
+            reinterpret_cast<double2 *>(stg[u] + NS)[64 + q] = b;
         }
     };
     auto load_b = [&](int64_t T0) -> T { return X[(size_t)row_of(T0 + q) * C + c]; };
@@ -214,47 +213,64 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     double yown = 0.0;
     T b_own = load_b(0), b_next = load_b(NS);
 
-    // one step: Q0 = position in the group (compile-time), U = staging row
-    auto step = [&]<int Q0>(std::integral_constant<int, Q0>, int u) __attribute__((always_inline)) {
-        const double y = static_cast<double>(b_own) - slot[0];   // meaningful in lane Q0
-        const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(y), Q0 << 5);
-        const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(y), Q0 << 5);
-        const double yb = __hiloint2double(hi, lo);
-        yown = q == Q0 ? yb : yown;
-        // coefficient for slot s (distance d = q - Q0 + 32 s): staged index
-        // 32 + 256 - d, zero unless 1 <= d <= 256
+    // coefficients of a step (position Q0 in the group, staging row u) for
+    // slot s: distance d = q - Q0 + 64 s, staged index 64 + 256 - d (zero
+    // unless 1 <= d <= 256)
+    double ca[NR + 1], cb[NR + 1];
+    auto coefs = [&](int Q0, int u, double (&c_)[NR + 1]) __attribute__((always_inline)) {
         const double *sr = stg[u] + (NS - q + Q0);
 #pragma unroll
-        for (int s2 = 0; s2 <= NR; ++s2) slot[s2] += sr[NS * (NR - s2)] * yb;
+        for (int s2 = 0; s2 <= NR; ++s2) c_[s2] = sr[NS * (NR - s2)];
     };
-    auto half = [&]<int H>(int64_t T0, std::integral_constant<int, H>) __attribute__((always_inline)) {
+    // one step: Q0 = position in the group (compile-time), U = staging row
+    auto step = [&]<int Q0>(std::integral_constant<int, Q0>, int u) __attribute__((always_inline)) {
+        double(&cur)[NR + 1] = (Q0 & 1) ? cb : ca;
+        double(&nxt)[NR + 1] = (Q0 & 1) ? ca : cb;
+        if (u + 1 < kBatch) coefs(Q0 + 1, u + 1, nxt);
+        const double y = static_cast<double>(b_own) - slot[0];   // meaningful in lane Q0
+        const int lo = __builtin_amdgcn_readlane(__double2loint(y), Q0);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(y), Q0);
+        const double yb = __hiloint2double(hi, lo);
+        yown = q == Q0 ? yb : yown;
+#pragma unroll
+        for (int s2 = 0; s2 <= NR; ++s2) slot[s2] += cur[s2] * yb;
+    };
+    // batch B of the group (steps 16 B .. 16 B + 15), staged in stg
+    auto batch = [&]<int B>(int64_t T0, std::integral_constant<int, B>) __attribute__((always_inline)) {
+        if constexpr ((B * kBatch) & 1) coefs(B * kBatch, 0, cb);
+        else coefs(B * kBatch, 0, ca);
         [&]<int... U>(std::integer_sequence<int, U...>) __attribute__((always_inline)) {
-            ((T0 + H * kBatch + U < n ? step(std::integral_constant<int, H * kBatch + U>{}, U)
+            ((T0 + B * kBatch + U < n ? step(std::integral_constant<int, B * kBatch + U>{}, U)
                                       : void()),
              ...);
         }(std::make_integer_sequence<int, kBatch>{});
+    };
+    // after a batch: stage the next one (loaded one batch ago), load the one after it
+    auto advance = [&](int64_t t_next) __attribute__((always_inline)) {
+        if (t_next < n) {
+            stage_batch();
+            load_batch(t_next + kBatch);
+        }
     };
 
     load_batch(0);
     stage_batch();
     load_batch(kBatch);
     for (int64_t T0 = 0; T0 < n; T0 += NS) {
-        half(T0, std::integral_constant<int, 0>{});
-        if (T0 + kBatch < n) {
-            stage_batch();                 // steps T0+16 .. T0+31, loaded 16 steps ago
-            load_batch(T0 + 2 * kBatch);
-        }
-        half(T0, std::integral_constant<int, 1>{});
+        batch(T0, std::integral_constant<int, 0>{});
+        advance(T0 + kBatch);
+        batch(T0, std::integral_constant<int, 1>{});
+        advance(T0 + 2 * kBatch);
+        batch(T0, std::integral_constant<int, 2>{});
+        advance(T0 + 3 * kBatch);
+        batch(T0, std::integral_constant<int, 3>{});
         if (ok && T0 + q < n) Y[(size_t)row_of(T0 + q) * C + c] = static_cast<T>(yown);
 #pragma unroll
         for (int s2 = 0; s2 < NR; ++s2) slot[s2] = slot[s2 + 1];
         slot[NR] = 0.0;
         b_own = b_next;
         b_next = load_b(T0 + 2 * NS);
-        if (T0 + NS < n) {
-            stage_batch();                 // steps T0+32 .. T0+47
-            load_batch(T0 + 3 * kBatch);
-        }
+        advance(T0 + NS);
     }
 }
 
@@ -299,7 +315,7 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
             set.lo[k] = lo;
             set.hi[k] = hi;
             set.band[k] = what == 1 ? bb : bf;
-            set.blk0[k + 1] = set.blk0[k] + (hi - lo + 1) / 2;
+            set.blk0[k + 1] = set.blk0[k] + (hi - lo);   // one wavefront per column
         }
         if (set.nsh == 0) return;
         const unsigned grid = (unsigned)set.blk0[set.nsh];
