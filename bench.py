@@ -463,6 +463,7 @@ def bench_batched(args, name: str, ceilings=None):
         "eager_kernel_ms": total_kernel_ms,
         "result": {"sum_negcounts": float(r.negcounts.sum()),
                    "counts_first_problem": [float(x) for x in r.counts[0]]},
+        "accuracy": batch_accuracy(r),
         "kernel_sources_sha": kernel_sources_sha(),
     }
     if not args.no_cpu_baseline:
@@ -473,6 +474,24 @@ def bench_batched(args, name: str, ceilings=None):
         pp = btd.run().per_probe.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline_batch(items, V, off, k, args.cpu_seconds, m, pp)
     print(json.dumps(out), flush=True)
+
+
+def batch_accuracy(r):
+    """The batch's slice counts against the exact counts of the 64 problems
+    (LDL^T inertia at every shift, tests/golden/exact_counts.json)."""
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "exact_counts.json"))).get("c4")
+    if not golden or len(golden["items"]) < r.counts.shape[0]:
+        return None
+    ex = np.array([it["counts"] for it in golden["items"][:r.counts.shape[0]]], dtype=np.float64)
+    est = np.asarray(r.counts)
+    rel = (est - ex) / np.maximum(ex, 1.0)
+    tot_est, tot_ex = float(est.sum()), float(ex.sum())
+    return {"slices": int(ex.size), "exact_total": tot_ex, "estimate_total": tot_est,
+            "total_rel_error": (tot_est - tot_ex) / tot_ex,
+            "median_abs_rel_error": float(np.median(np.abs(rel))),
+            "mean_abs_rel_error": float(np.mean(np.abs(rel))),
+            "slices_within_5pct": float(np.mean(np.abs(rel) <= 0.05)),
+            "method_exact": "LDL^T Sylvester inertia (nested dissection)"}
 
 
 CEILING_KIND = {"lz_update": "update_mix", "bw_update": "update_mix", "blk_update": "update_mix",

@@ -71,3 +71,24 @@ def test_stored_exact_counts_small():
         Ad = W.make_problem(wl).A.to_dense()
         assert data[name]["count"] == exact.dense_negcount(Ad, wl.eta) - exact.dense_negcount(Ad, wl.xi)
     assert data["c1"]["count"] == 72
+
+
+def test_stored_batch_exact_counts_consistent():
+    """The 64 stored counts of the batched family: each item's grid and shifts
+    are those the generator draws for it, its slice counts are differences of
+    its stored inertia counts, and the smallest item (16^3) recomputes by the
+    dense eigenvalue count."""
+    data = json.load(open(os.path.join(GOLDEN, "exact_counts.json")))["c4"]
+    items = data["items"]
+    assert [it["problem"] for it in items] == list(range(64))
+    for it in items:
+        B = W.batched_item(it["problem"], base_seed=data["base_seed"])
+        assert list(B.dims) == it["dims"]
+        np.testing.assert_array_equal(np.asarray(it["shifts"]), B.shifts)
+        neg = it["negcounts"]
+        assert it["counts"] == [neg[i + 1] - neg[i] for i in range(len(neg) - 1)]
+        assert all(c >= 0 for c in it["counts"])
+    small = min(items, key=lambda it: it["dims"][0])
+    B = W.batched_item(small["problem"], base_seed=data["base_seed"])
+    lam = np.linalg.eigvalsh(B.A.to_dense())
+    assert small["negcounts"] == [int(np.sum(lam < t)) for t in B.shifts]
