@@ -20,10 +20,9 @@
 // D[4v + l/16][l%16].
 //
 // Quadrature (k_blk_quad): T_k (order 16 k_used, half-bandwidth 16) is reduced
-// to tridiagonal form by Givens rotations with bulge chasing (Schwarz), then
-// diagonalized by implicit QR sweeps with Wilkinson shifts; every rotation is
-// also applied to the first 16 rows of the accumulated eigenvector matrix,
-// all in LDS.
+// to tridiagonal form by Householder bulge chasing, then diagonalized by
+// implicit QR sweeps with Wilkinson shifts; the first 16 rows of the
+// accumulated eigenvector matrix follow every transform, all in LDS.
 #include <float.h>
 
 #include "device_common.h"
@@ -389,17 +388,83 @@ __global__ __launch_bounds__(256) void k_blk_norm_fin(int mode, int step, int k,
 
 // ---- quadrature: one workgroup (one wavefront) per block ----
 constexpr int kQMax = kBlk * kBlkMaxK;   // largest order of T_k
-// LDS row stride: one double more than the order, so that lanes walking a row
-// of the band (one diagonal to the next) or the 16 rows of Z hit distinct banks
-constexpr int kQN = kQMax + 1;
-constexpr int kBand = kBlk + 2;         // diagonals kept: 0..16 and the bulge
+// LDS row stride (one row per diagonal).  Lanes that walk the columns of a
+// block touch (r - c) kQN + c, a stride of kQN - 1 doubles, and the rows of
+// Z (below) are kQN - 1 apart too: kQN - 1 odd keeps both free of bank
+// conflicts.  The 18 columns past the largest order hold the start of Z's
+// rows 1..15 for its first columns.
+constexpr int kQN = kQMax + 18;
+// diagonals held: the half-bandwidth kBlk plus the fill that the chase leaves
+// behind (distance at most 2 kBlk - 2 from the diagonal)
+constexpr int kDiag = 2 * kBlk - 1;
 
 __device__ __forceinline__ int bidx(int r, int c)
 {
-    // symmetric band storage: (r, c) with |r - c| <= 17 -> diagonal |r-c| at column min(r, c)
+    // symmetric band storage: (r, c) -> diagonal |r - c| at column min(r, c)
     return r >= c ? (r - c) * kQN + c : (c - r) * kQN + r;
 }
 
+// Z[r][c] (r < 16) after the chase: diagonal 2 + r at column c - r, a slot
+// whose band column is finished once Z's column c is (columns c - r <= c;
+// for c < r the address falls in diagonal 1 + r's columns past the order)
+__device__ __forceinline__ int zidx(int r, int c)
+{
+    return (2 + r) * kQN + c - r;
+}
+
+// sum over the 16 lanes of a row of the wavefront (every lane gets the same
+// value: each butterfly stage adds two equal partial sums in either order)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    // every lane has a source under a row rotation: bound_ctrl set, no old value
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_sum16(double x)
+{
+    x += dpp_f64<0x128>(x);   // row_ror:8
+    x += dpp_f64<0x124>(x);   // row_ror:4
+    x += dpp_f64<0x122>(x);   // row_ror:2
+    x += dpp_f64<0x121>(x);   // row_ror:1
+    return x;
+}
+// sum over the 4 rows of the wavefront (lanes l, l^16, l^32, l^48), by the
+// row swaps of v_permlane16_swap / v_permlane32_swap (both halves of a pair
+// get the same operands in the same order, so all four lanes agree)
+__device__ __forceinline__ double group_sum4(double x)
+{
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    x = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+    lo = __double2loint(x);
+    hi = __double2hiint(x);
+    a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+// Quadrature of one block.  T_k (order N = 16 k_used, half-bandwidth 16) is
+// brought to tridiagonal form by Householder bulge chasing: sweep j takes
+// column j with one reflector on rows j+1..j+16, and the fill that the
+// reflector's right side leaves in the 16 x 16 block below is removed one
+// column at a time, each step's reflector acting on the next 16 rows (the
+// rest of that fill is removed by the following sweeps, so it never reaches
+// beyond distance 30 from the diagonal).  A step is done by the whole
+// wavefront on 16 x 16 blocks, lane (kk, g) holding rows 4g..4g+3 of column kk:
+//   (a) H on the rows of the window, columns left of it (the column that gave
+//       the reflector becomes (beta, 0, ..., 0)),
+//   (b) H D H on the diagonal block,
+//   (c) the rows below times H; their first column gives the next reflector.
+// Z = E_1^T Q (the first 16 rows of the accumulated transform) starts as
+// [I 0]; only the first reflector of each sweep meets its nonzero columns
+// (they grow by one column per sweep), so it is kept as a sliding 16 x 16
+// window in registers, and each finished column is stored in the band slots
+// of its T column, which the chase no longer uses.  Then implicit QR sweeps
+// with Wilkinson shifts diagonalize the tridiagonal form, every rotation also
+// applied to Z, all in LDS.
 __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smooth_w,
                                                  const double *__restrict__ Ab,
                                                  const double *__restrict__ Bb,
@@ -409,9 +474,11 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
                                                  double *__restrict__ minabs,
                                                  int32_t *__restrict__ flags)
 {
-    __shared__ double Lb[kBand * kQN];
-    __shared__ double Z[kBlk * kQN];
+    __shared__ double Lb[kDiag * kQN];
     __shared__ double F[256];
+    __shared__ double xbuf[kBlk];     // the column that gives the next reflector
+    __shared__ double dump[64];       // per-lane target of the writes a lane does not make
+    __shared__ double zslot[1];       // 0.0: the source of the reads a lane does not make
     const int blk = blockIdx.x, lane = threadIdx.x;
     const int col0 = c_off + blk * kBlk;
     const int ku = kused[col0];
@@ -424,8 +491,8 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
     }
     const int N = ku * kBlk;
     // T_k into band storage: A_i on the diagonal blocks, B_{i+1} (upper
-    // triangular) in block (i, i-1); the bulge diagonal starts at zero
-    for (int e = lane; e < kBand * N; e += 64) {
+    // triangular) in block (i, i-1); the fill diagonals start at zero
+    for (int e = lane; e < kDiag * N; e += 64) {
         const int d = e / N, c = e - d * N, r = c + d;
         double v = 0.0;
         if (d <= kBlk && r < N) {
@@ -435,74 +502,184 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
         }
         Lb[d * kQN + c] = v;
     }
-    for (int e = lane; e < kBlk * N; e += 64) {
-        const int r = e / N, c = e - r * N;
-        Z[r * kQN + c] = (r == c) ? 1.0 : 0.0;
+    if (lane == 0) zslot[0] = 0.0;
+    __syncthreads();
+
+    const int kk = lane & 15, g = lane >> 4;
+    double *const mydump = dump + lane;
+    // Lane (kk, g) holds rows i = 4g + t (t = 0..3) of column kk of a 16 x 16
+    // block.  Its element offsets are fixed: in the diagonal block at w0,
+    // (w0 + i, w0 + kk) sits at w0 + offD[t]; in a block of the 16 rows below a
+    // full window (and in the window's rows left of it, 16 columns back),
+    // (w0 + 16 + i, w0 + kk) sits at w0 + offE[t] (distance 16 + i - kk,
+    // held when at most kDiag - 1: all but (15, 0)).
+    int offD[4], offE[4];
+    bool lowD[4], heldE[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int i = 4 * g + t;
+        offD[t] = i >= kk ? (i - kk) * kQN + kk : (kk - i) * kQN + i;
+        lowD[t] = i >= kk;
+        offE[t] = (kBlk + i - kk) * kQN + kk;
+        heldE[t] = kBlk + i - kk < kDiag;
+    }
+    const int offX = (1 + kk) * kQN;           // column j, row j + 1 + kk
+    int offXr[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) offXr[t] = (1 + 4 * g + t) * kQN;
+    const int offA1 = (1 + lane) * kQN, offA16 = (kBlk + lane) * kQN;   // column writes of (a)
+
+    // ---- band -> tridiagonal ----
+    double zw[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) zw[t] = (1 + 4 * g + t == kk) ? 1.0 : 0.0;   // Z columns 1..16
+    double zst = kk == 0 ? 1.0 : 0.0;                                        // Z column 0
+    for (int j = 0; j + 2 < N; ++j) {
+        int w0 = j + 1, c = j;
+        int w1 = min(w0 + kBlk - 1, N - 1), L = w1 - w0 + 1;
+        int Ln = min(kBlk, N - 1 - w1);
+        // the first step's blocks: D (rows and columns w0..w1), E (the rows
+        // below; a block below exists only under a full window); later steps
+        // get them loaded one step ahead, and P (the window's rows left of
+        // it) is the previous step's E, kept in registers
+        double D[4], E[4], P[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            D[t] = *(4 * g + t < L && kk < L ? &Lb[w0 + offD[t]] : zslot);
+            E[t] = *(4 * g + t < Ln && heldE[t] ? &Lb[w0 + offE[t]] : zslot);
+            P[t] = 0.0;
+        }
+        for (int s = 0;; ++s) {
+            const bool more = w1 + 1 <= N - 2;   // a next window of at least 2 rows
+            // the reflector: x = column c on the window's rows (band column j
+            // in the first step, else the column kept in xbuf by step (c))
+            const double x0 = s == 0 ? Lb[kQN + j] : xbuf[0];
+            const double xk = *(kk < L ? (s == 0 ? &Lb[offX + j] : &xbuf[kk]) : zslot);
+            double xr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                xr[t] = *(4 * g + t < L ? (s == 0 ? &Lb[offXr[t] + j] : &xbuf[4 * g + t]) : zslot);
+            // the next step's D and E (regions this step does not write)
+            const int w0n = w1 + 1, w1n = min(w0n + kBlk - 1, N - 1);
+            const int Lnn = min(kBlk, N - 1 - w1n);
+            double Dn[4], En[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                Dn[t] = *(more && 4 * g + t < Ln && kk < Ln ? &Lb[w0n + offD[t]] : zslot);
+                En[t] = *(more && 4 * g + t < Lnn && heldE[t] ? &Lb[w0n + offE[t]] : zslot);
+            }
+            const double sig2 = row_sum16(kk >= 1 ? xk * xk : 0.0);
+            const bool refl = sig2 > 0.0;
+            const double mu = sqrt(x0 * x0 + sig2);
+            const double bc = x0 >= 0.0 ? -mu : mu;
+            const double inv = refl ? 1.0 / (x0 - bc) : 0.0;
+            const double tau = refl ? (bc - x0) / bc : 0.0;
+            const double beta = refl ? bc : x0;
+            const double vk = kk == 0 ? 1.0 : xk * inv;
+            double vr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) vr[t] = 4 * g + t == 0 ? 1.0 : xr[t] * inv;
+            // (c) the 16 rows below, columns of the window: E <- E H (only under
+            // a full window, so Ln >= 1 means L = 16).  Column 0 gives the next
+            // step's reflector (xbuf); the other columns are the next step's P.
+            // With no next step all of E goes back into the band.
+            if (Ln >= 1) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    // (15, 0) is not held (distance 31) and reads 0, but E H
+                    // fills it: it goes to xbuf like the rest of column 0 (with no
+                    // next step there is one row below at most, all held)
+                    const int i = 4 * g + t;
+                    const bool ok = i < Ln;
+                    const double z = tau * row_sum16(E[t] * vk);
+                    E[t] -= z * vk;
+                    double *dst = ok && !more ? &Lb[w0 + offE[t]] : (kk == 0 ? &xbuf[i] : mydump);
+                    *dst = ok ? E[t] : 0.0;
+                }
+            }
+            if (s == 0) {
+                // Z <- Z H on the sweep's first window (lane (kk, g): row kk)
+                double y = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) y += zw[t] * vr[t];
+                y = group_sum4(y);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) zw[t] -= tau * y * vr[t];
+            }
+            // (a) rows w0.., columns c..w0-1: column c becomes (beta, 0, ..., 0)
+            // (distance 1 + lane in the first step, 16 + lane after)
+            {
+                const bool ok = lane < L && (s == 0 || kBlk + lane < kDiag);
+                double *dst = ok ? &Lb[(s == 0 ? offA1 : offA16) + c] : mydump;
+                *dst = lane == 0 ? beta : 0.0;
+            }
+            if (s > 0) {
+                double y = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) y += vr[t] * P[t];
+                y = tau * group_sum4(y);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = kk >= 1 && 4 * g + t < L;
+                    double *dst = ok ? &Lb[c + offE[t]] : mydump;
+                    *dst = P[t] - y * vr[t];
+                }
+            }
+            // (b) D <- H D H = D - v w^T - w v^T, w = p - (tau/2)(v^T p) v, p = tau D v
+            {
+                double p = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) p += vr[t] * D[t];
+                p = tau * group_sum4(p);
+                const double K = 0.5 * tau * row_sum16(vk * p);
+                const double wk = p - K * vk;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double wi = __shfl(wk, 4 * g + t, 64);
+                    const bool ok = 4 * g + t < L && kk < L && lowD[t];
+                    double *dst = ok ? &Lb[w0 + offD[t]] : mydump;
+                    *dst = D[t] - (vr[t] * wk + wi * vk);
+                }
+            }
+            if (!more) break;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                P[t] = E[t];
+                D[t] = Dn[t];
+                E[t] = En[t];
+            }
+            c = w0;
+            w0 = w0n;
+            w1 = w1n;
+            L = Ln;
+            Ln = Lnn;
+        }
+        // column j is finished (so are the band columns Z's column j goes to);
+        // column j+1 leaves the window, which moves down by one
+        if (g == 0) Lb[zidx(kk, j)] = zst;
+        zst = zw[0];
+        const double nxt = __shfl_down(zw[0], 16, 64);
+        zw[0] = zw[1];
+        zw[1] = zw[2];
+        zw[2] = zw[3];
+        zw[3] = g < 3 ? nxt : 0.0;
+    }
+    {
+        const int jl = N - 2;   // the last two columns (N >= 16)
+        if (g == 0) {
+            Lb[zidx(kk, jl)] = zst;
+            Lb[zidx(kk, jl + 1)] = zw[0];
+        }
     }
     __syncthreads();
 
-    // one Givens rotation in the plane (p, p+1) that zeroes T[p+1][t]
-    auto rotate = [&](int p, int t) {
-        const int q = p + 1;
-        const double x = Lb[bidx(p, t)], y = Lb[bidx(q, t)];
-        // |x|, |y| far from the under/overflow range: T_k holds O(|C|) entries
-        const double q2 = x * x + y * y;
-        if (q2 == 0.0) return;
-        const double ir = rsqrt(q2);
-        const double rr = q2 * ir;
-        const double c = x * ir, s = y * ir;
-        const int hi = min(N - 1, q + kBlk);
-        // reads
-        const int xx = t + lane;
-        const bool el = lane < 2 * kBlk + 2 && xx <= hi && xx != p && xx != q;
-        double u = 0.0, w = 0.0;
-        if (el) {
-            u = Lb[bidx(p, xx)];
-            w = Lb[bidx(q, xx)];
-        }
-        const double a = Lb[bidx(p, p)], bb = Lb[bidx(q, p)], dd = Lb[bidx(q, q)];
-        const int zr = lane - 48;
-        double zp = 0.0, zq = 0.0;
-        if (zr >= 0) {
-            zp = Z[zr * kQN + p];
-            zq = Z[zr * kQN + q];
-        }
-        // one wavefront: every lane's reads above are issued before any write below
-        if (el) {
-            Lb[bidx(p, xx)] = c * u + s * w;
-            Lb[bidx(q, xx)] = -s * u + c * w;
-        }
-        if (lane == 0) {
-            Lb[bidx(p, t)] = rr;
-            Lb[bidx(q, t)] = 0.0;
-            Lb[bidx(p, p)] = c * c * a + 2.0 * c * s * bb + s * s * dd;
-            Lb[bidx(q, q)] = s * s * a - 2.0 * c * s * bb + c * c * dd;
-            Lb[bidx(q, p)] = c * s * (dd - a) + (c * c - s * s) * bb;
-        }
-        if (zr >= 0) {
-            Z[zr * kQN + p] = c * zp + s * zq;
-            Z[zr * kQN + q] = -s * zp + c * zq;
-        }
-        __syncthreads();
-    };
-    // band -> tridiagonal: zero column j below the first subdiagonal from the
-    // bottom of the band up, chasing each bulge off the end
-    for (int j = 0; j + 2 < N; ++j) {
-        for (int d = min(kBlk, N - 1 - j); d >= 2; --d) {
-            const int p = j + d - 1;
-            rotate(p, j);
-            int pc = p, r = p + 1 + kBlk;
-            while (r < N) {
-                rotate(r - 1, pc);
-                pc = r - 1;
-                r += kBlk;
-            }
-        }
-    }
-    // implicit QR sweeps with Wilkinson shifts on (diagonal 0, diagonal 1);
+    // ---- implicit QR sweeps with Wilkinson shifts on (diagonal 0, diagonal 1) ----
     // every lane runs the scalar chain, lanes 0..15 rotate their row of Z
     double *A_ = Lb;
     double *B_ = Lb + kQN;
+    const int zrow = lane & 15;
+    double *Zr = Lb + zidx(zrow, 0);   // row zrow of Z (lanes 16.. repeat rows 0..15)
+    const bool zlane = lane < kBlk;
     int hi = N - 1, iter = 0;
     bool failed = false;
     while (hi > 0) {
@@ -514,11 +691,20 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
             --hi;
             continue;
         }
-        int lo = hi - 1;
-        while (lo > 0) {
-            const double bl = fabs(B_[lo - 1]);
-            if (bl <= DBL_EPSILON * (fabs(A_[lo - 1]) + fabs(A_[lo])) || bl < DBL_MIN) break;
-            --lo;
+        // the largest lo < hi with B_[lo-1] negligible (or 0), 64 candidates at a time
+        int lo = 0;
+        for (int base = hi - 1; base > 0; base -= 64) {
+            const int i = base - lane;
+            bool neg = false;
+            if (i >= 1) {
+                const double bl = fabs(B_[i - 1]);
+                neg = bl <= DBL_EPSILON * (fabs(A_[i - 1]) + fabs(A_[i])) || bl < DBL_MIN;
+            }
+            const unsigned long long m = __ballot(neg);
+            if (m) {
+                lo = base - (__ffsll((long long)m) - 1);
+                break;
+            }
         }
         if (++iter > 60 * N) {
             failed = true;
@@ -530,50 +716,72 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
         const double mu = A_[hi] - (den != 0.0 ? bb0 * bb0 / den : 0.0);
         double x = A_[lo] - mu, y = B_[lo];
         if (lo > 0 && lane == 0) B_[lo - 1] = 0.0;   // the split found above (not read by the sweep)
-        // the values a rotation changes and the next one reads (A[kk], B[kk],
-        // row `lane` of Z at kk) are carried in registers; what it reads ahead
-        // (A[kk+1], B[kk+1], Z at kk+1) is not yet written in this sweep
+        // the values a rotation changes and the next one reads (A[q], B[q],
+        // row `zrow` of Z at q) are carried in registers; the ones it reads
+        // ahead (A[q+1], B[q+1], Z at q+1, not yet written in this sweep) come
+        // from three register sets by position mod 3, each reloaded three
+        // indices ahead once its rotation has used it.  The main loop runs
+        // three rotations with no condition inside (the first (hi - lo) mod 3
+        // rotations read their operands directly), so every load lands in the
+        // register that carries it and stays in flight for two rotations.
+        // Indices are clamped to hi: B[hi] is 0 (set when hi last moved down,
+        // or beyond the matrix), which is what a sweep's last rotation takes
+        // for B[q+1].
         double ak = A_[lo], bk = B_[lo];
-        double zk = lane < kBlk ? Z[lane * kQN + lo] : 0.0;
+        double zk = Zr[lo];
         double nbk = bk;
-        double ak1 = A_[lo + 1];
-        double bk1 = lo + 1 < hi ? B_[lo + 1] : 0.0;
-        double z1 = lane < kBlk ? Z[lane * kQN + lo + 1] : 0.0;
-        for (int kk = lo; kk < hi; ++kk) {
-            // next iteration's operands, loaded before this iteration's writes
-            const double ak2 = kk + 2 <= hi ? A_[kk + 2] : 0.0;
-            const double bk2 = kk + 2 < hi ? B_[kk + 2] : 0.0;
-            const double z2 = (lane < kBlk && kk + 2 <= hi) ? Z[lane * kQN + kk + 2] : 0.0;
+        auto rot = [&](int q, double ak1, double bk1, double z1) __attribute__((always_inline)) {
             const double q2 = x * x + y * y;
-            double cs = 1.0, sn = 0.0, r = 0.0;
-            if (q2 > 0.0) {
-                const double ir = rsqrt(q2);
-                r = q2 * ir;
-                cs = x * ir;
-                sn = y * ir;
-            }
+            const bool nz = q2 > 0.0;
+            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double r = nz ? q2 * ir : 0.0;
+            const double cs = nz ? x * ir : 1.0;
+            const double sn = nz ? y * ir : 0.0;
             const double na = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
             const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
             nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-            if (lane == 0) {
-                if (kk > lo) B_[kk - 1] = r;
-                A_[kk] = na;
-            }
-            if (lane < kBlk) Z[lane * kQN + kk] = cs * zk + sn * z1;
+            *(lane == 0 && q > lo ? &B_[q - 1] : mydump) = r;
+            *(lane == 0 ? &A_[q] : mydump) = na;
+            *(zlane ? &Zr[q] : mydump) = cs * zk + sn * z1;
             zk = -sn * zk + cs * z1;
             ak = na1;
             bk = cs * bk1;
             x = nbk;
             y = sn * bk1;
-            ak1 = ak2;
-            bk1 = bk2;
-            z1 = z2;
+        };
+        int q = lo;
+        for (const int q0 = lo + (hi - lo) % 3; q < q0; ++q) {
+            const int i = q + 1;
+            rot(q, A_[i], B_[i], Zr[i]);
+        }
+        if (q < hi) {
+            int i0 = q + 1, i1 = min(q + 2, hi), i2 = min(q + 3, hi);
+            double a0 = A_[i0], b0 = B_[i0], z0 = Zr[i0];
+            double a1 = A_[i1], b1 = B_[i1], z1 = Zr[i1];
+            double a2 = A_[i2], b2 = B_[i2], z2 = Zr[i2];
+            for (; q < hi; q += 3) {
+                rot(q, a0, b0, z0);
+                i0 = min(q + 4, hi);
+                a0 = A_[i0];
+                b0 = B_[i0];
+                z0 = Zr[i0];
+                rot(q + 1, a1, b1, z1);
+                i1 = min(q + 5, hi);
+                a1 = A_[i1];
+                b1 = B_[i1];
+                z1 = Zr[i1];
+                rot(q + 2, a2, b2, z2);
+                i2 = min(q + 6, hi);
+                a2 = A_[i2];
+                b2 = B_[i2];
+                z2 = Zr[i2];
+            }
         }
         if (lane == 0) {
             A_[hi] = ak;
             B_[hi - 1] = nbk;
         }
-        if (lane < kBlk) Z[lane * kQN + hi] = zk;
+        if (zlane) Zr[hi] = zk;
         __syncthreads();
     }
     __syncthreads();
@@ -581,7 +789,7 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
     for (int e = lane; e < 256; e += 64) {
         const int a = e >> 4, b = e & 15;
         double s = 0.0;
-        for (int q = 0; q < N; ++q) s += Z[a * kQN + q] * Z[b * kQN + q] * blk_step(A_[q], smooth_w);
+        for (int q = 0; q < N; ++q) s += Lb[zidx(a, q)] * Lb[zidx(b, q)] * blk_step(A_[q], smooth_w);
         F[e] = s;
     }
     __syncthreads();
