@@ -181,11 +181,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         return FWD ? tt : n - 1 - tt;
     };
     double nv[kBatch][4];   // next batch: band values 2 q, 2 q + 1, 128 + 2 q, 129 + 2 q
+    // rows of steps t0 .. t0 + 15: consecutive band rows (up in FWD, down in
+    // BWD) from one row pointer, the offset clamped at the last step
     auto load_batch = [&](int64_t t0) __attribute__((always_inline)) {
+        const int64_t tc = t0 < n ? t0 : n - 1;
+        const int last = (int)(n - 1 - tc < kBatch - 1 ? n - 1 - tc : kBatch - 1);
+        const double2 *row0 = reinterpret_cast<const double2 *>(band + (size_t)row_of(tc) * kRing);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const double2 *row =
-                reinterpret_cast<const double2 *>(band + (size_t)row_of(t0 + u) * kRing);
+            const int uu = u < last ? u : last;
+            const double2 *row = row0 + (FWD ? uu : -uu) * (kRing / 2);
             const double2 a = row[q], b = row[64 + q];
             nv[u][0] = a.x;
             nv[u][1] = a.y;
@@ -210,12 +215,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     double slot[NR + 1];
 #pragma unroll
     for (int s2 = 0; s2 <= NR; ++s2) slot[s2] = 0.0;
-    double yown = 0.0;
     T b_own = load_b(0), b_next = load_b(NS);
 
     // coefficients of a step (position Q0 in the group, staging row u) for
     // slot s: distance d = q - Q0 + 64 s, staged index 64 + 256 - d (zero
-    // unless 1 <= d <= 256)
+    // unless 1 <= d <= 256).  Lane q's slot 0 takes only zeros from step
+    // T0 + q on, so its y is b - slot[0] at the end of the group.
     double ca[NR + 1], cb[NR + 1];
     auto coefs = [&](int Q0, int u, double (&c_)[NR + 1]) __attribute__((always_inline)) {
         const double *sr = stg[u] + (NS - q + Q0);
@@ -231,17 +236,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         const int lo = __builtin_amdgcn_readlane(__double2loint(y), Q0);
         const int hi = __builtin_amdgcn_readlane(__double2hiint(y), Q0);
         const double yb = __hiloint2double(hi, lo);
-        yown = q == Q0 ? yb : yown;
 #pragma unroll
         for (int s2 = 0; s2 <= NR; ++s2) slot[s2] += cur[s2] * yb;
+        // every pending sum is complete after its step (the compiler would
+        // otherwise defer the FMAs of slots 1.. to the end of the group and
+        // hold every step's coefficients and y until then)
+#pragma unroll
+        for (int s2 = 1; s2 <= NR; ++s2) asm volatile("" : "+v"(slot[s2]));
     };
-    // batch B of the group (steps 16 B .. 16 B + 15), staged in stg
-    auto batch = [&]<int B>(int64_t T0, std::integral_constant<int, B>) __attribute__((always_inline)) {
+    // batch B of the group (steps 16 B .. 16 B + 15), staged in stg; FULL: the
+    // whole group lies before step n (no test per step)
+    auto batch = [&]<int B, bool FULL>(int64_t T0, std::integral_constant<int, B>,
+                                       std::bool_constant<FULL>) __attribute__((always_inline)) {
         if constexpr ((B * kBatch) & 1) coefs(B * kBatch, 0, cb);
         else coefs(B * kBatch, 0, ca);
         [&]<int... U>(std::integer_sequence<int, U...>) __attribute__((always_inline)) {
-            ((T0 + B * kBatch + U < n ? step(std::integral_constant<int, B * kBatch + U>{}, U)
-                                      : void()),
+            ((FULL || T0 + B * kBatch + U < n ? step(std::integral_constant<int, B * kBatch + U>{}, U)
+                                              : void()),
              ...);
         }(std::make_integer_sequence<int, kBatch>{});
     };
@@ -252,25 +263,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
             load_batch(t_next + kBatch);
         }
     };
+    auto group = [&]<bool FULL>(int64_t T0, std::bool_constant<FULL> f) __attribute__((always_inline)) {
+        batch(T0, std::integral_constant<int, 0>{}, f);
+        advance(T0 + kBatch);
+        batch(T0, std::integral_constant<int, 1>{}, f);
+        advance(T0 + 2 * kBatch);
+        batch(T0, std::integral_constant<int, 2>{}, f);
+        advance(T0 + 3 * kBatch);
+        batch(T0, std::integral_constant<int, 3>{}, f);
+    };
 
     load_batch(0);
     stage_batch();
     load_batch(kBatch);
-    for (int64_t T0 = 0; T0 < n; T0 += NS) {
-        batch(T0, std::integral_constant<int, 0>{});
-        advance(T0 + kBatch);
-        batch(T0, std::integral_constant<int, 1>{});
-        advance(T0 + 2 * kBatch);
-        batch(T0, std::integral_constant<int, 2>{});
-        advance(T0 + 3 * kBatch);
-        batch(T0, std::integral_constant<int, 3>{});
-        if (ok && T0 + q < n) Y[(size_t)row_of(T0 + q) * C + c] = static_cast<T>(yown);
+    // after a group: store its y, shift the pending sums by one slot
+    auto finish_group = [&](int64_t T0) __attribute__((always_inline)) {
+        if (ok && T0 + q < n)
+            Y[(size_t)row_of(T0 + q) * C + c] = static_cast<T>(static_cast<double>(b_own) - slot[0]);
 #pragma unroll
         for (int s2 = 0; s2 < NR; ++s2) slot[s2] = slot[s2 + 1];
         slot[NR] = 0.0;
         b_own = b_next;
         b_next = load_b(T0 + 2 * NS);
         advance(T0 + NS);
+    };
+    // the groups that end before step n, then the partial last group
+    int64_t T0 = 0;
+    for (; T0 + NS <= n; T0 += NS) {
+        group(T0, std::true_type{});
+        finish_group(T0);
+    }
+    if (T0 < n) {
+        group(T0, std::false_type{});
+        finish_group(T0);
     }
 }
 
