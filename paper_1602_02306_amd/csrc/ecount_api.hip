@@ -147,8 +147,7 @@ size_t plan_layout(Plan &p, char *base)
     p.st_diag = (double *)take(p.stencil_a ? sizeof(double) * p.n : 0);
     p.st_coff = (double *)take(p.stencil_a ? sizeof(double) : 0);
     p.e_blk = (double *)take(p.prec_kind == ECNT_PREC_LDL ? sizeof(double) * 2 * p.S * p.n : 0);
-    p.band = (double *)take(p.prec_kind == ECNT_PREC_LDL
-                                ? sizeof(double) * 2 * p.S * p.n * (size_t)ldl_ring_rows() : 0);
+    p.band = (double *)take(p.prec_kind == ECNT_PREC_LDL ? ldl_band_bytes(p.n, p.S) : 0);
     p.result = (double *)take(sizeof(double) * kResStride * p.nseg);
     p.active = (int32_t *)take(sizeof(int32_t) * NC);
     p.kused = (int32_t *)take(sizeof(int32_t) * NCt);

@@ -234,6 +234,7 @@ void launch_blk_quad(const Plan &p, hipStream_t st);
 void launch_ldl_eblocks(const Plan &p, hipStream_t st);
 void launch_ldl(const Plan &p, int what, const void *X, const double *xs, void *Y, hipStream_t st);
 int ldl_ring_rows();
+size_t ldl_band_bytes(int64_t n, int S);   // the band forms of S factors, with their padding
 
 // bandwidth probes (k_probe.hip): 0 copy, 1 read, 2 update mix; 0 ok, -1 HIP error
 int run_probe(int kind, void *buf, size_t bytes, int reps, hipStream_t st, double *gbs);

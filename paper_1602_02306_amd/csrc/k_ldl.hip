@@ -19,6 +19,9 @@ namespace ecnt {
 
 namespace {
 constexpr int kRing = 256;   // band width (the largest bandwidth served)
+// rows of padding before and after each band: a batch of rows staged past
+// either end of the walk reads them (never used), so no row index is clamped
+constexpr int kPad = 32;
 }
 
 // |D|^{-1/2} block by block, for one shift.  A 2 x 2 block [[a, b], [b, c]]
@@ -80,10 +83,13 @@ __global__ __launch_bounds__(256) void k_ldl_eapply(int64_t n, int C, int c_lo, 
 
 // Band form of one factor, built once per call: row i of L as 256 values
 // bf[i][256 - d] = l_{i, i-d}, and row i of L^T as bb[i][256 - d] = l_{i+d, i}
-// (d = 1..256; zeros where L has no entry).
+// (d = 1..256; zeros where L has no entry), each with kPad zero rows before
+// and after (bf and bb point at row 0).
 __global__ void k_ldl_band_zero(int64_t n, double *__restrict__ bf, double *__restrict__ bb)
 {
-    const int64_t total = n * kRing;
+    const int64_t total = (n + 2 * kPad) * kRing;
+    bf -= (size_t)kPad * kRing;
+    bb -= (size_t)kPad * kRing;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (int64_t)gridDim.x * blockDim.x) {
         bf[g] = 0.0;
@@ -182,15 +188,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     };
     double nv[kBatch][4];   // next batch: band values 2 q, 2 q + 1, 128 + 2 q, 129 + 2 q
     // rows of steps t0 .. t0 + 15: consecutive band rows (up in FWD, down in
-    // BWD) from one row pointer, the offset clamped at the last step
+    // BWD) from one row pointer; t0 < n + 16, so the rows stay within the
+    // kPad rows of padding past either end
     auto load_batch = [&](int64_t t0) __attribute__((always_inline)) {
-        const int64_t tc = t0 < n ? t0 : n - 1;
-        const int last = (int)(n - 1 - tc < kBatch - 1 ? n - 1 - tc : kBatch - 1);
-        const double2 *row0 = reinterpret_cast<const double2 *>(band + (size_t)row_of(tc) * kRing);
+        const double2 *row0 =
+            reinterpret_cast<const double2 *>(band + (FWD ? t0 : n - 1 - t0) * (int64_t)kRing);
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int uu = u < last ? u : last;
-            const double2 *row = row0 + (FWD ? uu : -uu) * (kRing / 2);
+            const double2 *row = row0 + (FWD ? u : -u) * (kRing / 2);
             const double2 a = row[q], b = row[64 + q];
             nv[u][0] = a.x;
             nv[u][1] = a.y;
@@ -301,13 +306,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 
 int ldl_ring_rows() { return kRing; }
 
+size_t ldl_band_bytes(int64_t n, int S) { return sizeof(double) * 2 * (size_t)S * (n + 2 * kPad) * kRing; }
+
+// row 0 of the band of shift s: which = 0 rows of L, 1 rows of L^T
+static double *band_of(const Plan &p, int s, int which)
+{
+    return p.band + ((size_t)(2 * s + which) * (p.n + 2 * kPad) + kPad) * kRing;
+}
+
 void launch_ldl_eblocks(const Plan &p, hipStream_t st)
 {
     for (int s = 0; s < p.S; ++s) {
         double *ed = p.e_blk + (size_t)s * 2 * p.n, *eo = ed + p.n;
         k_ldl_eblocks<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(p.n, p.ldl[s].dd, p.ldl[s].doff,
                                                                      ed, eo);
-        double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
+        double *bf = band_of(p, s, 0), *bb = band_of(p, s, 1);
         k_ldl_band_zero<<<1024, 256, 0, st>>>(p.n, bf, bb);
         k_ldl_band_fill<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(
             p.n, p.ldl[s].nnz, p.ldl[s].lrp, p.ldl[s].lci, p.ldl[s].lval, bf, bb);
@@ -335,7 +348,7 @@ static void ldl_t(const Plan &p, int what, const void *X, const double *xs, void
         for (int s = 0; s < p.S; ++s) {
             int lo, hi;
             if (!shift_cols(p, s, lo, hi)) continue;
-            const double *bf = p.band + (size_t)s * 2 * p.n * kRing, *bb = bf + (size_t)p.n * kRing;
+            const double *bf = band_of(p, s, 0), *bb = band_of(p, s, 1);
             const int k = set.nsh++;
             set.lo[k] = lo;
             set.hi[k] = hi;
