@@ -30,7 +30,11 @@ __device__ __forceinline__ double step_fn(double th, double w)
 }
 
 // One lane per virtual column vc = seg*C + c (alpha, beta, nu indexed [row][NC]);
-// kused, s_out and minabs are global: [seg*ld + off + c].
+// kused, s_out and minabs are global: [seg*ld + off + c].  A workgroup is
+// blockDim.x lanes (at most QuadGeom<KMAX>::lanes): the columns' QR
+// iterations diverge, so a wavefront runs as long as the union of its lanes'
+// paths, and few columns go one to a wavefront (the launcher's choice).  The
+// matrices live in dynamic LDS, 3 * KMAX doubles per lane.
 template <int KMAX>
 __global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, int k, int rule,
                                                 double smooth_w,
@@ -42,8 +46,8 @@ __global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, 
                                                 double *__restrict__ minabs_all,
                                                 int32_t *__restrict__ flags)
 {
-    constexpr int LN = QuadGeom<KMAX>::lanes;
-    __shared__ double lds[3 * KMAX * LN];
+    extern __shared__ double lds[];
+    const int LN = blockDim.x;
     const int lane = threadIdx.x;
     const int vc = blockIdx.x * LN + lane;
     if (vc >= NC) return;
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, 
         for (int i = 0; i < N - 1; ++i) B_(i) = beta[(size_t)(i + 1) * C + c];
     }
     for (int i = 0; i < N; ++i) Z_(i) = i == 0 ? 1.0 : 0.0;
+    B_(N - 1) = 0.0;   // past the last row: what a sweep's last rotation reads
 
     int hi = N - 1;
     int iter = 0;
@@ -107,29 +112,62 @@ __global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, 
         const double den = d + copysign(hypot(d, bb), d);
         const double mu = A_(hi) - (den != 0.0 ? bb * bb / den : 0.0);
         double x = A_(lo) - mu, y = B_(lo);
-        for (int kk = lo; kk < hi; ++kk) {
-            const double r = hypot(x, y);
-            double cs = 1.0, sn = 0.0;
-            if (r > 0.0) {
-                cs = x / r;
-                sn = y / r;
-            }
+        // The values a rotation changes and the next one reads (A(kk), B(kk),
+        // Z(kk)) are carried in registers; the ones it reads ahead (A(kk+1),
+        // B(kk+1), Z(kk+1), not yet written in this sweep) come from three
+        // register sets by position mod 3, each reloaded three indices ahead
+        // once its rotation has used it (the first (hi - lo) mod 3 rotations
+        // read theirs directly).  Indices are clamped to hi, with no
+        // condition on a load: B(hi) is 0 (set when hi moved down, or past
+        // the last row), which is what a sweep's last rotation takes.
+        double ak = A_(lo), bk = B_(lo), zk = Z_(lo), nbk = bk;
+        auto rot = [&](int kk, double ak1, double bk1, double z1) __attribute__((always_inline)) {
+            // |x|, |y| far from the under/overflow range: J_k holds O(|C|) entries
+            const double q2 = x * x + y * y;
+            const bool nz = q2 > 0.0;
+            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double r = nz ? q2 * ir : 0.0;
+            const double cs = nz ? x * ir : 1.0;
+            const double sn = nz ? y * ir : 0.0;
             if (kk > lo) B_(kk - 1) = r;
-            const double ak = A_(kk), ak1 = A_(kk + 1), bk = B_(kk);
             A_(kk) = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
-            A_(kk + 1) = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
-            const double nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-            B_(kk) = nbk;
-            if (kk + 1 < hi) {
-                const double bk1 = B_(kk + 1);
-                y = sn * bk1;
-                B_(kk + 1) = cs * bk1;
-                x = nbk;
+            const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
+            nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
+            Z_(kk) = cs * zk + sn * z1;
+            zk = -sn * zk + cs * z1;
+            ak = na1;
+            bk = cs * bk1;
+            x = nbk;
+            y = sn * bk1;
+        };
+        int kk = lo;
+        for (const int k0 = lo + (hi - lo) % 3; kk < k0; ++kk) rot(kk, A_(kk + 1), B_(kk + 1), Z_(kk + 1));
+        if (kk < hi) {
+            int i0 = kk + 1, i1 = min(kk + 2, hi), i2 = min(kk + 3, hi);
+            double a0 = A_(i0), b0 = B_(i0), z0 = Z_(i0);
+            double a1 = A_(i1), b1 = B_(i1), z1 = Z_(i1);
+            double a2 = A_(i2), b2 = B_(i2), z2 = Z_(i2);
+            for (; kk < hi; kk += 3) {
+                rot(kk, a0, b0, z0);
+                i0 = min(kk + 4, hi);
+                a0 = A_(i0);
+                b0 = B_(i0);
+                z0 = Z_(i0);
+                rot(kk + 1, a1, b1, z1);
+                i1 = min(kk + 5, hi);
+                a1 = A_(i1);
+                b1 = B_(i1);
+                z1 = Z_(i1);
+                rot(kk + 2, a2, b2, z2);
+                i2 = min(kk + 6, hi);
+                a2 = A_(i2);
+                b2 = B_(i2);
+                z2 = Z_(i2);
             }
-            const double z0 = Z_(kk), z1 = Z_(kk + 1);
-            Z_(kk) = cs * z0 + sn * z1;
-            Z_(kk + 1) = -sn * z0 + cs * z1;
         }
+        A_(hi) = ak;
+        B_(hi - 1) = nbk;
+        Z_(hi) = zk;
     }
     double s = 0.0, mn = INFINITY;
     for (int i = 0; i < N; ++i) {
@@ -208,11 +246,15 @@ __global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__re
 template <int KMAX>
 static void tridiag_t(const Plan &p, hipStream_t st)
 {
-    constexpr int LN = QuadGeom<KMAX>::lanes;
+    // lanes per workgroup: one column per wavefront up to 2048 columns (about
+    // two wavefronts per CU), then doubling to keep about 2048 workgroups
     const int NC = p.nseg * p.C;
+    int LN = 1;
+    while (LN < QuadGeom<KMAX>::lanes && NC > 2048 * LN) LN *= 2;
     const int blocks = (NC + LN - 1) / LN;
-    k_tridiag<KMAX><<<blocks, LN, 0, st>>>(NC, p.C, p.Ct, p.c_off, p.k, p.rule, p.smooth_w, p.alpha,
-                                           p.beta, p.kused, p.nu, p.s_out, p.minabs, p.flags);
+    const size_t lds = sizeof(double) * 3 * KMAX * LN;
+    k_tridiag<KMAX><<<blocks, LN, lds, st>>>(NC, p.C, p.Ct, p.c_off, p.k, p.rule, p.smooth_w, p.alpha,
+                                             p.beta, p.kused, p.nu, p.s_out, p.minabs, p.flags);
 }
 
 void launch_tridiag(const Plan &p, hipStream_t st)
