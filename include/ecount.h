@@ -184,6 +184,13 @@ typedef struct {
                            neighbours and the diagonal, all off-diagonal values equal),
                            else row by row from the CSR arrays; 1: always from the CSR
                            arrays.  Both sum each row in the same order. */
+    int32_t fused;      /* 0: a problem whose segments have at most 3072 rows, FP64 vectors,
+                           k <= 64, M = I or Jacobi and no derivative runs all k steps
+                           of every column in one launch (one workgroup per column, its
+                           basis column-contiguous in the workspace); otherwise, and
+                           with 1, the column-wave kernels (about five launches per
+                           step).  Both compute the same recurrence; sums are in a
+                           different order. */
 } ecnt_opts;
 
 /* Optional outputs.  Device arrays may be NULL. */

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libecount.so")
 OBJ = os.path.join(PKG, "_build")
 SOURCES = ["ecount_api.hip", "k_operator.hip", "k_lanczos.hip", "k_quad.hip", "k_backward.hip", "k_arnoldi.hip",
-           "ildl_factor.hip", "k_ldl.hip", "k_block.hip", "k_probe.hip"]
+           "ildl_factor.hip", "k_ldl.hip", "k_block.hip", "k_probe.hip", "k_small.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -19,13 +19,13 @@ namespace ecnt {
 // ------------------------------------------------------------------ profiling
 enum Family { F_CHEB = 0, F_CSR, F_DOTS, F_UPDATE, F_SETUP, F_FIN, F_QUAD, F_BDOTS, F_BUPD,
               F_VGRAD, F_CHEB2, F_LDL, F_LDLE, F_BKDOTS, F_BKUPD, F_BKNORM, F_BKQUAD,
-              F_STA, F_COUNT };
+              F_STA, F_FUSED, F_COUNT };
 static const char *kFamilyName[F_COUNT] = {"op_cheb_sweep", "op_csr", "lz_dots", "lz_update",
                                            "lz_setup", "lz_finalize", "quadrature", "bw_dots",
                                            "bw_update", "bw_vgrad", "op_cheb_quad",
                                            "op_ldl_solve", "op_ldl_elementwise", "blk_dots",
                                            "blk_update", "blk_normalize", "blk_quadrature",
-                                           "op_a_stencil"};
+                                           "op_a_stencil", "lz_fused"};
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
 static ecnt_kernel_stat g_stats[F_COUNT];
@@ -253,6 +253,9 @@ static void row_geometry(Plan &p, SegHost &sh)
     p.ntiles = sh.tile[p.nseg];
     p.max_d2 = 1;
     for (int b = 0; b < p.nseg; ++b) p.max_d2 = sh.dims[3 * b + 2] > p.max_d2 ? sh.dims[3 * b + 2] : p.max_d2;
+    p.max_rows = 0;
+    for (int b = 0; b < p.nseg; ++b)
+        p.max_rows = sh.row[b + 1] - sh.row[b] > p.max_rows ? sh.row[b + 1] - sh.row[b] : p.max_rows;
 }
 
 // ---- product form of the preconditioner polynomial ----
@@ -368,6 +371,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
     if (o->csr_vw != 0 && o->csr_vw != 1 && o->csr_vw != 2 && o->csr_vw != 4)
         return fail(ECNT_EINVAL, "opts.csr_vw must be 0, 1, 2 or 4");
     if (o->a_form != 0 && o->a_form != 1) return fail(ECNT_EINVAL, "opts.a_form must be 0 or 1");
+    if (o->fused != 0 && o->fused != 1) return fail(ECNT_EINVAL, "opts.fused must be 0 or 1");
     const int kmax = o->rule == ECNT_RULE_GA ? kMaxK / 2 : kMaxK;
     if (o->k > kmax) return fail(ECNT_EUNSUPPORTED, "k above %d is not supported", kmax);
     p.n = n;
@@ -452,6 +456,7 @@ static ecnt_status make_plan(Plan &p, int64_t n, int64_t m, int S, const ecnt_pr
         p.product = factorize(p) ? 1 : 0;
     // the grid of the Laplacian preconditioner is where A may be a stencil
     p.stencil_a = (p.prec_kind == ECNT_PREC_CHEB_LAPLACIAN && o->a_form == 0) ? 1 : 0;
+    p.req_fused = o->fused;
     return ECNT_OK;
 }
 
@@ -844,6 +849,16 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         return;
     }
     const double blk_b = block_bytes(p);
+    if (fused_applies(p)) {
+        // a small problem: all k steps in one launch (one workgroup per column)
+        {
+            Timed t(F_FUSED, 0.0, st);
+            launch_lanczos_fused(p, A->row_ptr, A->col_idx, A->val, probes, st);
+        }
+        Timed t(F_QUAD, 0.0, st);
+        launch_tridiag(p, st);
+        return;
+    }
     {
         Timed t(F_SETUP, blk_b + (double)p.n * p.C * (p.vec_f32 ? 4 : 8) / p.S, st);
         launch_setup(p, probes, st);

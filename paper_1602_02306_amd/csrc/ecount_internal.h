@@ -53,6 +53,7 @@ struct Plan {
     int prec_kind = 0;
     int ndim = 0, dims[3] = {1, 1, 1};
     int max_d2 = 1;            // largest z extent of the segments' grids
+    int64_t max_rows = 0;      // largest segment (rows)
     int degree = 0;
     double coef[17] = {0};
     double s = 0, lo = 0, hi = 0;
@@ -68,6 +69,7 @@ struct Plan {
     // geometry
     int vw = 1;           // columns per lane in the CSR sweep
     int req_tile = 0, req_red_waves = 0, req_vw = 0;   // launch-shape requests (0: default)
+    int req_fused = 0;    // opts.fused: 0 the one-launch form when it applies, 1 never
     int nct = 0;          // column tiles of 64 (setup kernel)
     int nchunk = 0;       // row chunks of the two-phase column reductions (all segments)
     int64_t rpc = 0;      // rows per chunk
@@ -205,6 +207,12 @@ void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStre
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st);
 void launch_norm_fin(const Plan &p, int step, hipStream_t st);
 void launch_tridiag(const Plan &p, hipStream_t st);
+// the one-launch Lanczos form of small problems (k_small.hip)
+constexpr int kFusedMaxRows = 3072;   // rows of the largest segment (q and w in LDS)
+constexpr int kFusedMaxK = 64;
+bool fused_applies(const Plan &p);
+void launch_lanczos_fused(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
+                          const void *probes, hipStream_t st);
 void launch_reduce(const Plan &p, hipStream_t st);
 // Arnoldi estimator
 void launch_arn_fin(const Plan &p, int step, int l0, int nb, int pass, hipStream_t st);

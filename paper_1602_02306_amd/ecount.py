@@ -56,11 +56,12 @@ class OptsT(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("vec_type", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("max_cols", ctypes.c_int32), ("smooth_w", ctypes.c_double),
                 ("tile", ctypes.c_int32), ("red_waves", ctypes.c_int32), ("csr_vw", ctypes.c_int32),
-                ("a_form", ctypes.c_int32)]
+                ("a_form", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 TILES = {"auto": 0, "4x4": 1, "2x4": 2, "1x8": 3, "4x4-unfused": 4, "8x8-wg": 5}
 A_FORMS = {"auto": 0, "csr": 1}
+FUSED = {"auto": 0, "off": 1}
 
 
 class InfoT(ctypes.Structure):
@@ -325,11 +326,12 @@ def _check_factors(prec, nshift: int):
 def opts_struct(k: int, vec: str = "f64", rule: str = "gauss", smooth_w: float = 0.0,
                 max_cols: int = 0, tune: dict | None = None) -> OptsT:
     """ecnt_opts; `tune` holds optional launch-shape tunables:
-    {"tile": "4x4"|"2x4"|"1x8", "red_waves": int, "csr_vw": int, "a_form": "auto"|"csr"}."""
+    {"tile": "4x4"|"2x4"|"1x8", "red_waves": int, "csr_vw": int, "a_form": "auto"|"csr",
+    "fused": "auto"|"off"}."""
     t = tune or {}
     return OptsT(int(k), DTYPES[vec], RULES[rule], int(max_cols), float(smooth_w),
                  TILES[t.get("tile", "auto")], int(t.get("red_waves", 0)), int(t.get("csr_vw", 0)),
-                 A_FORMS[t.get("a_form", "auto")])
+                 A_FORMS[t.get("a_form", "auto")], FUSED[t.get("fused", "auto")])
 
 
 def workspace_bytes(n: int, m: int, nshift: int, prec, k: int, vec: str = "f64",

@@ -97,6 +97,7 @@ def _call_count(A=True, prec=None, xi=0.0, eta=1.0, probes=0x1000, m=4, k=3, ws=
     (dict(opts=ec.OptsT(3, 0, 0, 0, 0.0, 0, 32)), ec.ECNT_EINVAL),
     (dict(opts=ec.OptsT(3, 0, 0, 0, 0.0, 0, 0, 3)), ec.ECNT_EINVAL),
     (dict(opts=ec.OptsT(3, 0, 0, 0, 0.0, 0, 0, 0, 2)), ec.ECNT_EINVAL),
+    (dict(opts=ec.OptsT(3, 0, 0, 0, 0.0, 0, 0, 0, 0, 2)), ec.ECNT_EINVAL),
 ])
 def test_invalid_calls_rejected_on_host(kw, code):
     rc, msg = _call_count(**kw)

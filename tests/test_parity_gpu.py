@@ -149,14 +149,19 @@ def test_full_krylov_exact_count_gpu(ec, prec):
     assert rel(r.estimate, ref.estimate) <= TOL
 
 
-def test_ideal_preconditioner_breakdown_gpu(ec):
+FORMS = {"fused": {}, "waves": {"fused": "off"}}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_ideal_preconditioner_breakdown_gpu(ec, form):
     """Diagonal A with |A - tau I|^(-1/2): two distinct eigenvalues of C, the
-    Lanczos run stops after 2 steps and s_j equals the count (Section 6)."""
+    Lanczos run stops after 2 steps and s_j equals the count (Section 6).
+    Both the one-launch form of small problems and the column waves."""
     rng = np.random.default_rng(5)
     d = rng.uniform(-3.0, 3.0, 300)
     A = W.CSR(300, np.arange(301, dtype=np.int32), np.arange(300, dtype=np.int32), d)
     V = W.rademacher(300, 70, 11)
-    r = gpu_count(ec, A, W.PrecSpec("jacobi", ()), -0.5, 0.7, V, 6)
+    r = gpu_count(ec, A, W.PrecSpec("jacobi", ()), -0.5, 0.7, V, 6, tune=FORMS[form])
     ku = r.k_used.cpu().numpy()
     assert np.all(ku == 2)
     s = r.per_probe.cpu().numpy()
@@ -165,11 +170,13 @@ def test_ideal_preconditioner_breakdown_gpu(ec):
     assert abs(r.estimate - np.sum((d >= -0.5) & (d < 0.7))) < 1e-9
 
 
-def test_breakdown_mixed_within_a_wave(ec):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_breakdown_mixed_within_a_wave(ec, form):
     """Diagonal A without preconditioner: probes that are unit vectors span an
     invariant space at once (k_used = 1), a probe on two coordinates after two
     steps, Rademacher probes run to k; all in one wave, each column against the
-    oracle (its k_used and s_j) while the others keep iterating."""
+    oracle (its k_used and s_j) while the others keep iterating.  Both the
+    one-launch form of small problems and the column waves."""
     rng = np.random.default_rng(8)
     n = 300
     d = np.sort(rng.uniform(-3.0, 3.0, n))
@@ -182,8 +189,8 @@ def test_breakdown_mixed_within_a_wave(ec):
     V[:, 4] = 0.0
     V[10, 4] = 1.0
     V[250, 4] = -1.0
-    print("mixed breakdown", flush=True)
-    r = gpu_count(ec, A, W.PrecSpec("none", ()), -0.5, 0.7, V, 12)
+    print("mixed breakdown", form, flush=True)
+    r = gpu_count(ec, A, W.PrecSpec("none", ()), -0.5, 0.7, V, 12, tune=FORMS[form])
     ref = oracle.count(A, W.PrecSpec("none", ()), -0.5, 0.7, V, 12)
     ku = np.concatenate([ref.lan_xi.k_used, ref.lan_eta.k_used])
     assert set(ku.tolist()) >= {1, 2, 12}
@@ -694,3 +701,35 @@ def test_hbm_probes_plausible(ec):
         g = ec.hbm_probe(kind, 1 << 30, reps=3)
         print("probe", kind, g, flush=True)
         assert 500.0 < g < 9000.0
+
+
+@pytest.mark.parametrize("prec,k,rule", [("jacobi", 20, "gauss"), ("none", 12, "gauss"),
+                                         ("jacobi", 30, "ga"), ("jacobi", 64, "gauss")])
+def test_fused_small_form_against_oracle_and_waves(ec, prec, k, rule):
+    """c1 (900 rows) runs by default in the one-launch form of small problems
+    (M = I or Jacobi, FP64 vectors, k <= 64): against the oracle to the stated
+    bar, and against the column-wave kernels (opts.fused = 1), which sum in
+    another order, to the same bar.  The profile shows which kernels ran."""
+    wl = W.WORKLOADS["c1"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    pr = P.prec if prec == "jacobi" else W.PrecSpec("none", ())
+    print("case fused", prec, k, rule, flush=True)
+    ec.profile_enable(True)
+    a = gpu_count(ec, P.A, pr, wl.xi, wl.eta, V, k, rule=rule)
+    pa = ec.profile_read()
+    ec.profile_enable(True)
+    b = gpu_count(ec, P.A, pr, wl.xi, wl.eta, V, k, rule=rule, tune={"fused": "off"})
+    pb = ec.profile_read()
+    ec.profile_enable(False)
+    assert pa["lz_fused"]["launches"] == 1 and pa["lz_dots"]["launches"] == 0
+    assert pb["lz_fused"]["launches"] == 0 and pb["lz_dots"]["launches"] >= k
+    ref = oracle.count(P.A, pr, wl.xi, wl.eta, V, k, rule=rule)
+    scale = "nu" if k >= 40 else "rel"
+    assert_parity(a, ref, k, probe_scale=scale)
+    assert_parity(b, ref, k, probe_scale=scale)
+    assert np.array_equal(a.k_used.cpu().numpy(), b.k_used.cpu().numpy())
+    sa, sb = a.per_probe.cpu().numpy(), b.per_probe.cpu().numpy()
+    bound = TOL * (np.maximum(1.0, np.abs(sb)) if scale == "rel" else
+                   np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu]))
+    assert np.all(np.abs(sa - sb) <= bound)
