@@ -243,12 +243,180 @@ __global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__re
     if (threadIdx.x == 0) res[3 * S - 2] = sh[0];
 }
 
+// The same eigensolve with one wavefront per column (few columns): every lane
+// runs the rotation chain on the same values, the search for the unreduced
+// block takes 64 candidates at a time (a ballot), and each sweep carries its
+// changing values in registers with the values ahead loaded three rotations
+// early, as the lane form does.  Lane 0 makes the writes (the other lanes
+// write to a slot of their own).
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int off, int k, int rule,
+                                                     double smooth_w,
+                                                     const double *__restrict__ alpha,
+                                                     const double *__restrict__ beta,
+                                                     const int32_t *__restrict__ kused_all,
+                                                     const double *__restrict__ nu,
+                                                     double *__restrict__ s_all,
+                                                     double *__restrict__ minabs_all,
+                                                     int32_t *__restrict__ flags)
+{
+    __shared__ double A_[KMAX + 1], B_[KMAX + 1], Z_[KMAX + 1];
+    __shared__ double dump[64];
+    const int lane = threadIdx.x;
+    const int vc = blockIdx.x;
+    const int seg = vc / C;
+    const size_t gidx = (size_t)seg * ld + off + (vc - seg * C);
+    const int c = vc;
+    C = NC;   // alpha, beta, nu below are indexed [row][NC] by the virtual column
+    double *const mydump = dump + lane;
+    const int ku = kused_all[gidx];
+    if (ku < 1) {
+        if (lane == 0) {
+            s_all[gidx] = 0.0;
+            minabs_all[gidx] = INFINITY;
+        }
+        return;
+    }
+    int N;
+    if (rule == 1 && ku == k && k >= 2) {
+        // eq. GA_Tk: diag (a_1..a_k, a_{k-1}..a_1), off (b_2..b_k, b_{k+1}, b_{k-1}..b_2)
+        N = 2 * k - 1;
+        for (int i = lane; i < N; i += 64) {
+            A_[i] = alpha[(size_t)(i < k ? i : 2 * k - 2 - i) * C + c];
+            if (i < N - 1) B_[i] = beta[(size_t)(i < k ? i + 1 : 2 * k - 2 - i) * C + c];
+        }
+    } else {
+        N = ku;
+        for (int i = lane; i < N; i += 64) {
+            A_[i] = alpha[(size_t)i * C + c];
+            if (i < N - 1) B_[i] = beta[(size_t)(i + 1) * C + c];
+        }
+    }
+    for (int i = lane; i < N; i += 64) Z_[i] = i == 0 ? 1.0 : 0.0;
+    if (lane == 0) B_[N - 1] = 0.0;   // past the last row: what a sweep's last rotation reads
+    __syncthreads();
+
+    int hi = N - 1, iter = 0;
+    bool failed = false;
+    while (hi > 0) {
+        if (fabs(B_[hi - 1]) <= DBL_EPSILON * (fabs(A_[hi - 1]) + fabs(A_[hi])) ||
+            fabs(B_[hi - 1]) < DBL_MIN) {
+            __syncthreads();
+            if (lane == 0) B_[hi - 1] = 0.0;
+            __syncthreads();
+            --hi;
+            continue;
+        }
+        // the largest lo < hi with B[lo-1] negligible (or 0), 64 candidates at a time
+        int lo = 0;
+        for (int base = hi - 1; base > 0; base -= 64) {
+            const int i = base - lane;
+            bool neg = false;
+            if (i >= 1) {
+                const double bl = fabs(B_[i - 1]);
+                neg = bl <= DBL_EPSILON * (fabs(A_[i - 1]) + fabs(A_[i])) || bl < DBL_MIN;
+            }
+            const unsigned long long msk = __ballot(neg);
+            if (msk) {
+                lo = base - (__ffsll((long long)msk) - 1);
+                break;
+            }
+        }
+        if (++iter > 60 * N) {
+            failed = true;
+            break;
+        }
+        // Wilkinson shift from the trailing 2x2 block of the active window
+        const double bb = B_[hi - 1];
+        const double d = 0.5 * (A_[hi - 1] - A_[hi]);
+        const double den = d + copysign(hypot(d, bb), d);
+        const double mu = A_[hi] - (den != 0.0 ? bb * bb / den : 0.0);
+        if (lo > 0 && lane == 0) B_[lo - 1] = 0.0;   // the split found above (not read by the sweep)
+        double x = A_[lo] - mu, y = B_[lo];
+        double ak = A_[lo], bk = B_[lo], zk = Z_[lo], nbk = bk;
+        auto rot = [&](int q, double ak1, double bk1, double z1) __attribute__((always_inline)) {
+            // |x|, |y| far from the under/overflow range: J_k holds O(|C|) entries
+            const double q2 = x * x + y * y;
+            const bool nz = q2 > 0.0;
+            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double r = nz ? q2 * ir : 0.0;
+            const double cs = nz ? x * ir : 1.0;
+            const double sn = nz ? y * ir : 0.0;
+            *(lane == 0 && q > lo ? &B_[q - 1] : mydump) = r;
+            *(lane == 0 ? &A_[q] : mydump) = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
+            nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
+            *(lane == 0 ? &Z_[q] : mydump) = cs * zk + sn * z1;
+            zk = -sn * zk + cs * z1;
+            ak = na1;
+            bk = cs * bk1;
+            x = nbk;
+            y = sn * bk1;
+        };
+        int q = lo;
+        for (const int q0 = lo + (hi - lo) % 3; q < q0; ++q) rot(q, A_[q + 1], B_[q + 1], Z_[q + 1]);
+        if (q < hi) {
+            int i0 = q + 1, i1 = min(q + 2, hi), i2 = min(q + 3, hi);
+            double a0 = A_[i0], b0 = B_[i0], z0 = Z_[i0];
+            double a1 = A_[i1], b1 = B_[i1], z1 = Z_[i1];
+            double a2 = A_[i2], b2 = B_[i2], z2 = Z_[i2];
+            for (; q < hi; q += 3) {
+                rot(q, a0, b0, z0);
+                i0 = min(q + 4, hi);
+                a0 = A_[i0];
+                b0 = B_[i0];
+                z0 = Z_[i0];
+                rot(q + 1, a1, b1, z1);
+                i1 = min(q + 5, hi);
+                a1 = A_[i1];
+                b1 = B_[i1];
+                z1 = Z_[i1];
+                rot(q + 2, a2, b2, z2);
+                i2 = min(q + 6, hi);
+                a2 = A_[i2];
+                b2 = B_[i2];
+                z2 = Z_[i2];
+            }
+        }
+        if (lane == 0) {
+            A_[hi] = ak;
+            B_[hi - 1] = nbk;
+            Z_[hi] = zk;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // s = |v|^2 sum_i z_i(1)^2 h(theta_i): lanes take i = lane, lane + 64, ...,
+    // then the butterfly (the same sum in every lane)
+    double s = 0.0, mn = INFINITY;
+    for (int i = lane; i < N; i += 64) {
+        const double th = A_[i], zz = Z_[i];
+        s += zz * zz * step_fn(th, smooth_w);
+        mn = fmin(mn, fabs(th));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+    }
+    if (lane == 0) {
+        s_all[gidx] = nu[c] * s;
+        minabs_all[gidx] = mn;
+        if (failed) atomicOr(&flags[1], 1);
+    }
+}
+
 template <int KMAX>
 static void tridiag_t(const Plan &p, hipStream_t st)
 {
-    // lanes per workgroup: one column per wavefront up to 2048 columns (about
-    // two wavefronts per CU), then doubling to keep about 2048 workgroups
+    // up to 2048 columns (about two wavefronts per CU): a wavefront per column;
+    // beyond, lanes per workgroup doubling to keep about 2048 workgroups
     const int NC = p.nseg * p.C;
+    if (NC <= 2048) {
+        k_tridiag_wave<KMAX><<<NC, 64, 0, st>>>(NC, p.C, p.Ct, p.c_off, p.k, p.rule, p.smooth_w,
+                                                p.alpha, p.beta, p.kused, p.nu, p.s_out, p.minabs,
+                                                p.flags);
+        return;
+    }
     int LN = 1;
     while (LN < QuadGeom<KMAX>::lanes && NC > 2048 * LN) LN *= 2;
     const int blocks = (NC + LN - 1) / LN;

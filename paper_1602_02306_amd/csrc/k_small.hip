@@ -124,20 +124,34 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
                 ws[rl] = y;
             }
             __syncthreads();
-            // g_l and p_l: wavefront wv takes l = wv, wv + 4, ..., all rows
-            for (int l = wv; l < i; l += kSmallWaves) {
-                const double *Ql = Q + (size_t)l * ns;
-                double g = 0.0, pq = 0.0;
+            // g_l and p_l: wavefront wv takes l = wv + 4u, all rows, in one pass
+            // (a lane keeps the sums of all its l, so their loads overlap)
+            {
+                constexpr int U = kFusedMaxK / kSmallWaves;
+                const int nu_ = (i - wv + kSmallWaves - 1) / kSmallWaves;   // l's of this wavefront
+                double g[U], pq[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) g[u] = pq[u] = 0.0;
                 for (int rl = lane; rl < ns; rl += 64) {
-                    const double q = Ql[rl];
-                    g += q * ws[rl];
-                    pq += q * qs[rl];
+                    const double wr = ws[rl], qr = qs[rl];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (u < nu_) {
+                            const double q = Q[(size_t)(wv + kSmallWaves * u) * ns + rl];
+                            g[u] += q * wr;
+                            pq[u] += q * qr;
+                        }
+                    }
                 }
-                g = wave_sum(g);
-                pq = wave_sum(pq);
-                if (lane == 0) {
-                    gp[0][l] = g;
-                    gp[1][l] = pq;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (u < nu_) {
+                        const double gs = wave_sum(g[u]), ps = wave_sum(pq[u]);
+                        if (lane == 0) {
+                            gp[0][wv + kSmallWaves * u] = gs;
+                            gp[1][wv + kSmallWaves * u] = ps;
+                        }
+                    }
                 }
             }
             __syncthreads();
@@ -149,6 +163,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
             double ss = 0.0;
             for (int rl = t; rl < ns; rl += kSmallThreads) {
                 double w = ws[rl];
+#pragma unroll 4
                 for (int l = 0; l < i; ++l) w -= cf[l] * Q[(size_t)l * ns + rl];
                 ws[rl] = w;
                 ss += w * w;
