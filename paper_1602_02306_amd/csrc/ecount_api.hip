@@ -849,11 +849,11 @@ static void enqueue_wave(const Plan &p, const ecnt_csr *A, const void *probes, h
         return;
     }
     const double blk_b = block_bytes(p);
-    if (fused_applies(p)) {
+    if (fused_applies(p, A->nnz)) {
         // a small problem: all k steps in one launch (one workgroup per column)
         {
             Timed t(F_FUSED, 0.0, st);
-            launch_lanczos_fused(p, A->row_ptr, A->col_idx, A->val, probes, st);
+            launch_lanczos_fused(p, A->row_ptr, A->col_idx, A->val, A->nnz, probes, st);
         }
         Timed t(F_QUAD, 0.0, st);
         launch_tridiag(p, st);

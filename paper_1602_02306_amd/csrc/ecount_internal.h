@@ -208,11 +208,12 @@ void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool las
 void launch_norm_fin(const Plan &p, int step, hipStream_t st);
 void launch_tridiag(const Plan &p, hipStream_t st);
 // the one-launch Lanczos form of small problems (k_small.hip)
-constexpr int kFusedMaxRows = 3072;   // rows of the largest segment (q and w in LDS)
+constexpr int kFusedMaxRows = 3072;   // rows of the largest segment
 constexpr int kFusedMaxK = 64;
-bool fused_applies(const Plan &p);
+constexpr size_t kFusedLdsBytes = 150 * 1024;   // the column's operator, q and w in LDS
+bool fused_applies(const Plan &p, int64_t nnz);
 void launch_lanczos_fused(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                          const void *probes, hipStream_t st);
+                          int64_t nnz, const void *probes, hipStream_t st);
 void launch_reduce(const Plan &p, hipStream_t st);
 // Arnoldi estimator
 void launch_arn_fin(const Plan &p, int step, int l0, int nb, int pass, hipStream_t st);

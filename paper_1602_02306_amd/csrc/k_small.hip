@@ -12,8 +12,11 @@
 // (Section 5, the diagonal preconditioner), and the same breakdown rule
 // (beta_{i+1} <= 1e3 eps max(|alpha_l|, beta_l)).  A small count is latency
 // bound: the column-wave form spends about five launches per step, this form
-// one per count.  Sums are in a fixed order (a wavefront sums all rows of one
-// basis vector, lanes then the butterfly), so results are reproducible.
+// one per count.  The workgroup first copies its column's operator into LDS
+// (the segment's rows of A with both scalings folded into the values, column
+// indices local, and tau d_r^2 per row), so every product reads LDS only.
+// Sums are in a fixed order (a wavefront sums all rows of one basis vector,
+// lanes then the butterfly), so results are reproducible.
 #include <float.h>
 
 #include "device_common.h"
@@ -55,11 +58,13 @@ __device__ __forceinline__ double group_sum(double x, double *red)
 // of its segment are r0 .. r0 + ns - 1; slot l of its basis (q_{l+1},
 // normalized) is basis + (k+1) (C r0 + c ns) + l ns.  Outputs as the
 // column-wave form: alpha[(i-1) NC + vc], beta[i NC + vc] (beta_1 = 0),
-// nu[vc] = |v|^2, kused[seg ku_ld + ku_off + c].  Dynamic LDS: q and w,
-// 2 * nmax doubles (nmax >= every segment's rows).
+// nu[vc] = |v|^2, kused[seg ku_ld + ku_off + c].  Dynamic LDS (fused_lds_bytes):
+// q, w and tau d_r^2 (nmax doubles each, nmax >= every segment's rows), the
+// scaled values (nzmax doubles, nzmax >= every segment's nonzeros), their
+// local columns (nzmax ints) and row starts (nmax + 1 ints).
 template <typename VT, bool JAC>
 __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
-    int C, int nseg, int m, int c_off, int k, int S, int64_t n, int nmax,
+    int C, int nseg, int m, int c_off, int k, int S, int64_t n, int nmax, int64_t nzmax,
     const int64_t *__restrict__ seg_row, const double *__restrict__ seg_taus,
     const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const double *__restrict__ jac, const double *__restrict__ V, double *__restrict__ basis,
@@ -70,7 +75,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
     __shared__ double gp[2][kFusedMaxK];   // g_l, p_l
     __shared__ double cf[kFusedMaxK];      // c_l
     __shared__ double red[kSmallWaves];
-    double *qs = lds, *ws = lds + nmax;
+    double *qs = lds, *ws = lds + nmax, *dt = lds + 2 * (size_t)nmax, *lv = lds + 3 * (size_t)nmax;
+    int32_t *lc = reinterpret_cast<int32_t *>(lv + nzmax), *lr = lc + nzmax;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int vc = blockIdx.x;
     const int seg = vc / C, c = vc - seg * C;
@@ -82,6 +88,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
     double *Q = basis + (size_t)(k + 1) * ((size_t)C * r0 + (size_t)c * ns);
     const size_t NC = (size_t)nseg * C;
 
+    // the column's operator: values d_r a_rj d_j (d = 1 without preconditioner),
+    // local columns (an index outside the segment, which a block-diagonal A
+    // does not have, gets value 0), row starts, and tau d_r^2
+    const int p0 = rp[r0], nz = rp[r0 + ns] - p0;
+    for (int e = t; e <= ns; e += kSmallThreads) lr[e] = rp[r0 + e] - p0;
+    for (int rl = t; rl < ns; rl += kSmallThreads) {
+        const double dr = JAC ? d[r0 + rl] : 1.0;
+        dt[rl] = tau * dr * dr;
+    }
+    __syncthreads();
+    for (int rl = t; rl < ns; rl += kSmallThreads) {
+        const double dr = JAC ? d[r0 + rl] : 1.0;
+        for (int e = lr[rl]; e < lr[rl + 1]; ++e) {
+            const int cj = ci[p0 + e];
+            const int lj = (int)(cj - r0);
+            const bool in = (unsigned)lj < (unsigned)ns;
+            lc[e] = in ? lj : 0;
+            lv[e] = in ? dr * static_cast<double>(val[p0 + e]) * (JAC ? d[cj] : 1.0) : 0.0;
+        }
+    }
+    (void)nz;
     // q_1 = v / |v|
     double acc = 0.0;
     for (int rl = t; rl < ns; rl += kSmallThreads) {
@@ -105,53 +132,31 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
         __syncthreads();
         double rm = 0.0, bprev = 0.0;
         for (int i = 1; i <= k; ++i) {
-            // w = C q_i - beta_i q_{i-1} (a column index outside the segment,
-            // which a block-diagonal A does not have, contributes 0)
+            // w = C q_i - beta_i q_{i-1}
             const double *Qi1 = i >= 2 ? Q + (size_t)(i - 2) * ns : Q;
             for (int rl = t; rl < ns; rl += kSmallThreads) {
-                const int64_t r = r0 + rl;
                 double sum = 0.0;
-                for (int p = rp[r]; p < rp[r + 1]; ++p) {
-                    const int cj = ci[p];
-                    const int lj = (int)(cj - r0);
-                    const bool in = (unsigned)lj < (unsigned)ns;
-                    const double x = qs[in ? lj : 0];
-                    sum += in ? static_cast<double>(val[p]) * (JAC ? d[cj] : 1.0) * x : 0.0;
-                }
-                const double dr = JAC ? d[r] : 1.0;
-                double y = dr * (sum - tau * dr * qs[rl]);
+                for (int e = lr[rl]; e < lr[rl + 1]; ++e) sum += lv[e] * qs[lc[e]];
+                double y = sum - dt[rl] * qs[rl];
                 if (i >= 2) y -= bprev * Qi1[rl];
                 ws[rl] = y;
             }
             __syncthreads();
-            // g_l and p_l: wavefront wv takes l = wv + 4u, all rows, in one pass
-            // (a lane keeps the sums of all its l, so their loads overlap)
-            {
-                constexpr int U = kFusedMaxK / kSmallWaves;
-                const int nu_ = (i - wv + kSmallWaves - 1) / kSmallWaves;   // l's of this wavefront
-                double g[U], pq[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) g[u] = pq[u] = 0.0;
+            // g_l and p_l: wavefront wv takes l = wv, wv + 4, ..., all rows
+            for (int l = wv; l < i; l += kSmallWaves) {
+                const double *Ql = Q + (size_t)l * ns;
+                double g = 0.0, pq = 0.0;
+#pragma unroll 4
                 for (int rl = lane; rl < ns; rl += 64) {
-                    const double wr = ws[rl], qr = qs[rl];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (u < nu_) {
-                            const double q = Q[(size_t)(wv + kSmallWaves * u) * ns + rl];
-                            g[u] += q * wr;
-                            pq[u] += q * qr;
-                        }
-                    }
+                    const double q = Ql[rl];
+                    g += q * ws[rl];
+                    pq += q * qs[rl];
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (u < nu_) {
-                        const double gs = wave_sum(g[u]), ps = wave_sum(pq[u]);
-                        if (lane == 0) {
-                            gp[0][wv + kSmallWaves * u] = gs;
-                            gp[1][wv + kSmallWaves * u] = ps;
-                        }
-                    }
+                g = wave_sum(g);
+                pq = wave_sum(pq);
+                if (lane == 0) {
+                    gp[0][l] = g;
+                    gp[1][l] = pq;
                 }
             }
             __syncthreads();
@@ -195,26 +200,37 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
     if (t == 0) kused[(size_t)seg * ku_ld + ku_off + c] = ku;
 }
 
-bool fused_applies(const Plan &p)
+static size_t fused_lds_bytes(int64_t nmax, int64_t nzmax)
 {
+    return sizeof(double) * 3 * nmax + (sizeof(double) + sizeof(int32_t)) * nzmax +
+           sizeof(int32_t) * (nmax + 1);
+}
+
+bool fused_applies(const Plan &p, int64_t nnz)
+{
+    // nnz bounds every segment's nonzeros
     return p.req_fused == 0 && !p.vec_f32 && !p.grad && !p.arnoldi && !p.block &&
            (p.prec_kind == ECNT_PREC_NONE || p.prec_kind == ECNT_PREC_JACOBI) &&
-           p.max_rows <= kFusedMaxRows && p.k <= kFusedMaxK;
+           p.max_rows <= kFusedMaxRows && p.k <= kFusedMaxK &&
+           fused_lds_bytes(p.max_rows, nnz) <= kFusedLdsBytes;
 }
 
 void launch_lanczos_fused(const Plan &p, const int32_t *row_ptr, const int32_t *col_idx, const void *val,
-                          const void *probes, hipStream_t st)
+                          int64_t nnz, const void *probes, hipStream_t st)
 {
     const int NC = p.nseg * p.C;
     const int nmax = (int)p.max_rows;
-    const size_t lds = sizeof(double) * 2 * (size_t)nmax;
+    const size_t lds = fused_lds_bytes(nmax, nnz);
     const double eps = DBL_EPSILON;
     const bool jac = p.prec_kind == ECNT_PREC_JACOBI;
     auto go = [&](auto vt, auto jc) {
         using VT = decltype(vt);
         constexpr bool J = decltype(jc)::value;
+        // more than the default 64 KiB of dynamic LDS (not a stream operation)
+        (void)hipFuncSetAttribute((const void *)k_lanczos_fused<VT, J>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes);
         k_lanczos_fused<VT, J><<<NC, kSmallThreads, lds, st>>>(
-            p.C, p.nseg, p.m, p.c_off, p.k, p.S, p.n, nmax, p.seg_row, p.seg_taus, row_ptr, col_idx,
+            p.C, p.nseg, p.m, p.c_off, p.k, p.S, p.n, nmax, nnz, p.seg_row, p.seg_taus, row_ptr, col_idx,
             (const VT *)val, p.jac, (const double *)probes, (double *)p.basis, p.alpha, p.beta, p.nu,
             p.kused, p.Ct, p.c_off, eps);
     };
