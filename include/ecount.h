@@ -184,13 +184,16 @@ typedef struct {
                            neighbours and the diagonal, all off-diagonal values equal),
                            else row by row from the CSR arrays; 1: always from the CSR
                            arrays.  Both sum each row in the same order. */
-    int32_t fused;      /* 0: a problem whose segments have at most 3072 rows, FP64 vectors,
-                           k <= 64, M = I or Jacobi and no derivative runs all k steps
-                           of every column in one launch (one workgroup per column, its
-                           basis column-contiguous in the workspace); otherwise, and
-                           with 1, the column-wave kernels (about five launches per
-                           step).  Both compute the same recurrence; sums are in a
-                           different order. */
+    int32_t fused;      /* 0: a problem whose segments have at most 3072 rows, with FP64
+                           vectors, k <= 64, M = I or Jacobi, no derivative, and whose
+                           operator fits in a workgroup's LDS (12 bytes per nonzero of A,
+                           counted over all segments, plus 28 per row of the largest
+                           segment, at most 150 KiB), runs all k steps of every column
+                           in one launch (one workgroup per column, its basis
+                           column-contiguous in the workspace); otherwise, and with 1,
+                           the column-wave kernels (about five launches per step).  Both
+                           compute the same recurrence; sums are in a different
+                           order. */
 } ecnt_opts;
 
 /* Optional outputs.  Device arrays may be NULL. */
