@@ -11,9 +11,9 @@ JSON file (path: $ECNT_TUNE_CACHE, else ~/.cache/ecount/tune.json).
 
 Search: coordinate descent from the built-in defaults, one parameter at a
 time, keeping a change only if it is at least 2% faster; each trial is the
-median of a few event-timed runs with k_tune Lanczos steps (the per-step mix
-of kernels is the same as in the full run, the reorthogonalization share
-slightly smaller).
+median of a few event-timed runs with k_tune Lanczos steps (32 by default, so
+the full run for k <= 32: the reorthogonalization sweeps and the partial sums
+they reduce grow with the step, and a short trial undervalues them).
 """
 from __future__ import annotations
 
@@ -110,7 +110,7 @@ def _timed(fn, reps: int) -> float:
 
 
 def tune_batch(A, prec, sizes, taus, probes, k: int, dims=None, vec: str = "f64",
-               mem_bytes: int | None = None, k_tune: int = 8, reps: int = 3,
+               mem_bytes: int | None = None, k_tune: int = 32, reps: int = 3,
                cache: str | None = None, retune: bool = False, log=None) -> dict:
     """Best launch shape for a batch (ecount.Batch arguments).  Returns
     {"max_cols", "tile", "red_waves", "csr_vw", "key", "ms", "source"}.
@@ -185,7 +185,7 @@ def _search(key, Ct, k, kt, vec, need_bytes, make_run, mem_bytes, device, cache,
 
 
 def tune_count(A, prec, xi: float, eta: float, probes, k: int, vec: str = "f64",
-               mem_bytes: int | None = None, k_tune: int = 8, reps: int = 3,
+               mem_bytes: int | None = None, k_tune: int = 32, reps: int = 3,
                cache: str | None = None, retune: bool = False, log=None) -> dict:
     """Best launch shape for an interval count (ecount.count arguments), as
     tune_batch for a single problem."""
