@@ -112,6 +112,29 @@ __device__ __forceinline__ void vload_nt(const T *__restrict__ p, size_t e, doub
     }
 }
 
+// vload_nt without the conversion: the values stay in the storage type (half
+// the registers for FP32) until they are used
+template <typename T, int VW>
+__device__ __forceinline__ void vload_nt_raw(const T *__restrict__ p, size_t e, T (&o)[VW])
+{
+    if constexpr (sizeof(T) * VW == 8 && VW == 1) {
+        o[0] = __builtin_nontemporal_load(reinterpret_cast<const double *>(p + e));
+    } else if constexpr (sizeof(T) * VW == 8 && VW == 2) {
+        // two floats in one 8-byte load, split by bit casts (no memory copy)
+        const unsigned long long bits =
+            __builtin_nontemporal_load(reinterpret_cast<const unsigned long long *>(p + e));
+        o[0] = __uint_as_float((unsigned)(bits & 0xffffffffull));
+        o[1] = __uint_as_float((unsigned)(bits >> 32));
+    } else if constexpr (sizeof(T) * VW == 4) {
+        o[0] = __builtin_nontemporal_load(reinterpret_cast<const float *>(p + e));
+    } else {
+        double t[VW];
+        vload<T, VW>(p, e, t);
+#pragma unroll
+        for (int v = 0; v < VW; ++v) o[v] = static_cast<T>(t[v]);
+    }
+}
+
 template <typename T, int VW>
 __device__ __forceinline__ void vstore(T *__restrict__ p, size_t e, const double (&o)[VW])
 {

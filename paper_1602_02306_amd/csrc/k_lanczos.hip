@@ -243,17 +243,18 @@ __device__ __forceinline__ void update_rows(int C, int c0, int64_t r0, int64_t r
 {
     for (int64_t r = r0; r < r1; ++r) {
         const size_t e = (size_t)r * C + c0;
-        double w[VW], qm[VW], q[NB][VW];
+        double w[VW], qm[VW];
+        T q[NB][VW];   // in the storage type until used (half the registers for FP32)
         vload<T, VW>(W, e, w);
         if (HASM) vload<T, VW>(Qm, e, qm);
 #pragma unroll
-        for (int l = 0; l < NB; ++l) vload_nt<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
+        for (int l = 0; l < NB; ++l) vload_nt_raw<T, VW>(Q0 + (size_t)l * ss, e, q[l]);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int v = 0; v < VW; ++v) {
             double x = HASM ? w[v] - kap[v] * qm[v] : w[v];
 #pragma unroll
-            for (int l = 0; l < NB; ++l) x -= co[l][v] * q[l][v];
+            for (int l = 0; l < NB; ++l) x -= co[l][v] * static_cast<double>(q[l][v]);
             w[v] = x;
             const double xr = rounded<T>(x);
             nrm[v] += xr * xr;
