@@ -561,7 +561,8 @@ FAMILY_OF = [("k_blk_update<true>", "blk_normalize"), ("k_blk_update", "blk_upda
              ("k_dots", "lz_dots"), ("k_update", "lz_update"), ("k_setup_fin", "lz_finalize"),
              ("k_setup", "lz_setup"), ("k_norm_fin", "lz_finalize"), ("k_jacobi_diag", "lz_setup"),
              ("k_tridiag", "quadrature"), ("k_reduce", "quadrature"), ("k_init", "lz_finalize"),
-             ("k_probe", "hbm_probe"), ("copyBuffer", "copy"), ("FillFunc", "fill")]
+             ("k_probe", "hbm_probe"), ("k_lanczos_fused", "lz_fused"), ("copyBuffer", "copy"),
+             ("FillFunc", "fill")]
 
 
 def family(kernel_name: str) -> str:
