@@ -82,18 +82,21 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
     if wl.method == "block":
         batch = 16
     worst, worst_rel = 0.0, 0.0
+
+    def run(lo, s):
+        if wl.method == "arnoldi":
+            return oracle.count_arnoldi(P.A, P.prec, wl.xi, wl.eta, V[:, lo:lo + s], wl.k,
+                                        nthreads=threads)
+        if wl.method == "block":
+            return oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V[:, lo:lo + s], wl.k,
+                                      nthreads=threads)
+        return oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, lo:lo + s], wl.k,
+                            nthreads=threads, smooth_w=wl.smooth_w)
+
     while done < m:
         s = min(batch, m - done)
         t0 = time.perf_counter()
-        if wl.method == "arnoldi":
-            ref = oracle.count_arnoldi(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
-                                       nthreads=threads)
-        elif wl.method == "block":
-            ref = oracle.block_count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
-                                     nthreads=threads)
-        else:
-            ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, done:done + s], wl.k,
-                               nthreads=threads, smooth_w=wl.smooth_w)
+        ref = run(done, s)
         dt = time.perf_counter() - t0
         if gpu_per_probe is not None:
             gx, ge = gpu_per_probe[done:done + s], gpu_per_probe[m + done:m + done + s]
@@ -110,10 +113,19 @@ def cpu_baseline(P, V, wl, target_s: float, gpu_per_probe=None):
         batch = max(1, min(m - done, int((target_s - t_tot) / per) + 1, 4 * threads))
         if wl.method == "block":   # whole blocks of 16 probes
             batch = min(m - done, max(16, (batch + 15) // 16 * 16))
-    steps = 2 * done * wl.k
+    # a whole workload that runs in far less than a second is timed over
+    # repeated passes (about 2 s), so that thread start-up does not dominate
+    passes = 1
+    if done == m and t_tot < 2.0:
+        t0 = time.perf_counter()
+        while t_tot + (time.perf_counter() - t0) < 2.0:
+            run(0, m)
+            passes += 1
+        t_tot += time.perf_counter() - t0
+    steps = 2 * done * wl.k * passes
     out = {"value": steps / t_tot, "unit": "probe-steps/s", "cores": threads, "kind": "oracle",
-           "sample": "%d of %d probes x 2 shifts x k=%d (%d probe-steps, %.1f s)"
-                     % (done, m, wl.k, steps, t_tot)}
+           "sample": "%d of %d probes x 2 shifts x k=%d, %d pass%s (%d probe-steps, %.1f s)"
+                     % (done, m, wl.k, passes, "" if passes == 1 else "es", steps, t_tot)}
     if gpu_per_probe is not None:
         out["gpu_vs_oracle_max_abs_per_probe_over_n"] = worst / wl.n
         out["gpu_vs_oracle_max_rel_per_probe"] = worst_rel
@@ -286,12 +298,22 @@ def bench_negcount_ldl(args, wl, ceilings=None):
             t_tot += time.perf_counter() - t0
             worst = max(worst, float(np.max(np.abs(gpu_pp[done:done + s_] - s_ref))))
             done += s_
-        steps_ = done * wl.k
+        # a whole workload that runs in far less than a second is timed over
+        # repeated passes (about 2 s), so that thread start-up does not dominate
+        passes = 1
+        if done == wl.m and t_tot < 2.0:
+            t0 = time.perf_counter()
+            while t_tot + (time.perf_counter() - t0) < 2.0:
+                oracle.quadrature(oracle.lanczos_ldl(P.A, F, taus[0], V, wl.k, nthreads=threads))
+                passes += 1
+            t_tot += time.perf_counter() - t0
+        steps_ = done * wl.k * passes
         out["cpu_baseline"] = {"value": steps_ / t_tot, "unit": "probe-steps/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": "%d of %d probes x 1 shift x k=%d (%d probe-steps, %.1f s; "
-                                         "the oracle's own ILDL factorization, %.1f s, not counted)"
-                                         % (done, wl.m, wl.k, steps_, t_tot, t_ofac),
+                               "sample": "%d of %d probes x 1 shift x k=%d, %d pass%s (%d probe-steps, "
+                                         "%.1f s; the oracle's own ILDL factorization, %.1f s, not "
+                                         "counted)" % (done, wl.m, wl.k, passes, "" if passes == 1 else "es",
+                                                       steps_, t_tot, t_ofac),
                                "gpu_vs_oracle_max_abs_per_probe_over_n": worst / wl.n}
     print(json.dumps(out), flush=True)
 
