@@ -733,3 +733,24 @@ def test_fused_small_form_against_oracle_and_waves(ec, prec, k, rule):
     bound = TOL * (np.maximum(1.0, np.abs(sb)) if scale == "rel" else
                    np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu]))
     assert np.all(np.abs(sa - sb) <= bound)
+
+
+@pytest.mark.parametrize("side,fused", [(40, True), (44, False)])
+def test_fused_form_lds_limit(ec, side, fused):
+    """The one-launch form holds a column's operator, q and w in LDS (at most
+    150 KiB: 28 bytes per row and 12 per nonzero): a 40 x 40 five-point
+    operator (1600 rows, 136 KiB) runs in it, 44 x 44 (1936 rows, 164 KiB) in
+    the column waves.  Both against the oracle, Jacobi, k = 24."""
+    rng = np.random.default_rng(side)
+    A = W.laplacian_csr((side, side), rng.uniform(0.0, 1.0, side * side))
+    prec = W.PrecSpec("jacobi", ())
+    V = W.rademacher(A.n, 8, 77)
+    print("case fused limit", side, flush=True)
+    ec.profile_enable(True)
+    r = gpu_count(ec, A, prec, 0.5, 1.5, V, 24)
+    prof = ec.profile_read()
+    ec.profile_enable(False)
+    assert (prof["lz_fused"]["launches"] == 1) == fused
+    assert (prof["lz_dots"]["launches"] > 0) == (not fused)
+    ref = oracle.count(A, prec, 0.5, 1.5, V, 24)
+    assert_parity(r, ref, 24)
