@@ -539,6 +539,12 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
 {
     using namespace quadwg;
     using V = typename VecT<T, VW>::type;
+    // arithmetic in the storage type: FP32 storage already bounds the FP32
+    // form's accuracy, and FP64 temporaries for two columns per lane would
+    // not fit the 128 registers that sixteen wavefronts per CU leave
+    using R = T;
+    const R rc1 = (R)c1, rbd1 = (R)bd1, rbo1 = (R)bo1, rc2 = (R)c2, rbd2 = (R)bd2, rbo2 = (R)bo2,
+            rcz = (R)cz;
     constexpr int NT = 6;   // lines of a wavefront: 4 of its quadrant, 2 of the ring
     __shared__ V su[UW * UW * 64];
     __shared__ V stp[TW * TW * 64];
@@ -582,12 +588,12 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         }
         return v;
     };
-    auto fromV = [](const V &v, int e) -> double {
+    auto fromV = [](const V &v, int e) -> R {
         if constexpr (VW == 1) {
             (void)e;
-            return (double)v;
+            return (R)v;
         } else {
-            return (double)(e == 0 ? v.x : v.y);
+            return (R)(e == 0 ? v.x : v.y);
         }
     };
     const T zero = T(0);
@@ -624,9 +630,9 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         w2[s] = has2[s] && inside(i, j) ? 1.0 : 0.0;
         slot2[s] = (i + 2) * UW + (j + 2);
     }
-    double xsc[VW];
+    R xsc[VW];
 #pragma unroll
-    for (int v = 0; v < VW; ++v) xsc[v] = xs ? xs[c0 + v] : 1.0;
+    for (int v = 0; v < VW; ++v) xsc[v] = xs ? (R)xs[c0 + v] : R(1);
     // u of the own lines at z-1, z, z+1 (um, u0, un); ring-2 u at z (r2)
     T um[NT][VW], u0[NT][VW], un[NT][VW], r2[3][VW], tm2[4][VW], tm1[4][VW];
     const int64_t e1 = d2 > 1 ? zs : 0;
@@ -687,7 +693,7 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
         }
         __syncthreads();
         // t at z on this wavefront's lines
-        const double zn = has_n ? 1.0 : 0.0;
+        const R zn = has_n ? R(1) : R(0);
         T tn[NT][VW];
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
@@ -709,20 +715,20 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
             if (!in_xp) vxp = su[((i + 3) * UW + (j + 2)) * 64 + lane];
 #pragma unroll
             for (int v = 0; v < VW; ++v) {
-                const double cu = u0[q][v];
-                const double uym = in_ym ? (double)u0[q - 1][v] : fromV(vym, v);
-                const double uyp = in_yp ? (double)u0[q + 1][v] : fromV(vyp, v);
-                const double uxm = in_xm ? (double)u0[q - 2][v] : fromV(vxm, v);
-                const double uxp = in_xp ? (double)u0[q + 2][v] : fromV(vxp, v);
-                const double nb = (double)um[q][v] + zn * (double)un[q][v] + uym + uyp + uxm + uxp;
-                double t = c1 * xsc[v] * cu;
-                t += xsc[v] * (bd1 * cu - bo1 * nb);
+                const R cu = u0[q][v];
+                const R uym = in_ym ? (R)u0[q - 1][v] : fromV(vym, v);
+                const R uyp = in_yp ? (R)u0[q + 1][v] : fromV(vyp, v);
+                const R uxm = in_xm ? (R)u0[q - 2][v] : fromV(vxm, v);
+                const R uxp = in_xp ? (R)u0[q + 2][v] : fromV(vxp, v);
+                const R nb = (R)um[q][v] + zn * (R)un[q][v] + uym + uyp + uxm + uxp;
+                R t = rc1 * xsc[v] * cu;
+                t += xsc[v] * (rbd1 * cu - rbo1 * nb);
                 tn[q][v] = w[q] != 0.0 ? static_cast<T>(t) : zero;
             }
         }
         // out at z-1 on the quadrant (t at z-1 of the neighbours outside it from LDS)
         if (z >= 1) {
-            const double znt = has_t ? 1.0 : 0.0;
+            const R znt = has_t ? R(1) : R(0);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = LI[q], j = LJ[q];
@@ -735,16 +741,15 @@ __global__ __launch_bounds__(1024) void k_quad_sweep_wg(int C, int ncg, int nseg
                 double o[VW];
 #pragma unroll
                 for (int v = 0; v < VW; ++v) {
-                    const double tyn = in_ym ? (double)tm1[q - 1][v] : fromV(tym, v);
-                    const double typn = in_ym ? fromV(typ, v) : (double)tm1[q + 1][v];
-                    const double txn = in_xm ? (double)tm1[q - 2][v] : fromV(txm, v);
-                    const double txpn = in_xm ? fromV(txp, v) : (double)tm1[q + 2][v];
-                    const double nb = (double)tm2[q][v] + znt * (double)tn[q][v] + tyn + typn + txn +
-                                      txpn;
-                    double val = c2 * xsc[v] * (double)um[q][v];
-                    val += 1.0 * (bd2 * (double)tm1[q][v] - bo2 * nb);
-                    if (HASZ) val -= cz * (double)zv[q][v];
-                    o[v] = val;
+                    const R tyn = in_ym ? (R)tm1[q - 1][v] : fromV(tym, v);
+                    const R typn = in_ym ? fromV(typ, v) : (R)tm1[q + 1][v];
+                    const R txn = in_xm ? (R)tm1[q - 2][v] : fromV(txm, v);
+                    const R txpn = in_xm ? fromV(txp, v) : (R)tm1[q + 2][v];
+                    const R nb = (R)tm2[q][v] + znt * (R)tn[q][v] + tyn + typn + txn + txpn;
+                    R val = rc2 * xsc[v] * (R)um[q][v];
+                    val += R(1) * (rbd2 * (R)tm1[q][v] - rbo2 * nb);
+                    if (HASZ) val -= rcz * (R)zv[q][v];
+                    o[v] = (double)val;
                 }
                 if (w[q] != 0.0 && colok) vstore_nt<T, VW>(out, base + ep + off[q], o);
             }
@@ -1232,7 +1237,11 @@ void launch_quad_sweep(const Plan &p, const void *X, const double *xs, double c1
     const double bo = 2.0 / w;
     const double bd1 = cb * bd, bo1 = cb * 2.0 / w;
     if (p.tx == 8) {   // workgroup-cooperative form on 8 x 8 line blocks, one column per lane
-        if (p.vec_f32) {
+        // (two in FP32 when the width is even: the planes then take what FP64's do)
+        if (p.vec_f32 && p.C % 2 == 0) {
+            if (Z) quad_sweep_wg_t<float, 2, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+            else quad_sweep_wg_t<float, 2, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
+        } else if (p.vec_f32) {
             if (Z) quad_sweep_wg_t<float, 1, true>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
             else quad_sweep_wg_t<float, 1, false>(p, X, xs, c1, bd1, bo1, c2, bd, bo, Z, cz, out, st);
         } else {

@@ -26,7 +26,7 @@
 namespace ecnt {
 
 namespace {
-constexpr int kSmallThreads = 256;
+constexpr int kSmallThreads = 512;
 constexpr int kSmallWaves = kSmallThreads / 64;
 }
 
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
                 ws[rl] = y;
             }
             __syncthreads();
-            // g_l and p_l: wavefront wv takes l = wv, wv + 4, ..., all rows
+            // g_l and p_l: wavefront wv takes l = wv, wv + kSmallWaves, ..., all rows
             for (int l = wv; l < i; l += kSmallWaves) {
                 const double *Ql = Q + (size_t)l * ns;
                 double g = 0.0, pq = 0.0;

@@ -408,6 +408,29 @@ def test_fp32_form_within_stated_bound(ec, name):
     assert e_probe <= FP32_BOUND
 
 
+@pytest.mark.parametrize("name,max_cols", [("c2_small", 0), ("c2_ragged", 0), ("c2_ragged", 37)])
+def test_fp32_workgroup_sweep_within_stated_bound(ec, name, max_cols):
+    """The FP32 form with the preconditioner's quadratic factors in the
+    workgroup sweep on 8 x 8 line blocks: an even wave width (two columns per
+    lane) and an odd one (waves of 37 columns, one per lane), each within the
+    FP32 bound of the FP64 oracle."""
+    wl = W.WORKLOADS[name]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    kw = {"max_cols": max_cols} if max_cols else {}
+    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec="f32", val="f32",
+                  tune={"tile": "8x8-wg"}, **kw)
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    s = r.per_probe.cpu().numpy()
+    s_ref = np.concatenate([ref.s_xi, ref.s_eta])
+    nu = np.concatenate([ref.lan_xi.nu, ref.lan_eta.nu])
+    e_est = rel(r.estimate, ref.estimate)
+    e_probe = float(np.max(np.abs(s - s_ref) / nu))
+    print("fp32 wg %s/%d: rel %.2e  max|ds|/nu %.2e" % (name, max_cols, e_est, e_probe), flush=True)
+    assert e_est <= FP32_BOUND
+    assert e_probe <= FP32_BOUND
+
+
 @pytest.mark.parametrize("prec_kind", ["none", "jacobi"])
 @pytest.mark.parametrize("n", [1, 2, 3])
 def test_tiny_problems(ec, n, prec_kind):
