@@ -296,6 +296,29 @@ def test_bench_configuration_sampled(ec):
     print("c2 estimate %.4f +- %.4f exact %s" % (r.estimate, math.sqrt(r.variance), exact), flush=True)
 
 
+def test_bench_configuration_sampled_fp32(ec):
+    """The benchmark workload at full size in the FP32 storage form (the
+    launch configuration of its bench line): sampled probes against the FP64
+    oracle and the estimate against the FP64 path, within the FP32 bound."""
+    wl = W.WORKLOADS["c2"]
+    P = W.make_problem(wl)
+    V = W.make_probes(wl)
+    print("case c2 full fp32", flush=True)
+    r = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k, vec="f32", val="f32")
+    s = r.per_probe.cpu().numpy().reshape(2, -1)
+    sample = [3, 128]
+    ref = oracle.count(P.A, P.prec, wl.xi, wl.eta, V[:, sample], wl.k)
+    nu = float(P.A.n)   # |v_j|^2 of a Rademacher probe
+    for t, (sx, se) in enumerate(zip(ref.s_xi, ref.s_eta)):
+        j = sample[t]
+        print("probe %d: fp32 %.6f %.6f oracle %.6f %.6f" % (j, s[0, j], s[1, j], sx, se), flush=True)
+        assert abs(s[0, j] - sx) <= FP32_BOUND * nu
+        assert abs(s[1, j] - se) <= FP32_BOUND * nu
+    r64 = gpu_count(ec, P.A, P.prec, wl.xi, wl.eta, V, wl.k)
+    print("estimate fp32 %.8f fp64 %.8f" % (r.estimate, r64.estimate), flush=True)
+    assert rel(r.estimate, r64.estimate) <= FP32_BOUND
+
+
 @pytest.mark.parametrize("name", ["c2_small", "c2_ragged"])
 def test_parity_clenshaw_evaluation(ec, name):
     """M evaluated by Clenshaw's recurrence instead of the product of its
