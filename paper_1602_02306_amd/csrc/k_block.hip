@@ -412,40 +412,6 @@ __device__ __forceinline__ int zidx(int r, int c)
     return (2 + r) * kQN + c - r;
 }
 
-// sum over the 16 lanes of a row of the wavefront (every lane gets the same
-// value: each butterfly stage adds two equal partial sums in either order)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x)
-{
-    // every lane has a source under a row rotation: bound_ctrl set, no old value
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double row_sum16(double x)
-{
-    x += dpp_f64<0x128>(x);   // row_ror:8
-    x += dpp_f64<0x124>(x);   // row_ror:4
-    x += dpp_f64<0x122>(x);   // row_ror:2
-    x += dpp_f64<0x121>(x);   // row_ror:1
-    return x;
-}
-// sum over the 4 rows of the wavefront (lanes l, l^16, l^32, l^48), by the
-// row swaps of v_permlane16_swap / v_permlane32_swap (both halves of a pair
-// get the same operands in the same order, so all four lanes agree)
-__device__ __forceinline__ double group_sum4(double x)
-{
-    int lo = __double2loint(x), hi = __double2hiint(x);
-    auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    x = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
-    lo = __double2loint(x);
-    hi = __double2hiint(x);
-    a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
-}
-
 // Quadrature of one block.  T_k (order N = 16 k_used, half-bandwidth 16) is
 // brought to tridiagonal form by Householder bulge chasing: sweep j takes
 // column j with one reflector on rows j+1..j+16, and the fill that the

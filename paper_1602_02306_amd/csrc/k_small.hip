@@ -16,7 +16,7 @@
 // (the segment's rows of A with both scalings folded into the values, column
 // indices local, and tau d_r^2 per row), so every product reads LDS only.
 // Sums are in a fixed order (a wavefront sums all rows of one basis vector,
-// lanes then the butterfly), so results are reproducible.
+// lanes then DPP row rotations and row swaps), so results are reproducible.
 #include <float.h>
 
 #include "device_common.h"
@@ -28,21 +28,14 @@ namespace ecnt {
 namespace {
 constexpr int kSmallThreads = 512;
 constexpr int kSmallWaves = kSmallThreads / 64;
-}
-
-// sum over the wavefront; every lane gets the same value (each butterfly
-// stage adds two equal partial sums in either order)
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+constexpr int kLPer = (kFusedMaxK + kSmallWaves - 1) / kSmallWaves;   // basis vectors per wavefront
+static_assert(kLPer % 2 == 0, "the dots reduce two basis vectors at a time");
 }
 
 // sum over the workgroup, wavefronts in order; every thread gets the value
 __device__ __forceinline__ double group_sum(double x, double *red)
 {
-    x = wave_sum(x);
+    x = wave_sum_dpp(x);
     const int wv = threadIdx.x >> 6;
     __syncthreads();   // red is free (its last readers are past this point)
     if ((threadIdx.x & 63) == 0) red[wv] = x;
@@ -142,21 +135,39 @@ __global__ __launch_bounds__(kSmallThreads) void k_lanczos_fused(
                 ws[rl] = y;
             }
             __syncthreads();
-            // g_l and p_l: wavefront wv takes l = wv, wv + kSmallWaves, ..., all rows
-            for (int l = wv; l < i; l += kSmallWaves) {
-                const double *Ql = Q + (size_t)l * ns;
-                double g = 0.0, pq = 0.0;
+            // g_l and p_l: wavefront wv takes l = wv + j kSmallWaves, each over
+            // all rows, and reduces its partial sums two vectors at a time
+            // (four independent chains)
+            double g[kLPer], pq[kLPer];
+#pragma unroll
+            for (int j = 0; j < kLPer; ++j) {
+                g[j] = 0.0;
+                pq[j] = 0.0;
+                const int l = wv + j * kSmallWaves;
+                if (l < i) {
+                    const double *Ql = Q + (size_t)l * ns;
 #pragma unroll 4
-                for (int rl = lane; rl < ns; rl += 64) {
-                    const double q = Ql[rl];
-                    g += q * ws[rl];
-                    pq += q * qs[rl];
+                    for (int rl = lane; rl < ns; rl += 64) {
+                        const double q = Ql[rl];
+                        g[j] += q * ws[rl];
+                        pq[j] += q * qs[rl];
+                    }
                 }
-                g = wave_sum(g);
-                pq = wave_sum(pq);
-                if (lane == 0) {
-                    gp[0][l] = g;
-                    gp[1][l] = pq;
+            }
+#pragma unroll
+            for (int j = 0; j < kLPer; j += 2) {
+                const int l = wv + j * kSmallWaves;
+                if (l < i) {
+                    const double g0 = wave_sum_dpp(g[j]), p0 = wave_sum_dpp(pq[j]);
+                    const double g1 = wave_sum_dpp(g[j + 1]), p1 = wave_sum_dpp(pq[j + 1]);
+                    if (lane == 0) {
+                        gp[0][l] = g0;
+                        gp[1][l] = p0;
+                        if (l + kSmallWaves < i) {
+                            gp[0][l + kSmallWaves] = g1;
+                            gp[1][l + kSmallWaves] = p1;
+                        }
+                    }
                 }
             }
             __syncthreads();
