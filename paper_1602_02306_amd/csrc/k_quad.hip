@@ -247,8 +247,7 @@ __global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__re
 // runs the rotation chain on the same values, the search for the unreduced
 // block takes 64 candidates at a time (a ballot), and each sweep carries its
 // changing values in registers with the values ahead loaded three rotations
-// early, as the lane form does.  Lane 0 makes the writes (the other lanes
-// write to a slot of their own).
+// early, as the lane form does.  Lane 0 makes the writes.
 template <int KMAX>
 __global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int off, int k, int rule,
                                                      double smooth_w,
@@ -261,14 +260,12 @@ __global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int 
                                                      int32_t *__restrict__ flags)
 {
     __shared__ double A_[KMAX + 1], B_[KMAX + 1], Z_[KMAX + 1];
-    __shared__ double dump[64];
     const int lane = threadIdx.x;
     const int vc = blockIdx.x;
     const int seg = vc / C;
     const size_t gidx = (size_t)seg * ld + off + (vc - seg * C);
     const int c = vc;
     C = NC;   // alpha, beta, nu below are indexed [row][NC] by the virtual column
-    double *const mydump = dump + lane;
     const int ku = kused_all[gidx];
     if (ku < 1) {
         if (lane == 0) {
@@ -336,17 +333,23 @@ __global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int 
         double ak = A_[lo], bk = B_[lo], zk = Z_[lo], nbk = bk;
         auto rot = [&](int q, double ak1, double bk1, double z1) __attribute__((always_inline)) {
             // |x|, |y| far from the under/overflow range: J_k holds O(|C|) entries
+            // (q2 = 0 only when x = y = 0: then r = sn = 0 as they stand)
             const double q2 = x * x + y * y;
             const bool nz = q2 > 0.0;
             const double ir = rsqrt(nz ? q2 : 1.0);
-            const double r = nz ? q2 * ir : 0.0;
+            const double r = q2 * ir;
             const double cs = nz ? x * ir : 1.0;
-            const double sn = nz ? y * ir : 0.0;
-            *(lane == 0 && q > lo ? &B_[q - 1] : mydump) = r;
-            *(lane == 0 ? &A_[q] : mydump) = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            const double sn = y * ir;
+            const double na = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
+            const double nz1 = cs * zk + sn * z1;
+            // every lane holds the same values and writes them to the same
+            // slots; the first rotation of a sweep has no B to write (slot
+            // KMAX is never read)
+            B_[q > lo ? q - 1 : KMAX] = r;
+            A_[q] = na;
+            Z_[q] = nz1;
             const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
             nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-            *(lane == 0 ? &Z_[q] : mydump) = cs * zk + sn * z1;
             zk = -sn * zk + cs * z1;
             ak = na1;
             bk = cs * bk1;
