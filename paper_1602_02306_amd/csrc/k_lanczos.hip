@@ -433,9 +433,10 @@ static void update_nb(const Plan &p, int step, int l0, int nb, bool first, bool 
     }
 }
 
-// Columns per lane of the reduction kernels: FP32 pairs (8-byte loads) when the
-// wave width is even; FP64 one column per lane (the NB accumulators per column
-// already fill the register budget).  Must match the geometry of the plan.
+// Columns per lane of the FP32 dots: pairs (8-byte loads) when the wave width
+// is even; FP64 takes one column per lane (the NB accumulators per column
+// already fill the register budget).  Each launch derives its column tiles
+// from its own width; the partial sums are indexed by column.
 static inline int red_vw(const Plan &p) { return (p.vec_f32 && p.C % 2 == 0) ? 2 : 1; }
 
 void launch_dots(const Plan &p, int step, int l0, int nb, bool gram, hipStream_t st)
@@ -460,8 +461,10 @@ void launch_dots_fin(const Plan &p, int step, int l0, int nb, bool gram, hipStre
 void launch_update(const Plan &p, int step, int l0, int nb, bool first, bool last, hipStream_t st)
 {
     if (p.vec_f32) {
-        if (red_vw(p) == 2) update_nb<float, 2>(p, step, l0, nb, first, last, st);
-        else update_nb<float, 1>(p, step, l0, nb, first, last, st);
+        // one column per lane: column pairs would hold 2 x nb FP64 coefficients
+        // per lane, and the fewer wavefronts resident cost more than the
+        // 4-byte loads (measured at every basis size)
+        update_nb<float, 1>(p, step, l0, nb, first, last, st);
     } else {
         update_nb<double, 1>(p, step, l0, nb, first, last, st);
     }
