@@ -645,7 +645,6 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
     double *B_ = Lb + kQN;
     const int zrow = lane & 15;
     double *Zr = Lb + zidx(zrow, 0);   // row zrow of Z (lanes 16.. repeat rows 0..15)
-    const bool zlane = lane < kBlk;
     int hi = N - 1, iter = 0;
     bool failed = false;
     while (hi > 0) {
@@ -697,18 +696,23 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
         double zk = Zr[lo];
         double nbk = bk;
         auto rot = [&](int q, double ak1, double bk1, double z1) __attribute__((always_inline)) {
+            // (q2 = 0 only when x = y = 0: then r = sn = 0 as they stand)
             const double q2 = x * x + y * y;
             const bool nz = q2 > 0.0;
             const double ir = rsqrt(nz ? q2 : 1.0);
-            const double r = nz ? q2 * ir : 0.0;
+            const double r = q2 * ir;
             const double cs = nz ? x * ir : 1.0;
-            const double sn = nz ? y * ir : 0.0;
+            const double sn = y * ir;
             const double na = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
             const double na1 = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
             nbk = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-            *(lane == 0 && q > lo ? &B_[q - 1] : mydump) = r;
-            *(lane == 0 ? &A_[q] : mydump) = na;
-            *(zlane ? &Zr[q] : mydump) = cs * zk + sn * z1;
+            // every lane writes: the scalar values are the same in all lanes,
+            // and lanes 16.. repeat the Z rows of lanes 0..15 with the same
+            // values; the first rotation of a sweep has no B to write (slot
+            // kQN - 1, past every B the sweeps read and before Z's first row)
+            B_[q > lo ? q - 1 : kQN - 1] = r;
+            A_[q] = na;
+            Zr[q] = cs * zk + sn * z1;
             zk = -sn * zk + cs * z1;
             ak = na1;
             bk = cs * bk1;
@@ -747,7 +751,7 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
             A_[hi] = ak;
             B_[hi - 1] = nbk;
         }
-        if (zlane) Zr[hi] = zk;
+        Zr[hi] = zk;
         __syncthreads();
     }
     __syncthreads();
