@@ -215,4 +215,14 @@ __device__ __forceinline__ double group_sum4(double x)
 // every lane gets the same value, in a fixed order
 __device__ __forceinline__ double wave_sum_dpp(double x) { return group_sum4(row_sum16(x)); }
 
+// 1/sqrt(x) for a positive, finite, normal x (no special-case handling): the
+// hardware estimate y0 refined by the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8
+// + ... to second order, e = 1 - x y0^2.
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
 }  // namespace ecnt

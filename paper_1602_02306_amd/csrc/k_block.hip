@@ -699,7 +699,7 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
             // (q2 = 0 only when x = y = 0: then r = sn = 0 as they stand)
             const double q2 = x * x + y * y;
             const bool nz = q2 > 0.0;
-            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double ir = rsqrt_pos(nz ? q2 : 1.0);
             const double r = q2 * ir;
             const double cs = nz ? x * ir : 1.0;
             const double sn = y * ir;

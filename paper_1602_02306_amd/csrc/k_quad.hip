@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void k_tridiag(int NC, int C, int ld, int off, 
             // |x|, |y| far from the under/overflow range: J_k holds O(|C|) entries
             const double q2 = x * x + y * y;
             const bool nz = q2 > 0.0;
-            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double ir = rsqrt_pos(nz ? q2 : 1.0);
             const double r = nz ? q2 * ir : 0.0;
             const double cs = nz ? x * ir : 1.0;
             const double sn = nz ? y * ir : 0.0;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int 
             // (q2 = 0 only when x = y = 0: then r = sn = 0 as they stand)
             const double q2 = x * x + y * y;
             const bool nz = q2 > 0.0;
-            const double ir = rsqrt(nz ? q2 : 1.0);
+            const double ir = rsqrt_pos(nz ? q2 : 1.0);
             const double r = q2 * ir;
             const double cs = nz ? x * ir : 1.0;
             const double sn = y * ir;
