@@ -50,10 +50,20 @@ __device__ __forceinline__ double block_chunk_sum(const double *__restrict__ par
 {
     __shared__ double red[kFinWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double s = 0.0;
-    if (valid)
-        for (int64_t ch = ch0 + w; ch < ch1; ch += kFinWaves)
-            s += part[((size_t)ch * rows + row) * C + c];
+    // four running sums per wavefront (chunks ch, ch + kFinWaves, ... taken in
+    // turn), so four loads are in flight; combined in a fixed order
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (valid) {
+        int64_t ch = ch0 + w;
+        for (; ch + 3 * kFinWaves < ch1; ch += 4 * kFinWaves) {
+            s0 += part[((size_t)ch * rows + row) * C + c];
+            s1 += part[((size_t)(ch + kFinWaves) * rows + row) * C + c];
+            s2 += part[((size_t)(ch + 2 * kFinWaves) * rows + row) * C + c];
+            s3 += part[((size_t)(ch + 3 * kFinWaves) * rows + row) * C + c];
+        }
+        for (; ch < ch1; ch += kFinWaves) s0 += part[((size_t)ch * rows + row) * C + c];
+    }
+    const double s = (s0 + s1) + (s2 + s3);
     red[w][lane] = s;
     __syncthreads();
     double t = 0.0;
