@@ -101,12 +101,15 @@ __global__ void k_ldl_band_fill(int64_t n, int64_t nnz, const int32_t *__restric
                                 const int32_t *__restrict__ ci, const double *__restrict__ lv,
                                 double *__restrict__ bf, double *__restrict__ bb)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a wavefront per row, its lanes over the row's entries (each entry has
+    // its own slot in either band)
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= n) return;
     int64_t p0 = rp[i], p1 = rp[i + 1];
     p0 = p0 < 0 ? 0 : (p0 > nnz ? nnz : p0);
     p1 = p1 < p0 ? p0 : (p1 > nnz ? nnz : p1);
-    for (int64_t p = p0; p < p1; ++p) {
+    for (int64_t p = p0 + lane; p < p1; p += 64) {
         const int64_t j = ci[p], d = i - j;
         if (j < 0 || j >= n || d < 1 || d > kRing) continue;   // outside the declared bandwidth
         bf[(size_t)i * kRing + kRing - d] = lv[p];
@@ -322,7 +325,7 @@ void launch_ldl_eblocks(const Plan &p, hipStream_t st)
                                                                      ed, eo);
         double *bf = band_of(p, s, 0), *bb = band_of(p, s, 1);
         k_ldl_band_zero<<<1024, 256, 0, st>>>(p.n, bf, bb);
-        k_ldl_band_fill<<<(unsigned)((p.n + 255) / 256), 256, 0, st>>>(
+        k_ldl_band_fill<<<(unsigned)((p.n + 3) / 4), 256, 0, st>>>(
             p.n, p.ldl[s].nnz, p.ldl[s].lrp, p.ldl[s].lci, p.ldl[s].lval, bf, bb);
     }
 }
