@@ -640,7 +640,7 @@ __global__ __launch_bounds__(64) void k_blk_quad(int nblk, int c_off, double smo
     __syncthreads();
 
     // ---- implicit QR sweeps with Wilkinson shifts on (diagonal 0, diagonal 1) ----
-    // every lane runs the scalar chain, lanes 0..15 rotate their row of Z
+    // every lane runs the scalar chain and rotates row lane mod 16 of Z
     double *A_ = Lb;
     double *B_ = Lb + kQN;
     const int zrow = lane & 15;

@@ -247,7 +247,8 @@ __global__ __launch_bounds__(256) void k_reduce(int S, int m, const double *__re
 // runs the rotation chain on the same values, the search for the unreduced
 // block takes 64 candidates at a time (a ballot), and each sweep carries its
 // changing values in registers with the values ahead loaded three rotations
-// early, as the lane form does.  Lane 0 makes the writes.
+// early, as the lane form does.  A rotation's writes come from every lane (the
+// same values to the same slots); lane 0 makes the others.
 template <int KMAX>
 __global__ __launch_bounds__(64) void k_tridiag_wave(int NC, int C, int ld, int off, int k, int rule,
                                                      double smooth_w,
