@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -51,12 +52,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_sources_sha() -> str:
+def _code_only(text: str) -> str:
+    """Source text without comments and trailing blanks (the kernels' code:
+    counters taken on it stay valid when only a comment changes)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
+def kernel_sources_sha(csrc: str | None = None) -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1602_02306_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_1602_02306_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            h.update(f.encode())
+            h.update(_code_only(open(os.path.join(csrc, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 
